@@ -1,0 +1,133 @@
+"""The five lattice workloads and a generator for small variants.
+
+Each problem is a plain dict of numpy arrays and scalars:
+
+  nx, ny       cells along x and y (cell (ix, iy) has index iy*nx + ix)
+  p, q         GLL degree of the cell element and of the coefficient
+               interpolation used by the fast assembly
+  m            Bernstein order of the map; the shared control net has
+               (m*ny+1) x (m*nx+1) points, ctrl[jy, jx] = (x, y)
+  ctrl         float64 [(m*ny+1), (m*nx+1), 2]
+  family       int32 [ncell] level-set family per cell (0 circle, 1 cross)
+  t            float64 [ncell] thickness parameter per cell
+  E, nu, rho   material (plane strain) and stabilisation factor
+  traction     float64 [nrhs, ny, 2] constant traction on the right-edge
+               segment of each cell of the last column (physical units)
+  moments      whether edge-moment coarse dofs are used
+  rtol         PCG relative residual tolerance
+  rom          {family: dict(lo, hi, n_k, n_s, n_r, r)} ROM settings
+
+The left side x = 0 is clamped; the other outer sides are traction free
+except the right side, which carries the traction.
+"""
+import numpy as np
+
+FAMILY_NAMES = {0: "circle", 1: "cross"}
+
+
+def family_name(f):
+    return FAMILY_NAMES[int(f)]
+
+
+CONFIGS = {
+    # plain FP64 method, tiny: affine (identity) map, circle holes r~U[0.2,0.4]
+    1: dict(nx=4, ny=4, p=3, q=2, m=1, jitter=0.0, warp=0.0, topo="circle",
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=0.0, moments=False,
+            rtol=1e-8, nrhs=1, load="unit",
+            rom={0: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=20, r=6)}),
+    # plain FP64 at scale: order-2 jittered map, hole radius graded in x
+    2: dict(nx=64, ny=64, p=6, q=2, m=2, jitter=0.03, warp=0.0, topo="circle",
+            t_mode="graded", t_lo=0.08, t_hi=0.37, rho=5e-4, moments=True,
+            rtol=1e-10, nrhs=1, load="unit",
+            rom={0: dict(lo=0.05, hi=0.40, n_k=2, n_s=300, n_r=40, r=6)}),
+    # the measured workload: 128x128 p=8, mixed circle/cross topologies
+    3: dict(nx=128, ny=128, p=8, q=2, m=2, jitter=0.03, warp=0.0, topo="mixed",
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=5e-4, moments=True,
+            rtol=1e-8, nrhs=1, load="unit",
+            rom={0: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6),
+                 1: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6)}),
+    # differentiation: order-3 map, circle, t~U[0.1,0.3]
+    4: dict(nx=64, ny=64, p=6, q=2, m=3, jitter=0.02, warp=0.0, topo="circle",
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=5e-4, moments=True,
+            rtol=1e-13, nrhs=1, load="unit",
+            rom={0: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6)}),
+    # large multi-RHS: order-3 sinusoidal warp, two topologies, 8 loads
+    5: dict(nx=256, ny=256, p=8, q=2, m=3, jitter=0.0, warp=0.05, topo="mixed",
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=5e-4, moments=True,
+            rtol=1e-8, nrhs=8, load="random",
+            rom={0: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6),
+                 1: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6)}),
+}
+
+
+def _uniform_net(nx, ny, m):
+    gx = np.arange(m * nx + 1, dtype=np.float64) / m
+    gy = np.arange(m * ny + 1, dtype=np.float64) / m
+    net = np.zeros((m * ny + 1, m * nx + 1, 2))
+    net[:, :, 0] = gx[None, :]
+    net[:, :, 1] = gy[:, None]
+    return net
+
+
+def make_problem(config=1, seed=None, **overrides):
+    """Build the seeded inputs of workload `config` (1..5).
+
+    `overrides` replace entries of the config table (e.g. nx=8, ny=4, p=4)
+    so tests can draw smaller lattices with the same recipe.  The seed
+    defaults to the config number.
+    """
+    cfg = dict(CONFIGS[config])
+    cfg["rom"] = {k: dict(v) for k, v in cfg["rom"].items()}
+    cfg.update(overrides)
+    if seed is None:
+        seed = config
+    rng = np.random.default_rng(seed)
+    nx, ny, m = cfg["nx"], cfg["ny"], cfg["m"]
+    net = _uniform_net(nx, ny, m)
+    interior = np.zeros(net.shape[:2], dtype=bool)
+    interior[1:-1, 1:-1] = True
+    jit = rng.normal(0.0, 1.0, size=net.shape)
+    if cfg["jitter"] > 0:
+        net = net + cfg["jitter"] * jit * interior[:, :, None]
+    if cfg["warp"] > 0:
+        gxy = _uniform_net(nx, ny, m)
+        wx = np.sin(2 * np.pi * gxy[:, :, 1] / ny)
+        wy = np.sin(2 * np.pi * gxy[:, :, 0] / nx)
+        net[:, :, 0] += cfg["warp"] * wx * interior
+        net[:, :, 1] += cfg["warp"] * wy * interior
+    ncell = nx * ny
+    coin = rng.random(ncell)
+    if cfg["topo"] == "circle":
+        family = np.zeros(ncell, dtype=np.int32)
+    elif cfg["topo"] == "cross":
+        family = np.ones(ncell, dtype=np.int32)
+    else:
+        family = (coin < 0.5).astype(np.int32)
+    u = rng.random(ncell)
+    if cfg["t_mode"] == "graded":
+        # hole radius r = 0.15 + 0.25 * xc / nx + U[-0.02, 0.02], t = 1/2 - r
+        ix = np.arange(ncell) % nx
+        r = 0.15 + 0.25 * (ix + 0.5) / nx + (u * 0.04 - 0.02)
+        t = 0.5 - r
+    else:
+        t = cfg["t_lo"] + (cfg["t_hi"] - cfg["t_lo"]) * u
+    nrhs = cfg["nrhs"]
+    if cfg["load"] == "unit":
+        traction = np.zeros((nrhs, ny, 2))
+        traction[:, :, 0] = 1.0
+    else:
+        traction = rng.normal(0.0, 1.0, size=(nrhs, ny, 2))
+    present = sorted(set(int(f) for f in np.unique(family)))
+    rom = {f: cfg["rom"][f] for f in cfg["rom"] if f in present or len(present) == 0}
+    return dict(config=config, seed=seed, nx=nx, ny=ny, p=cfg["p"], q=cfg["q"],
+                m=m, ctrl=np.ascontiguousarray(net), family=family,
+                t=np.ascontiguousarray(t, dtype=np.float64), E=1.0, nu=0.3,
+                rho=cfg["rho"], moments=cfg["moments"], rtol=cfg["rtol"],
+                traction=np.ascontiguousarray(traction), rom=rom)
+
+
+def rom_lhs_uniforms(family, n_k, n_s):
+    """The U[0,1) draws of the stratified Latin-hypercube sampling of each
+    cluster of `family` (d = 1): returns [n_k, n_s]."""
+    rng = np.random.default_rng(100 + int(family))
+    return rng.random((n_k, n_s))
