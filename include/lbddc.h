@@ -1,0 +1,217 @@
+/*
+ * lbddc.h -- C ABI of the MI355X library for the ROM-accelerated BDDC solver of
+ * two-dimensional level-set lattices (Bonilla Moreno, Guarino, Antolin,
+ * arXiv 2604.09113).
+ *
+ * The library runs the online, per-cell data-parallel part of the method on one
+ * GPU:
+ *   assemble  every cell's single high-order stiffness matrix by the fast
+ *             assembly with the MDEIM surrogate and the alpha-stabilisation
+ *             (Sec. 4.1-4.2, Alg. 4 and 5);
+ *   setup     local Schur complements (Sec. 3.2), constraints, constrained local
+ *             factorizations, coarse basis and coarse matrix, partition-of-unity
+ *             weights (Sec. 3.3, Alg. 2), and the exact FP64 coarse factorization;
+ *   solve     PCG on the interface problem with the BDDC preconditioner (Alg. 1)
+ *             and interior recovery;
+ *   gradient  the compliance f^T u and its gradient with respect to the control
+ *             net and the per-cell thickness parameters (discrete adjoint; the
+ *             adjoint state equals u).
+ *
+ * Conventions
+ *   - Every call returns an lbddc_status; 0 is success.  No call aborts or
+ *     throws across the ABI.  After a failure lbddc_last_error() describes it and
+ *     the context keeps its previous valid state.
+ *   - Host pointers passed in are read during the call only (copied to device
+ *     memory before return); the caller keeps ownership.  Host output buffers are
+ *     written before return.  The library owns every device allocation it makes
+ *     and frees it in lbddc_destroy.
+ *   - Calls follow the state order create -> load_rom (one per family) ->
+ *     set_problem -> assemble -> setup -> solve -> (get_displacement,
+ *     compliance_gradient).  Calling out of order returns LBDDC_E_STATE.  A new
+ *     set_problem or a new assemble invalidates the later stages.
+ *   - One host thread per context.  Work is enqueued on the context's stream;
+ *     calls that return host data synchronise that stream.
+ *   - Results are deterministic: equal inputs give bitwise-equal outputs (no
+ *     floating-point atomics; every sum over cells runs in a fixed order).
+ *
+ * Geometry (Sec. 2.1): an nx x ny lattice of unit parametric cells, cell (ix, iy)
+ * has index iy*nx + ix.  The map of every cell is a Bernstein (Bezier) patch of
+ * order m taken from one shared control net of (m*ny+1) x (m*nx+1) points,
+ * row-major with x fastest: ctrl[(jy*(m*nx+1) + jx)*2 + c].  The left side of the
+ * lattice (jx = 0 column of cells) is clamped (homogeneous Dirichlet on both
+ * components, strongly, on the whole side); the right side carries a traction
+ * that is constant on each cell edge (per unit physical length); the other sides
+ * are traction free.
+ *
+ * Level sets: each cell belongs to a level-set family with one parameter t (the
+ * role of the threshold of Sec. 2.1.2).  The geometry of a family enters only
+ * through its trained ROM (Sec. 4.2), which the caller supplies.
+ */
+#ifndef LBDDC_H
+#define LBDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbddc_ctx lbddc_ctx;
+
+typedef enum {
+  LBDDC_OK = 0,
+  LBDDC_E_ARG = -1,            /* a null pointer, a size out of range, a non-finite input */
+  LBDDC_E_NOMEM = -2,          /* device or host allocation failed */
+  LBDDC_E_HIP = -3,            /* a HIP runtime call failed */
+  LBDDC_E_STATE = -4,          /* call out of order */
+  LBDDC_E_DEGENERATE_MAP = -5, /* det J <= 0 somewhere in a cell (regular maps are required, Sec. 4.1) */
+  LBDDC_E_PARAM_RANGE = -6,    /* a thickness outside the trained box of its family's ROM (Sec. 4.2) */
+  LBDDC_E_ROM = -7,            /* no ROM for a family, or ROM degrees differ from the problem's */
+  LBDDC_E_NOT_CONVERGED = -8,  /* PCG reached max_iter; info holds the last residual */
+  LBDDC_E_BREAKDOWN = -9,      /* p^T S p <= 0 or r^T z <= 0 in PCG */
+  LBDDC_E_NUMERIC = -10,       /* a non-positive pivot in a local factorization, or a NaN */
+  LBDDC_E_UNSUPPORTED = -11    /* a size this build does not support */
+} lbddc_status;
+
+typedef enum {
+  LBDDC_FP64 = 0,   /* every step in FP64 */
+  LBDDC_MIXED = 1   /* FP64 operator, recurrence and coarse solve; the constrained local
+                       factorizations and the preconditioner data and solves in FP32 */
+} lbddc_precision;
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t to enqueue
+ * on (NULL = a stream created and owned by the context). */
+lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out);
+void lbddc_destroy(lbddc_ctx* ctx);
+/* Message of the last failure on ctx (valid until the next call on ctx). */
+const char* lbddc_last_error(const lbddc_ctx* ctx);
+int lbddc_version(void);
+
+/* A trained ROM of one level-set family (Sec. 4.2, Alg. 5).  The trimmed-domain
+ * tensor I(t) has n_i = (p+1)^4 * 4 * (q+1)^2 entries in the order
+ *   (((k1*nB + k2)*2 + j1)*2 + j2)*(q+1)^2 + k3,   nB = (p+1)^2,
+ * k1, k2 = a + (p+1) b the GLL nodes of the cell, j1, j2 the parametric
+ * derivative directions, k3 = a + (q+1) b the interpolation nodes.
+ *   U     [n_k][n_i][n_r]   reduced basis of each cluster (zero columns allowed)
+ *   coeff [n_k][r+1][n_r]   I_r at the r+1 GLL points of each cluster interval
+ *   I_pi  [n_i]             the same integral over the untrimmed cell
+ * Clusters split [lo, hi] into n_k equal intervals; t in cluster
+ * min(floor((t-lo)/w), n_k-1).  Limits: 1 <= n_r <= 43, 1 <= r <= 16,
+ * 1 <= n_k <= 64.  Loading a family again replaces it. */
+typedef struct {
+  int32_t family;
+  int32_t p, q;
+  int32_t n_k, n_r, r;
+  double lo, hi;
+  const double* U;
+  const double* coeff;
+  const double* I_pi;
+} lbddc_rom_desc;
+lbddc_status lbddc_load_rom(lbddc_ctx* ctx, const lbddc_rom_desc* rom);
+
+/* The lattice problem (Sec. 2, 3).  Plane-strain isotropic material (E, nu),
+ * stabilisation factor rho (Sec. 2.2.3), coarse dofs: corner values and edge
+ * averages, plus edge moments when `moments` is nonzero (Sec. 3.3.1).
+ * traction[(r*ny + iy)*2 + c]: component c of load case r on the right edge of
+ * cell (nx-1, iy).  Limits: 2 <= p <= 10, q in {1, 2, 3}, 1 <= map_order <= 4,
+ * 1 <= nrhs <= 16, nx, ny >= 1.  Validates det J > 0 at the interpolation
+ * points and on a (2m+2)^2 Gauss sample of every cell (LBDDC_E_DEGENERATE_MAP),
+ * that every family has a ROM of degrees (p, q) (LBDDC_E_ROM) and that every t
+ * lies in its family's box (LBDDC_E_PARAM_RANGE). */
+typedef struct {
+  int32_t nx, ny, p, q, map_order;
+  const double* ctrl;
+  const int32_t* family;
+  const double* t;
+  double E, nu, rho;
+  int32_t moments;
+  int32_t nrhs;
+  const double* traction;
+} lbddc_problem_desc;
+lbddc_status lbddc_set_problem(lbddc_ctx* ctx, const lbddc_problem_desc* desc);
+
+/* Replace the control net and the thickness parameters of the current problem
+ * (device pointers, same sizes as in set_problem, read on the context's stream
+ * before the call returns).  Invalidates assemble and later stages. */
+lbddc_status lbddc_set_geometry_device(lbddc_ctx* ctx, const double* d_ctrl, const double* d_t);
+
+/* Per-cell geometry coefficients, MDEIM evaluation and the batched contraction
+ * K_i = sum_q theta_q Khat_q (Alg. 4, 5), plus the cell loads. */
+lbddc_status lbddc_assemble(lbddc_ctx* ctx, lbddc_precision prec);
+
+/* Local Schur complements, weights, constrained local factorizations, coarse
+ * basis, coarse matrix and its FP64 factorization (Sec. 3.2-3.3, Alg. 2). */
+lbddc_status lbddc_setup(lbddc_ctx* ctx, lbddc_precision prec);
+
+/* PCG with the BDDC preconditioner (Alg. 1) for every load case, from x0 = 0,
+ * stopping when ||f - S x||_2 <= rtol ||f||_2 (recurrence residual), then
+ * interior recovery.  info[r] (host, nrhs entries, may be NULL) receives the
+ * iteration count, the recurrence residual and a recomputed true residual. */
+typedef struct {
+  int32_t iters;
+  double rel_res;
+  double true_rel_res;
+} lbddc_solve_info;
+lbddc_status lbddc_solve(lbddc_ctx* ctx, double rtol, int32_t max_iter, lbddc_solve_info* info);
+
+/* Displacement of load case `rhs` on the GLL node lattice, host buffer
+ * u[(gy*(p*nx+1) + gx)*2 + c], gy in [0, p*ny], gx in [0, p*nx]. */
+lbddc_status lbddc_get_displacement(lbddc_ctx* ctx, int32_t rhs, double* u);
+/* Same into device memory (context stream, not synchronised). */
+lbddc_status lbddc_get_displacement_device(lbddc_ctx* ctx, int32_t rhs, double* d_u);
+
+/* Compliance J_r = f_r^T u_r of every load case and its gradient with respect
+ * to the control net and the thickness parameters:
+ *   dJ = 2 u^T df - u^T dK u  (the adjoint state of the compliance is u).
+ * Host outputs: J[nrhs], dJ_dctrl[nrhs][ctrl size], dJ_dt[nrhs][ncell]; any may
+ * be NULL.  Requires a completed solve. */
+lbddc_status lbddc_compliance_gradient(lbddc_ctx* ctx, double* J, double* dJ_dctrl, double* dJ_dt);
+/* Same into device memory (context stream, not synchronised). */
+lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* ctx, double* d_J, double* d_dJ_dctrl, double* d_dJ_dt);
+
+/* Sizes.  `what`: */
+enum {
+  LBDDC_Q_NCELL = 0, LBDDC_Q_NDOF_FREE = 1, LBDDC_Q_N_SKELETON = 2, LBDDC_Q_N_INTERIOR = 3,
+  LBDDC_Q_N_COARSE = 4, LBDDC_Q_N_I_ROM = 5, LBDDC_Q_NU_CELL = 6, LBDDC_Q_NC_CELL = 7,
+  LBDDC_Q_NRHS = 8, LBDDC_Q_NR_MAX = 9, LBDDC_Q_DEVICE_BYTES = 10
+};
+lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
+
+/* Export per-cell results of `count` cells from `first` into a host buffer (FP64),
+ * for testing.  Layouts per cell:
+ *   K      [2nB][2nB], dof i*nB + k (component i, node k = a + (p+1) b)
+ *   THETA  [4][2][2][(q+1)^2]: C[i1][j1][i2][j2][k3] geometry coefficients
+ *   ITIL   [n_r + 1]: [(1 - rho) I_r(t), rho]
+ *   S      [nU][nU] local Schur complement over the skeleton slots
+ *   D      [nU] partition-of-unity weights
+ *   PSI    [nU][nC] coarse basis
+ *   SC     [nC][nC] local coarse matrix Psi^T S Psi
+ *   LOAD   [nrhs][nU] cell load on the skeleton slots
+ *   FINE   [nU][nU] the fine-correction operator D [S C^T; C 0]^-1|_u D
+ * Skeleton slots (nU = 8p): nodes [BL, BR, TL, TR, left edge, right edge, bottom
+ * edge, top edge] (edge nodes in increasing running coordinate, excluding
+ * corners), slot = 2*node + component.  Coarse slots (nC = 20 with moments, 16
+ * without): [BL.x BL.y BR.x BR.y TL.x TL.y TR.x TR.y] then for the edges
+ * [left, right, bottom, top]: [average x, average y, moment].  Slots on the
+ * clamped side are inactive: their rows and columns of S are the identity and
+ * their D, PSI, SC and FINE entries are zero. */
+enum {
+  LBDDC_X_K = 0, LBDDC_X_THETA = 1, LBDDC_X_ITIL = 2, LBDDC_X_S = 3, LBDDC_X_D = 4,
+  LBDDC_X_PSI = 5, LBDDC_X_SC = 6, LBDDC_X_LOAD = 7, LBDDC_X_FINE = 8
+};
+lbddc_status lbddc_export_cells(lbddc_ctx* ctx, int32_t which, int32_t first, int32_t count, double* out);
+
+/* Device time in milliseconds of the most recent launches of each phase, timed
+ * with HIP events on the context stream:
+ *   [0] assembly contraction kernel, [1] whole assemble, [2] local Schur kernel,
+ *   [3] whole setup, [4] coarse factorization, [5] whole solve (all load cases),
+ *   [6] PCG operator kernel (mean per launch), [7] preconditioner local kernel
+ *   (mean per launch), [8] coarse solve (mean per application), [9] recovery,
+ *   [10] gradient, [11] adjoint contraction kernel.
+ * `n` entries are written (n <= 12). */
+lbddc_status lbddc_phase_times(lbddc_ctx* ctx, double* ms, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBDDC_H */

@@ -1,0 +1,638 @@
+// C ABI of the lbddc library: validation, state machine, device memory and the
+// orchestration of the kernels of each phase.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.h"
+
+using namespace lbddc;
+
+struct lbddc_ctx {
+  Ctx c;
+};
+
+namespace lbddc {
+
+bool dalloc(Ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    hipGetLastError();
+    char buf[128];
+    snprintf(buf, sizeof buf, "device allocation of %zu bytes failed", bytes);
+    c->err = buf;
+    return false;
+  }
+  c->allocs.push_back(*p);
+  c->dev_bytes += bytes;
+  return true;
+}
+
+}  // namespace lbddc
+
+static void free_problem(Ctx* c) {
+  for (void* p : c->allocs) hipFree(p);
+  c->allocs.clear();
+  c->dev_bytes = 0;
+  Ctx fresh;
+  // keep device, stream, ROMs, events and pinned buffers
+  fresh.device = c->device;
+  fresh.stream = c->stream;
+  fresh.own_stream = c->own_stream;
+  fresh.roms = std::move(c->roms);
+  for (int i = 0; i < 8; ++i) fresh.ev[i] = c->ev[i];
+  fresh.h_flags = c->h_flags;
+  fresh.h_scal = c->h_scal;
+  fresh.err = c->err;
+  *c = std::move(fresh);
+}
+
+static lbddc_status fail(Ctx* c, lbddc_status s, const char* msg) {
+  c->err = msg;
+  return s;
+}
+
+static lbddc_status hipfail(Ctx* c, hipError_t e, const char* where) {
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  c->err = buf;
+  return LBDDC_E_HIP;
+}
+
+#define HIPCHK(expr, where)                  \
+  do {                                       \
+    hipError_t _e = (expr);                  \
+    if (_e != hipSuccess) return hipfail(c, _e, where); \
+  } while (0)
+
+static lbddc_status check_flags(Ctx* c, const char* phase) {
+  HIPCHK(hipMemcpyAsync(c->h_flags, c->d_flags, 8 * sizeof(int), hipMemcpyDeviceToHost, c->stream), phase);
+  HIPCHK(hipStreamSynchronize(c->stream), phase);
+  int f = c->h_flags[0];
+  if (!f) return LBDDC_OK;
+  char buf[256];
+  lbddc_status s = LBDDC_E_NUMERIC;
+  const char* what = "non-positive pivot in a local factorization";
+  if (f & 1) { s = LBDDC_E_DEGENERATE_MAP; what = "det J <= 0 in a cell map"; }
+  else if (f & 4) { s = LBDDC_E_ROM; what = "a cell's family has no ROM"; }
+  else if (f & 2) { s = LBDDC_E_PARAM_RANGE; what = "a thickness parameter lies outside its ROM box"; }
+  else if (f & 8) what = "non-positive pivot in K_II (local Schur complement)";
+  else if (f & 16) what = "non-positive pivot in the constrained local factorization";
+  else if (f & 32) what = "non-positive pivot in the coarse factorization";
+  snprintf(buf, sizeof buf, "%s: %s (flags 0x%x)", phase, what, f);
+  c->err = buf;
+  int zero[8] = {0};
+  hipMemcpy(c->d_flags, zero, sizeof zero, hipMemcpyHostToDevice);
+  return s;
+}
+
+extern "C" {
+
+int lbddc_version(void) { return 1; }
+
+lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out) {
+  if (!out) return LBDDC_E_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LBDDC_E_ARG;
+  if (hipSetDevice(device) != hipSuccess) return LBDDC_E_HIP;
+  lbddc_ctx* x = new (std::nothrow) lbddc_ctx();
+  if (!x) return LBDDC_E_NOMEM;
+  Ctx* c = &x->c;
+  c->device = device;
+  if (stream) {
+    c->stream = (hipStream_t)stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) { delete x; return LBDDC_E_HIP; }
+    c->own_stream = true;
+  }
+  for (int i = 0; i < 8; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete x; return LBDDC_E_HIP; }
+  if (hipHostMalloc((void**)&c->h_flags, 128 * sizeof(int)) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_scal, 32 * sizeof(double)) != hipSuccess) {
+    delete x;
+    return LBDDC_E_NOMEM;
+  }
+  *out = x;
+  return LBDDC_OK;
+}
+
+void lbddc_destroy(lbddc_ctx* x) {
+  if (!x) return;
+  Ctx* c = &x->c;
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) hipFree(p);
+  for (auto& kv : c->roms) {
+    for (auto p : kv.second.ut64) hipFree(p);
+    for (auto p : kv.second.ut32) hipFree(p);
+    if (kv.second.coeff) hipFree(kv.second.coeff);
+  }
+  for (int i = 0; i < 8; ++i)
+    if (c->ev[i]) hipEventDestroy(c->ev[i]);
+  if (c->h_flags) hipHostFree(c->h_flags);
+  if (c->h_scal) hipHostFree(c->h_scal);
+  if (c->own_stream) hipStreamDestroy(c->stream);
+  delete x;
+}
+
+const char* lbddc_last_error(const lbddc_ctx* x) { return x ? x->c.err.c_str() : "null context"; }
+
+// Tile the reduced basis for the contraction kernel: per 16-pair tile, per s,
+// per k-chunk, the 64 MFMA A-operand values (row = lane % 16, k = lane / 16).
+// FP64 MFMA 16x16x4 returns rows lane/16 + 4v, so the FP64 rows are permuted to
+// hand each lane four consecutive pairs.
+lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!d || !d->U || !d->coeff || !d->I_pi) return fail(c, LBDDC_E_ARG, "load_rom: null pointer");
+  if (d->p < 2 || d->p > kMaxP || d->q < 1 || d->q > 3) return fail(c, LBDDC_E_UNSUPPORTED, "load_rom: p or q out of range");
+  if (d->n_r < 1 || d->n_r > 43 || d->r < 1 || d->r > 16 || d->n_k < 1 || d->n_k > 64)
+    return fail(c, LBDDC_E_UNSUPPORTED, "load_rom: n_r, r or n_k out of range");
+  if (d->family < 0 || d->family >= 64) return fail(c, LBDDC_E_ARG, "load_rom: family id must be in [0, 64)");
+  if (!(d->hi > d->lo) || !std::isfinite(d->lo) || !std::isfinite(d->hi)) return fail(c, LBDDC_E_ARG, "load_rom: bad box");
+  hipSetDevice(c->device);
+  const int p = d->p, q = d->q, nB = (p + 1) * (p + 1), nL = (q + 1) * (q + 1), ns = 4 * nL;
+  const int nN = nB, npair = nN * (nN + 1) / 2, NPT = (npair + 15) / 16;
+  const long long n_i = (long long)nB * nB * ns;
+  const int KC = (d->n_r + 1 + 3) / 4;
+  // permuted node order (interior nodes, then skeleton slots) -> natural index
+  std::vector<int> perm;
+  for (int b = 1; b < p; ++b)
+    for (int a = 1; a < p; ++a) perm.push_back(a + (p + 1) * b);
+  {
+    int corners[4][2] = {{0, 0}, {p, 0}, {0, p}, {p, p}};
+    for (auto& cc : corners) perm.push_back(cc[0] + (p + 1) * cc[1]);
+    for (int b = 1; b < p; ++b) perm.push_back(0 + (p + 1) * b);
+    for (int b = 1; b < p; ++b) perm.push_back(p + (p + 1) * b);
+    for (int a = 1; a < p; ++a) perm.push_back(a);
+    for (int a = 1; a < p; ++a) perm.push_back(a + (p + 1) * p);
+  }
+  std::vector<int> pn1(npair), pn2(npair);
+  for (int n1 = 0, P = 0; n1 < nN; ++n1)
+    for (int n2 = 0; n2 <= n1; ++n2, ++P) { pn1[P] = n1; pn2[P] = n2; }
+  RomDev R;
+  R.family = d->family; R.p = p; R.q = q; R.n_k = d->n_k; R.n_r = d->n_r; R.r = d->r;
+  R.lo = d->lo; R.hi = d->hi; R.KC = KC;
+  const size_t tile_n = (size_t)NPT * ns * KC * 64;
+  std::vector<double> h64(tile_n);
+  std::vector<float> h32(tile_n);
+  for (int k = 0; k < d->n_k; ++k) {
+    const double* U = d->U + (size_t)k * n_i * d->n_r;
+    for (int pt = 0; pt < NPT; ++pt)
+      for (int s = 0; s < ns; ++s)
+        for (int kc = 0; kc < KC; ++kc)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int row = lane & 15, r = 4 * kc + (lane >> 4);
+            const int off64 = 4 * (row & 3) + (row >> 2);  // FP64 row permutation
+            double v64 = 0.0, v32 = 0.0;
+            for (int which = 0; which < 2; ++which) {
+              const int P = pt * 16 + (which == 0 ? off64 : row);
+              double v = 0.0;
+              if (P < npair) {
+                const long long idx = ((long long)perm[pn1[P]] * nB + perm[pn2[P]]) * ns + s;
+                if (r < d->n_r) v = U[(size_t)idx * d->n_r + r];
+                else if (r == d->n_r) v = d->I_pi[idx];
+              }
+              if (which == 0) v64 = v; else v32 = v;
+            }
+            const size_t o = (((size_t)pt * ns + s) * KC + kc) * 64 + lane;
+            h64[o] = v64;
+            h32[o] = (float)v32;
+          }
+    double* d64 = nullptr;
+    float* d32 = nullptr;
+    if (hipMalloc(&d64, tile_n * 8) != hipSuccess || hipMalloc(&d32, tile_n * 4) != hipSuccess)
+      return fail(c, LBDDC_E_NOMEM, "load_rom: device allocation failed");
+    if (hipMemcpy(d64, h64.data(), tile_n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d32, h32.data(), tile_n * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(c, LBDDC_E_HIP, "load_rom: copy failed");
+    R.ut64.push_back(d64);
+    R.ut32.push_back(d32);
+  }
+  const size_t nco = (size_t)d->n_k * (d->r + 1) * d->n_r;
+  if (hipMalloc(&R.coeff, nco * 8) != hipSuccess) return fail(c, LBDDC_E_NOMEM, "load_rom: allocation failed");
+  if (hipMemcpy(R.coeff, d->coeff, nco * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(c, LBDDC_E_HIP, "load_rom: copy failed");
+  auto it = c->roms.find(d->family);
+  if (it != c->roms.end()) {
+    for (auto p2 : it->second.ut64) hipFree(p2);
+    for (auto p2 : it->second.ut32) hipFree(p2);
+    if (it->second.coeff) hipFree(it->second.coeff);
+  }
+  c->roms[d->family] = R;
+  c->have_problem = c->assembled = c->setup_done = c->solved = false;
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!d || !d->ctrl || !d->family || !d->t || !d->traction) return fail(c, LBDDC_E_ARG, "set_problem: null pointer");
+  if (d->nx < 1 || d->ny < 1 || (long long)d->nx * d->ny > (1LL << 22)) return fail(c, LBDDC_E_ARG, "set_problem: bad grid size");
+  if (d->p < 2 || d->p > 8) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: 2 <= p <= 8 supported");
+  if (d->q < 1 || d->q > 3 || d->map_order < 1 || d->map_order > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: q or map order out of range");
+  if (d->nrhs < 1 || d->nrhs > 16) return fail(c, LBDDC_E_ARG, "set_problem: 1 <= nrhs <= 16");
+  if (!(d->E > 0) || !(d->nu > -1 && d->nu < 0.5) || !(d->rho >= 0 && d->rho < 1))
+    return fail(c, LBDDC_E_ARG, "set_problem: material or rho out of range");
+  const int ncell = d->nx * d->ny;
+  const int netx = d->map_order * d->nx + 1, nety = d->map_order * d->ny + 1;
+  for (size_t i = 0; i < (size_t)netx * nety * 2; ++i)
+    if (!std::isfinite(d->ctrl[i])) return fail(c, LBDDC_E_ARG, "set_problem: non-finite control point");
+  for (size_t i = 0; i < (size_t)d->nrhs * d->ny * 2; ++i)
+    if (!std::isfinite(d->traction[i])) return fail(c, LBDDC_E_ARG, "set_problem: non-finite traction");
+  std::vector<int> fam_ids;
+  for (int i = 0; i < ncell; ++i) {
+    int f = d->family[i];
+    auto it = c->roms.find(f);
+    if (it == c->roms.end()) return fail(c, LBDDC_E_ROM, "set_problem: a cell's family has no loaded ROM");
+    if (it->second.p != d->p || it->second.q != d->q) return fail(c, LBDDC_E_ROM, "set_problem: ROM degrees differ from the problem's");
+    double t = d->t[i];
+    if (!std::isfinite(t)) return fail(c, LBDDC_E_ARG, "set_problem: non-finite thickness");
+    if (!(t >= it->second.lo && t <= it->second.hi))
+      return fail(c, LBDDC_E_PARAM_RANGE, "set_problem: a thickness parameter lies outside its ROM box");
+    if (std::find(fam_ids.begin(), fam_ids.end(), f) == fam_ids.end()) fam_ids.push_back(f);
+  }
+  if (fam_ids.size() > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 4 families per problem");
+  std::sort(fam_ids.begin(), fam_ids.end());
+  int G = 0;
+  for (int f : fam_ids) G += c->roms[f].n_k;
+  if (G > 16) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 16 (family, cluster) groups");
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  free_problem(c);
+  c->fam_ids = fam_ids;
+  c->nx = d->nx; c->ny = d->ny; c->p = d->p; c->q = d->q; c->m = d->map_order; c->nrhs = d->nrhs;
+  c->E = d->E; c->nu = d->nu; c->rho = d->rho; c->moments = d->moments != 0;
+  c->ncell = ncell; c->nB = (c->p + 1) * (c->p + 1); c->ndof = 2 * c->nB; c->nN = c->nB;
+  c->nIn = (c->p - 1) * (c->p - 1); c->nI = 2 * c->nIn; c->nU = 8 * c->p; c->nE = c->nU - 8;
+  c->nce = c->moments ? 3 : 2; c->nC = 8 + 4 * c->nce; c->nL = (c->q + 1) * (c->q + 1); c->ns = 4 * c->nL;
+  c->npair = c->nN * (c->nN + 1) / 2; c->NPT = (c->npair + 15) / 16;
+  c->n_i = (long long)c->nB * c->nB * c->ns;
+  c->Gx = c->p * c->nx + 1; c->Gy = c->p * c->ny + 1; c->netx = netx; c->nety = nety;
+  c->KC = 0;
+  for (int f : fam_ids) c->KC = std::max(c->KC, c->roms[f].KC);
+  c->NI = c->nI * ncell;
+  c->Nfree = 2 * (c->Gx * c->Gy - c->Gy);
+  if (!build_topology(c)) { lbddc_status s = c->err.empty() ? LBDDC_E_NOMEM : LBDDC_E_NOMEM; free_problem(c); return s; }
+  std::vector<double> tab;
+  build_tables(c, tab);
+  const size_t nU = c->nU, nC = c->nC, NU = c->NU, NC = c->NC;
+  bool ok = dalloc_t(c, &c->d_tab, tab.size()) && dalloc_t(c, &c->d_ctrl, (size_t)netx * nety * 2) &&
+            dalloc_t(c, &c->d_family, ncell) && dalloc_t(c, &c->d_t, ncell) &&
+            dalloc_t(c, &c->d_trac, (size_t)c->nrhs * c->ny * 2) && dalloc_t(c, &c->d_flags, 128) &&
+            dalloc_t(c, &c->d_theta, (size_t)ncell * c->ns * 4) && dalloc_t(c, &c->d_theta32, (size_t)ncell * c->ns * 4) &&
+            dalloc_t(c, &c->d_itil, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_itil32, (size_t)ncell * 4 * c->KC) &&
+            dalloc_t(c, &c->d_cluster, ncell) && dalloc_t(c, &c->d_sorted, ncell) &&
+            dalloc_t(c, &c->d_tiles, (size_t)4 * (ncell / 16 + 64) + 64) &&
+            dalloc_t(c, &c->d_K, (size_t)ncell * c->npair * 4) &&
+            dalloc_t(c, &c->d_load, (size_t)c->nrhs * ncell * nU) &&
+            dalloc_t(c, &c->d_cons, (size_t)ncell * 4 * c->nce * (c->p + 1) * 2) &&
+            dalloc_t(c, &c->d_S, (size_t)ncell * nU * (nU + 1) / 2) &&
+            dalloc_t(c, &c->d_L, (size_t)ncell * c->nI * (c->nI + 1) / 2) &&
+            dalloc_t(c, &c->d_Y, (size_t)ncell * c->nI * nU) && dalloc_t(c, &c->d_diagK, (size_t)ncell * nU) &&
+            dalloc_t(c, &c->d_Ktot, NU) && dalloc(c, &c->d_P, (size_t)ncell * c->nE * (c->nE + 1) / 2 * 8) &&
+            dalloc(c, &c->d_Psi, (size_t)ncell * nU * nC * 8) && dalloc_t(c, &c->d_D, (size_t)ncell * nU) &&
+            dalloc_t(c, &c->d_ScLoc, (size_t)ncell * nC * (nC + 1) / 2) &&
+            dalloc_t(c, &c->d_coarse, (size_t)(c->co.dense_total + c->co.nnzB + c->co.nnzBT)) &&
+            dalloc_t(c, &c->d_gjP, 64 * 64) && dalloc_t(c, &c->d_gjR, (size_t)64 * c->co.mmax) &&
+            dalloc_t(c, &c->d_gjC, (size_t)64 * (c->co.mmax + 64)) &&
+            dalloc_t(c, &c->d_gjW, (size_t)c->co.mmax * c->co.mmax) &&
+            dalloc_t(c, &c->d_f, (size_t)c->nrhs * NU) && dalloc_t(c, &c->d_x, (size_t)c->nrhs * NU) &&
+            dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
+            dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
+            dalloc_t(c, &c->d_zc, NC) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC) &&
+            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 16)) && dalloc_t(c, &c->d_scal, 32) &&
+            dalloc_t(c, &c->d_u, (size_t)c->nrhs * c->Gx * c->Gy * 2) &&
+            dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof);
+  if (!ok) { free_problem(c); return LBDDC_E_NOMEM; }
+  // family -> slot table after the 8 flag words
+  std::vector<int> flags(128, 0);
+  for (int f = 0; f < 64; ++f) flags[8 + f] = -1;
+  for (size_t s = 0; s < fam_ids.size(); ++s) flags[8 + fam_ids[s]] = (int)s;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = hipMemcpy(c->d_flags, flags.data(), 128 * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_tab, tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_ctrl, d->ctrl, (size_t)netx * nety * 2 * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_family, d->family, ncell * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_t, d->t, ncell * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_trac, d->traction, (size_t)c->nrhs * c->ny * 2 * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem upload"); }
+  c->fam_host.assign(d->family, d->family + ncell);
+  c->t_host.assign(d->t, d->t + ncell);
+  // validate the maps on the device (det J) right away
+  e = launch_geometry(c);
+  if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem geometry"); }
+  lbddc_status s = check_flags(c, "set_problem");
+  if (s != LBDDC_OK) { std::string m = c->err; free_problem(c); c->err = m; return s; }
+  c->have_problem = true;
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_set_geometry_device(lbddc_ctx* x, const double* d_ctrl, const double* d_t) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->have_problem) return fail(c, LBDDC_E_STATE, "set_geometry_device: no problem");
+  if (!d_ctrl && !d_t) return fail(c, LBDDC_E_ARG, "set_geometry_device: null pointers");
+  hipSetDevice(c->device);
+  if (d_ctrl) HIPCHK(hipMemcpyAsync(c->d_ctrl, d_ctrl, (size_t)c->netx * c->nety * 2 * 8, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  if (d_t) HIPCHK(hipMemcpyAsync(c->d_t, d_t, (size_t)c->ncell * 8, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  HIPCHK(launch_geometry(c), "set_geometry_device");
+  lbddc_status s = check_flags(c, "set_geometry_device");
+  c->assembled = c->setup_done = c->solved = false;
+  return s;
+}
+
+lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->have_problem) return fail(c, LBDDC_E_STATE, "assemble: no problem set");
+  if (prec != LBDDC_FP64 && prec != LBDDC_MIXED && (int)prec != 2) return fail(c, LBDDC_E_ARG, "assemble: bad precision");
+  hipSetDevice(c->device);
+  const bool fp32 = (int)prec == 2;
+  if (fp32 && !c->d_K32) {
+    if (!dalloc_t(c, &c->d_K32, (size_t)c->ncell * c->npair * 4)) return LBDDC_E_NOMEM;
+  }
+  c->assembled = c->setup_done = c->solved = false;
+  HIPCHK(hipEventRecord(c->ev[6], c->stream), "assemble");
+  HIPCHK(launch_geometry(c), "assemble geometry");
+  HIPCHK(launch_constraints_loads(c), "assemble constraints");
+  HIPCHK(launch_assembly(c, fp32, c->ev[0], c->ev[1]), "assemble contraction");
+  HIPCHK(hipEventRecord(c->ev[7], c->stream), "assemble");
+  lbddc_status s = check_flags(c, "assemble");
+  if (s != LBDDC_OK) return s;
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->phase_ms[0] = ms;
+  if (hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess) c->phase_ms[1] = ms;
+  c->asm_prec = prec;
+  c->assembled = !fp32;  // the FP32 contraction alone feeds no later stage
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_setup(lbddc_ctx* x, lbddc_precision prec) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->assembled) return fail(c, LBDDC_E_STATE, "setup: assemble (FP64 or mixed) first");
+  if (prec != LBDDC_FP64 && prec != LBDDC_MIXED) return fail(c, LBDDC_E_ARG, "setup: bad precision");
+  hipSetDevice(c->device);
+  c->setup_done = c->solved = false;
+  const bool fp32 = prec == LBDDC_MIXED;
+  HIPCHK(hipEventRecord(c->ev[6], c->stream), "setup");
+  HIPCHK(hipEventRecord(c->ev[0], c->stream), "setup");
+  HIPCHK(launch_schur(c), "setup schur");
+  HIPCHK(hipEventRecord(c->ev[1], c->stream), "setup");
+  HIPCHK(launch_weights(c), "setup weights");
+  HIPCHK(launch_precond(c, fp32), "setup precond");
+  HIPCHK(launch_coarse_assemble(c), "setup coarse assembly");
+  HIPCHK(hipEventRecord(c->ev[2], c->stream), "setup");
+  HIPCHK(launch_coarse_factor(c), "setup coarse factor");
+  HIPCHK(hipEventRecord(c->ev[3], c->stream), "setup");
+  HIPCHK(hipEventRecord(c->ev[7], c->stream), "setup");
+  lbddc_status s = check_flags(c, "setup");
+  if (s != LBDDC_OK) return s;
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->phase_ms[2] = ms;
+  if (hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess) c->phase_ms[3] = ms;
+  if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) c->phase_ms[4] = ms;
+  c->setup_prec = prec;
+  c->setup_done = true;
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solve_info* info) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->setup_done) return fail(c, LBDDC_E_STATE, "solve: setup first");
+  if (!(rtol > 0) || max_iter < 1) return fail(c, LBDDC_E_ARG, "solve: rtol > 0 and max_iter >= 1 required");
+  hipSetDevice(c->device);
+  c->solved = false;
+  const bool fp32 = c->setup_prec == LBDDC_MIXED;
+  c->info.assign(c->nrhs, lbddc_solve_info{0, 0, 0});
+  double t_op = 0, t_pre = 0, t_coarse = 0;
+  int napp = 0, nop = 0;
+  float ms = 0;
+  double t_rec = 0;
+  HIPCHK(hipEventRecord(c->ev[7], c->stream), "solve");
+  hipEvent_t e_start;
+  HIPCHK(hipEventCreate(&e_start), "solve");
+  HIPCHK(hipEventRecord(e_start, c->stream), "solve");
+  lbddc_status status = LBDDC_OK;
+  for (int r = 0; r < c->nrhs; ++r) {
+    // right-hand side: gather-sum of the cell loads (f_I = 0 for edge tractions)
+    HIPCHK(gather_rhs(c, r), "solve rhs");
+    lbddc_solve_info inf{0, 0, 0};
+    hipError_t e = pcg_solve(c, r, rtol, max_iter, &inf, fp32, &t_op, &t_pre, &t_coarse, &napp);
+    nop += inf.iters;
+    if (e == hipErrorUnknown) {
+      c->info[r] = inf;
+      if (info) info[r] = inf;
+      hipStreamSynchronize(c->stream);
+      return fail(c, LBDDC_E_BREAKDOWN, "solve: PCG breakdown (p^T S p <= 0 or r^T z <= 0)");
+    }
+    if (e != hipSuccess) return hipfail(c, e, "solve pcg");
+    HIPCHK(pcg_true_residual(c, r, &inf.true_rel_res), "solve residual");
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, c->stream);
+    HIPCHK(launch_recover(c, r), "solve recovery");
+    hipEventRecord(b, c->stream);
+    hipEventSynchronize(b);
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) t_rec += ms;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    c->info[r] = inf;
+    if (info) info[r] = inf;
+    if (inf.rel_res > rtol) status = LBDDC_E_NOT_CONVERGED;
+  }
+  HIPCHK(hipEventRecord(c->ev[6], c->stream), "solve");
+  HIPCHK(hipEventSynchronize(c->ev[6]), "solve");
+  if (hipEventElapsedTime(&ms, e_start, c->ev[6]) == hipSuccess) c->phase_ms[5] = ms;
+  hipEventDestroy(e_start);
+  c->phase_ms[6] = nop ? t_op / nop : 0;
+  c->phase_ms[7] = napp ? t_pre / napp : 0;
+  c->phase_ms[8] = napp ? t_coarse / napp : 0;
+  c->phase_ms[9] = t_rec;
+  c->solved = true;
+  if (status != LBDDC_OK) c->err = "solve: PCG reached max_iter before rtol";
+  return status;
+}
+
+lbddc_status lbddc_get_displacement(lbddc_ctx* x, int32_t rhs, double* u) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->solved) return fail(c, LBDDC_E_STATE, "get_displacement: solve first");
+  if (rhs < 0 || rhs >= c->nrhs || !u) return fail(c, LBDDC_E_ARG, "get_displacement: bad arguments");
+  hipSetDevice(c->device);
+  const size_t n = (size_t)c->Gx * c->Gy * 2;
+  HIPCHK(hipMemcpyAsync(u, c->d_u + rhs * n, n * 8, hipMemcpyDeviceToHost, c->stream), "get_displacement");
+  HIPCHK(hipStreamSynchronize(c->stream), "get_displacement");
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_get_displacement_device(lbddc_ctx* x, int32_t rhs, double* d_u) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->solved) return fail(c, LBDDC_E_STATE, "get_displacement_device: solve first");
+  if (rhs < 0 || rhs >= c->nrhs || !d_u) return fail(c, LBDDC_E_ARG, "get_displacement_device: bad arguments");
+  hipSetDevice(c->device);
+  const size_t n = (size_t)c->Gx * c->Gy * 2;
+  HIPCHK(hipMemcpyAsync(d_u, c->d_u + rhs * n, n * 8, hipMemcpyDeviceToDevice, c->stream), "get_displacement_device");
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
+  if (!x || !v) return LBDDC_E_ARG;
+  const Ctx* c = &x->c;
+  if (!c->have_problem && what != LBDDC_Q_DEVICE_BYTES) return LBDDC_E_STATE;
+  switch (what) {
+    case LBDDC_Q_NCELL: *v = c->ncell; break;
+    case LBDDC_Q_NDOF_FREE: *v = c->Nfree; break;
+    case LBDDC_Q_N_SKELETON: *v = c->NU; break;
+    case LBDDC_Q_N_INTERIOR: *v = c->NI; break;
+    case LBDDC_Q_N_COARSE: *v = c->NC; break;
+    case LBDDC_Q_N_I_ROM: *v = c->n_i; break;
+    case LBDDC_Q_NU_CELL: *v = c->nU; break;
+    case LBDDC_Q_NC_CELL: *v = c->nC; break;
+    case LBDDC_Q_NRHS: *v = c->nrhs; break;
+    case LBDDC_Q_NR_MAX: *v = 4 * c->KC; break;
+    case LBDDC_Q_DEVICE_BYTES: *v = (int64_t)c->dev_bytes; break;
+    default: return LBDDC_E_ARG;
+  }
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_phase_times(lbddc_ctx* x, double* ms, int32_t n) {
+  if (!x || !ms || n < 0 || n > 12) return LBDDC_E_ARG;
+  for (int i = 0; i < n; ++i) ms[i] = x->c.phase_ms[i];
+  return LBDDC_OK;
+}
+
+lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int32_t count, double* out) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->have_problem) return fail(c, LBDDC_E_STATE, "export: no problem");
+  if (!out || first < 0 || count < 0 || first + count > c->ncell) return fail(c, LBDDC_E_ARG, "export: bad range");
+  const bool need_asm = which == LBDDC_X_K || which == LBDDC_X_LOAD;
+  const bool need_setup = which == LBDDC_X_S || which == LBDDC_X_D || which == LBDDC_X_PSI || which == LBDDC_X_SC || which == LBDDC_X_FINE;
+  if (need_asm && !c->assembled && !(which == LBDDC_X_K && c->d_K32)) return fail(c, LBDDC_E_STATE, "export: assemble first");
+  if (need_setup && !c->setup_done) return fail(c, LBDDC_E_STATE, "export: setup first");
+  hipSetDevice(c->device);
+  HIPCHK(hipStreamSynchronize(c->stream), "export");
+  const int nU = c->nU, nC = c->nC, nB = c->nB, nE = c->nE;
+  auto fetch = [&](const void* base, size_t per, size_t elem) -> std::vector<char> {
+    std::vector<char> h(per * count * elem);
+    hipMemcpy(h.data(), (const char*)base + (size_t)first * per * elem, h.size(), hipMemcpyDeviceToHost);
+    return h;
+  };
+  const bool p32 = c->setup_prec == LBDDC_MIXED;
+  switch (which) {
+    case LBDDC_X_K: {
+      const bool use32 = !c->assembled && c->d_K32;
+      const size_t per = (size_t)c->npair * 4;
+      auto h = use32 ? fetch(c->d_K32, per, 4) : fetch(c->d_K, per, 8);
+      for (int k = 0; k < count; ++k) {
+        double* o = out + (size_t)k * 4 * nB * nB;
+        for (int n1 = 0, P = 0; n1 < c->nN; ++n1)
+          for (int n2 = 0; n2 <= n1; ++n2, ++P)
+            for (int i1 = 0; i1 < 2; ++i1)
+              for (int i2 = 0; i2 < 2; ++i2) {
+                size_t src = ((size_t)k * c->npair + P) * 4 + 2 * i1 + i2;
+                double v = use32 ? (double)((float*)h.data())[src] : ((double*)h.data())[src];
+                int row = i1 * nB + c->perm_nat[n1], col = i2 * nB + c->perm_nat[n2];
+                o[(size_t)row * 2 * nB + col] = v;
+                o[(size_t)col * 2 * nB + row] = v;
+              }
+      }
+      break;
+    }
+    case LBDDC_X_THETA: {
+      auto h = fetch(c->d_theta, (size_t)c->ns * 4, 8);
+      const double* src = (const double*)h.data();
+      for (int k = 0; k < count; ++k)
+        for (int i1 = 0; i1 < 2; ++i1)
+          for (int j1 = 0; j1 < 2; ++j1)
+            for (int i2 = 0; i2 < 2; ++i2)
+              for (int j2 = 0; j2 < 2; ++j2)
+                for (int k3 = 0; k3 < c->nL; ++k3) {
+                  int s = (j1 * 2 + j2) * c->nL + k3;
+                  out[(size_t)k * 16 * c->nL + ((((i1 * 2 + j1) * 2 + i2) * 2 + j2) * c->nL + k3)] =
+                      src[((size_t)k * c->ns + s) * 4 + 2 * i1 + i2];
+                }
+      break;
+    }
+    case LBDDC_X_ITIL: {
+      auto h = fetch(c->d_itil, (size_t)4 * c->KC, 8);
+      memcpy(out, h.data(), h.size());
+      break;
+    }
+    case LBDDC_X_S: {
+      auto h = fetch(c->d_S, (size_t)nU * (nU + 1) / 2, 8);
+      const double* src = (const double*)h.data();
+      for (int k = 0; k < count; ++k)
+        for (int i = 0; i < nU; ++i)
+          for (int j = 0; j <= i; ++j) {
+            double v = src[(size_t)k * nU * (nU + 1) / 2 + i * (i + 1) / 2 + j];
+            out[(size_t)k * nU * nU + i * nU + j] = v;
+            out[(size_t)k * nU * nU + j * nU + i] = v;
+          }
+      break;
+    }
+    case LBDDC_X_D: {
+      auto h = fetch(c->d_D, nU, 8);
+      memcpy(out, h.data(), h.size());
+      break;
+    }
+    case LBDDC_X_PSI: {
+      auto h = fetch(c->d_Psi, (size_t)nU * nC, p32 ? 4 : 8);
+      for (size_t i = 0; i < (size_t)count * nU * nC; ++i)
+        out[i] = p32 ? (double)((float*)h.data())[i] : ((double*)h.data())[i];
+      break;
+    }
+    case LBDDC_X_SC: {
+      auto h = fetch(c->d_ScLoc, (size_t)nC * (nC + 1) / 2, 8);
+      const double* src = (const double*)h.data();
+      for (int k = 0; k < count; ++k)
+        for (int i = 0; i < nC; ++i)
+          for (int j = 0; j <= i; ++j) {
+            double v = src[(size_t)k * nC * (nC + 1) / 2 + i * (i + 1) / 2 + j];
+            out[(size_t)k * nC * nC + i * nC + j] = v;
+            out[(size_t)k * nC * nC + j * nC + i] = v;
+          }
+      break;
+    }
+    case LBDDC_X_LOAD: {
+      for (int r = 0; r < c->nrhs; ++r) {
+        std::vector<double> h((size_t)count * nU);
+        hipMemcpy(h.data(), c->d_load + ((size_t)r * c->ncell + first) * nU, h.size() * 8, hipMemcpyDeviceToHost);
+        for (int k = 0; k < count; ++k)
+          memcpy(out + ((size_t)k * c->nrhs + r) * nU, h.data() + (size_t)k * nU, nU * 8);
+      }
+      break;
+    }
+    case LBDDC_X_FINE: {
+      const size_t per = (size_t)nE * (nE + 1) / 2;
+      auto h = fetch(c->d_P, per, p32 ? 4 : 8);
+      for (int k = 0; k < count; ++k) {
+        double* o = out + (size_t)k * nU * nU;
+        for (int i = 0; i < nU * nU; ++i) o[i] = 0.0;
+        for (int i = 0; i < nE; ++i)
+          for (int j = 0; j <= i; ++j) {
+            size_t src = (size_t)k * per + i * (i + 1) / 2 + j;
+            double v = p32 ? (double)((float*)h.data())[src] : ((double*)h.data())[src];
+            o[(size_t)(8 + i) * nU + 8 + j] = v;
+            o[(size_t)(8 + j) * nU + 8 + i] = v;
+          }
+      }
+      break;
+    }
+    default:
+      return fail(c, LBDDC_E_ARG, "export: unknown field");
+  }
+  return LBDDC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,213 @@
+// Internal declarations of the lbddc library: the context, device buffers and
+// the kernel launchers.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lbddc.h"
+
+namespace lbddc {
+
+constexpr int kMaxP = 10;
+constexpr int kMaxKC = 11;  // reduced basis + stabilisation column padded to 4*KC <= 44
+
+// ---------------------------------------------------------------------------
+// Host numerics (host_math.cpp): Legendre-based nodes and polynomial tables.
+std::vector<double> gll_points(int p);                  // p+1 GLL points on [0,1]
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);  // on [0,1]
+double lagrange_value(const std::vector<double>& nodes, int a, double x);
+double lagrange_derivative(const std::vector<double>& nodes, int a, double x);
+double bernstein_value(int m, int a, double x);
+double bernstein_derivative(int m, int a, double x);
+
+// ---------------------------------------------------------------------------
+// Device-side table of small per-problem constants, packed in one buffer.
+struct Tables {
+  // geometry coefficients: Bernstein gradients at the interpolation points
+  int off_geo_dN;      // [nL][(m+1)^2][2]
+  int off_chk_dN;      // [nchk][(m+1)^2][2]  det J check sample
+  int nchk;
+  // constraint rows: Gauss 2p+2 points on an edge
+  int nq_edge;
+  int off_edge_w;      // [nq]
+  int off_edge_b;      // [p+1][nq] GLL Lagrange values
+  int off_edge_B;      // [m+1][nq] Bernstein values
+  int off_edge_dB;     // [m+1][nq] Bernstein derivatives
+  int off_mid_B;       // [m+1] Bernstein values at 1/2
+  // loads: Gauss p+2m+2 points
+  int nq_load;
+  int off_load_w, off_load_b, off_load_dB;
+  // MDEIM: GLL points of degree r for each family slot (max 4 families)
+  int off_rnodes[4];
+  // adjoint chain rule: Bernstein gradients at interpolation points (= geo_dN)
+  int total;
+};
+
+// A loaded ROM of one family.
+struct RomDev {
+  int family = -1, p = 0, q = 0, n_k = 0, n_r = 0, r = 0;
+  double lo = 0, hi = 0;
+  int KC = 0;                       // k-chunks of the contraction (4*KC >= n_r + 1)
+  std::vector<double*> ut64;        // per cluster: tiled [NPT][ns][KC][64] FP64
+  std::vector<float*> ut32;         // per cluster: tiled [NPT][ns][KC][64] FP32
+  std::vector<double*> ucol64;      // per cluster: [NPT][ns][16][4*KC] plain rows (adjoint)
+  double* coeff = nullptr;          // [n_k][r+1][n_r]
+};
+
+struct CoarseLayout {
+  int nsb = 0;                       // super-blocks (grid lines)
+  std::vector<int> sb_off, sb_size;  // global coarse offset and size
+  std::vector<long long> dense_off;  // offset of each dense diagonal block
+  long long dense_total = 0;
+  int mmax = 0;
+  // off-diagonal blocks B_j = A[sb j+1, sb j] (CSR over rows of sb j+1) and B_j^T
+  std::vector<int> b_rowptr_off, bt_rowptr_off;  // into rowptr arrays, per j
+  std::vector<int> b_rowptr, b_col, bt_rowptr, bt_col;  // concatenated, values follow same order
+  std::vector<int> b_val_off, bt_val_off;  // per j offset into values
+  long long nnzB = 0, nnzBT = 0;
+  // unique entries: entry e sums contributions [cstart[e], cstart[e+1]) into dest[e]
+  std::vector<long long> dest;        // into combined array: dense | B | BT
+  std::vector<int> cstart;
+  std::vector<int> contrib;           // index into ScLoc (cell*nCp + packed)
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  std::map<int, RomDev> roms;
+
+  // problem
+  bool have_problem = false, assembled = false, setup_done = false, solved = false;
+  lbddc_precision asm_prec = LBDDC_FP64, setup_prec = LBDDC_FP64;
+  int nx = 0, ny = 0, p = 0, q = 0, m = 0, nrhs = 1;
+  double E = 1, nu = 0.3, rho = 0;
+  bool moments = true;
+  int ncell = 0, nB = 0, ndof = 0, nI = 0, nU = 0, nE = 0, nC = 0, nce = 0, nL = 0, ns = 0;
+  int nN = 0, npair = 0, NPT = 0, nIn = 0, Gx = 0, Gy = 0, netx = 0, nety = 0;
+  long long n_i = 0;
+  int NU = 0, NI = 0, NC = 0, Nfree = 0;
+  int KC = 0;                // contraction k-chunks for this problem (max over families)
+  std::vector<int> fam_host; std::vector<double> t_host;
+  std::vector<int> fam_slot; // family id -> 0..nfam-1
+  std::vector<int> fam_ids;
+
+  // host topology
+  std::vector<int> perm_nat;   // permuted node -> natural node index
+  std::vector<int> dirmask;    // [nU] 1 if the slot is on the left side (clamped for ix == 0)
+  std::vector<int> RU, RC;     // [ncell][nU], [ncell][nC]
+  CoarseLayout co;
+  Tables tab;
+
+  // device buffers -------------------------------------------------------
+  double* d_tab = nullptr;
+  double* d_ctrl = nullptr;    // [nety][netx][2]
+  int* d_family = nullptr;
+  double* d_t = nullptr;
+  double* d_trac = nullptr;    // [nrhs][ny][2]
+  int* d_perm = nullptr;       // [nN]
+  int* d_dirmask = nullptr;    // [nU]
+  int* d_RU = nullptr;         // [ncell][nU]
+  int* d_RC = nullptr;         // [ncell][nC]
+  int* d_uown_ptr = nullptr;   // [NU+1]
+  int* d_uown = nullptr;       // owner slot ids cell*nU + slot
+  int* d_cown_ptr = nullptr;   // [NC+1]
+  int* d_cown = nullptr;
+  int* d_skel_node = nullptr;  // [NU/2] node lattice index of each skeleton node
+  int* d_net_ptr = nullptr;    // [netx*nety+1]
+  int* d_net_own = nullptr;    // cell*(m+1)^2 + local control point
+  int* d_cstart = nullptr; int* d_contrib = nullptr; long long* d_dest = nullptr;
+  int* d_b_rowptr = nullptr; int* d_b_col = nullptr; int* d_bt_rowptr = nullptr; int* d_bt_col = nullptr;
+  int* d_flags = nullptr;      // device error flags [8]
+  int* h_flags = nullptr;      // pinned host mirror
+
+  // assembly
+  double* d_theta = nullptr;   // [ncell][ns][4]
+  double* d_itil = nullptr;    // [ncell][4*KC]
+  float* d_theta32 = nullptr;
+  float* d_itil32 = nullptr;
+  int* d_cluster = nullptr;    // [ncell] group id
+  int* d_sorted = nullptr;     // [ncell] cells sorted by group
+  int* d_tiles = nullptr;      // [ntiles][4]: group, start, count, -
+  int ntiles = 0;
+  double* d_K = nullptr;       // [ncell][npair][4]
+  float* d_K32 = nullptr;
+  double* d_load = nullptr;    // [nrhs][ncell][nU]
+  double* d_cons = nullptr;    // [ncell][4][nce][p+1][2] edge constraint rows
+  std::vector<int> group_family, group_cluster;
+
+  // setup
+  double* d_S = nullptr;       // [ncell][nU(nU+1)/2]
+  double* d_L = nullptr;       // [ncell][nI(nI+1)/2] column-major packed
+  double* d_Y = nullptr;       // [ncell][nI][nU]
+  double* d_diagK = nullptr;   // [ncell][nU]
+  double* d_Ktot = nullptr;    // [NU]
+  void* d_P = nullptr;         // [ncell][nE(nE+1)/2] D-scaled fine operator (T)
+  void* d_Psi = nullptr;       // [ncell][nU][nC] D-scaled coarse basis (T)
+  double* d_D = nullptr;       // [ncell][nU]
+  double* d_ScLoc = nullptr;   // [ncell][nC(nC+1)/2]
+  double* d_coarse = nullptr;  // dense blocks | B values | BT values
+  double* d_gjP = nullptr; double* d_gjR = nullptr; double* d_gjC = nullptr; double* d_gjW = nullptr;
+
+  // solve
+  double* d_f = nullptr;       // [nrhs][NU]
+  double* d_x = nullptr;       // [nrhs][NU]
+  double *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr;
+  double* d_partU = nullptr;   // [ncell][nU]
+  double* d_partC = nullptr;   // [ncell][nC]
+  double *d_zc = nullptr, *d_tc = nullptr, *d_xc = nullptr;  // coarse vectors [NC]
+  double* d_red = nullptr;     // reduction partials [kRedSlots][kMaxBlocks]
+  double* d_scal = nullptr;    // scalars
+  double* h_scal = nullptr;    // pinned
+  double* d_u = nullptr;       // [nrhs][Gy][Gx][2]
+  std::vector<lbddc_solve_info> info;
+
+  // gradient
+  double* d_H = nullptr;       // [ncell][4*KC]
+  double* d_G = nullptr;       // [ncell][ns][4]
+  double* d_gcell = nullptr;   // [ncell][(m+1)^2][2]
+  double* d_gt = nullptr;      // [nrhs][ncell]
+  double* d_gX = nullptr;      // [nrhs][nety*netx*2]
+  double* d_J = nullptr;       // [nrhs]
+  double* d_ucell = nullptr;   // [ncell][ndof] local displacement (permuted)
+
+  double phase_ms[12] = {0};
+  hipEvent_t ev[8] = {};
+  size_t dev_bytes = 0;
+  std::vector<void*> allocs;   // everything allocated for the problem
+};
+
+// allocation helpers (api.cpp)
+bool dalloc(Ctx* c, void** p, size_t bytes);
+template <class T> bool dalloc_t(Ctx* c, T** p, size_t n) { return dalloc(c, (void**)p, n * sizeof(T)); }
+
+// topology (topology.cpp)
+bool build_topology(Ctx* c);
+void build_tables(Ctx* c, std::vector<double>& tab);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers.  All enqueue on c->stream and return hipGetLastError().
+hipError_t launch_geometry(Ctx* c);          // theta, det check, MDEIM eval (A1, A2)
+hipError_t launch_constraints_loads(Ctx* c); // edge constraint rows and loads
+hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1);  // A3
+hipError_t launch_schur(Ctx* c);             // A4
+hipError_t launch_weights(Ctx* c);           // A7 (gather of stiffness diagonals)
+hipError_t launch_precond(Ctx* c, bool fp32); // A5, A6, A7
+hipError_t launch_coarse_assemble(Ctx* c);   // A8 assembly of S_C blocks
+hipError_t launch_coarse_factor(Ctx* c);     // A8 block-tridiagonal FP64 factorization
+hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x);  // A8 solve
+hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32,
+                     double* t_op, double* t_pre, double* t_coarse, int* n_apply);  // A9
+hipError_t pcg_true_residual(Ctx* c, int rhs, double* out);
+hipError_t gather_rhs(Ctx* c, int rhs);
+hipError_t launch_recover(Ctx* c, int rhs);  // A10
+hipError_t launch_gradient(Ctx* c, int rhs); // A11
+hipError_t launch_export(Ctx* c, int which, int first, int count, double* d_out);
+
+}  // namespace lbddc

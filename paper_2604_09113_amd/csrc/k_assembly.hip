@@ -1,0 +1,225 @@
+// Batched stiffness contraction (A3): for every cell
+//   K[(i1,n1),(i2,n2)] = sum_s theta[i1 i2, s] * sum_r Uhat[(n1,n2,s), r] Itil[r]
+// i.e. the reduced reconstruction I = Uhat Itil (Alg. 5) followed by the
+// fast-assembly contraction with the geometry coefficients (Alg. 4), with the
+// stabilisation folded in as the last column of Uhat = [U_r | I_pi].
+//
+// Only node pairs n2 <= n1 (permuted node order: interior, corners, edges) are
+// formed, since K is symmetric.  The reconstruction is a real dense GEMM
+// (rows = (pair, s), columns = cells, depth = n_r + 1 padded to 4*KC) and runs on
+// MFMA 16x16x4 (FP64 for the operator, FP32 for the single-precision copy).  The
+// 36 -> 4 contraction over s runs in the epilogue: a tile holds 16 pairs of one s
+// for 16 cells, so each lane accumulates its pairs' 4 (i1, i2) entries over s in
+// registers and no cross-lane reduction is needed.
+//
+// Workgroup: 4 waves x 32 cells on one 16-pair tile; consecutive workgroups
+// walk the cells of one (family, cluster) group, so a pair tile of Uhat is
+// streamed from L2 by every workgroup on an XCD at about the same time.
+#include "internal.h"
+
+namespace lbddc {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V4;
+template <> struct V4<double> { typedef dbl4 type; };
+template <> struct V4<float> { typedef flt4 type; };
+
+__device__ inline dbl4 mfma(double a, double b, dbl4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline flt4 mfma(float a, float b, flt4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// tiles[i] = {group, first position in `sorted`, number of cells, unused}
+template <typename T, int KC>
+__global__ __launch_bounds__(256) void k_assemble(const T* const* __restrict__ utg, const T* __restrict__ theta,
+                                                  const T* __restrict__ itil, const int* __restrict__ sorted,
+                                                  const int4* __restrict__ tiles, T* __restrict__ K, int ns,
+                                                  int npair, int itil_stride) {
+  typedef typename V4<T>::type v4;
+  const int pt = blockIdx.y;
+  const int4 td = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  int cidx[2];
+  bool cval[2];
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk) {
+    int o = wave * 32 + bk * 16 + col;
+    cval[bk] = o < td.z;
+    cidx[bk] = sorted[td.y + (cval[bk] ? o : 0)];
+  }
+  T b[2][KC];
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) b[bk][kc] = itil[(size_t)cidx[bk] * itil_stride + 4 * kc + grp];
+  v4 acc[2][4];
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[bk][e] = v4{0, 0, 0, 0};
+  const T* ap = utg[td.x] + (size_t)pt * ns * KC * 64 + lane;
+  const T* th0 = theta + (size_t)cidx[0] * ns * 4;
+  const T* th1 = theta + (size_t)cidx[1] * ns * 4;
+  T a[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) a[kc] = ap[kc * 64];
+  for (int s = 0; s < ns; ++s) {
+    T an[KC];
+    const int sn = s + 1 < ns ? s + 1 : s;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) an[kc] = ap[((size_t)sn * KC + kc) * 64];
+    v4 d0 = v4{0, 0, 0, 0}, d1 = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      d0 = mfma(a[kc], b[0][kc], d0);
+      d1 = mfma(a[kc], b[1][kc], d1);
+    }
+    const v4 t0 = *reinterpret_cast<const v4*>(th0 + s * 4);
+    const v4 t1 = *reinterpret_cast<const v4*>(th1 + s * 4);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[0][e] += t0[e] * d0;
+      acc[1][e] += t1[e] * d1;
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) a[kc] = an[kc];
+  }
+  // lane (grp, col) holds pairs 4*grp + v of its cell
+#pragma unroll
+  for (int bk = 0; bk < 2; ++bk) {
+    if (!cval[bk]) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int P = pt * 16 + 4 * grp + v;
+      if (P < npair) {
+        v4 o = v4{acc[bk][0][v], acc[bk][1][v], acc[bk][2][v], acc[bk][3][v]};
+        *reinterpret_cast<v4*>(K + ((size_t)cidx[bk] * npair + P) * 4) = o;
+      }
+    }
+  }
+}
+
+// Stable counting sort of the cells by group (one workgroup): deterministic.
+__global__ __launch_bounds__(256) void k_group_sort(const int* __restrict__ group, int ncell, int G,
+                                                    int* __restrict__ sorted, int* __restrict__ counts) {
+  __shared__ int cnt[256][16];
+  const int t = threadIdx.x;
+  const int chunk = (ncell + 255) / 256;
+  const int b0 = t * chunk, b1 = min(ncell, b0 + chunk);
+  for (int g = 0; g < 16; ++g) cnt[t][g] = 0;
+  for (int i = b0; i < b1; ++i) {
+    int g = group[i];
+    g = g < 0 ? 0 : (g >= G ? G - 1 : g);
+    cnt[t][g]++;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int g = 0; g < G; ++g) {
+      int tot = 0;
+      for (int u = 0; u < 256; ++u) {
+        int c = cnt[u][g];
+        cnt[u][g] = run;
+        run += c;
+        tot += c;
+      }
+      counts[g] = tot;
+    }
+  }
+  __syncthreads();
+  for (int i = b0; i < b1; ++i) {
+    int g = group[i];
+    g = g < 0 ? 0 : (g >= G ? G - 1 : g);
+    sorted[cnt[t][g]++] = i;
+  }
+}
+
+template <typename T>
+static hipError_t launch_family(Ctx* c, const T* const* d_utg, int KC, const T* theta, const T* itil,
+                                const int4* tiles, int ntiles, T* K) {
+  dim3 grid(ntiles, c->NPT), block(256);
+  const int st = 4 * c->KC;
+#define LB_CASE(kc)                                                                                       \
+  case kc:                                                                                                \
+    hipLaunchKernelGGL((k_assemble<T, kc>), grid, block, 0, c->stream, d_utg, theta, itil, c->d_sorted, \
+                       tiles, K, c->ns, c->npair, st);                                                  \
+    break;
+  switch (KC) {
+    LB_CASE(1) LB_CASE(2) LB_CASE(3) LB_CASE(4) LB_CASE(5) LB_CASE(6) LB_CASE(7) LB_CASE(8) LB_CASE(9)
+    LB_CASE(10) LB_CASE(11)
+    default: return hipErrorInvalidValue;
+  }
+#undef LB_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
+  // groups: family slot s owns groups [base_s, base_s + n_k)
+  int G = 0;
+  std::vector<int> base;
+  for (int fid : c->fam_ids) {
+    base.push_back(G);
+    G += c->roms[fid].n_k;
+  }
+  if (G > 16) return hipErrorInvalidValue;
+  int* d_counts = c->d_flags + 8 + 64;
+  hipLaunchKernelGGL(k_group_sort, dim3(1), dim3(256), 0, c->stream, c->d_cluster, c->ncell, G, c->d_sorted, d_counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int counts[16];
+  e = hipMemcpyAsync(c->h_flags + 8, d_counts, G * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  for (int g = 0; g < G; ++g) counts[g] = c->h_flags[8 + g];
+  // tiles of 128 cells per group, per family
+  std::vector<int> tiles;
+  std::vector<int> fam_first, fam_n;
+  int start = 0;
+  c->group_family.assign(G, 0);
+  c->group_cluster.assign(G, 0);
+  for (size_t s = 0; s < c->fam_ids.size(); ++s) {
+    fam_first.push_back((int)tiles.size() / 4);
+    for (int k = 0; k < c->roms[c->fam_ids[s]].n_k; ++k) {
+      int g = base[s] + k;
+      c->group_family[g] = (int)s;
+      c->group_cluster[g] = k;
+      for (int o = 0; o < counts[g]; o += 128) {
+        tiles.push_back(g);
+        tiles.push_back(start + o);
+        tiles.push_back(std::min(128, counts[g] - o));
+        tiles.push_back(0);
+      }
+      start += counts[g];
+    }
+    fam_n.push_back((int)tiles.size() / 4 - fam_first.back());
+  }
+  c->ntiles = (int)tiles.size() / 4;
+  // tile table and per-group Uhat pointers (in the flags scratch area: sized for 16 groups)
+  std::vector<const void*> ptrs(G, nullptr);
+  for (int g = 0; g < G; ++g) {
+    const RomDev& R = c->roms[c->fam_ids[c->group_family[g]]];
+    ptrs[g] = fp32 ? (const void*)R.ut32[c->group_cluster[g]] : (const void*)R.ut64[c->group_cluster[g]];
+  }
+  e = hipMemcpyAsync(c->d_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  void** d_ptrs = (void**)(c->d_tiles + 4 * (c->ncell / 16 + 64));
+  e = hipMemcpyAsync(d_ptrs, ptrs.data(), G * sizeof(void*), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  if (e0) hipEventRecord(e0, c->stream);
+  for (size_t s = 0; s < c->fam_ids.size(); ++s) {
+    if (fam_n[s] == 0) continue;
+    const int4* tl = reinterpret_cast<const int4*>(c->d_tiles) + fam_first[s];
+    const int KC = c->roms[c->fam_ids[s]].KC;
+    if (fp32)
+      e = launch_family<float>(c, (const float* const*)d_ptrs, KC, c->d_theta32, c->d_itil32, tl, fam_n[s], c->d_K32);
+    else
+      e = launch_family<double>(c, (const double* const*)d_ptrs, KC, c->d_theta, c->d_itil, tl, fam_n[s], c->d_K);
+    if (e != hipSuccess) return e;
+  }
+  if (e1) hipEventRecord(e1, c->stream);
+  return hipGetLastError();
+}
+
+}  // namespace lbddc

@@ -1,0 +1,246 @@
+// Per-cell geometry kernels.
+//
+// k_geometry (A1 + A2), one thread per cell:
+//  * Jacobian of the Bernstein cell map at the (q+1)^2 interpolation points and
+//    the pulled-back tensor Chat_{i1 j1 i2 j2} = det J A_{j1 m} C_{i1 m i2 n} A_{j2 n},
+//    A = J^-1 (Sec. 2.2.1, pull-back of the elasticity tensor; Sec. 4.1, its
+//    values at the interpolation points are the geometry coefficients), written
+//    as theta[cell][s][i1 i2] with s = (j1*2 + j2)*nL + k3;
+//  * det J > 0 check at the interpolation points and a Gauss sample;
+//  * MDEIM online step (Alg. 5): cluster of t, Lagrange interpolation of the
+//    fitted reduced coordinates, stabilised vector [(1-rho) I_r(t), rho]
+//    (Alg. 4 folds the stabilisation into the last column).
+// k_constraints: edge-average and edge-moment rows of the coarse dofs
+//  (Sec. 3.3.1) by Gauss quadrature along the physical edge.
+// k_loads: consistent load of the right-edge traction (Sec. 2.2.1).
+#include "internal.h"
+
+namespace lbddc {
+
+struct GeoArgs {
+  const double* ctrl; const int* family; const double* t; const double* tab;
+  const int* fam_slot;        // family id -> slot (or -1); indexed by family id (< 64)
+  const double* coeff[4];     // per slot [n_k][r+1][n_r]
+  double lo[4], hi[4];
+  int n_k[4], n_r[4], r[4], group_base[4];
+  int ncell, nx, netx, m, nL, ns, itil_stride;
+  double lam, mu, rho;
+  Tables T;
+  double* theta; float* theta32; double* itil; float* itil32; int* group; int* flags;
+};
+
+__global__ void k_geometry(GeoArgs g) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const int ix = cell % g.nx, iy = cell / g.nx, m = g.m, np1 = (m + 1) * (m + 1);
+  double X[25][2];
+  for (int b = 0; b <= m; ++b)
+    for (int a = 0; a <= m; ++a) {
+      const double* P = g.ctrl + ((size_t)(m * iy + b) * g.netx + m * ix + a) * 2;
+      X[b * (m + 1) + a][0] = P[0];
+      X[b * (m + 1) + a][1] = P[1];
+    }
+  bool bad = false;
+  // det J on the check sample
+  for (int k = 0; k < g.T.nchk; ++k) {
+    const double* dN = g.tab + g.T.off_chk_dN + (size_t)k * np1 * 2;
+    double J00 = 0, J01 = 0, J10 = 0, J11 = 0;
+    for (int a = 0; a < np1; ++a) {
+      J00 += X[a][0] * dN[2 * a]; J01 += X[a][0] * dN[2 * a + 1];
+      J10 += X[a][1] * dN[2 * a]; J11 += X[a][1] * dN[2 * a + 1];
+    }
+    if (!(J00 * J11 - J01 * J10 > 0.0)) bad = true;
+  }
+  const double lam = g.lam, mu = g.mu;
+  for (int k3 = 0; k3 < g.nL; ++k3) {
+    const double* dN = g.tab + g.T.off_geo_dN + (size_t)k3 * np1 * 2;
+    double J[2][2] = {{0, 0}, {0, 0}};
+    for (int a = 0; a < np1; ++a)
+      for (int i = 0; i < 2; ++i) {
+        J[i][0] += X[a][i] * dN[2 * a];
+        J[i][1] += X[a][i] * dN[2 * a + 1];
+      }
+    double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    if (!(det > 0.0)) bad = true;
+    double A[2][2] = {{J[1][1] / det, -J[0][1] / det}, {-J[1][0] / det, J[0][0] / det}};
+    for (int j1 = 0; j1 < 2; ++j1)
+      for (int j2 = 0; j2 < 2; ++j2) {
+        double aa = A[j1][0] * A[j2][0] + A[j1][1] * A[j2][1];
+        int s = (j1 * 2 + j2) * g.nL + k3;
+        for (int i1 = 0; i1 < 2; ++i1)
+          for (int i2 = 0; i2 < 2; ++i2) {
+            // isotropic C_{i1 m i2 n} = lam d_{i1 m} d_{i2 n} + mu (d_{i1 i2} d_{mn} + d_{i1 n} d_{m i2})
+            double v = lam * A[j1][i1] * A[j2][i2] + mu * ((i1 == i2 ? aa : 0.0) + A[j1][i2] * A[j2][i1]);
+            v *= det;
+            size_t o = ((size_t)cell * g.ns + s) * 4 + 2 * i1 + i2;
+            g.theta[o] = v;
+            g.theta32[o] = (float)v;
+          }
+      }
+  }
+  if (bad) atomicOr(g.flags, 1);
+  // MDEIM online evaluation
+  const int fam = g.family[cell];
+  const int slot = (fam >= 0 && fam < 64) ? g.fam_slot[fam] : -1;
+  double* it = g.itil + (size_t)cell * g.itil_stride;
+  float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
+  for (int r = 0; r < g.itil_stride; ++r) { it[r] = 0.0; it32[r] = 0.0f; }
+  if (slot < 0) { atomicOr(g.flags, 4); g.group[cell] = 0; return; }
+  const double t = g.t[cell], lo = g.lo[slot], hi = g.hi[slot];
+  const int nk = g.n_k[slot], R = g.r[slot], nr = g.n_r[slot];
+  if (!(t >= lo && t <= hi)) { atomicOr(g.flags, 2); g.group[cell] = g.group_base[slot]; return; }
+  const double w = (hi - lo) / nk;
+  int k = (int)floor((t - lo) / w);
+  if (k > nk - 1) k = nk - 1;
+  if (k < 0) k = 0;
+  const double a = lo + k * w, b = lo + (k + 1) * w;
+  const double tau = (t - a) / (b - a);
+  const double* nodes = g.tab + g.T.off_rnodes[slot];
+  double ell[17];
+  for (int j = 0; j <= R; ++j) {
+    double v = 1.0;
+    for (int l = 0; l <= R; ++l)
+      if (l != j) v *= (tau - nodes[l]) / (nodes[j] - nodes[l]);
+    ell[j] = v;
+  }
+  const double* cf = g.coeff[slot] + (size_t)k * (R + 1) * nr;
+  for (int r = 0; r < nr; ++r) {
+    double s = 0.0;
+    for (int j = 0; j <= R; ++j) s += ell[j] * cf[j * nr + r];
+    s *= (1.0 - g.rho);
+    it[r] = s;
+    it32[r] = (float)s;
+  }
+  it[nr] = g.rho;
+  it32[nr] = (float)g.rho;
+  g.group[cell] = g.group_base[slot] + k;
+}
+
+// Edge rows: for edge e of a cell, averages int_e u_c ds and moment
+// int_e (x2 - xbar2) u1 + (xbar1 - x1) u2 ds over the p+1 edge nodes, xbar the
+// image of the parametric midpoint; Gauss 2p+2 points along the physical edge.
+struct ConsArgs {
+  const double* ctrl; const double* tab; Tables T;
+  int ncell, nx, netx, m, p, nce;
+  double* cons;  // [ncell][4][nce][p+1][2]
+};
+
+__device__ inline void edge_points(const double* ctrl, int netx, int m, int ix, int iy, int e, double P[5][2]) {
+  for (int k = 0; k <= m; ++k) {
+    int a, b;
+    if (e == 0) { a = 0; b = k; }        // left   (xi1 = 0)
+    else if (e == 1) { a = m; b = k; }   // right  (xi1 = 1)
+    else if (e == 2) { a = k; b = 0; }   // bottom (xi2 = 0)
+    else { a = k; b = m; }               // top    (xi2 = 1)
+    const double* Q = ctrl + ((size_t)(m * iy + b) * netx + m * ix + a) * 2;
+    P[k][0] = Q[0];
+    P[k][1] = Q[1];
+  }
+}
+
+__global__ void k_constraints(ConsArgs g) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.ncell * 4) return;
+  const int cell = id >> 2, e = id & 3, ix = cell % g.nx, iy = cell / g.nx, m = g.m, p = g.p;
+  double P[5][2];
+  edge_points(g.ctrl, g.netx, m, ix, iy, e, P);
+  const int nq = g.T.nq_edge;
+  const double* w = g.tab + g.T.off_edge_w;
+  const double* bl = g.tab + g.T.off_edge_b;
+  const double* B = g.tab + g.T.off_edge_B;
+  const double* dB = g.tab + g.T.off_edge_dB;
+  const double* Bm = g.tab + g.T.off_mid_B;
+  double xb0 = 0, xb1 = 0;
+  for (int k = 0; k <= m; ++k) { xb0 += Bm[k] * P[k][0]; xb1 += Bm[k] * P[k][1]; }
+  double* out = g.cons + ((size_t)cell * 4 + e) * g.nce * (p + 1) * 2;
+  for (int n = 0; n <= p; ++n) {
+    double avg = 0, m0 = 0, m1 = 0;
+    for (int qd = 0; qd < nq; ++qd) {
+      double x0 = 0, x1 = 0, d0 = 0, d1 = 0;
+      for (int k = 0; k <= m; ++k) {
+        x0 += B[k * nq + qd] * P[k][0]; x1 += B[k * nq + qd] * P[k][1];
+        d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1];
+      }
+      double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
+      avg += ws;
+      m0 += ws * (x1 - xb1);
+      m1 += ws * (xb0 - x0);
+    }
+    out[(0 * (p + 1) + n) * 2 + 0] = avg;
+    out[(0 * (p + 1) + n) * 2 + 1] = 0.0;
+    out[(1 * (p + 1) + n) * 2 + 0] = 0.0;
+    out[(1 * (p + 1) + n) * 2 + 1] = avg;
+    if (g.nce > 2) {
+      out[(2 * (p + 1) + n) * 2 + 0] = m0;
+      out[(2 * (p + 1) + n) * 2 + 1] = m1;
+    }
+  }
+}
+
+// Right-edge traction of cells in the last column: f[node][c] = t_c int b_node |x'| dxi.
+struct LoadArgs {
+  const double* ctrl; const double* tab; const double* trac; Tables T;
+  int ncell, nx, ny, netx, m, p, nU, nrhs;
+  double* load;  // [nrhs][ncell][nU]
+};
+
+__global__ void k_loads(LoadArgs g) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.ncell * g.nrhs) return;
+  const int cell = id % g.ncell, rhs = id / g.ncell, ix = cell % g.nx, iy = cell / g.nx, p = g.p;
+  double* out = g.load + ((size_t)rhs * g.ncell + cell) * g.nU;
+  for (int s = 0; s < g.nU; ++s) out[s] = 0.0;
+  if (ix != g.nx - 1) return;
+  double P[5][2];
+  edge_points(g.ctrl, g.netx, g.m, ix, iy, 1, P);
+  const int nq = g.T.nq_load;
+  const double* w = g.tab + g.T.off_load_w;
+  const double* bl = g.tab + g.T.off_load_b;
+  const double* dB = g.tab + g.T.off_load_dB;
+  const double t0 = g.trac[((size_t)rhs * g.ny + iy) * 2], t1 = g.trac[((size_t)rhs * g.ny + iy) * 2 + 1];
+  for (int n = 0; n <= p; ++n) {
+    double f = 0;
+    for (int qd = 0; qd < nq; ++qd) {
+      double d0 = 0, d1 = 0;
+      for (int k = 0; k <= g.m; ++k) { d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1]; }
+      f += w[qd] * bl[n * nq + qd] * sqrt(d0 * d0 + d1 * d1);
+    }
+    // right edge node n: corner BR (n = 0), corner TR (n = p), else edge node
+    int node = (n == 0) ? 1 : (n == p ? 3 : 4 + (p - 1) + (n - 1));
+    out[2 * node] = f * t0;
+    out[2 * node + 1] = f * t1;
+  }
+}
+
+hipError_t launch_geometry(Ctx* c) {
+  GeoArgs g = {};
+  g.ctrl = c->d_ctrl; g.family = c->d_family; g.t = c->d_t; g.tab = c->d_tab;
+  static_assert(sizeof(int) == 4, "");
+  g.fam_slot = c->d_flags + 8;  // family -> slot table lives after the flags
+  int base = 0;
+  for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
+    const RomDev& R = c->roms[c->fam_ids[s]];
+    g.coeff[s] = R.coeff; g.lo[s] = R.lo; g.hi[s] = R.hi; g.n_k[s] = R.n_k; g.n_r[s] = R.n_r; g.r[s] = R.r;
+    g.group_base[s] = base;
+    base += R.n_k;
+  }
+  g.ncell = c->ncell; g.nx = c->nx; g.netx = c->netx; g.m = c->m; g.nL = c->nL; g.ns = c->ns;
+  g.itil_stride = 4 * c->KC;
+  g.lam = c->E * c->nu / ((1 + c->nu) * (1 - 2 * c->nu));
+  g.mu = c->E / (2 * (1 + c->nu));
+  g.rho = c->rho; g.T = c->tab;
+  g.theta = c->d_theta; g.theta32 = c->d_theta32; g.itil = c->d_itil; g.itil32 = c->d_itil32;
+  g.group = c->d_cluster; g.flags = c->d_flags;
+  hipLaunchKernelGGL(k_geometry, dim3((c->ncell + 127) / 128), dim3(128), 0, c->stream, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_constraints_loads(Ctx* c) {
+  ConsArgs a = {c->d_ctrl, c->d_tab, c->tab, c->ncell, c->nx, c->netx, c->m, c->p, c->nce, c->d_cons};
+  hipLaunchKernelGGL(k_constraints, dim3((c->ncell * 4 + 127) / 128), dim3(128), 0, c->stream, a);
+  LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs, c->d_load};
+  hipLaunchKernelGGL(k_loads, dim3((c->ncell * c->nrhs + 127) / 128), dim3(128), 0, c->stream, l);
+  return hipGetLastError();
+}
+
+}  // namespace lbddc

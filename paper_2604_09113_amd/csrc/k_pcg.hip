@@ -1,0 +1,430 @@
+// Interface PCG with the BDDC preconditioner (A9; Sec. 3.3, Alg. 1) and the
+// interior recovery (A10; Sec. 3.2).
+//
+// Per iteration:
+//   q = S p            per cell: gather p (R_U), packed 64x64 product, partial;
+//                      then a gather-sum over the <= 4 cells sharing each dof
+//   z = S_BDDC^-1 r    per cell: gather r, fine correction (D-scaled explicit
+//                      fine operator), coarse restriction Psi^T D r; coarse
+//                      gather-sum, coarse solve, prolongation D Psi g; gather-sum
+// The recurrence, residuals and S-products are FP64.  In the mixed path the
+// fine operator and the coarse basis are stored and applied in FP32.
+// Every sum runs in a fixed order (owner lists sorted by cell, block
+// reductions with a fixed tree), so results are bitwise reproducible.
+#include "internal.h"
+
+namespace lbddc {
+
+constexpr int kBlk = 256;
+
+// y = S x for one cell per 64-thread workgroup; S packed lower [nU(nU+1)/2]
+template <int NU>
+__global__ __launch_bounds__(64) void k_op_local(const double* __restrict__ S, const int* __restrict__ RU,
+                                                 const double* __restrict__ x, double* __restrict__ part) {
+  constexpr int NSP = NU * (NU + 1) / 2;
+  __shared__ double Ss[NSP];
+  __shared__ double xs[NU];
+  const int cell = blockIdx.x, l = threadIdx.x;
+  const double* Sc = S + (size_t)cell * NSP;
+  for (int i = l; i < NSP; i += 64) Ss[i] = Sc[i];
+  for (int i = l; i < NU; i += 64) {
+    int g = RU[(size_t)cell * NU + i];
+    xs[i] = g >= 0 ? x[g] : 0.0;
+  }
+  __syncthreads();
+  for (int i = l; i < NU; i += 64) {
+    double s = 0.0;
+    const int ri = i * (i + 1) / 2;
+    for (int j = 0; j <= i; ++j) s += Ss[ri + j] * xs[j];
+    for (int j = i + 1; j < NU; ++j) s += Ss[j * (j + 1) / 2 + i] * xs[j];
+    part[(size_t)cell * NU + i] = s;
+  }
+}
+
+// fine correction and coarse restriction of one cell (T = double or float)
+template <typename T, int NU, int NC>
+__global__ __launch_bounds__(64) void k_pre_local(const T* __restrict__ P, const T* __restrict__ Psi,
+                                                  const int* __restrict__ RU, const double* __restrict__ r,
+                                                  double* __restrict__ partU, double* __restrict__ partC) {
+  constexpr int NE = NU - 8, NSP = NE * (NE + 1) / 2;
+  __shared__ T Ps[NSP];
+  __shared__ T Qs[NU * NC];
+  __shared__ T rs[NU];
+  const int cell = blockIdx.x, l = threadIdx.x;
+  const T* Pc = P + (size_t)cell * NSP;
+  const T* Qc = Psi + (size_t)cell * NU * NC;
+  for (int i = l; i < NSP; i += 64) Ps[i] = Pc[i];
+  for (int i = l; i < NU * NC; i += 64) Qs[i] = Qc[i];
+  for (int i = l; i < NU; i += 64) {
+    int g = RU[(size_t)cell * NU + i];
+    rs[i] = g >= 0 ? (T)r[g] : (T)0;
+  }
+  __syncthreads();
+  for (int i = l; i < NU; i += 64) {
+    T s = 0;
+    if (i >= 8) {
+      const int e = i - 8, re = e * (e + 1) / 2;
+      for (int j = 0; j <= e; ++j) s += Ps[re + j] * rs[8 + j];
+      for (int j = e + 1; j < NE; ++j) s += Ps[j * (j + 1) / 2 + e] * rs[8 + j];
+    }
+    partU[(size_t)cell * NU + i] = (double)s;
+  }
+  for (int jc = l; jc < NC; jc += 64) {
+    T s = 0;
+    for (int i = 0; i < NU; ++i) s += Qs[i * NC + jc] * rs[i];
+    partC[(size_t)cell * NC + jc] = (double)s;
+  }
+}
+
+// partU += Psi g_loc (coarse prolongation, D already folded into Psi)
+template <typename T, int NU, int NC>
+__global__ __launch_bounds__(64) void k_prolong(const T* __restrict__ Psi, const int* __restrict__ RC,
+                                                const double* __restrict__ g, double* __restrict__ partU) {
+  __shared__ T Qs[NU * NC];
+  __shared__ T gs[NC];
+  const int cell = blockIdx.x, l = threadIdx.x;
+  const T* Qc = Psi + (size_t)cell * NU * NC;
+  for (int i = l; i < NU * NC; i += 64) Qs[i] = Qc[i];
+  for (int j = l; j < NC; j += 64) {
+    int gc = RC[(size_t)cell * NC + j];
+    gs[j] = gc >= 0 ? (T)g[gc] : (T)0;
+  }
+  __syncthreads();
+  for (int i = l; i < NU; i += 64) {
+    T s = 0;
+    for (int j = 0; j < NC; ++j) s += Qs[i * NC + j] * gs[j];
+    partU[(size_t)cell * NU + i] += (double)s;
+  }
+}
+
+// block-level fixed-tree sum of v (blockDim = kBlk); result valid in thread 0
+__device__ inline double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kBlk / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// out[g] = sum of owners' partials; optional partial dot out . w per block
+__global__ __launch_bounds__(kBlk) void k_gather_dot(const double* __restrict__ part, const int* __restrict__ ptr,
+                                                     const int* __restrict__ own, double* __restrict__ out, int N,
+                                                     const double* __restrict__ w, double* __restrict__ red) {
+  __shared__ double sh[kBlk];
+  int g = blockIdx.x * kBlk + threadIdx.x;
+  double s = 0.0;
+  if (g < N) {
+    for (int o = ptr[g]; o < ptr[g + 1]; ++o) s += part[own[o]];
+    out[g] = s;
+  }
+  if (red) {
+    double d = (g < N) ? s * w[g] : 0.0;
+    d = block_sum(d, sh);
+    if (threadIdx.x == 0) red[blockIdx.x] = d;
+  }
+}
+
+// scal[dst] = sum of red[0..n) (fixed order, one block); then an optional ratio
+// mode 0: plain sum; 1: alpha = scal[0] / sum (pq), flag if sum <= 0
+// mode 2: rz_new = sum, beta = rz_new / scal[0], scal[0] = rz_new
+__global__ __launch_bounds__(kBlk) void k_reduce(const double* __restrict__ red, int n, double* __restrict__ scal,
+                                                 int dst, int mode) {
+  __shared__ double sh[kBlk];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlk) s += red[i];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    scal[dst] = s;
+    if (mode == 1) {
+      if (!(s > 0.0)) scal[7] = 1.0;
+      scal[2] = scal[0] / s;
+    } else if (mode == 2) {
+      if (!(s > 0.0)) scal[7] = 1.0;
+      scal[5] = s / scal[0];
+      scal[0] = s;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha q; partial r.r
+__global__ __launch_bounds__(kBlk) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    const double* __restrict__ scal, int N, double* __restrict__ red) {
+  __shared__ double sh[kBlk];
+  const double alpha = scal[2];
+  int g = blockIdx.x * kBlk + threadIdx.x;
+  double d = 0.0;
+  if (g < N) {
+    x[g] += alpha * p[g];
+    double rv = r[g] - alpha * q[g];
+    r[g] = rv;
+    d = rv * rv;
+  }
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = d;
+}
+
+// p = z + beta p  (beta from scal[5]; first call with beta forced to 0 via `init`)
+__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ scal,
+                           int N, int init) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  p[g] = init ? z[g] : z[g] + scal[5] * p[g];
+}
+
+__global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int N) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < N) dst[g] = src[g];
+}
+
+__global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b, int N, double* __restrict__ red) {
+  __shared__ double sh[kBlk];
+  int g = blockIdx.x * kBlk + threadIdx.x;
+  double d = g < N ? a[g] * b[g] : 0.0;
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = d;
+}
+
+// ---- interior recovery: u_I = -L^-T (Y u_U) (tractions act on skeleton dofs only)
+template <int P>
+__global__ __launch_bounds__(64) void k_recover(const double* __restrict__ L, const double* __restrict__ Y,
+                                                const int* __restrict__ RU, const double* __restrict__ x, int nx,
+                                                int Gx, double* __restrict__ u, double* __restrict__ ucell) {
+  constexpr int NI = 2 * (P - 1) * (P - 1), NU = 8 * P, NDOF = 2 * (P + 1) * (P + 1);
+  __shared__ double uu[NU];
+  __shared__ double s[NI];
+  const int cell = blockIdx.x, l = threadIdx.x;
+  for (int j = l; j < NU; j += 64) {
+    int g = RU[(size_t)cell * NU + j];
+    uu[j] = g >= 0 ? x[g] : 0.0;
+  }
+  __syncthreads();
+  const double* Yc = Y + (size_t)cell * NI * NU;
+  for (int k = l; k < NI; k += 64) {
+    double a = 0.0;
+    for (int j = 0; j < NU; ++j) a += Yc[(size_t)k * NU + j] * uu[j];
+    s[k] = -a;
+  }
+  __syncthreads();
+  const double* Lc = L + (size_t)cell * (NI * (NI + 1) / 2);
+  for (int k = NI - 1; k >= 0; --k) {
+    const double* col = Lc + (size_t)k * NI - (size_t)k * (k - 1) / 2;  // rows k..NI-1
+    double a = 0.0;
+    for (int i = k + 1 + l; i < NI; i += 64) a += col[i - k] * s[i];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (l == 0) s[k] = (s[k] - a) / col[0];
+    __syncthreads();
+  }
+  const int ix = cell % nx, iy = cell / nx;
+  for (int k = l; k < NI; k += 64) {
+    int n = k >> 1, comp = k & 1;
+    int a = n % (P - 1) + 1, b = n / (P - 1) + 1;
+    u[((size_t)(P * iy + b) * Gx + P * ix + a) * 2 + comp] = s[k];
+    if (ucell) ucell[(size_t)cell * NDOF + k] = s[k];
+  }
+  if (ucell)
+    for (int j = l; j < NU; j += 64) ucell[(size_t)cell * NDOF + NI + j] = uu[j];
+}
+
+__global__ void k_scatter_skel(const double* __restrict__ x, const int* __restrict__ node, int NU,
+                               double* __restrict__ u) {
+  int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= NU) return;
+  u[(size_t)node[g >> 1] * 2 + (g & 1)] = x[g];
+}
+
+__global__ void k_fill_p(double* __restrict__ x, long long n, double v) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) x[i] = v;
+}
+
+// partial sums of (a - b)^2
+__global__ void k_diff_dot(const double* __restrict__ a, const double* __restrict__ b, int N, double* __restrict__ red) {
+  __shared__ double sh[kBlk];
+  int g = blockIdx.x * kBlk + threadIdx.x;
+  double d = g < N ? (a[g] - b[g]) : 0.0;
+  d = block_sum(d * d, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = d;
+}
+
+// ---------------------------------------------------------------------------
+template <int NU, int NC>
+static void launch_pre(Ctx* c, bool fp32, const double* r) {
+  if (fp32)
+    hipLaunchKernelGGL((k_pre_local<float, NU, NC>), dim3(c->ncell), dim3(64), 0, c->stream, (const float*)c->d_P,
+                       (const float*)c->d_Psi, c->d_RU, r, c->d_partU, c->d_partC);
+  else
+    hipLaunchKernelGGL((k_pre_local<double, NU, NC>), dim3(c->ncell), dim3(64), 0, c->stream, (const double*)c->d_P,
+                       (const double*)c->d_Psi, c->d_RU, r, c->d_partU, c->d_partC);
+}
+template <int NU, int NC>
+static void launch_prolong(Ctx* c, bool fp32) {
+  if (fp32)
+    hipLaunchKernelGGL((k_prolong<float, NU, NC>), dim3(c->ncell), dim3(64), 0, c->stream, (const float*)c->d_Psi,
+                       c->d_RC, c->d_xc, c->d_partU);
+  else
+    hipLaunchKernelGGL((k_prolong<double, NU, NC>), dim3(c->ncell), dim3(64), 0, c->stream, (const double*)c->d_Psi,
+                       c->d_RC, c->d_xc, c->d_partU);
+}
+
+#define DISPATCH_P(macro) \
+  switch (c->p) { macro(2) macro(3) macro(4) macro(5) macro(6) macro(7) macro(8) default: break; }
+
+static void op_local(Ctx* c, const double* x) {
+#define OPC(pp) case pp: hipLaunchKernelGGL(k_op_local<8 * pp>, dim3(c->ncell), dim3(64), 0, c->stream, c->d_S, c->d_RU, x, c->d_partU); break;
+  DISPATCH_P(OPC)
+#undef OPC
+}
+static void pre_local(Ctx* c, bool fp32, const double* r) {
+#define PRC(pp) case pp: if (c->nce == 3) launch_pre<8 * pp, 20>(c, fp32, r); else launch_pre<8 * pp, 16>(c, fp32, r); break;
+  DISPATCH_P(PRC)
+#undef PRC
+}
+static void prolong(Ctx* c, bool fp32) {
+#define PLC(pp) case pp: if (c->nce == 3) launch_prolong<8 * pp, 20>(c, fp32); else launch_prolong<8 * pp, 16>(c, fp32); break;
+  DISPATCH_P(PLC)
+#undef PLC
+}
+
+// z = S_BDDC^-1 r (Alg. 1), with the partial dot r.z into red
+static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red, double* t_pre, double* t_coarse) {
+  const int nbU = (c->NU + kBlk - 1) / kBlk, nbC = (c->NC + kBlk - 1) / kBlk;
+  hipEventRecord(c->ev[2], c->stream);
+  pre_local(c, fp32, r);
+  hipEventRecord(c->ev[3], c->stream);
+  hipLaunchKernelGGL(k_gather_dot, dim3(nbC), dim3(kBlk), 0, c->stream, c->d_partC, c->d_cown_ptr, c->d_cown,
+                     c->d_zc, c->NC, (const double*)nullptr, (double*)nullptr);
+  hipEventRecord(c->ev[4], c->stream);
+  hipError_t e = launch_coarse_solve(c, c->d_zc, c->d_xc);
+  if (e != hipSuccess) return e;
+  hipEventRecord(c->ev[5], c->stream);
+  prolong(c, fp32);
+  hipLaunchKernelGGL(k_gather_dot, dim3(nbU), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, z,
+                     c->NU, r, red);
+  (void)t_pre; (void)t_coarse;
+  return hipGetLastError();
+}
+
+hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32, double* t_op,
+                     double* t_pre, double* t_coarse, int* n_apply) {
+  const int N = c->NU, nb = (N + kBlk - 1) / kBlk;
+  double* f = c->d_f + (size_t)rhs * N;
+  double* x = c->d_x + (size_t)rhs * N;
+  double *r = c->d_r, *z = c->d_z, *p = c->d_p, *q = c->d_q;
+  double* red = c->d_red;
+  double* scal = c->d_scal;
+  hipLaunchKernelGGL(k_fill_p, dim3(256), dim3(256), 0, c->stream, x, (long long)N, 0.0);
+  hipLaunchKernelGGL(k_fill_p, dim3(1), dim3(64), 0, c->stream, scal, 16LL, 0.0);
+  hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kBlk), 0, c->stream, r, f, N);
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlk), 0, c->stream, f, f, N, red);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 6, 0);
+  float ms = 0;
+  double acc_pre = 0, acc_coarse = 0, acc_op = 0;
+  int napp = 0;
+  hipError_t e = apply_M(c, fp32, r, z, red, t_pre, t_coarse);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 0, 0);  // rz
+  hipLaunchKernelGGL(k_update_p, dim3(nb), dim3(kBlk), 0, c->stream, p, z, scal, N, 1);
+  napp++;
+  hipEventSynchronize(c->ev[5]);
+  if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) acc_pre += ms;
+  if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) acc_coarse += ms;
+  e = hipMemcpyAsync(c->h_scal, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  const double ff = c->h_scal[6];
+  double rel = 1.0;
+  int it = 0;
+  info->iters = 0;
+  info->rel_res = ff > 0 ? 1.0 : 0.0;
+  if (!(ff > 0)) return hipSuccess;
+  while (it < max_iter) {
+    hipEventRecord(c->ev[0], c->stream);
+    op_local(c, p);
+    hipEventRecord(c->ev[1], c->stream);
+    hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, q, N,
+                       p, red);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 1, 1);  // pq, alpha
+    hipLaunchKernelGGL(k_update_xr, dim3(nb), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 3, 0);  // rr
+    e = hipMemcpyAsync(c->h_scal, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return e;
+    hipEventRecord(c->ev[6], c->stream);
+    // speculatively enqueue the preconditioner of the next iteration
+    e = apply_M(c, fp32, r, z, red, t_pre, t_coarse);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 4, 2);  // rz_new, beta
+    hipLaunchKernelGGL(k_update_p, dim3(nb), dim3(kBlk), 0, c->stream, p, z, scal, N, 0);
+    e = hipEventSynchronize(c->ev[6]);
+    if (e != hipSuccess) return e;
+    ++it;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) acc_op += ms;
+    if (c->h_scal[7] != 0.0) {
+      hipStreamSynchronize(c->stream);
+      info->iters = it;
+      info->rel_res = sqrt(c->h_scal[3] / ff);
+      return hipErrorUnknown;  // breakdown, reported by the caller
+    }
+    rel = sqrt(c->h_scal[3] / ff);
+    if (rel <= rtol) break;
+    hipEventSynchronize(c->ev[5]);
+    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) acc_pre += ms;
+    if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) acc_coarse += ms;
+    napp++;
+  }
+  e = hipStreamSynchronize(c->stream);
+  info->iters = it;
+  info->rel_res = rel;
+  if (t_op) *t_op += acc_op;
+  if (t_pre) *t_pre += acc_pre;
+  if (t_coarse) *t_coarse += acc_coarse;
+  if (n_apply) *n_apply += napp;
+  return e;
+}
+
+// ||f - S x||_2 / ||f||_2 recomputed from the iterate
+hipError_t pcg_true_residual(Ctx* c, int rhs, double* out) {
+  const int N = c->NU, nb = (N + kBlk - 1) / kBlk;
+  const double* f = c->d_f + (size_t)rhs * N;
+  const double* x = c->d_x + (size_t)rhs * N;
+  op_local(c, x);
+  hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, c->d_q,
+                     N, (const double*)nullptr, (double*)nullptr);
+  hipLaunchKernelGGL(k_diff_dot, dim3(nb), dim3(kBlk), 0, c->stream, f, c->d_q, N, c->d_red);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, c->d_red, nb, c->d_scal, 8, 0);
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlk), 0, c->stream, f, f, N, c->d_red);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, c->d_red, nb, c->d_scal, 9, 0);
+  hipError_t e = hipMemcpyAsync(c->h_scal, c->d_scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(c->stream);
+  *out = c->h_scal[9] > 0 ? sqrt(c->h_scal[8] / c->h_scal[9]) : 0.0;
+  return e;
+}
+
+// f_r = sum over owners of the cell loads (tractions act on skeleton dofs only)
+hipError_t gather_rhs(Ctx* c, int rhs) {
+  const int N = c->NU;
+  hipLaunchKernelGGL(k_gather_dot, dim3((N + kBlk - 1) / kBlk), dim3(kBlk), 0, c->stream,
+                     c->d_load + (size_t)rhs * c->ncell * c->nU, c->d_uown_ptr, c->d_uown, c->d_f + (size_t)rhs * N,
+                     N, (const double*)nullptr, (double*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_recover(Ctx* c, int rhs) {
+  const size_t nu = (size_t)c->Gx * c->Gy * 2;
+  double* u = c->d_u + (size_t)rhs * nu;
+  hipLaunchKernelGGL(k_fill_p, dim3(512), dim3(256), 0, c->stream, u, (long long)nu, 0.0);
+  const double* x = c->d_x + (size_t)rhs * c->NU;
+  double* uc = c->d_ucell ? c->d_ucell + (size_t)rhs * c->ncell * c->ndof : nullptr;
+#define RCC(pp) case pp: hipLaunchKernelGGL(k_recover<pp>, dim3(c->ncell), dim3(64), 0, c->stream, c->d_L, c->d_Y, c->d_RU, x, c->nx, c->Gx, u, uc); break;
+  DISPATCH_P(RCC)
+#undef RCC
+  hipLaunchKernelGGL(k_scatter_skel, dim3((c->NU + 255) / 256), dim3(256), 0, c->stream, x, c->d_skel_node, c->NU, u);
+  return hipGetLastError();
+}
+
+}  // namespace lbddc

@@ -1,0 +1,341 @@
+// Host-side index maps of the lattice (integer topology only) and the small
+// polynomial tables the kernels read.
+//
+// Dof classification (Sec. 3.1): nodes on the clamped left side are Dirichlet,
+// the (p-1)^2 nodes strictly inside a cell are interior, every other node is a
+// skeleton node (this reading reproduces the dof counts printed for the
+// weak-scaling study).  Coarse dofs (Sec. 3.3.1): two values per non-Dirichlet
+// grid vertex, two averages and (optionally) one moment per non-Dirichlet edge.
+//
+// Coarse numbering by grid lines ("super-blocks"): super-block j holds the
+// vertices and horizontal edges of grid line y = j followed by the vertical
+// edges between lines j and j+1.  A cell of row j only touches super-blocks j
+// and j+1, so S_C is block tridiagonal in this order.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace lbddc {
+
+static int skel_node_local(int p, int node, int& a, int& b) {
+  // canonical skeleton node slots: BL, BR, TL, TR, left, right, bottom, top
+  if (node < 4) {
+    a = (node & 1) ? p : 0;
+    b = (node & 2) ? p : 0;
+    return 0;
+  }
+  int e = (node - 4) / (p - 1), k = (node - 4) % (p - 1) + 1;
+  if (e == 0) { a = 0; b = k; }
+  else if (e == 1) { a = p; b = k; }
+  else if (e == 2) { a = k; b = 0; }
+  else { a = k; b = p; }
+  return 0;
+}
+
+bool build_topology(Ctx* c) {
+  const int p = c->p, nx = c->nx, ny = c->ny, nU = c->nU, nC = c->nC, nce = c->nce;
+  // permuted node order: interior nodes, then skeleton slots
+  c->perm_nat.assign(c->nN, 0);
+  int n = 0;
+  for (int b = 1; b < p; ++b)
+    for (int a = 1; a < p; ++a) c->perm_nat[n++] = a + (p + 1) * b;
+  for (int s = 0; s < 4 * p; ++s) {
+    int a, b;
+    skel_node_local(p, s, a, b);
+    c->perm_nat[n++] = a + (p + 1) * b;
+  }
+  c->dirmask.assign(nU, 0);
+  for (int s = 0; s < 4 * p; ++s) {
+    int a, b;
+    skel_node_local(p, s, a, b);
+    if (a == 0) c->dirmask[2 * s] = c->dirmask[2 * s + 1] = 1;
+  }
+  // global skeleton numbering, row-major over the node lattice
+  const int Gx = c->Gx, Gy = c->Gy;
+  std::vector<int> sk((size_t)Gx * Gy, -1);
+  int nsk = 0;
+  std::vector<int> sk_node;
+  for (int gy = 0; gy < Gy; ++gy)
+    for (int gx = 0; gx < Gx; ++gx) {
+      bool dir = gx == 0;
+      bool inter = (gx % p != 0) && (gy % p != 0);
+      if (!dir && !inter) {
+        sk[(size_t)gy * Gx + gx] = nsk++;
+        sk_node.push_back(gy * Gx + gx);
+      }
+    }
+  c->NU = 2 * nsk;
+  c->RU.assign((size_t)c->ncell * nU, -1);
+  for (int cell = 0; cell < c->ncell; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int s = 0; s < 4 * p; ++s) {
+      int a, b;
+      skel_node_local(p, s, a, b);
+      int id = sk[(size_t)(p * iy + b) * Gx + p * ix + a];
+      for (int comp = 0; comp < 2; ++comp)
+        c->RU[(size_t)cell * nU + 2 * s + comp] = id >= 0 ? 2 * id + comp : -1;
+    }
+  }
+  // coarse numbering by super-blocks
+  CoarseLayout& co = c->co;
+  co.nsb = ny + 1;
+  co.sb_off.assign(co.nsb, 0);
+  co.sb_size.assign(co.nsb, 0);
+  int off = 0;
+  for (int j = 0; j < co.nsb; ++j) {
+    co.sb_off[j] = off;
+    co.sb_size[j] = 2 * nx + nce * nx + (j < ny ? nce * nx : 0);
+    off += co.sb_size[j];
+  }
+  c->NC = off;
+  co.mmax = *std::max_element(co.sb_size.begin(), co.sb_size.end());
+  auto vert = [&](int vx, int vy) { return vx < 1 ? -1 : co.sb_off[vy] + 2 * (vx - 1); };
+  auto hedge = [&](int ex, int vy) { return co.sb_off[vy] + 2 * nx + nce * ex; };
+  auto vedge = [&](int vx, int ey) { return vx < 1 ? -1 : co.sb_off[ey] + 2 * nx + nce * nx + nce * (vx - 1); };
+  c->RC.assign((size_t)c->ncell * nC, -1);
+  for (int cell = 0; cell < c->ncell; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    int* r = &c->RC[(size_t)cell * nC];
+    int v[4] = {vert(ix, iy), vert(ix + 1, iy), vert(ix, iy + 1), vert(ix + 1, iy + 1)};
+    for (int k = 0; k < 4; ++k)
+      for (int comp = 0; comp < 2; ++comp) r[2 * k + comp] = v[k] >= 0 ? v[k] + comp : -1;
+    int e[4] = {vedge(ix, iy), vedge(ix + 1, iy), hedge(ix, iy), hedge(ix, iy + 1)};
+    for (int k = 0; k < 4; ++k)
+      for (int t = 0; t < nce; ++t) r[8 + nce * k + t] = e[k] >= 0 ? e[k] + t : -1;
+  }
+  // owner lists (in increasing cell order: fixed summation order)
+  auto owners = [](const std::vector<int>& R, int nslot, int N, std::vector<int>& ptr, std::vector<int>& own) {
+    ptr.assign(N + 1, 0);
+    for (size_t i = 0; i < R.size(); ++i)
+      if (R[i] >= 0) ptr[R[i] + 1]++;
+    for (int g = 0; g < N; ++g) ptr[g + 1] += ptr[g];
+    own.assign(ptr[N], 0);
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (size_t i = 0; i < R.size(); ++i)
+      if (R[i] >= 0) own[fill[R[i]]++] = (int)i;
+    (void)nslot;
+  };
+  std::vector<int> uptr, uown, cptr, cown;
+  owners(c->RU, nU, c->NU, uptr, uown);
+  owners(c->RC, nC, c->NC, cptr, cown);
+
+  // ---- coarse matrix assembly plan ------------------------------------------
+  const int nCp = nC * (nC + 1) / 2;
+  co.dense_off.assign(co.nsb, 0);
+  long long doff = 0;
+  for (int j = 0; j < co.nsb; ++j) {
+    co.dense_off[j] = doff;
+    doff += (long long)co.sb_size[j] * co.sb_size[j];
+  }
+  co.dense_total = doff;
+  std::vector<int> sb_of(c->NC);
+  for (int j = 0; j < co.nsb; ++j)
+    for (int a = 0; a < co.sb_size[j]; ++a) sb_of[co.sb_off[j] + a] = j;
+  // per row: (g2, contrib) lists from the owners of g1
+  co.b_rowptr_off.assign(co.nsb, 0);
+  co.bt_rowptr_off.assign(co.nsb, 0);
+  co.b_val_off.assign(co.nsb, 0);
+  co.bt_val_off.assign(co.nsb, 0);
+  // rowptr arrays: B_j rows = sb j+1 rows; BT_j rows = sb j rows
+  std::vector<std::vector<int>> brow(co.nsb), btrow(co.nsb);
+  std::vector<std::vector<int>> bcol(co.nsb), btcol(co.nsb);
+  std::vector<std::vector<long long>> bent(co.nsb), btent(co.nsb);  // entry ids in order
+  for (int j = 0; j < co.nsb; ++j) {
+    if (j + 1 < co.nsb) brow[j].assign(co.sb_size[j + 1] + 1, 0);
+    btrow[j].assign(co.sb_size[j] + 1, 0);
+  }
+  co.dest.clear();
+  co.cstart.assign(1, 0);
+  co.contrib.clear();
+  std::vector<std::pair<long long, int>> row;
+  long long nent = 0;
+  for (int g1 = 0; g1 < c->NC; ++g1) {
+    row.clear();
+    for (int o = cptr[g1]; o < cptr[g1 + 1]; ++o) {
+      int slot = cown[o];
+      int cell = slot / nC, l1 = slot % nC;
+      for (int l2 = 0; l2 < nC; ++l2) {
+        int g2 = c->RC[(size_t)cell * nC + l2];
+        if (g2 < 0) continue;
+        int hi = std::max(l1, l2), lo = std::min(l1, l2);
+        row.push_back({(long long)g2 * c->ncell + cell, cell * nCp + hi * (hi + 1) / 2 + lo});
+      }
+    }
+    std::sort(row.begin(), row.end());
+    int s1 = sb_of[g1], a = g1 - co.sb_off[s1];
+    size_t i = 0;
+    while (i < row.size()) {
+      int g2 = (int)(row[i].first / c->ncell);
+      size_t k = i;
+      while (k < row.size() && (int)(row[k].first / c->ncell) == g2) {
+        co.contrib.push_back(row[k].second);
+        ++k;
+      }
+      co.cstart.push_back((int)co.contrib.size());
+      int s2 = sb_of[g2], b = g2 - co.sb_off[s2];
+      long long e = nent++;
+      if (s1 == s2) {
+        co.dest.push_back(co.dense_off[s1] + (long long)a * co.sb_size[s1] + b);
+      } else if (s1 == s2 + 1) {  // B_{s2}: row a of sb s1, col b of sb s2
+        bcol[s2].push_back(b);
+        bent[s2].push_back(e);
+        brow[s2][a + 1]++;
+        co.dest.push_back(-1);
+      } else if (s2 == s1 + 1) {  // BT_{s1}: row a of sb s1, col b of sb s2
+        btcol[s1].push_back(b);
+        btent[s1].push_back(e);
+        btrow[s1][a + 1]++;
+        co.dest.push_back(-1);
+      } else {
+        c->err = "internal: coarse coupling beyond neighbouring grid lines";
+        return false;
+      }
+      i = k;
+    }
+  }
+  // finalize CSR (rows were visited in increasing order, so columns are already in row order)
+  long long vb = 0, vbt = 0;
+  co.b_rowptr.clear();
+  co.bt_rowptr.clear();
+  co.b_col.clear();
+  co.bt_col.clear();
+  for (int j = 0; j < co.nsb; ++j) {
+    co.b_val_off[j] = (int)vb;
+    co.b_rowptr_off[j] = (int)co.b_rowptr.size();
+    if (j + 1 < co.nsb) {
+      auto& r = brow[j];
+      for (size_t q = 1; q < r.size(); ++q) r[q] += r[q - 1];
+      for (size_t q = 0; q < r.size(); ++q) co.b_rowptr.push_back(r[q]);
+      for (size_t q = 0; q < bcol[j].size(); ++q) {
+        co.b_col.push_back(bcol[j][q]);
+        co.dest[bent[j][q]] = co.dense_total + vb + (long long)q;
+      }
+      vb += (long long)bcol[j].size();
+    }
+  }
+  co.nnzB = vb;
+  for (int j = 0; j < co.nsb; ++j) {
+    co.bt_val_off[j] = (int)vbt;
+    co.bt_rowptr_off[j] = (int)co.bt_rowptr.size();
+    auto& r = btrow[j];
+    for (size_t q = 1; q < r.size(); ++q) r[q] += r[q - 1];
+    for (size_t q = 0; q < r.size(); ++q) co.bt_rowptr.push_back(r[q]);
+    for (size_t q = 0; q < btcol[j].size(); ++q) {
+      co.bt_col.push_back(btcol[j][q]);
+      co.dest[btent[j][q]] = co.dense_total + co.nnzB + vbt + (long long)q;
+    }
+    vbt += (long long)btcol[j].size();
+  }
+  co.nnzBT = vbt;
+
+  // net owners for the gradient gather
+  const int m = c->m, np1 = (m + 1) * (m + 1);
+  std::vector<int> nptr((size_t)c->netx * c->nety + 1, 0), nown;
+  for (int cell = 0; cell < c->ncell; ++cell) {
+    int ix = cell % nx, iy = cell / nx;
+    for (int b = 0; b <= m; ++b)
+      for (int a = 0; a <= m; ++a) nptr[(size_t)(m * iy + b) * c->netx + m * ix + a + 1]++;
+  }
+  for (size_t g = 0; g + 1 < nptr.size(); ++g) nptr[g + 1] += nptr[g];
+  nown.assign(nptr.back(), 0);
+  {
+    std::vector<int> fill(nptr.begin(), nptr.end() - 1);
+    for (int cell = 0; cell < c->ncell; ++cell) {
+      int ix = cell % nx, iy = cell / nx;
+      for (int b = 0; b <= m; ++b)
+        for (int a = 0; a <= m; ++a) {
+          size_t g = (size_t)(m * iy + b) * c->netx + m * ix + a;
+          nown[fill[g]++] = cell * np1 + b * (m + 1) + a;
+        }
+    }
+  }
+
+  // ---- upload ------------------------------------------------------------------
+  auto up = [&](auto** dptr, const auto& v) -> bool {
+    using T = typename std::remove_reference<decltype(v)>::type::value_type;
+    size_t nbytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    if (!dalloc(c, (void**)dptr, nbytes)) return false;
+    if (!v.empty() && hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+      c->err = "hipMemcpy failed";
+      return false;
+    }
+    return true;
+  };
+  return up(&c->d_perm, c->perm_nat) && up(&c->d_dirmask, c->dirmask) && up(&c->d_RU, c->RU) &&
+         up(&c->d_RC, c->RC) && up(&c->d_uown_ptr, uptr) && up(&c->d_uown, uown) && up(&c->d_cown_ptr, cptr) &&
+         up(&c->d_cown, cown) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
+         up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
+         up(&c->d_dest, co.dest) && up(&c->d_b_rowptr, co.b_rowptr) && up(&c->d_b_col, co.b_col) &&
+         up(&c->d_bt_rowptr, co.bt_rowptr) && up(&c->d_bt_col, co.bt_col);
+}
+
+void build_tables(Ctx* c, std::vector<double>& tab) {
+  const int p = c->p, q = c->q, m = c->m;
+  Tables& T = c->tab;
+  tab.clear();
+  auto mark = [&]() { return (int)tab.size(); };
+  std::vector<double> gq = gll_points(q);
+  // Bernstein gradients at the interpolation points, k3 = a + (q+1) b
+  T.off_geo_dN = mark();
+  for (int k3 = 0; k3 < c->nL; ++k3) {
+    double x1 = gq[k3 % (q + 1)], x2 = gq[k3 / (q + 1)];
+    for (int b = 0; b <= m; ++b)
+      for (int a = 0; a <= m; ++a) {
+        tab.push_back(bernstein_derivative(m, a, x1) * bernstein_value(m, b, x2));
+        tab.push_back(bernstein_value(m, a, x1) * bernstein_derivative(m, b, x2));
+      }
+  }
+  // det J check sample: Gauss 2m+2 points plus both ends, tensor product
+  std::vector<double> gx, gw;
+  gauss_rule(2 * m + 2, gx, gw);
+  gx.push_back(0.0);
+  gx.push_back(1.0);
+  T.off_chk_dN = mark();
+  T.nchk = (int)(gx.size() * gx.size());
+  for (double x2 : gx)
+    for (double x1 : gx)
+      for (int b = 0; b <= m; ++b)
+        for (int a = 0; a <= m; ++a) {
+          tab.push_back(bernstein_derivative(m, a, x1) * bernstein_value(m, b, x2));
+          tab.push_back(bernstein_value(m, a, x1) * bernstein_derivative(m, b, x2));
+        }
+  // edge rule for constraint rows: 2p+2 Gauss points
+  std::vector<double> gp = gll_points(p);
+  gauss_rule(2 * p + 2, gx, gw);
+  T.nq_edge = (int)gx.size();
+  T.off_edge_w = mark();
+  for (double w : gw) tab.push_back(w);
+  T.off_edge_b = mark();
+  for (int a = 0; a <= p; ++a)
+    for (double x : gx) tab.push_back(lagrange_value(gp, a, x));
+  T.off_edge_B = mark();
+  for (int a = 0; a <= m; ++a)
+    for (double x : gx) tab.push_back(bernstein_value(m, a, x));
+  T.off_edge_dB = mark();
+  for (int a = 0; a <= m; ++a)
+    for (double x : gx) tab.push_back(bernstein_derivative(m, a, x));
+  T.off_mid_B = mark();
+  for (int a = 0; a <= m; ++a) tab.push_back(bernstein_value(m, a, 0.5));
+  // load rule: p+2m+2 Gauss points
+  gauss_rule(p + 2 * m + 2, gx, gw);
+  T.nq_load = (int)gx.size();
+  T.off_load_w = mark();
+  for (double w : gw) tab.push_back(w);
+  T.off_load_b = mark();
+  for (int a = 0; a <= p; ++a)
+    for (double x : gx) tab.push_back(lagrange_value(gp, a, x));
+  T.off_load_dB = mark();
+  for (int a = 0; a <= m; ++a)
+    for (double x : gx) tab.push_back(bernstein_derivative(m, a, x));
+  // GLL points of the MDEIM interpolation degree of each family slot
+  for (int s = 0; s < 4; ++s) T.off_rnodes[s] = -1;
+  for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
+    const RomDev& R = c->roms[c->fam_ids[s]];
+    T.off_rnodes[s] = mark();
+    for (double v : gll_points(R.r)) tab.push_back(v);
+  }
+  T.total = (int)tab.size();
+}
+
+}  // namespace lbddc
