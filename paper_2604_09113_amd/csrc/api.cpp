@@ -9,10 +9,6 @@
 
 using namespace lbddc;
 
-struct lbddc_ctx {
-  Ctx c;
-};
-
 namespace lbddc {
 
 bool dalloc(Ctx* c, void** p, size_t bytes) {
@@ -129,6 +125,7 @@ void lbddc_destroy(lbddc_ctx* x) {
   for (auto& kv : c->roms) {
     for (auto p : kv.second.ut64) hipFree(p);
     for (auto p : kv.second.ut32) hipFree(p);
+    for (auto p : kv.second.ucol64) hipFree(p);
     if (kv.second.coeff) hipFree(kv.second.coeff);
   }
   for (int i = 0; i < 8; ++i)
@@ -178,7 +175,9 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
   R.family = d->family; R.p = p; R.q = q; R.n_k = d->n_k; R.n_r = d->n_r; R.r = d->r;
   R.lo = d->lo; R.hi = d->hi; R.KC = KC;
   const size_t tile_n = (size_t)NPT * ns * KC * 64;
-  std::vector<double> h64(tile_n);
+  const int RB = (4 * KC + 15) / 16;
+  const size_t tile2_n = (size_t)NPT * ns * RB * 4 * 64;
+  std::vector<double> h64(tile_n), h2(tile2_n);
   std::vector<float> h32(tile_n);
   for (int k = 0; k < d->n_k; ++k) {
     const double* U = d->U + (size_t)k * n_i * d->n_r;
@@ -203,15 +202,34 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
             h64[o] = v64;
             h32[o] = (float)v32;
           }
+    // transposed tiles of the adjoint: [pt][s][rb][kk][lane], row = r, k = pair 4*(lane/16) + kk
+    for (int pt = 0; pt < NPT; ++pt)
+      for (int s = 0; s < ns; ++s)
+        for (int rb = 0; rb < RB; ++rb)
+          for (int kk = 0; kk < 4; ++kk)
+            for (int lane = 0; lane < 64; ++lane) {
+              const int r = 16 * rb + (lane & 15), P = pt * 16 + 4 * (lane >> 4) + kk;
+              double v = 0.0;
+              if (P < npair) {
+                const long long idx = ((long long)perm[pn1[P]] * nB + perm[pn2[P]]) * ns + s;
+                if (r < d->n_r) v = U[(size_t)idx * d->n_r + r];
+                else if (r == d->n_r) v = d->I_pi[idx];
+              }
+              h2[((((size_t)pt * ns + s) * RB + rb) * 4 + kk) * 64 + lane] = v;
+            }
     double* d64 = nullptr;
+    double* d2 = nullptr;
     float* d32 = nullptr;
-    if (hipMalloc(&d64, tile_n * 8) != hipSuccess || hipMalloc(&d32, tile_n * 4) != hipSuccess)
+    if (hipMalloc(&d64, tile_n * 8) != hipSuccess || hipMalloc(&d32, tile_n * 4) != hipSuccess ||
+        hipMalloc(&d2, tile2_n * 8) != hipSuccess)
       return fail(c, LBDDC_E_NOMEM, "load_rom: device allocation failed");
     if (hipMemcpy(d64, h64.data(), tile_n * 8, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d32, h32.data(), tile_n * 4, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(d32, h32.data(), tile_n * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d2, h2.data(), tile2_n * 8, hipMemcpyHostToDevice) != hipSuccess)
       return fail(c, LBDDC_E_HIP, "load_rom: copy failed");
     R.ut64.push_back(d64);
     R.ut32.push_back(d32);
+    R.ucol64.push_back(d2);
   }
   const size_t nco = (size_t)d->n_k * (d->r + 1) * d->n_r;
   if (hipMalloc(&R.coeff, nco * 8) != hipSuccess) return fail(c, LBDDC_E_NOMEM, "load_rom: allocation failed");
@@ -221,6 +239,7 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
   if (it != c->roms.end()) {
     for (auto p2 : it->second.ut64) hipFree(p2);
     for (auto p2 : it->second.ut32) hipFree(p2);
+    for (auto p2 : it->second.ucol64) hipFree(p2);
     if (it->second.coeff) hipFree(it->second.coeff);
   }
   c->roms[d->family] = R;
@@ -307,7 +326,13 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_zc, NC) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC) &&
             dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 16)) && dalloc_t(c, &c->d_scal, 32) &&
             dalloc_t(c, &c->d_u, (size_t)c->nrhs * c->Gx * c->Gy * 2) &&
-            dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof);
+            dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&
+            dalloc_t(c, &c->d_H, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_G, (size_t)ncell * c->ns * 4) &&
+            dalloc_t(c, &c->d_gcell, (size_t)ncell * (c->m + 1) * (c->m + 1) * 2) &&
+            dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) &&
+            dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
+            dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8) &&
+            dalloc_t(c, &c->d_pairs, (size_t)2 * c->npair);
   if (!ok) { free_problem(c); return LBDDC_E_NOMEM; }
   // family -> slot table after the 8 flag words
   std::vector<int> flags(128, 0);
@@ -321,6 +346,13 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
   if (e == hipSuccess) e = hipMemcpy(c->d_t, d->t, ncell * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_trac, d->traction, (size_t)c->nrhs * c->ny * 2 * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem upload"); }
+  {
+    std::vector<int> pr(2 * c->npair);
+    for (int n1 = 0, P = 0; n1 < c->nN; ++n1)
+      for (int n2 = 0; n2 <= n1; ++n2, ++P) { pr[2 * P] = n1; pr[2 * P + 1] = n2; }
+    if (e == hipSuccess) e = hipMemcpy(c->d_pairs, pr.data(), pr.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem upload"); }
+  }
   c->fam_host.assign(d->family, d->family + ncell);
   c->t_host.assign(d->t, d->t + ncell);
   // validate the maps on the device (det J) right away

@@ -175,6 +175,10 @@ struct Ctx {
   double* d_gt = nullptr;      // [nrhs][ncell]
   double* d_gX = nullptr;      // [nrhs][nety*netx*2]
   double* d_J = nullptr;       // [nrhs]
+  int* d_adj_tiles = nullptr;  // 16-cell tiles of the adjoint contraction
+  void* d_adj_ptrs = nullptr;  // per-group tile pointers (A and transposed layouts)
+  int* d_pairs = nullptr;      // [npair] (n1, n2) of each node pair
+  std::vector<int> group_counts;
   double* d_ucell = nullptr;   // [ncell][ndof] local displacement (permuted)
 
   double phase_ms[12] = {0};
@@ -211,3 +215,7 @@ hipError_t launch_gradient(Ctx* c, int rhs); // A11
 hipError_t launch_export(Ctx* c, int which, int first, int count, double* d_out);
 
 }  // namespace lbddc
+
+struct lbddc_ctx {
+  lbddc::Ctx c;
+};

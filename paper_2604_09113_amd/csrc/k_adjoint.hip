@@ -1,6 +1,431 @@
-// Compliance gradient (A11).  Placeholder entry points; the adjoint
-// contraction kernels are added in the same file.
+// Compliance J = f^T u and its gradient (A11).
+//
+// With K u = f and J = f^T u, dJ = 2 u^T df - u^T dK u: the adjoint state of
+// the compliance is u itself, so the gradient reuses the PCG solution (no
+// second solve).  Per cell, with the fast-assembly contraction of Alg. 4/5,
+//   E = u^T K u = sum_{pairs P, s} Z[P, s] * Ihat[P, s],
+//   Ihat[P, s] = sum_r Uhat[P, s, r] Itil[r],
+//   Z[P, s]   = w_P sum_{i1 i2} theta[i1 i2, s] u[n1, i1] u[n2, i2]
+// (w_P = 2 for n1 > n2, 1 on the diagonal node pairs), hence
+//   H[r]        = dE/dItil[r]        = sum_{P, s} Uhat[P, s, r] Z[P, s]
+//   G[i1 i2, s] = dE/dtheta[i1 i2,s] = sum_P w_P u u Ihat[P, s].
+// k_adjoint computes both on MFMA with the same Uhat tiles as the assembly
+// (Ihat as in the assembly; H as a second, transposed product).  k_chain
+// applies the chain rule: dItil/dt through the derivative of the Lagrange
+// interpolant of the reduced coordinates, and dtheta/dX through the
+// pulled-back tensor Chat(J) and the Bernstein map.  The traction load depends
+// on the loaded edge's control points through the curve Jacobian.
 #include "internal.h"
 
-extern "C" lbddc_status lbddc_compliance_gradient(lbddc_ctx*, double*, double*, double*) { return LBDDC_E_UNSUPPORTED; }
-extern "C" lbddc_status lbddc_compliance_gradient_device(lbddc_ctx*, double*, double*, double*) { return LBDDC_E_UNSUPPORTED; }
+namespace lbddc {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// tiles16[i] = {group, first position in `sorted`, number of cells (<= 16), unused}
+template <int KC, int RB>
+__global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict__ utg,
+                                                 const double* const* __restrict__ ut2g,
+                                                 const double* __restrict__ theta, const double* __restrict__ itil,
+                                                 const double* __restrict__ ucell, const int* __restrict__ sorted,
+                                                 const int4* __restrict__ tiles, const int2* __restrict__ pairs,
+                                                 double* __restrict__ Hout, double* __restrict__ Gout, int ns,
+                                                 int npair, int NPT, int itil_stride, int ndof) {
+  extern __shared__ double lds[];
+  const int4 td = tiles[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const bool valid = col < td.z;
+  const int cell = sorted[td.y + (valid ? col : 0)];
+  const int GW = 16 * ns * 4;
+  double* Gw = lds + wave * GW;
+  for (int i = lane; i < GW; i += 64) Gw[i] = 0.0;
+  double b[KC];
+#pragma unroll
+  for (int kc = 0; kc < KC; ++kc) b[kc] = itil[(size_t)cell * itil_stride + 4 * kc + grp];
+  dbl4 hacc[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) hacc[rb] = dbl4{0, 0, 0, 0};
+  const double* uc = ucell + (size_t)cell * ndof;
+  const double* th = theta + (size_t)cell * ns * 4;
+  const double* ut = utg[td.x];
+  const double* ut2 = ut2g[td.x];
+  __syncthreads();
+  for (int pt = wave; pt < NPT; pt += 4) {
+    double uu[4][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int P = pt * 16 + 4 * grp + v;
+      if (P < npair && valid) {
+        const int2 nn = pairs[P];
+        const double w = nn.x == nn.y ? 1.0 : 2.0;
+        const double a0 = uc[2 * nn.x], a1 = uc[2 * nn.x + 1], c0 = uc[2 * nn.y], c1 = uc[2 * nn.y + 1];
+        uu[v][0] = w * a0 * c0; uu[v][1] = w * a0 * c1; uu[v][2] = w * a1 * c0; uu[v][3] = w * a1 * c1;
+      } else {
+        uu[v][0] = uu[v][1] = uu[v][2] = uu[v][3] = 0.0;
+      }
+    }
+    const double* ap = ut + (size_t)pt * ns * KC * 64 + lane;
+    const double* ap2 = ut2 + (size_t)pt * ns * RB * 4 * 64 + lane;
+    for (int s = 0; s < ns; ++s) {
+      dbl4 d = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) d = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(s * KC + kc) * 64], b[kc], d, 0, 0, 0);
+      double g[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double t = uu[0][e] * d[0] + uu[1][e] * d[1] + uu[2][e] * d[2] + uu[3][e] * d[3];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        g[e] = t;
+      }
+      const double gm = grp == 0 ? g[0] : grp == 1 ? g[1] : grp == 2 ? g[2] : g[3];
+      Gw[(col * ns + s) * 4 + grp] += gm;
+      const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + s * 4);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap2[((s * RB + rb) * 4 + kk) * 64], z, hacc[rb], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+  // G: sum the four waves in a fixed order and write
+  for (int i = threadIdx.x; i < GW; i += 256) {
+    double v = lds[i] + lds[GW + i] + lds[2 * GW + i] + lds[3 * GW + i];
+    const int c = i / (ns * 4), rest = i % (ns * 4);
+    if (c < td.z) Gout[(size_t)sorted[td.y + c] * ns * 4 + rest] = v;
+  }
+  __syncthreads();
+  // H: lane (grp, col) holds r = 16 rb + grp + 4 v
+  const int HW = 16 * 16 * RB;
+  double* Hw = lds + wave * HW;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Hw[col * 16 * RB + 16 * rb + grp + 4 * v] = hacc[rb][v];
+  __syncthreads();
+  for (int i = threadIdx.x; i < HW; i += 256) {
+    const double v = lds[i] + lds[HW + i] + lds[2 * HW + i] + lds[3 * HW + i];
+    const int c = i / (16 * RB), r = i % (16 * RB);
+    if (c < td.z && r < itil_stride) Hout[(size_t)sorted[td.y + c] * itil_stride + r] = v;
+  }
+}
+
+struct ChainArgs {
+  const double* ctrl; const int* family; const double* t; const double* tab; const int* fam_slot;
+  const double* coeff[4];
+  double lo[4], hi[4];
+  int n_k[4], n_r[4], r[4];
+  int ncell, nx, ny, netx, m, nL, ns, itil_stride, p, ndof, nI;
+  double lam, mu, rho;
+  Tables T;
+  const double* H; const double* G; const double* ucell; const double* trac;
+  double* gcell;  // [ncell][(m+1)^2][2] per-cell dJ/dX (already with the minus sign and load term)
+  double* gt;     // [ncell] dJ/dt
+};
+
+__global__ void k_chain(ChainArgs g) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const int ix = cell % g.nx, iy = cell / g.nx, m = g.m, np1 = (m + 1) * (m + 1);
+  // dJ/dt = -H . dItil/dt
+  const int fam = g.family[cell];
+  const int slot = g.fam_slot[fam];
+  {
+    const double t = g.t[cell], lo = g.lo[slot], hi = g.hi[slot];
+    const int nk = g.n_k[slot], R = g.r[slot], nr = g.n_r[slot];
+    const double w = (hi - lo) / nk;
+    int k = (int)floor((t - lo) / w);
+    if (k > nk - 1) k = nk - 1;
+    if (k < 0) k = 0;
+    const double a = lo + k * w, b = lo + (k + 1) * w, h = b - a, tau = (t - a) / h;
+    const double* nodes = g.tab + g.T.off_rnodes[slot];
+    double dl[17];
+    for (int j = 0; j <= R; ++j) {
+      double s = 0.0;
+      for (int l = 0; l <= R; ++l) {
+        if (l == j) continue;
+        double term = 1.0 / (nodes[j] - nodes[l]);
+        for (int q = 0; q <= R; ++q)
+          if (q != j && q != l) term *= (tau - nodes[q]) / (nodes[j] - nodes[q]);
+        s += term;
+      }
+      dl[j] = s / h;
+    }
+    const double* cf = g.coeff[slot] + (size_t)k * (R + 1) * nr;
+    double dE = 0.0;
+    for (int r = 0; r < nr; ++r) {
+      double s = 0.0;
+      for (int j = 0; j <= R; ++j) s += dl[j] * cf[j * nr + r];
+      dE += g.H[(size_t)cell * g.itil_stride + r] * (1.0 - g.rho) * s;
+    }
+    g.gt[cell] = -dE;
+  }
+  // dE/dX through Chat(J) at the interpolation points
+  double X[25][2];
+  for (int b = 0; b <= m; ++b)
+    for (int a = 0; a <= m; ++a) {
+      const double* P = g.ctrl + ((size_t)(m * iy + b) * g.netx + m * ix + a) * 2;
+      X[b * (m + 1) + a][0] = P[0];
+      X[b * (m + 1) + a][1] = P[1];
+    }
+  double gX[25][2];
+  for (int a = 0; a < np1; ++a) gX[a][0] = gX[a][1] = 0.0;
+  const double lam = g.lam, mu = g.mu;
+  for (int k3 = 0; k3 < g.nL; ++k3) {
+    const double* dN = g.tab + g.T.off_geo_dN + (size_t)k3 * np1 * 2;
+    double J[2][2] = {{0, 0}, {0, 0}};
+    for (int a = 0; a < np1; ++a)
+      for (int i = 0; i < 2; ++i) { J[i][0] += X[a][i] * dN[2 * a]; J[i][1] += X[a][i] * dN[2 * a + 1]; }
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double A[2][2] = {{J[1][1] / det, -J[0][1] / det}, {-J[1][0] / det, J[0][0] / det}};
+    // forward-mode derivative of Chat along each unit perturbation E_pq of J
+    double dEdJ[2][2];
+    for (int pp = 0; pp < 2; ++pp)
+      for (int qq = 0; qq < 2; ++qq) {
+        double dA[2][2];
+        for (int j = 0; j < 2; ++j)
+          for (int mm = 0; mm < 2; ++mm) dA[j][mm] = -A[j][pp] * A[qq][mm];
+        const double ddet = det * A[qq][pp];
+        double acc = 0.0;
+        for (int j1 = 0; j1 < 2; ++j1)
+          for (int j2 = 0; j2 < 2; ++j2) {
+            const double aa = A[j1][0] * A[j2][0] + A[j1][1] * A[j2][1];
+            const double daa = dA[j1][0] * A[j2][0] + A[j1][0] * dA[j2][0] + dA[j1][1] * A[j2][1] + A[j1][1] * dA[j2][1];
+            const int s = (j1 * 2 + j2) * g.nL + k3;
+            for (int i1 = 0; i1 < 2; ++i1)
+              for (int i2 = 0; i2 < 2; ++i2) {
+                const double v = lam * A[j1][i1] * A[j2][i2] + mu * ((i1 == i2 ? aa : 0.0) + A[j1][i2] * A[j2][i1]);
+                const double dv = lam * (dA[j1][i1] * A[j2][i2] + A[j1][i1] * dA[j2][i2]) +
+                                  mu * ((i1 == i2 ? daa : 0.0) + dA[j1][i2] * A[j2][i1] + A[j1][i2] * dA[j2][i1]);
+                const double dC = ddet * v + det * dv;
+                acc += g.G[((size_t)cell * g.ns + s) * 4 + 2 * i1 + i2] * dC;
+              }
+          }
+        dEdJ[pp][qq] = acc;
+      }
+    for (int a = 0; a < np1; ++a)
+      for (int c = 0; c < 2; ++c) gX[a][c] -= dEdJ[c][0] * dN[2 * a] + dEdJ[c][1] * dN[2 * a + 1];
+  }
+  // traction load on the right edge: 2 u . df/dX for the right column of control points
+  if (ix == g.nx - 1) {
+    const int nq = g.T.nq_load, p = g.p;
+    const double* w = g.tab + g.T.off_load_w;
+    const double* bl = g.tab + g.T.off_load_b;
+    const double* dB = g.tab + g.T.off_load_dB;
+    const double t0 = g.trac[iy * 2], t1 = g.trac[iy * 2 + 1];
+    const double* u = g.ucell + (size_t)cell * g.ndof;
+    // u . t at the right-edge nodes (permuted dofs: skeleton slots after the interior ones)
+    double ut[17];
+    for (int n = 0; n <= p; ++n) {
+      const int node = (n == 0) ? 1 : (n == p ? 3 : 4 + (p - 1) + (n - 1));
+      ut[n] = u[g.nI + 2 * node] * t0 + u[g.nI + 2 * node + 1] * t1;
+    }
+    for (int qd = 0; qd < nq; ++qd) {
+      double d0 = 0, d1 = 0;
+      for (int k = 0; k <= m; ++k) {
+        const double* P = &X[k * (m + 1) + m][0];
+        d0 += dB[k * nq + qd] * P[0];
+        d1 += dB[k * nq + qd] * P[1];
+      }
+      const double ds = sqrt(d0 * d0 + d1 * d1);
+      double ub = 0.0;
+      for (int n = 0; n <= p; ++n) ub += ut[n] * bl[n * nq + qd];
+      const double f = 2.0 * w[qd] * ub / ds;
+      for (int k = 0; k <= m; ++k) {
+        gX[k * (m + 1) + m][0] += f * d0 * dB[k * nq + qd];
+        gX[k * (m + 1) + m][1] += f * d1 * dB[k * nq + qd];
+      }
+    }
+  }
+  double* out = g.gcell + (size_t)cell * np1 * 2;
+  for (int a = 0; a < np1; ++a) { out[2 * a] = gX[a][0]; out[2 * a + 1] = gX[a][1]; }
+}
+
+// net gradient: sum over the cells sharing each control point (fixed order)
+__global__ void k_net_gather(const double* __restrict__ gcell, const int* __restrict__ ptr,
+                             const int* __restrict__ own, double* __restrict__ gnet, int nnet) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnet) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int o = ptr[i]; o < ptr[i + 1]; ++o) { a0 += gcell[2 * (size_t)own[o]]; a1 += gcell[2 * (size_t)own[o] + 1]; }
+  gnet[2 * i] = a0;
+  gnet[2 * i + 1] = a1;
+}
+
+// J = f . x over the skeleton (tractions act on skeleton dofs only), one block
+__global__ void k_compliance(const double* __restrict__ f, const double* __restrict__ x, int N, double* __restrict__ J) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N; i += 256) s += f[i] * x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *J = sh[0];
+}
+
+template <int KC>
+static void launch_adj(Ctx* c, const double* const* pu, const double* const* pu2, const int4* tiles, int ntiles,
+                       const int2* pairs, const double* ucell) {
+  constexpr int RB = (4 * KC + 15) / 16;
+  const size_t lds = (size_t)4 * 16 * c->ns * 4 * sizeof(double);
+  hipLaunchKernelGGL((k_adjoint<KC, RB>), dim3(ntiles), dim3(256), lds, c->stream, pu, pu2, c->d_theta, c->d_itil,
+                     ucell, c->d_sorted, tiles, pairs, c->d_H, c->d_G, c->ns, c->npair, c->NPT, 4 * c->KC,
+                     c->ndof);
+}
+
+hipError_t launch_gradient(Ctx* c, int rhs) {
+  hipError_t e;
+  // 16-cell tiles per group, and the per-group tile pointers
+  const int G = (int)c->group_counts.size();
+  std::vector<int> tiles;
+  std::vector<int> fam_first, fam_n;
+  int start = 0, g0 = 0;
+  for (size_t s = 0; s < c->fam_ids.size(); ++s) {
+    fam_first.push_back((int)tiles.size() / 4);
+    for (int k = 0; k < c->roms[c->fam_ids[s]].n_k; ++k, ++g0) {
+      for (int o = 0; o < c->group_counts[g0]; o += 16) {
+        tiles.push_back(g0);
+        tiles.push_back(start + o);
+        tiles.push_back(std::min(16, c->group_counts[g0] - o));
+        tiles.push_back(0);
+      }
+      start += c->group_counts[g0];
+    }
+    fam_n.push_back((int)tiles.size() / 4 - fam_first.back());
+  }
+  std::vector<const void*> ptrs(2 * G);
+  for (int g = 0; g < G; ++g) {
+    const RomDev& R = c->roms[c->fam_ids[c->group_family[g]]];
+    ptrs[g] = R.ut64[c->group_cluster[g]];
+    ptrs[G + g] = R.ucol64[c->group_cluster[g]];
+  }
+  e = hipMemcpyAsync(c->d_adj_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(c->d_adj_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return e;
+  const double* const* pu = (const double* const*)c->d_adj_ptrs;
+  hipEventRecord(c->ev[0], c->stream);
+  for (size_t s = 0; s < c->fam_ids.size(); ++s) {
+    if (fam_n[s] == 0) continue;
+    const int4* tl = reinterpret_cast<const int4*>(c->d_adj_tiles) + fam_first[s];
+    const int2* pr = reinterpret_cast<const int2*>(c->d_pairs);
+    const double* uc = c->d_ucell + (size_t)rhs * c->ncell * c->ndof;
+    switch (c->roms[c->fam_ids[s]].KC) {
+      case 1: launch_adj<1>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 2: launch_adj<2>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 3: launch_adj<3>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 4: launch_adj<4>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 5: launch_adj<5>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 6: launch_adj<6>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 7: launch_adj<7>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 8: launch_adj<8>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 9: launch_adj<9>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 10: launch_adj<10>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 11: launch_adj<11>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      default: return hipErrorInvalidValue;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipEventRecord(c->ev[1], c->stream);
+  ChainArgs a = {};
+  a.ctrl = c->d_ctrl; a.family = c->d_family; a.t = c->d_t; a.tab = c->d_tab; a.fam_slot = c->d_flags + 8;
+  for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
+    const RomDev& R = c->roms[c->fam_ids[s]];
+    a.coeff[s] = R.coeff; a.lo[s] = R.lo; a.hi[s] = R.hi; a.n_k[s] = R.n_k; a.n_r[s] = R.n_r; a.r[s] = R.r;
+  }
+  a.ncell = c->ncell; a.nx = c->nx; a.ny = c->ny; a.netx = c->netx; a.m = c->m; a.nL = c->nL; a.ns = c->ns;
+  a.itil_stride = 4 * c->KC; a.p = c->p; a.ndof = c->ndof; a.nI = c->nI;
+  a.lam = c->E * c->nu / ((1 + c->nu) * (1 - 2 * c->nu));
+  a.mu = c->E / (2 * (1 + c->nu));
+  a.rho = c->rho; a.T = c->tab;
+  a.H = c->d_H; a.G = c->d_G; a.ucell = c->d_ucell + (size_t)rhs * c->ncell * c->ndof;
+  a.trac = c->d_trac + (size_t)rhs * c->ny * 2;
+  a.gcell = c->d_gcell; a.gt = c->d_gt + (size_t)rhs * c->ncell;
+  hipLaunchKernelGGL(k_chain, dim3((c->ncell + 127) / 128), dim3(128), 0, c->stream, a);
+  const int nnet = c->netx * c->nety;
+  hipLaunchKernelGGL(k_net_gather, dim3((nnet + 255) / 256), dim3(256), 0, c->stream, c->d_gcell, c->d_net_ptr,
+                     c->d_net_own, c->d_gX + (size_t)rhs * nnet * 2, nnet);
+  hipLaunchKernelGGL(k_compliance, dim3(1), dim3(256), 0, c->stream, c->d_f + (size_t)rhs * c->NU,
+                     c->d_x + (size_t)rhs * c->NU, c->NU, c->d_J + rhs);
+  return hipGetLastError();
+}
+
+}  // namespace lbddc
+
+using namespace lbddc;
+
+static lbddc_status grad_common(lbddc_ctx* x) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->solved) { c->err = "compliance_gradient: solve first"; return LBDDC_E_STATE; }
+  hipSetDevice(c->device);
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  hipEventRecord(a, c->stream);
+  for (int r = 0; r < c->nrhs; ++r) {
+    hipError_t e = launch_gradient(c, r);
+    if (e != hipSuccess) {
+      c->err = std::string("compliance_gradient: ") + hipGetErrorString(e);
+      return LBDDC_E_HIP;
+    }
+    if (r == 0) {
+      hipEventSynchronize(c->ev[1]);
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->phase_ms[11] = ms;
+    }
+  }
+  hipEventRecord(b, c->stream);
+  hipEventSynchronize(b);
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, a, b) == hipSuccess) c->phase_ms[10] = ms;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return LBDDC_OK;
+}
+
+extern "C" lbddc_status lbddc_compliance_gradient(lbddc_ctx* x, double* J, double* dJ_dctrl, double* dJ_dt) {
+  lbddc_status s = grad_common(x);
+  if (s != LBDDC_OK) return s;
+  Ctx* c = &x->c;
+  const size_t nnet = (size_t)c->netx * c->nety;
+  hipError_t e = hipSuccess;
+  if (J) e = hipMemcpyAsync(J, c->d_J, c->nrhs * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && dJ_dctrl)
+    e = hipMemcpyAsync(dJ_dctrl, c->d_gX, c->nrhs * nnet * 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && dJ_dt)
+    e = hipMemcpyAsync(dJ_dt, c->d_gt, (size_t)c->nrhs * c->ncell * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("compliance_gradient copy: ") + hipGetErrorString(e);
+    return LBDDC_E_HIP;
+  }
+  return LBDDC_OK;
+}
+
+extern "C" lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* x, double* d_J, double* d_dJ_dctrl,
+                                                         double* d_dJ_dt) {
+  lbddc_status s = grad_common(x);
+  if (s != LBDDC_OK) return s;
+  Ctx* c = &x->c;
+  const size_t nnet = (size_t)c->netx * c->nety;
+  hipError_t e = hipSuccess;
+  if (d_J) e = hipMemcpyAsync(d_J, c->d_J, c->nrhs * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && d_dJ_dctrl)
+    e = hipMemcpyAsync(d_dJ_dctrl, c->d_gX, c->nrhs * nnet * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && d_dJ_dt)
+    e = hipMemcpyAsync(d_dJ_dt, c->d_gt, (size_t)c->nrhs * c->ncell * sizeof(double), hipMemcpyDeviceToDevice,
+                       c->stream);
+  if (e != hipSuccess) {
+    c->err = std::string("compliance_gradient_device copy: ") + hipGetErrorString(e);
+    return LBDDC_E_HIP;
+  }
+  return LBDDC_OK;
+}

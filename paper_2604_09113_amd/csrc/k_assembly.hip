@@ -173,6 +173,7 @@ hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return e;
   for (int g = 0; g < G; ++g) counts[g] = c->h_flags[8 + g];
+  c->group_counts.assign(counts, counts + G);
   // tiles of 128 cells per group, per family
   std::vector<int> tiles;
   std::vector<int> fam_first, fam_n;

@@ -108,3 +108,54 @@ def test_iterations_match_oracle(case):
     _, it, _ = P.pcg(F[:, 0], 1e-8)
     print(f"[{name}] iterations gpu {info[0]['iters']} oracle {it}")
     assert abs(info[0]["iters"] - it) <= 1
+
+
+def test_compliance_gradient_vs_oracle(case):
+    """GPU adjoint (u from PCG at rtol 1e-12) vs the oracle's FP64 adjoint on
+    the direct solution: relative error of J and of the gradient vectors."""
+    from oracle.adjoint import compliance_gradient
+    name, prob, roms, P, s, _ = case
+    s.solve(rtol=1e-12, max_iter=500)
+    J, gX, gt = s.compliance_gradient()
+    Jo, gXo, gto = compliance_gradient(P, P.direct_solve())
+    eJ = np.abs(J - Jo).max() / np.abs(Jo).max()
+    eX = np.linalg.norm(gX - gXo) / np.linalg.norm(gXo)
+    et = np.linalg.norm(gt - gto) / np.linalg.norm(gto)
+    print(f"[{name}] J {J[0]:.6e} rel err J {eJ:.2e} dJ/dX {eX:.2e} dJ/dt {et:.2e}")
+    assert eJ <= 1e-10 and eX <= 1e-8 and et <= 1e-8
+
+
+@pytest.mark.parametrize("cfg,over,h", [(4, dict(nx=3, ny=3, p=4), 1e-6), (5, dict(nx=3, ny=2, p=4, nrhs=2), 1e-5)])
+def test_gradient_vs_central_fd_on_gpu(cfg, over, h):
+    """Central finite differences of the GPU compliance along random directions
+    in (control net, thickness) agree with the GPU adjoint to 1e-5.  The
+    mixed-topology two-load lattice is rounding-limited at h = 1e-6 (the
+    oracle's own direct-solve differences are 2e-6 off there), so it uses
+    h = 1e-5."""
+    from gpu_helpers import make_solver
+    prob = make_problem(cfg, **over)
+    roms = oracle_roms(prob)
+
+    def compliance(pr):
+        sv = make_solver(pr, roms)
+        sv.assemble()
+        sv.setup()
+        sv.solve(rtol=1e-13, max_iter=1000)
+        J, gX, gt = sv.compliance_gradient()
+        sv.close()
+        return J, gX, gt
+
+    J, gX, gt = compliance(prob)
+    rng = np.random.default_rng(4242)
+    for _ in range(3):
+        dX = rng.normal(size=prob["ctrl"].shape)
+        dt = rng.normal(size=prob["t"].shape)
+        nrm = np.sqrt((dX ** 2).sum() + (dt ** 2).sum())
+        dX, dt = dX / nrm, dt / nrm
+        pp, pm = dict(prob), dict(prob)
+        pp["ctrl"], pm["ctrl"] = prob["ctrl"] + h * dX, prob["ctrl"] - h * dX
+        pp["t"], pm["t"] = prob["t"] + h * dt, prob["t"] - h * dt
+        fd = (compliance(pp)[0] - compliance(pm)[0]) / (2 * h)
+        ad = np.array([(gX[r] * dX).sum() + (gt[r] * dt).sum() for r in range(len(J))])
+        print(f"[fd cfg{cfg}] fd {fd} adjoint {ad}")
+        assert np.all(np.abs(fd - ad) <= 1e-5 * np.abs(ad))
