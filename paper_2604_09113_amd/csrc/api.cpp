@@ -316,10 +316,10 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_Ktot, NU) && dalloc(c, &c->d_P, (size_t)ncell * c->nE * (c->nE + 1) / 2 * 8) &&
             dalloc(c, &c->d_Psi, (size_t)ncell * nU * nC * 8) && dalloc_t(c, &c->d_D, (size_t)ncell * nU) &&
             dalloc_t(c, &c->d_ScLoc, (size_t)ncell * nC * (nC + 1) / 2) &&
-            dalloc_t(c, &c->d_coarse, (size_t)(c->co.dense_total + c->co.nnzB + c->co.nnzBT)) &&
-            dalloc_t(c, &c->d_gjP, 64 * 64) && dalloc_t(c, &c->d_gjR, (size_t)64 * c->co.mmax) &&
-            dalloc_t(c, &c->d_gjC, (size_t)64 * (c->co.mmax + 64)) &&
-            dalloc_t(c, &c->d_gjW, (size_t)c->co.mmax * c->co.mmax) &&
+            dalloc_t(c, &c->d_coarse, (size_t)c->co.nd_front_total) &&
+            dalloc_t(c, &c->d_up, (size_t)c->co.nd_up_total + 1) && dalloc_t(c, &c->d_beff, (size_t)c->co.nd_beff_total + 1) &&
+            dalloc_t(c, &c->d_gjP, 64 * 64) && dalloc_t(c, &c->d_gjR, (size_t)64 * (c->co.nd_nfmax + 64)) &&
+            dalloc_t(c, &c->d_gjC, (size_t)64 * (c->co.nd_nfmax + 64)) &&
             dalloc_t(c, &c->d_f, (size_t)c->nrhs * NU) && dalloc_t(c, &c->d_x, (size_t)c->nrhs * NU) &&
             dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
             dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -59,22 +60,35 @@ struct RomDev {
   double* coeff = nullptr;          // [n_k][r+1][n_r]
 };
 
+// Node of the nested-dissection tree of the coarse problem (same layout on the
+// host and the device).  Front = [own dofs | boundary dofs], nf = ns + nb,
+// stored row-major at foff; after the partial Gauss-Jordan sweep it holds
+// [[F_ss^-1, M^T], [-M, U]] with M = F_bs F_ss^-1 and U the update matrix.
+struct NDNodeH {
+  long long foff = 0;
+  int ns = 0, nb = 0, own_off = 0, bnd_off = 0, up_off = 0, beff_off = 0;
+  int child[2] = {-1, -1};
+  int cmap_off[2] = {-1, -1};
+  int parent = -1, level = 0;
+};
+
 struct CoarseLayout {
-  int nsb = 0;                       // super-blocks (grid lines)
-  std::vector<int> sb_off, sb_size;  // global coarse offset and size
-  std::vector<long long> dense_off;  // offset of each dense diagonal block
-  long long dense_total = 0;
-  int mmax = 0;
-  // off-diagonal blocks B_j = A[sb j+1, sb j] (CSR over rows of sb j+1) and B_j^T
-  std::vector<int> b_rowptr_off, bt_rowptr_off;  // into rowptr arrays, per j
-  std::vector<int> b_rowptr, b_col, bt_rowptr, bt_col;  // concatenated, values follow same order
-  std::vector<int> b_val_off, bt_val_off;  // per j offset into values
-  long long nnzB = 0, nnzBT = 0;
-  // unique entries: entry e sums contributions [cstart[e], cstart[e+1]) into dest[e]
-  std::vector<long long> dest;        // into combined array: dense | B | BT
+  std::vector<int> sb_off, sb_size;   // coarse numbering by grid lines (offset, size)
+  // unique entries of S_C: entry e sums contributions [cstart[e], cstart[e+1]) into dest[e]
+  std::vector<long long> dest;        // position in the front storage
   std::vector<int> cstart;
   std::vector<int> contrib;           // index into ScLoc (cell*nCp + packed)
+  // nested dissection
+  std::vector<NDNodeH> nd_nodes;
+  std::vector<int> nd_own, nd_bnd, nd_cmap;
+  std::vector<std::vector<int>> nd_levels;   // node ids per depth (0 = root)
+  long long nd_front_total = 0;
+  int nd_up_total = 0, nd_beff_total = 0, nd_nfmax = 0, nd_nsmax = 0;
+  // per-level work lists of the solve sweeps: (node, first row) items
+  std::vector<int> fw_items, bw_items, lvl_nodes;
+  std::vector<int> fw_off, bw_off, lvl_off;
 };
+
 
 struct Ctx {
   int device = 0;
@@ -123,7 +137,9 @@ struct Ctx {
   int* d_net_ptr = nullptr;    // [netx*nety+1]
   int* d_net_own = nullptr;    // cell*(m+1)^2 + local control point
   int* d_cstart = nullptr; int* d_contrib = nullptr; long long* d_dest = nullptr;
-  int* d_b_rowptr = nullptr; int* d_b_col = nullptr; int* d_bt_rowptr = nullptr; int* d_bt_col = nullptr;
+  NDNodeH* d_nd_nodes = nullptr;
+  int *d_nd_own = nullptr, *d_nd_bnd = nullptr, *d_nd_cmap = nullptr;
+  int *d_fw_items = nullptr, *d_bw_items = nullptr, *d_lvl_nodes = nullptr;
   int* d_flags = nullptr;      // device error flags [8]
   int* h_flags = nullptr;      // pinned host mirror
 
@@ -152,8 +168,10 @@ struct Ctx {
   void* d_Psi = nullptr;       // [ncell][nU][nC] D-scaled coarse basis (T)
   double* d_D = nullptr;       // [ncell][nU]
   double* d_ScLoc = nullptr;   // [ncell][nC(nC+1)/2]
-  double* d_coarse = nullptr;  // dense blocks | B values | BT values
-  double* d_gjP = nullptr; double* d_gjR = nullptr; double* d_gjC = nullptr; double* d_gjW = nullptr;
+  double* d_coarse = nullptr;  // nested-dissection fronts
+  double* d_up = nullptr;      // per node up-vectors of the forward sweep
+  double* d_beff = nullptr;    // per node effective right-hand sides
+  double* d_gjP = nullptr; double* d_gjR = nullptr; double* d_gjC = nullptr;
 
   // solve
   double* d_f = nullptr;       // [nrhs][NU]
@@ -193,6 +211,7 @@ template <class T> bool dalloc_t(Ctx* c, T** p, size_t n) { return dalloc(c, (vo
 
 // topology (topology.cpp)
 bool build_topology(Ctx* c);
+bool build_nested_dissection(Ctx* c, const std::vector<int>& ent_g1, const std::vector<int>& ent_g2);
 void build_tables(Ctx* c, std::vector<double>& tab);
 
 // ---------------------------------------------------------------------------

@@ -7,10 +7,10 @@
 // weak-scaling study).  Coarse dofs (Sec. 3.3.1): two values per non-Dirichlet
 // grid vertex, two averages and (optionally) one moment per non-Dirichlet edge.
 //
-// Coarse numbering by grid lines ("super-blocks"): super-block j holds the
-// vertices and horizontal edges of grid line y = j followed by the vertical
-// edges between lines j and j+1.  A cell of row j only touches super-blocks j
-// and j+1, so S_C is block tridiagonal in this order.
+// Coarse numbering by grid lines: line j holds the vertices and horizontal
+// edges of y = j followed by the vertical edges between y = j and y = j + 1.
+// The elimination order of the coarse problem is a nested dissection of the
+// cell grid (nd.cpp); this numbering only names the coarse dofs.
 #include <algorithm>
 #include <cmath>
 
@@ -77,19 +77,19 @@ bool build_topology(Ctx* c) {
         c->RU[(size_t)cell * nU + 2 * s + comp] = id >= 0 ? 2 * id + comp : -1;
     }
   }
-  // coarse numbering by super-blocks
+  // coarse numbering by grid lines: line j holds the vertices and horizontal
+  // edges of y = j, then the vertical edges between y = j and y = j + 1
   CoarseLayout& co = c->co;
-  co.nsb = ny + 1;
-  co.sb_off.assign(co.nsb, 0);
-  co.sb_size.assign(co.nsb, 0);
+  const int nsb = ny + 1;
+  co.sb_off.assign(nsb, 0);
+  co.sb_size.assign(nsb, 0);
   int off = 0;
-  for (int j = 0; j < co.nsb; ++j) {
+  for (int j = 0; j < nsb; ++j) {
     co.sb_off[j] = off;
     co.sb_size[j] = 2 * nx + nce * nx + (j < ny ? nce * nx : 0);
     off += co.sb_size[j];
   }
   c->NC = off;
-  co.mmax = *std::max_element(co.sb_size.begin(), co.sb_size.end());
   auto vert = [&](int vx, int vy) { return vx < 1 ? -1 : co.sb_off[vy] + 2 * (vx - 1); };
   auto hedge = [&](int ex, int vy) { return co.sb_off[vy] + 2 * nx + nce * ex; };
   auto vedge = [&](int vx, int ey) { return vx < 1 ? -1 : co.sb_off[ey] + 2 * nx + nce * nx + nce * (vx - 1); };
@@ -102,10 +102,10 @@ bool build_topology(Ctx* c) {
       for (int comp = 0; comp < 2; ++comp) r[2 * k + comp] = v[k] >= 0 ? v[k] + comp : -1;
     int e[4] = {vedge(ix, iy), vedge(ix + 1, iy), hedge(ix, iy), hedge(ix, iy + 1)};
     for (int k = 0; k < 4; ++k)
-      for (int t = 0; t < nce; ++t) r[8 + nce * k + t] = e[k] >= 0 ? e[k] + t : -1;
+      for (int t2 = 0; t2 < nce; ++t2) r[8 + nce * k + t2] = e[k] >= 0 ? e[k] + t2 : -1;
   }
   // owner lists (in increasing cell order: fixed summation order)
-  auto owners = [](const std::vector<int>& R, int nslot, int N, std::vector<int>& ptr, std::vector<int>& own) {
+  auto owners = [](const std::vector<int>& R, int N, std::vector<int>& ptr, std::vector<int>& own) {
     ptr.assign(N + 1, 0);
     for (size_t i = 0; i < R.size(); ++i)
       if (R[i] >= 0) ptr[R[i] + 1]++;
@@ -114,42 +114,17 @@ bool build_topology(Ctx* c) {
     std::vector<int> fill(ptr.begin(), ptr.end() - 1);
     for (size_t i = 0; i < R.size(); ++i)
       if (R[i] >= 0) own[fill[R[i]]++] = (int)i;
-    (void)nslot;
   };
   std::vector<int> uptr, uown, cptr, cown;
-  owners(c->RU, nU, c->NU, uptr, uown);
-  owners(c->RC, nC, c->NC, cptr, cown);
+  owners(c->RU, c->NU, uptr, uown);
+  owners(c->RC, c->NC, cptr, cown);
 
-  // ---- coarse matrix assembly plan ------------------------------------------
+  // unique entries of S_C with their contributions in increasing cell order
   const int nCp = nC * (nC + 1) / 2;
-  co.dense_off.assign(co.nsb, 0);
-  long long doff = 0;
-  for (int j = 0; j < co.nsb; ++j) {
-    co.dense_off[j] = doff;
-    doff += (long long)co.sb_size[j] * co.sb_size[j];
-  }
-  co.dense_total = doff;
-  std::vector<int> sb_of(c->NC);
-  for (int j = 0; j < co.nsb; ++j)
-    for (int a = 0; a < co.sb_size[j]; ++a) sb_of[co.sb_off[j] + a] = j;
-  // per row: (g2, contrib) lists from the owners of g1
-  co.b_rowptr_off.assign(co.nsb, 0);
-  co.bt_rowptr_off.assign(co.nsb, 0);
-  co.b_val_off.assign(co.nsb, 0);
-  co.bt_val_off.assign(co.nsb, 0);
-  // rowptr arrays: B_j rows = sb j+1 rows; BT_j rows = sb j rows
-  std::vector<std::vector<int>> brow(co.nsb), btrow(co.nsb);
-  std::vector<std::vector<int>> bcol(co.nsb), btcol(co.nsb);
-  std::vector<std::vector<long long>> bent(co.nsb), btent(co.nsb);  // entry ids in order
-  for (int j = 0; j < co.nsb; ++j) {
-    if (j + 1 < co.nsb) brow[j].assign(co.sb_size[j + 1] + 1, 0);
-    btrow[j].assign(co.sb_size[j] + 1, 0);
-  }
-  co.dest.clear();
+  std::vector<int> ent_g1, ent_g2;
   co.cstart.assign(1, 0);
   co.contrib.clear();
   std::vector<std::pair<long long, int>> row;
-  long long nent = 0;
   for (int g1 = 0; g1 < c->NC; ++g1) {
     row.clear();
     for (int o = cptr[g1]; o < cptr[g1 + 1]; ++o) {
@@ -163,7 +138,6 @@ bool build_topology(Ctx* c) {
       }
     }
     std::sort(row.begin(), row.end());
-    int s1 = sb_of[g1], a = g1 - co.sb_off[s1];
     size_t i = 0;
     while (i < row.size()) {
       int g2 = (int)(row[i].first / c->ncell);
@@ -173,61 +147,26 @@ bool build_topology(Ctx* c) {
         ++k;
       }
       co.cstart.push_back((int)co.contrib.size());
-      int s2 = sb_of[g2], b = g2 - co.sb_off[s2];
-      long long e = nent++;
-      if (s1 == s2) {
-        co.dest.push_back(co.dense_off[s1] + (long long)a * co.sb_size[s1] + b);
-      } else if (s1 == s2 + 1) {  // B_{s2}: row a of sb s1, col b of sb s2
-        bcol[s2].push_back(b);
-        bent[s2].push_back(e);
-        brow[s2][a + 1]++;
-        co.dest.push_back(-1);
-      } else if (s2 == s1 + 1) {  // BT_{s1}: row a of sb s1, col b of sb s2
-        btcol[s1].push_back(b);
-        btent[s1].push_back(e);
-        btrow[s1][a + 1]++;
-        co.dest.push_back(-1);
-      } else {
-        c->err = "internal: coarse coupling beyond neighbouring grid lines";
-        return false;
-      }
+      ent_g1.push_back(g1);
+      ent_g2.push_back(g2);
       i = k;
     }
   }
-  // finalize CSR (rows were visited in increasing order, so columns are already in row order)
-  long long vb = 0, vbt = 0;
-  co.b_rowptr.clear();
-  co.bt_rowptr.clear();
-  co.b_col.clear();
-  co.bt_col.clear();
-  for (int j = 0; j < co.nsb; ++j) {
-    co.b_val_off[j] = (int)vb;
-    co.b_rowptr_off[j] = (int)co.b_rowptr.size();
-    if (j + 1 < co.nsb) {
-      auto& r = brow[j];
-      for (size_t q = 1; q < r.size(); ++q) r[q] += r[q - 1];
-      for (size_t q = 0; q < r.size(); ++q) co.b_rowptr.push_back(r[q]);
-      for (size_t q = 0; q < bcol[j].size(); ++q) {
-        co.b_col.push_back(bcol[j][q]);
-        co.dest[bent[j][q]] = co.dense_total + vb + (long long)q;
-      }
-      vb += (long long)bcol[j].size();
+  if (!build_nested_dissection(c, ent_g1, ent_g2)) return false;
+  // solve work lists: forward rows = boundary rows (at least one item per node), backward rows = own rows
+  co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear();
+  co.fw_off.assign(1, 0); co.bw_off.assign(1, 0); co.lvl_off.assign(1, 0);
+  for (size_t l = 0; l < co.nd_levels.size(); ++l) {
+    for (int n : co.nd_levels[l]) {
+      const NDNodeH& d = co.nd_nodes[n];
+      for (int r = 0; r < std::max(1, d.nb); r += 4) { co.fw_items.push_back(n); co.fw_items.push_back(r); }
+      for (int r = 0; r < d.ns; r += 4) { co.bw_items.push_back(n); co.bw_items.push_back(r); }
+      co.lvl_nodes.push_back(n);
     }
+    co.fw_off.push_back((int)co.fw_items.size() / 2);
+    co.bw_off.push_back((int)co.bw_items.size() / 2);
+    co.lvl_off.push_back((int)co.lvl_nodes.size());
   }
-  co.nnzB = vb;
-  for (int j = 0; j < co.nsb; ++j) {
-    co.bt_val_off[j] = (int)vbt;
-    co.bt_rowptr_off[j] = (int)co.bt_rowptr.size();
-    auto& r = btrow[j];
-    for (size_t q = 1; q < r.size(); ++q) r[q] += r[q - 1];
-    for (size_t q = 0; q < r.size(); ++q) co.bt_rowptr.push_back(r[q]);
-    for (size_t q = 0; q < btcol[j].size(); ++q) {
-      co.bt_col.push_back(btcol[j][q]);
-      co.dest[btent[j][q]] = co.dense_total + co.nnzB + vbt + (long long)q;
-    }
-    vbt += (long long)btcol[j].size();
-  }
-  co.nnzBT = vbt;
 
   // net owners for the gradient gather
   const int m = c->m, np1 = (m + 1) * (m + 1);
@@ -266,8 +205,9 @@ bool build_topology(Ctx* c) {
          up(&c->d_RC, c->RC) && up(&c->d_uown_ptr, uptr) && up(&c->d_uown, uown) && up(&c->d_cown_ptr, cptr) &&
          up(&c->d_cown, cown) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
-         up(&c->d_dest, co.dest) && up(&c->d_b_rowptr, co.b_rowptr) && up(&c->d_b_col, co.b_col) &&
-         up(&c->d_bt_rowptr, co.bt_rowptr) && up(&c->d_bt_col, co.bt_col);
+         up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) && up(&c->d_nd_own, co.nd_own) &&
+         up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_fw_items, co.fw_items) &&
+         up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes);
 }
 
 void build_tables(Ctx* c, std::vector<double>& tab) {
