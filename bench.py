@@ -80,12 +80,6 @@ def kernel_bytes(prob, roms, nC):
     return out
 
 
-def coarse_solve_bytes(nx, ny, moments=True):
-    nce = 3 if moments else 2
-    sizes = [2 * nx + nce * nx + (nce * nx if j < ny else 0) for j in range(ny + 1)]
-    return float(sum(2 * 8 * m * m for m in sizes))
-
-
 def cpu_baseline(prob_full, roms, solver):
     """The CPU oracle on a bounded sample of the same workload: the 12 x 12
     sub-lattice drawn with the same recipe (the oracle's online phase: ROM
@@ -238,8 +232,10 @@ def main():
         "pcg_fine_restrict_fp32": dict(bound="hbm",
                                        achieved=kb["pre"](4) / (mixed["phases_ms"]["pre_kernel"] * 1e-3) / 1e9,
                                        peak=PEAK["hbm_GBs"], unit="GB/s"),
-        "coarse_solve": dict(bound="hbm", achieved=coarse_solve_bytes(prob["nx"], prob["ny"]) /
-                             (mixed["phases_ms"]["coarse_solve"] * 1e-3) / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s"),
+        # both nested-dissection sweeps read [F_ss^-1 | M^T] of every front: 8 ns (ns + 2 nb) bytes
+        "coarse_solve": dict(bound="hbm", achieved=s.query(lbddc.Q_COARSE_SOLVE_BYTES) /
+                             (mixed["phases_ms"]["coarse_solve"] * 1e-3) / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s",
+                             launches=2 * s.query(lbddc.Q_COARSE_LEVELS)),
     }
     for k in kernels.values():
         k["frac"] = k["achieved"] / k["peak"]

@@ -113,7 +113,7 @@ lbddc_status lbddc_load_rom(lbddc_ctx* ctx, const lbddc_rom_desc* rom);
  * stabilisation factor rho (Sec. 2.2.3), coarse dofs: corner values and edge
  * averages, plus edge moments when `moments` is nonzero (Sec. 3.3.1).
  * traction[(r*ny + iy)*2 + c]: component c of load case r on the right edge of
- * cell (nx-1, iy).  Limits: 2 <= p <= 10, q in {1, 2, 3}, 1 <= map_order <= 4,
+ * cell (nx-1, iy).  Limits: 2 <= p <= 8, q in {1, 2, 3}, 1 <= map_order <= 4,
  * 1 <= nrhs <= 16, nx, ny >= 1.  Validates det J > 0 at the interpolation
  * points and on a (2m+2)^2 Gauss sample of every cell (LBDDC_E_DEGENERATE_MAP),
  * that every family has a ROM of degrees (p, q) (LBDDC_E_ROM) and that every t
@@ -173,7 +173,11 @@ lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* ctx, double* d_J, doubl
 enum {
   LBDDC_Q_NCELL = 0, LBDDC_Q_NDOF_FREE = 1, LBDDC_Q_N_SKELETON = 2, LBDDC_Q_N_INTERIOR = 3,
   LBDDC_Q_N_COARSE = 4, LBDDC_Q_N_I_ROM = 5, LBDDC_Q_NU_CELL = 6, LBDDC_Q_NC_CELL = 7,
-  LBDDC_Q_NRHS = 8, LBDDC_Q_NR_MAX = 9, LBDDC_Q_DEVICE_BYTES = 10
+  LBDDC_Q_NRHS = 8, LBDDC_Q_NR_MAX = 9, LBDDC_Q_DEVICE_BYTES = 10,
+  /* bytes of coarse-factor data one coarse solve reads (both sweeps) */
+  LBDDC_Q_COARSE_SOLVE_BYTES = 11,
+  /* number of levels of the nested-dissection tree of the coarse problem */
+  LBDDC_Q_COARSE_LEVELS = 12
 };
 lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
 
@@ -181,10 +185,10 @@ lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
  * for testing.  Layouts per cell:
  *   K      [2nB][2nB], dof i*nB + k (component i, node k = a + (p+1) b)
  *   THETA  [4][2][2][(q+1)^2]: C[i1][j1][i2][j2][k3] geometry coefficients
- *   ITIL   [n_r + 1]: [(1 - rho) I_r(t), rho]
+ *   ITIL   [LBDDC_Q_NR_MAX]: [(1 - rho) I_r(t), rho, 0 ...] (zero padded)
  *   S      [nU][nU] local Schur complement over the skeleton slots
  *   D      [nU] partition-of-unity weights
- *   PSI    [nU][nC] coarse basis
+ *   PSI    [nU][nC] D-weighted coarse basis D Psi (the form the solver applies)
  *   SC     [nC][nC] local coarse matrix Psi^T S Psi
  *   LOAD   [nrhs][nU] cell load on the skeleton slots
  *   FINE   [nU][nU] the fine-correction operator D [S C^T; C 0]^-1|_u D

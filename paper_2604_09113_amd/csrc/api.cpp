@@ -318,8 +318,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_ScLoc, (size_t)ncell * nC * (nC + 1) / 2) &&
             dalloc_t(c, &c->d_coarse, (size_t)c->co.nd_front_total) &&
             dalloc_t(c, &c->d_up, (size_t)c->co.nd_up_total + 1) && dalloc_t(c, &c->d_beff, (size_t)c->co.nd_beff_total + 1) &&
-            dalloc_t(c, &c->d_gjP, 64 * 64) && dalloc_t(c, &c->d_gjR, (size_t)64 * (c->co.nd_nfmax + 64)) &&
-            dalloc_t(c, &c->d_gjC, (size_t)64 * (c->co.nd_nfmax + 64)) &&
+            dalloc_t(c, &c->d_gjC, (size_t)c->co.nd_cp_total + 1) &&
             dalloc_t(c, &c->d_f, (size_t)c->nrhs * NU) && dalloc_t(c, &c->d_x, (size_t)c->nrhs * NU) &&
             dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
             dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
@@ -532,6 +531,13 @@ lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
     case LBDDC_Q_NRHS: *v = c->nrhs; break;
     case LBDDC_Q_NR_MAX: *v = 4 * c->KC; break;
     case LBDDC_Q_DEVICE_BYTES: *v = (int64_t)c->dev_bytes; break;
+    case LBDDC_Q_COARSE_SOLVE_BYTES: {
+      int64_t b = 0;
+      for (const NDNodeH& d : c->co.nd_nodes) b += 8LL * d.ns * (d.ns + 2LL * d.nb);
+      *v = b;
+      break;
+    }
+    case LBDDC_Q_COARSE_LEVELS: *v = (int64_t)c->co.nd_levels.size(); break;
     default: return LBDDC_E_ARG;
   }
   return LBDDC_OK;

@@ -64,8 +64,14 @@ struct RomDev {
 // host and the device).  Front = [own dofs | boundary dofs], nf = ns + nb,
 // stored row-major at foff; after the partial Gauss-Jordan sweep it holds
 // [[F_ss^-1, M^T], [-M, U]] with M = F_bs F_ss^-1 and U the update matrix.
+// Fronts of at most this many dofs are swept with the whole front in LDS.
+constexpr int ND_LDS_NF = 140;
+// Own rows per workgroup of the backward coarse sweep (a multiple of 4).
+constexpr int ND_BW_ROWS = 16;
+
 struct NDNodeH {
   long long foff = 0;
+  long long cp_off = 0;  // offset of the node's pivot-column panel (blocked levels only)
   int ns = 0, nb = 0, own_off = 0, bnd_off = 0, up_off = 0, beff_off = 0;
   int child[2] = {-1, -1};
   int cmap_off[2] = {-1, -1};
@@ -84,6 +90,7 @@ struct CoarseLayout {
   std::vector<std::vector<int>> nd_levels;   // node ids per depth (0 = root)
   long long nd_front_total = 0;
   int nd_up_total = 0, nd_beff_total = 0, nd_nfmax = 0, nd_nsmax = 0;
+  long long nd_cp_total = 0;  // panel scratch of the largest blocked level
   // per-level work lists of the solve sweeps: (node, first row) items
   std::vector<int> fw_items, bw_items, lvl_nodes;
   std::vector<int> fw_off, bw_off, lvl_off;
@@ -171,7 +178,7 @@ struct Ctx {
   double* d_coarse = nullptr;  // nested-dissection fronts
   double* d_up = nullptr;      // per node up-vectors of the forward sweep
   double* d_beff = nullptr;    // per node effective right-hand sides
-  double* d_gjP = nullptr; double* d_gjR = nullptr; double* d_gjC = nullptr;
+  double* d_gjC = nullptr;     // pivot-column panels of the blocked front sweep
 
   // solve
   double* d_f = nullptr;       // [nrhs][NU]

@@ -37,6 +37,7 @@ __global__ void k_coarse_entries(const double* __restrict__ sc, const int* __res
 __global__ __launch_bounds__(256) void k_extend_add(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
                                                     const int* __restrict__ cmap, double* __restrict__ F, int slot) {
   const NDNodeH d = nodes[lvl[blockIdx.x]];
+  const int r0 = 16 * blockIdx.y;
   const int ch = d.child[slot];
   if (ch < 0) return;
   const NDNodeH c = nodes[ch];
@@ -44,62 +45,101 @@ __global__ __launch_bounds__(256) void k_extend_add(const NDNodeH* __restrict__ 
   const int* map = cmap + d.cmap_off[slot];
   const double* U = F + c.foff;
   double* P = F + d.foff;
-  for (long long idx = threadIdx.x; idx < (long long)c.nb * c.nb; idx += 256) {
-    const int i = (int)(idx / c.nb), j = (int)(idx % c.nb);
-    P[(long long)map[i] * nf + map[j]] += U[(long long)(c.ns + i) * nfc + c.ns + j];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = r0 + wave; i < min(c.nb, r0 + 16); i += 4) {
+    double* prow = P + (long long)map[i] * nf;
+    const double* urow = U + (long long)(c.ns + i) * nfc + c.ns;
+    for (int j = lane; j < c.nb; j += 64) prow[map[j]] += urow[j];
   }
 }
 
-// Partial Gauss-Jordan sweep over the ns own dofs of small fronts: one
-// workgroup per front, front in global memory, the pivot row and column staged
-// in LDS each step (all updates read the pre-step values).
-__global__ __launch_bounds__(256) void k_pgj_small(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
-                                                   double* __restrict__ F, int* __restrict__ flags) {
-  extern __shared__ double sh[];
+// ---- Gauss-Jordan sweep of a front over its own dofs ----
+//
+// Small fronts (nf <= ND_LDS_NF, the lower tree levels) are swept one
+// workgroup per front with the whole front resident in LDS: load, add the
+// children's update matrices, eliminate the ns pivots one by one, store.
+//
+// Larger fronts (upper levels: few nodes, fronts of several hundred dofs) are
+// swept in pivot blocks K = [k0, k0 + kn), kn <= 64, every front of the level
+// in the same launch, three kernels per block:
+//   diag   F[K][K] <- F[K][K]^-1                              (one WG per front)
+//   panel  F[K][j] <- F[K][K]^-1 F[K][j] for j outside K,
+//          Cp[i] <- F[i][K] for i outside K                    (column tiles)
+//   update F[i][j] -= Cp[i] F[K][j], F[i][K] <- -Cp[i] F[K][K]  (64 x 64 tiles)
+// which is the same elimination as the pivot-by-pivot sweep, regrouped.
+constexpr int GJB = 64;
+
+template <int NF>
+__global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
+                                                   const int* __restrict__ cmap, double* __restrict__ F,
+                                                   int* __restrict__ flags) {
+  __shared__ double S[NF * (NF + 1)];
+  __shared__ double rowl[NF], coll[NF];
   const NDNodeH d = nodes[lvl[blockIdx.x]];
-  const int nf = d.ns + d.nb;
+  const int nf = d.ns + d.nb, ld = nf + 1;
   double* A = F + d.foff;
-  double* rowl = sh;
-  double* coll = sh + nf;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i = wave; i < nf; i += 4)
+    for (int j = lane; j < nf; j += 64) S[i * ld + j] = A[(long long)i * nf + j];
+  __syncthreads();
+  for (int s = 0; s < 2; ++s) {
+    const int ch = d.child[s];
+    if (ch < 0) continue;
+    const NDNodeH c = nodes[ch];
+    const int nfc = c.ns + c.nb;
+    const int* map = cmap + d.cmap_off[s];
+    const double* U = F + c.foff + (long long)c.ns * nfc + c.ns;
+    for (int i = wave; i < c.nb; i += 4) {
+      const int r = map[i] * ld;
+      for (int j = lane; j < c.nb; j += 64) S[r + map[j]] += U[(long long)i * nfc + j];
+    }
+    __syncthreads();
+  }
   bool bad = false;
   for (int l = 0; l < d.ns; ++l) {
     for (int j = threadIdx.x; j < nf; j += 256) {
-      rowl[j] = A[(long long)l * nf + j];
-      coll[j] = A[(long long)j * nf + l];
+      rowl[j] = S[l * ld + j];
+      coll[j] = S[j * ld + l];
     }
     __syncthreads();
     double piv = rowl[l];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
     const double pinv = 1.0 / piv;
-    for (long long idx = threadIdx.x; idx < (long long)nf * nf; idx += 256) {
-      const int i = (int)(idx / nf), j = (int)(idx % nf);
-      double v;
-      if (i == l && j == l) v = pinv;
-      else if (i == l) v = rowl[j] * pinv;
-      else if (j == l) v = -coll[i] * pinv;
-      else v = A[idx] - coll[i] * rowl[j] * pinv;
-      A[idx] = v;
+    for (int i = wave; i < nf; i += 4) {
+      const double ci = coll[i] * pinv;
+      for (int j = lane; j < nf; j += 64) {
+        double v;
+        if (i == l) v = (j == l) ? pinv : rowl[j] * pinv;
+        else if (j == l) v = -ci;
+        else v = S[i * ld + j] - ci * rowl[j];
+        S[i * ld + j] = v;
+      }
     }
     __syncthreads();
   }
+  for (int i = wave; i < nf; i += 4)
+    for (int j = lane; j < nf; j += 64) A[(long long)i * nf + j] = S[i * ld + j];
   if (bad) atomicOr(flags, 32);
 }
 
-// ---- blocked Gauss-Jordan sweep over pivot rows [0, ns) of one large front ----
-constexpr int GJB = 64;
-
-// invert the kn x kn diagonal block at (k0, k0) into P [GJB][GJB] (identity padded)
-__global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, int m, int k0, int kn,
-                                                 double* __restrict__ P, int* __restrict__ flags) {
+// In-register inversion of the kn x kn block at A (row stride nf), identity
+// padded to 64 x 64: thread (tr, tc) = (t / 16, t % 16) holds entries
+// (tr + 16a, tc + 16b); one barrier per pivot (double-buffered pivot row and column).
+__global__ __launch_bounds__(256) void k_lv_diag(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
+                                                 double* __restrict__ F, int k0, int* __restrict__ flags) {
   __shared__ double rowb[2][GJB], colb[2][GJB];
+  const NDNodeH d = nodes[lvl[blockIdx.x]];
+  if (k0 >= d.ns) return;
+  const int kn = min(GJB, d.ns - k0), nf = d.ns + d.nb;
+  double* A = F + d.foff + (long long)k0 * nf + k0;
   const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
   double B[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      int i = tr + 16 * a, j = tc + 16 * b;
-      B[a][b] = (i < kn && j < kn) ? A[(size_t)(k0 + i) * m + k0 + j] : (i == j ? 1.0 : 0.0);
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      B[a][b] = (i < kn && j < kn) ? A[(long long)i * nf + j] : (i == j ? 1.0 : 0.0);
     }
   int buf = 0;
   bool bad = false;
@@ -129,7 +169,7 @@ __global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, i
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        int i = tr + 16 * a, j = tc + 16 * b;
+        const int i = tr + 16 * a, j = tc + 16 * b;
         double v = B[a][b];
         if (i == l && j == l) v = pinv;
         else if (i == l) v = v * pinv;
@@ -143,85 +183,102 @@ __global__ __launch_bounds__(256) void k_gj_diag(const double* __restrict__ A, i
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) P[(tr + 16 * a) * GJB + tc + 16 * b] = B[a][b];
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      if (i < kn && j < kn) A[(long long)i * nf + j] = B[a][b];
+    }
 }
 
-// R[l][j] = sum_q P[l][q] A[k0 + q][j] for every column j, and Cp[i][l] = A[i][k0 + l]
-__global__ __launch_bounds__(256) void k_gj_panel(const double* __restrict__ A, int m, int k0, int kn,
-                                                  const double* __restrict__ P, double* __restrict__ R,
-                                                  double* __restrict__ Cp) {
-  __shared__ double Ps[GJB][GJB + 1];
-  __shared__ double As[GJB][GJB + 1];
-  const int t = threadIdx.x, j0 = blockIdx.x * GJB;
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    int a = idx / GJB, b = idx % GJB;
-    Ps[a][b] = P[idx];
-    int j = j0 + b;
-    As[a][b] = (a < kn && j < m) ? A[(size_t)(k0 + a) * m + j] : 0.0;
-  }
-  __syncthreads();
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    int l = idx / GJB, b = idx % GJB, j = j0 + b;
-    if (l >= kn || j >= m) continue;
-    double s = 0.0;
-    for (int q = 0; q < kn; ++q) s += Ps[l][q] * As[q][b];
-    R[(size_t)l * m + j] = s;
-  }
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    int i = j0 + idx / GJB, l = idx % GJB;
-    if (i < m && l < kn) Cp[(size_t)i * GJB + l] = A[(size_t)i * m + k0 + l];
+// 64 x 64 x kn product on a 16 x 16 thread grid, 4 x 4 outputs per thread:
+// acc[a][b] = sum_q X[q][tr + 16a] Y[q][tc + 16b]  (X stored transposed)
+template <int LX>
+__device__ inline void tile_product(const double (*X)[LX], const double (*Y)[GJB], int kn, double (&acc)[4][4]) {
+  const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int q = 0; q < kn; ++q) {
+    double x[4], y[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) x[a] = X[q][tr + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) y[b] = Y[q][tc + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
   }
 }
 
-// element (i, j): pivot row and column -> P; pivot row -> R; pivot column ->
-// -Cp P; otherwise A -= Cp R.  Tiles are 64 x 64; pivot rows are [k0, k0 + kn).
-__global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ A, int m, int k0, int kn,
-                                                   const double* __restrict__ P, const double* __restrict__ R,
-                                                   const double* __restrict__ Cp) {
-  __shared__ double Cs[GJB][GJB + 1];
-  __shared__ double Rs[GJB][GJB + 1];
-  const int t = threadIdx.x, i0 = blockIdx.y * GJB, j0 = blockIdx.x * GJB;
+// grid (column tiles, fronts)
+__global__ __launch_bounds__(256) void k_lv_panel(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
+                                                  double* __restrict__ F, int k0, double* __restrict__ Cp) {
+  __shared__ double Pt[GJB][GJB + 1];  // Pt[q][a] = P[a][q]
+  __shared__ double As[GJB][GJB];  // As[q][b] = F[k0 + q][j0 + b]
+  const NDNodeH d = nodes[lvl[blockIdx.y]];
+  const int nf = d.ns + d.nb, j0 = blockIdx.x * GJB;
+  if (k0 >= d.ns || j0 >= nf) return;
+  const int kn = min(GJB, d.ns - k0);
+  double* A = F + d.foff;
+  const int t = threadIdx.x;
+  double* cp = Cp + d.cp_off;
   for (int idx = t; idx < GJB * GJB; idx += 256) {
-    int a = idx / GJB, b = idx % GJB;
-    int i = i0 + a, j = j0 + b;
-    Cs[a][b] = (i < m && b < kn) ? Cp[(size_t)i * GJB + b] : 0.0;
-    Rs[a][b] = (a < kn && j < m) ? R[(size_t)a * m + j] : 0.0;
+    const int r = idx >> 6, q = idx & 63, i = j0 + r;
+    if (i < nf && q < kn && (i < k0 || i >= k0 + kn)) cp[(long long)i * GJB + q] = A[(long long)i * nf + k0 + q];
+  }
+  const bool any = j0 != k0 || kn < GJB;  // the tile holds columns outside K
+  if (!any) return;
+  for (int idx = t; idx < GJB * GJB; idx += 256) {
+    const int a = idx >> 6, b = idx & 63, j = j0 + b;
+    Pt[b][a] = (a < kn && b < kn) ? A[(long long)(k0 + a) * nf + k0 + b] : 0.0;
+    As[a][b] = (a < kn && j < nf) ? A[(long long)(k0 + a) * nf + j] : 0.0;
   }
   __syncthreads();
+  double acc[4][4];
+  tile_product(Pt, As, kn, acc);
   const int tr = t >> 4, tc = t & 15;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      const int li = tr + 16 * a, lj = tc + 16 * b, i = i0 + li, j = j0 + lj;
-      if (i >= m || j >= m) continue;
-      const bool ip = i >= k0 && i < k0 + kn, jp = j >= k0 && j < k0 + kn;
-      if (ip && jp) {
-        A[(size_t)i * m + j] = P[(i - k0) * GJB + (j - k0)];
-      } else if (ip) {
-        A[(size_t)i * m + j] = Rs[i - k0][lj];
-      } else if (jp) {
-        double s = 0.0;
-        for (int q = 0; q < kn; ++q) s += Cs[li][q] * P[q * GJB + (j - k0)];
-        A[(size_t)i * m + j] = -s;
-      } else {
-        double s = 0.0;
-        for (int q = 0; q < kn; ++q) s += Cs[li][q] * Rs[q][lj];
-        A[(size_t)i * m + j] -= s;
-      }
+      const int r = tr + 16 * a, j = j0 + tc + 16 * b;
+      if (r < kn && j < nf && (j < k0 || j >= k0 + kn)) A[(long long)(k0 + r) * nf + j] = acc[a][b];
     }
 }
 
-static hipError_t gj_partial(Ctx* c, double* A, int m, int npiv) {
-  const int nblk = (m + GJB - 1) / GJB;
-  for (int k0 = 0; k0 < npiv; k0 += GJB) {
-    const int kn = std::min(GJB, npiv - k0);
-    hipLaunchKernelGGL(k_gj_diag, dim3(1), dim3(256), 0, c->stream, A, m, k0, kn, c->d_gjP, c->d_flags);
-    hipLaunchKernelGGL(k_gj_panel, dim3(nblk), dim3(256), 0, c->stream, A, m, k0, kn, c->d_gjP, c->d_gjR, c->d_gjC);
-    hipLaunchKernelGGL(k_gj_update, dim3(nblk, nblk), dim3(256), 0, c->stream, A, m, k0, kn, c->d_gjP, c->d_gjR,
-                       c->d_gjC);
+// grid (column tiles, row tiles, fronts)
+__global__ __launch_bounds__(256) void k_lv_update(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
+                                                   double* __restrict__ F, int k0, const double* __restrict__ Cp) {
+  __shared__ double Ct[GJB][GJB + 1];  // Ct[q][r] = Cp[i0 + r][q]
+  __shared__ double Rs[GJB][GJB];  // Rs[q][b] = F[k0 + q][j0 + b]
+  const NDNodeH d = nodes[lvl[blockIdx.z]];
+  const int nf = d.ns + d.nb, j0 = blockIdx.x * GJB, i0 = blockIdx.y * GJB;
+  if (k0 >= d.ns || j0 >= nf || i0 >= nf) return;
+  const int kn = min(GJB, d.ns - k0);
+  if (i0 == k0 && kn == GJB) return;  // pivot rows only
+  double* A = F + d.foff;
+  const double* cp = Cp + d.cp_off;
+  const int t = threadIdx.x;
+  for (int idx = t; idx < GJB * GJB; idx += 256) {
+    const int r = idx >> 6, q = idx & 63, i = i0 + r, j = j0 + q;
+    Ct[q][r] = (i < nf && q < kn && (i < k0 || i >= k0 + kn)) ? cp[(long long)i * GJB + q] : 0.0;
+    Rs[r][q] = (r < kn && j < nf) ? A[(long long)(k0 + r) * nf + j] : 0.0;
   }
-  return hipGetLastError();
+  __syncthreads();
+  double acc[4][4];
+  tile_product(Ct, Rs, kn, acc);
+  const int tr = t >> 4, tc = t & 15;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+      if (i >= nf || j >= nf || (i >= k0 && i < k0 + kn)) continue;
+      double* e = A + (long long)i * nf + j;
+      if (j >= k0 && j < k0 + kn) *e = -acc[a][b];
+      else *e -= acc[a][b];
+    }
 }
 
 hipError_t launch_coarse_assemble(Ctx* c) {
@@ -238,26 +295,50 @@ hipError_t launch_coarse_factor(Ctx* c) {
   for (int l = (int)co.nd_levels.size() - 1; l >= 0; --l) {
     const int n0 = co.lvl_off[l], nn = co.lvl_off[l + 1] - n0;
     const int* lvl = c->d_lvl_nodes + n0;
-    for (int s = 0; s < 2; ++s)
-      hipLaunchKernelGGL(k_extend_add, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_nd_cmap,
-                         c->d_coarse, s);
-    int nfmax = 0;
-    for (int n : co.nd_levels[l]) nfmax = std::max(nfmax, co.nd_nodes[n].ns + co.nd_nodes[n].nb);
-    if (nn >= 32) {
-      hipLaunchKernelGGL(k_pgj_small, dim3(nn), dim3(256), 2 * nfmax * sizeof(double), c->stream, c->d_nd_nodes,
-                         lvl, c->d_coarse, c->d_flags);
-    } else {
-      for (int n : co.nd_levels[l]) {
-        const NDNodeH& d = co.nd_nodes[n];
-        hipError_t e = gj_partial(c, c->d_coarse + d.foff, d.ns + d.nb, d.ns);
-        if (e != hipSuccess) return e;
-      }
+    int nbmax = 0, nfmax = 0, nsmax = 0;
+    for (int n : co.nd_levels[l]) {
+      const NDNodeH& d = co.nd_nodes[n];
+      nfmax = std::max(nfmax, d.ns + d.nb);
+      nsmax = std::max(nsmax, d.ns);
+      for (int s = 0; s < 2; ++s)
+        if (d.child[s] >= 0) nbmax = std::max(nbmax, co.nd_nodes[d.child[s]].nb);
+    }
+    if (nfmax <= 72) {
+      hipLaunchKernelGGL(k_front_lds<72>, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_nd_cmap,
+                         c->d_coarse, c->d_flags);
+      continue;
+    }
+    if (nfmax <= ND_LDS_NF) {
+      hipLaunchKernelGGL(k_front_lds<ND_LDS_NF>, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl,
+                         c->d_nd_cmap, c->d_coarse, c->d_flags);
+      continue;
+    }
+    if (nbmax > 0)
+      for (int s = 0; s < 2; ++s)
+        hipLaunchKernelGGL(k_extend_add, dim3(nn, (nbmax + 15) / 16), dim3(256), 0, c->stream, c->d_nd_nodes, lvl,
+                           c->d_nd_cmap, c->d_coarse, s);
+    const int nt = (nfmax + GJB - 1) / GJB;
+    for (int k0 = 0; k0 < nsmax; k0 += GJB) {
+      hipLaunchKernelGGL(k_lv_diag, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse, k0,
+                         c->d_flags);
+      hipLaunchKernelGGL(k_lv_panel, dim3(nt, nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse, k0,
+                         c->d_gjC);
+      hipLaunchKernelGGL(k_lv_update, dim3(nt, nt, nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse,
+                         k0, c->d_gjC);
     }
   }
   return hipGetLastError();
 }
 
-// forward sweep of one level: item = (node, first boundary row)
+// Both sweeps read only the top ns rows of a swept front, [F_ss^-1 | M^T]
+// (row-major, row stride nf); the lower rows are not needed once the parent
+// has taken U.
+
+// forward sweep of one level, item = (node, first boundary column r0):
+//   b_eff = b_s + (children's contributions to the own dofs),
+//   up[r] = w_b[r] - sum_k b_eff[k] M^T[k][r]   for r in [r0, r0 + 64)
+// lane = column r (coalesced rows of M^T), the four waves interleave the rows k
+// and their partial sums are added in a fixed order.
 __global__ __launch_bounds__(256) void k_nd_fwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
                                                 const int* __restrict__ own, const int* __restrict__ cmap,
                                                 const double* __restrict__ F, const double* __restrict__ b,
@@ -265,59 +346,95 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDNodeH* __restrict__ node
   extern __shared__ double sh[];
   const int nid = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
   const NDNodeH d = nodes[nid];
-  const int nf = d.ns + d.nb;
-  double* w = sh;        // [nf] children's contributions
-  double* be = sh + nf;  // [ns]
-  for (int i = threadIdx.x; i < nf; i += 256) w[i] = 0.0;
+  const int nf = d.ns + d.nb, t = threadIdx.x;
+  double* w = sh;          // [nf] children's contributions
+  double* be = sh + nf;    // [ns]
+  double* pr = be + d.ns;  // [4][64] wave partials
+  for (int i = t; i < nf; i += 256) w[i] = 0.0;
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
     const int ch = d.child[s];
     if (ch >= 0) {
       const NDNodeH c = nodes[ch];
       const int* map = cmap + d.cmap_off[s];
-      for (int i = threadIdx.x; i < c.nb; i += 256) w[map[i]] += up[c.up_off + i];
+      for (int i = t; i < c.nb; i += 256) w[map[i]] += up[c.up_off + i];
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < d.ns; i += 256) {
+  for (int i = t; i < d.ns; i += 256) {
     const double v = b[own[d.own_off + i]] + w[i];
     be[i] = v;
     if (r0 == 0) beff[d.beff_off + i] = v;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, r = r0 + (threadIdx.x >> 6);
-  if (r >= d.nb) return;
-  const double* row = F + d.foff + (long long)(d.ns + r) * nf;  // -M
+  const int lane = t & 63, wv = t >> 6, r = r0 + lane;
   double s = 0.0;
-  for (int k = lane; k < d.ns; k += 64) s += row[k] * be[k];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) up[d.up_off + r] = w[d.ns + r] + s;
+  if (r < d.nb) {
+    const double* col = F + d.foff + d.ns + r;
+    const long long st = 4LL * nf;
+    int k = wv;
+    for (; k + 28 < d.ns; k += 32) {
+      const double* c0 = col + (long long)k * nf;
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = c0[u * st];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += a[u] * be[k + 4 * u];
+    }
+    for (; k < d.ns; k += 4) s += col[(long long)k * nf] * be[k];
+  }
+  pr[wv * 64 + lane] = s;
+  __syncthreads();
+  if (wv == 0 && r < d.nb)
+    up[d.up_off + r] = w[d.ns + r] - (((pr[lane] + pr[64 + lane]) + pr[128 + lane]) + pr[192 + lane]);
 }
 
-// backward sweep of one level: item = (node, first own row); g_s = [F_ss^-1 | M^T] [b_eff; -g_b]
+// backward sweep of one level, item = (node, first own row k0): rows
+// [k0, k0 + ND_BW_ROWS) of g_s = [F_ss^-1 | M^T] [b_eff; -g_b]; wave wv takes
+// rows k0 + wv + 4q, lanes run along the row, a butterfly sums each row
 __global__ __launch_bounds__(256) void k_nd_bwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
                                                 const int* __restrict__ own, const int* __restrict__ bnd,
                                                 const double* __restrict__ F, const double* __restrict__ beff,
                                                 double* __restrict__ x) {
   extern __shared__ double sh[];
-  const int nid = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
+  const int nid = items[2 * blockIdx.x], k0 = items[2 * blockIdx.x + 1];
   const NDNodeH d = nodes[nid];
   const int nf = d.ns + d.nb;
   for (int i = threadIdx.x; i < nf; i += 256)
     sh[i] = i < d.ns ? beff[d.beff_off + i] : -x[bnd[d.bnd_off + i - d.ns]];
   __syncthreads();
-  const int lane = threadIdx.x & 63, r = r0 + (threadIdx.x >> 6);
-  if (r >= d.ns) return;
-  const double* row = F + d.foff + (long long)r * nf;
-  double s = 0.0;
-  for (int k = lane; k < nf; k += 64) s += row[k] * sh[k];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) x[own[d.own_off + r]] = s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int Q = ND_BW_ROWS / 4;
+  const double* rows[Q];
+  bool ok[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int k = k0 + wv + 4 * q;
+    ok[q] = k < d.ns;
+    rows[q] = F + d.foff + (long long)(ok[q] ? k : 0) * nf;
+  }
+  double s[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) s[q] = 0.0;
+  for (int j = lane; j < nf; j += 64) {
+    const double vj = sh[j];
+    double a[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) a[q] = ok[q] ? rows[q][j] : 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] += a[q] * vj;
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double v = s[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0 && ok[q]) x[own[d.own_off + k0 + wv + 4 * q]] = v;
+  }
 }
 
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x) {
   const CoarseLayout& co = c->co;
-  const size_t lds_f = (size_t)(co.nd_nfmax + co.nd_nsmax) * sizeof(double);
+  const size_t lds_f = (size_t)(co.nd_nfmax + co.nd_nsmax + 256) * sizeof(double);
   const size_t lds_b = (size_t)co.nd_nfmax * sizeof(double);
   const int L = (int)co.nd_levels.size();
   for (int l = L - 1; l >= 0; --l) {

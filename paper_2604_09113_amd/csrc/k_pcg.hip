@@ -17,83 +17,124 @@ namespace lbddc {
 
 constexpr int kBlk = 256;
 
-// y = S x for one cell per 64-thread workgroup; S packed lower [nU(nU+1)/2]
+// The per-cell kernels below run one cell per 64-lane workgroup (NU <= 64):
+// every lane first issues all of its loads of the cell's packed matrices (one
+// coalesced sweep over the cell's block), then the block is staged in LDS and
+// lane i forms row i.  A packed symmetric row is read as S[max(i,j)][min(i,j)]
+// with a select in a single unrolled loop, so no lane diverges.
+
+template <typename T, int N>
+__device__ inline T sym_row(const T* __restrict__ Sp, const T* __restrict__ xs, int i) {
+  const int ri = i * (i + 1) / 2;
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) s += Sp[j <= i ? ri + j : j * (j + 1) / 2 + i] * xs[j];
+  return s;
+}
+
+// y_i = S_i x_i for every cell; S packed lower [nU(nU+1)/2]
 template <int NU>
 __global__ __launch_bounds__(64) void k_op_local(const double* __restrict__ S, const int* __restrict__ RU,
                                                  const double* __restrict__ x, double* __restrict__ part) {
-  constexpr int NSP = NU * (NU + 1) / 2;
-  __shared__ double Ss[NSP];
-  __shared__ double xs[NU];
+  static_assert(NU <= 64, "one row per lane");
+  constexpr int NSP = NU * (NU + 1) / 2, NL = (NSP + 63) / 64;
+  __shared__ double Ss[NL * 64];
+  __shared__ double xs[64];
   const int cell = blockIdx.x, l = threadIdx.x;
   const double* Sc = S + (size_t)cell * NSP;
-  for (int i = l; i < NSP; i += 64) Ss[i] = Sc[i];
-  for (int i = l; i < NU; i += 64) {
-    int g = RU[(size_t)cell * NU + i];
-    xs[i] = g >= 0 ? x[g] : 0.0;
+  double v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int i = l + 64 * k;
+    v[k] = (i < NSP) ? Sc[i] : 0.0;
   }
+  const int g = l < NU ? RU[(size_t)cell * NU + l] : -1;
+  xs[l] = g >= 0 ? x[g] : 0.0;
+#pragma unroll
+  for (int k = 0; k < NL; ++k) Ss[l + 64 * k] = v[k];
   __syncthreads();
-  for (int i = l; i < NU; i += 64) {
-    double s = 0.0;
-    const int ri = i * (i + 1) / 2;
-    for (int j = 0; j <= i; ++j) s += Ss[ri + j] * xs[j];
-    for (int j = i + 1; j < NU; ++j) s += Ss[j * (j + 1) / 2 + i] * xs[j];
-    part[(size_t)cell * NU + i] = s;
-  }
+  if (l < NU) part[(size_t)cell * NU + l] = sym_row<double, NU>(Ss, xs, l);
 }
 
-// fine correction and coarse restriction of one cell (T = double or float)
+// fine correction and coarse restriction of one cell (T = double or float):
+// partU = [0; P r_E] (P packed over the nE = nU - 8 non-corner slots),
+// partC = Psi^T r  (Psi [nU][nC] row-major); nC columns x NCH row chunks over
+// the lanes, chunk partials summed in fixed order.
 template <typename T, int NU, int NC>
 __global__ __launch_bounds__(64) void k_pre_local(const T* __restrict__ P, const T* __restrict__ Psi,
                                                   const int* __restrict__ RU, const double* __restrict__ r,
                                                   double* __restrict__ partU, double* __restrict__ partC) {
-  constexpr int NE = NU - 8, NSP = NE * (NE + 1) / 2;
-  __shared__ T Ps[NSP];
-  __shared__ T Qs[NU * NC];
-  __shared__ T rs[NU];
+  static_assert(NU <= 64 && NC <= 32, "lane mapping");
+  constexpr int NE = NU - 8, NSP = NE * (NE + 1) / 2, NLP = (NSP + 63) / 64;
+  constexpr int NQ = NU * NC, NLQ = (NQ + 63) / 64;
+  constexpr int NCH = 64 / NC, RCH = (NU + NCH - 1) / NCH;
+  __shared__ T Ps[NLP * 64];
+  __shared__ T Qs[NLQ * 64];
+  __shared__ T rs[64];
+  __shared__ T cr[NCH][NC];
   const int cell = blockIdx.x, l = threadIdx.x;
   const T* Pc = P + (size_t)cell * NSP;
-  const T* Qc = Psi + (size_t)cell * NU * NC;
-  for (int i = l; i < NSP; i += 64) Ps[i] = Pc[i];
-  for (int i = l; i < NU * NC; i += 64) Qs[i] = Qc[i];
-  for (int i = l; i < NU; i += 64) {
-    int g = RU[(size_t)cell * NU + i];
-    rs[i] = g >= 0 ? (T)r[g] : (T)0;
+  const T* Qc = Psi + (size_t)cell * NQ;
+  T vp[NLP], vq[NLQ];
+#pragma unroll
+  for (int k = 0; k < NLP; ++k) {
+    const int i = l + 64 * k;
+    vp[k] = (i < NSP) ? Pc[i] : (T)0;
+  }
+#pragma unroll
+  for (int k = 0; k < NLQ; ++k) {
+    const int i = l + 64 * k;
+    vq[k] = (i < NQ) ? Qc[i] : (T)0;
+  }
+  const int g = l < NU ? RU[(size_t)cell * NU + l] : -1;
+  rs[l] = g >= 0 ? (T)r[g] : (T)0;
+#pragma unroll
+  for (int k = 0; k < NLP; ++k) Ps[l + 64 * k] = vp[k];
+#pragma unroll
+  for (int k = 0; k < NLQ; ++k) Qs[l + 64 * k] = vq[k];
+  __syncthreads();
+  if (l < NU) partU[(size_t)cell * NU + l] = l >= 8 ? (double)sym_row<T, NE>(Ps, rs + 8, l - 8) : 0.0;
+  const int ch = l / NC, jc = l - ch * NC;
+  if (ch < NCH) {
+    T s = 0;
+    const int i0 = ch * RCH;
+#pragma unroll
+    for (int q = 0; q < RCH; ++q)
+      if (i0 + q < NU) s += Qs[(i0 + q) * NC + jc] * rs[i0 + q];
+    cr[ch][jc] = s;
   }
   __syncthreads();
-  for (int i = l; i < NU; i += 64) {
-    T s = 0;
-    if (i >= 8) {
-      const int e = i - 8, re = e * (e + 1) / 2;
-      for (int j = 0; j <= e; ++j) s += Ps[re + j] * rs[8 + j];
-      for (int j = e + 1; j < NE; ++j) s += Ps[j * (j + 1) / 2 + e] * rs[8 + j];
-    }
-    partU[(size_t)cell * NU + i] = (double)s;
-  }
-  for (int jc = l; jc < NC; jc += 64) {
-    T s = 0;
-    for (int i = 0; i < NU; ++i) s += Qs[i * NC + jc] * rs[i];
-    partC[(size_t)cell * NC + jc] = (double)s;
+  if (l < NC) {
+    T s = cr[0][l];
+#pragma unroll
+    for (int q = 1; q < NCH; ++q) s += cr[q][l];
+    partC[(size_t)cell * NC + l] = (double)s;
   }
 }
 
-// partU += Psi g_loc (coarse prolongation, D already folded into Psi)
+// partU += Psi g_loc (coarse prolongation, D already folded into Psi); lane i
+// reads row i of the cell's Psi block straight from memory
 template <typename T, int NU, int NC>
 __global__ __launch_bounds__(64) void k_prolong(const T* __restrict__ Psi, const int* __restrict__ RC,
                                                 const double* __restrict__ g, double* __restrict__ partU) {
-  __shared__ T Qs[NU * NC];
-  __shared__ T gs[NC];
+  __shared__ T gs[64];
   const int cell = blockIdx.x, l = threadIdx.x;
-  const T* Qc = Psi + (size_t)cell * NU * NC;
-  for (int i = l; i < NU * NC; i += 64) Qs[i] = Qc[i];
-  for (int j = l; j < NC; j += 64) {
-    int gc = RC[(size_t)cell * NC + j];
-    gs[j] = gc >= 0 ? (T)g[gc] : (T)0;
+  T row[NC];
+  if (l < NU) {
+    const T* Qr = Psi + ((size_t)cell * NU + l) * NC;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) row[j] = Qr[j];
+  }
+  if (l < NC) {
+    const int gc = RC[(size_t)cell * NC + l];
+    gs[l] = gc >= 0 ? (T)g[gc] : (T)0;
   }
   __syncthreads();
-  for (int i = l; i < NU; i += 64) {
+  if (l < NU) {
     T s = 0;
-    for (int j = 0; j < NC; ++j) s += Qs[i * NC + j] * gs[j];
-    partU[(size_t)cell * NU + i] += (double)s;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) s += row[j] * gs[j];
+    partU[(size_t)cell * NU + l] += (double)s;
   }
 }
 

@@ -155,6 +155,19 @@ bool build_nested_dissection(Ctx* c, const std::vector<int>& ent_g1, const std::
     co.nd_levels[d.level].push_back(n);
   }
   co.nd_front_total = foff;
+  // pivot-column panels of the levels swept in blocks (fronts above ND_LDS_NF)
+  co.nd_cp_total = 0;
+  for (const auto& lv : co.nd_levels) {
+    int nfmax = 0;
+    for (int n : lv) nfmax = std::max(nfmax, co.nd_nodes[n].ns + co.nd_nodes[n].nb);
+    if (nfmax <= ND_LDS_NF) continue;
+    long long off = 0;
+    for (int n : lv) {
+      co.nd_nodes[n].cp_off = off;
+      off += 64LL * (co.nd_nodes[n].ns + co.nd_nodes[n].nb);
+    }
+    co.nd_cp_total = std::max(co.nd_cp_total, off);
+  }
   co.nd_up_total = uoff;
   co.nd_beff_total = eoff;
   // child maps: child bnd position -> parent front position

@@ -159,8 +159,8 @@ bool build_topology(Ctx* c) {
   for (size_t l = 0; l < co.nd_levels.size(); ++l) {
     for (int n : co.nd_levels[l]) {
       const NDNodeH& d = co.nd_nodes[n];
-      for (int r = 0; r < std::max(1, d.nb); r += 4) { co.fw_items.push_back(n); co.fw_items.push_back(r); }
-      for (int r = 0; r < d.ns; r += 4) { co.bw_items.push_back(n); co.bw_items.push_back(r); }
+      for (int r = 0; r < std::max(1, d.nb); r += 64) { co.fw_items.push_back(n); co.fw_items.push_back(r); }
+      for (int r = 0; r < d.ns; r += ND_BW_ROWS) { co.bw_items.push_back(n); co.bw_items.push_back(r); }
       co.lvl_nodes.push_back(n);
     }
     co.fw_off.push_back((int)co.fw_items.size() / 2);
