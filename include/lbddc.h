@@ -181,6 +181,7 @@ enum {
 };
 lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
 
+
 /* Export per-cell results of `count` cells from `first` into a host buffer (FP64),
  * for testing.  Layouts per cell:
  *   K      [2nB][2nB], dof i*nB + k (component i, node k = a + (p+1) b)

@@ -487,6 +487,10 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
   c->phase_ms[7] = napp ? t_pre / napp : 0;
   c->phase_ms[8] = napp ? t_coarse / napp : 0;
   c->phase_ms[9] = t_rec;
+  {
+    lbddc_status fs = check_flags(c, "solve");
+    if (fs != LBDDC_OK) return fs;
+  }
   c->solved = true;
   if (status != LBDDC_OK) c->err = "solve: PCG reached max_iter before rtol";
   return status;

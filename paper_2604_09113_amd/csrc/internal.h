@@ -94,6 +94,7 @@ struct CoarseLayout {
   // per-level work lists of the solve sweeps: (node, first row) items
   std::vector<int> fw_items, bw_items, lvl_nodes;
   std::vector<int> fw_off, bw_off, lvl_off;
+  std::vector<int> lvl_nfmax, lvl_nsmax;  // largest front and own-block size per level
 };
 
 
@@ -230,7 +231,7 @@ hipError_t launch_schur(Ctx* c);             // A4
 hipError_t launch_weights(Ctx* c);           // A7 (gather of stiffness diagonals)
 hipError_t launch_precond(Ctx* c, bool fp32); // A5, A6, A7
 hipError_t launch_coarse_assemble(Ctx* c);   // A8 assembly of S_C blocks
-hipError_t launch_coarse_factor(Ctx* c);     // A8 block-tridiagonal FP64 factorization
+hipError_t launch_coarse_factor(Ctx* c);     // A8 nested-dissection FP64 factorization
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x);  // A8 solve
 hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32,
                      double* t_op, double* t_pre, double* t_coarse, int* n_apply);  // A9

@@ -334,18 +334,15 @@ hipError_t launch_coarse_factor(Ctx* c) {
 // (row-major, row stride nf); the lower rows are not needed once the parent
 // has taken U.
 
-// forward sweep of one level, item = (node, first boundary column r0):
+// Forward item (node, first boundary column r0):
 //   b_eff = b_s + (children's contributions to the own dofs),
 //   up[r] = w_b[r] - sum_k b_eff[k] M^T[k][r]   for r in [r0, r0 + 64)
 // lane = column r (coalesced rows of M^T), the four waves interleave the rows k
-// and their partial sums are added in a fixed order.
-__global__ __launch_bounds__(256) void k_nd_fwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
-                                                const int* __restrict__ own, const int* __restrict__ cmap,
-                                                const double* __restrict__ F, const double* __restrict__ b,
-                                                double* __restrict__ up, double* __restrict__ beff) {
-  extern __shared__ double sh[];
-  const int nid = items[2 * blockIdx.x], r0 = items[2 * blockIdx.x + 1];
-  const NDNodeH d = nodes[nid];
+// and their partial sums are added in a fixed order.  LDS: nf + ns + 256 doubles.
+__device__ void nd_forward_item(const NDNodeH& d, int r0, const NDNodeH* __restrict__ nodes,
+                                const int* __restrict__ own, const int* __restrict__ cmap,
+                                const double* __restrict__ F, const double* __restrict__ b,
+                                double* __restrict__ up, double* __restrict__ beff, double* sh) {
   const int nf = d.ns + d.nb, t = threadIdx.x;
   double* w = sh;          // [nf] children's contributions
   double* be = sh + nf;    // [ns]
@@ -389,16 +386,12 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDNodeH* __restrict__ node
     up[d.up_off + r] = w[d.ns + r] - (((pr[lane] + pr[64 + lane]) + pr[128 + lane]) + pr[192 + lane]);
 }
 
-// backward sweep of one level, item = (node, first own row k0): rows
-// [k0, k0 + ND_BW_ROWS) of g_s = [F_ss^-1 | M^T] [b_eff; -g_b]; wave wv takes
-// rows k0 + wv + 4q, lanes run along the row, a butterfly sums each row
-__global__ __launch_bounds__(256) void k_nd_bwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
-                                                const int* __restrict__ own, const int* __restrict__ bnd,
-                                                const double* __restrict__ F, const double* __restrict__ beff,
-                                                double* __restrict__ x) {
-  extern __shared__ double sh[];
-  const int nid = items[2 * blockIdx.x], k0 = items[2 * blockIdx.x + 1];
-  const NDNodeH d = nodes[nid];
+// Backward item (node, first own row k0): rows [k0, k0 + ND_BW_ROWS) of
+// g_s = [F_ss^-1 | M^T] [b_eff; -g_b]; wave wv takes rows k0 + wv + 4q, lanes
+// run along the row, a butterfly sums each row.  LDS: nf doubles.
+__device__ void nd_backward_item(const NDNodeH& d, int k0, const int* __restrict__ own,
+                                 const int* __restrict__ bnd, const double* __restrict__ F,
+                                 const double* __restrict__ beff, double* __restrict__ x, double* sh) {
   const int nf = d.ns + d.nb;
   for (int i = threadIdx.x; i < nf; i += 256)
     sh[i] = i < d.ns ? beff[d.beff_off + i] : -x[bnd[d.bnd_off + i - d.ns]];
@@ -432,21 +425,41 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDNodeH* __restrict__ node
   }
 }
 
+// one launch per tree level and direction (a level's items are independent)
+__global__ __launch_bounds__(256) void k_nd_fwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
+                                                const int* __restrict__ own, const int* __restrict__ cmap,
+                                                const double* __restrict__ F, const double* __restrict__ b,
+                                                double* __restrict__ up, double* __restrict__ beff) {
+  extern __shared__ double sh[];
+  const NDNodeH d = nodes[items[2 * blockIdx.x]];
+  nd_forward_item(d, items[2 * blockIdx.x + 1], nodes, own, cmap, F, b, up, beff, sh);
+}
+
+__global__ __launch_bounds__(256) void k_nd_bwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
+                                                const int* __restrict__ own, const int* __restrict__ bnd,
+                                                const double* __restrict__ F, const double* __restrict__ beff,
+                                                double* __restrict__ x) {
+  extern __shared__ double sh[];
+  const NDNodeH d = nodes[items[2 * blockIdx.x]];
+  nd_backward_item(d, items[2 * blockIdx.x + 1], own, bnd, F, beff, x, sh);
+}
+
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x) {
   const CoarseLayout& co = c->co;
-  const size_t lds_f = (size_t)(co.nd_nfmax + co.nd_nsmax + 256) * sizeof(double);
-  const size_t lds_b = (size_t)co.nd_nfmax * sizeof(double);
   const int L = (int)co.nd_levels.size();
+  // LDS sized per level, so the many small fronts of the lower levels all fit on the chip
   for (int l = L - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
+    const size_t lds = (size_t)(co.lvl_nfmax[l] + co.lvl_nsmax[l] + 256) * sizeof(double);
     if (ni > 0)
-      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), lds_f, c->stream, c->d_nd_nodes, c->d_fw_items + 2 * i0,
+      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), lds, c->stream, c->d_nd_nodes, c->d_fw_items + 2 * i0,
                          c->d_nd_own, c->d_nd_cmap, c->d_coarse, rhs, c->d_up, c->d_beff);
   }
   for (int l = 0; l < L; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
+    const size_t lds = (size_t)std::max(1, co.lvl_nfmax[l]) * sizeof(double);
     if (ni > 0)
-      hipLaunchKernelGGL(k_nd_bwd, dim3(ni), dim3(256), lds_b, c->stream, c->d_nd_nodes, c->d_bw_items + 2 * i0,
+      hipLaunchKernelGGL(k_nd_bwd, dim3(ni), dim3(256), lds, c->stream, c->d_nd_nodes, c->d_bw_items + 2 * i0,
                          c->d_nd_own, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
   }
   return hipGetLastError();

@@ -156,11 +156,15 @@ bool build_topology(Ctx* c) {
   // solve work lists: forward rows = boundary rows (at least one item per node), backward rows = own rows
   co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear();
   co.fw_off.assign(1, 0); co.bw_off.assign(1, 0); co.lvl_off.assign(1, 0);
+  co.lvl_nfmax.assign(co.nd_levels.size(), 0);
+  co.lvl_nsmax.assign(co.nd_levels.size(), 0);
   for (size_t l = 0; l < co.nd_levels.size(); ++l) {
     for (int n : co.nd_levels[l]) {
       const NDNodeH& d = co.nd_nodes[n];
+      co.lvl_nfmax[l] = std::max(co.lvl_nfmax[l], d.ns + d.nb);
+      co.lvl_nsmax[l] = std::max(co.lvl_nsmax[l], d.ns);
       for (int r = 0; r < std::max(1, d.nb); r += 64) { co.fw_items.push_back(n); co.fw_items.push_back(r); }
-      for (int r = 0; r < d.ns; r += ND_BW_ROWS) { co.bw_items.push_back(n); co.bw_items.push_back(r); }
+      for (int r = 0; r < std::max(1, d.ns); r += ND_BW_ROWS) { co.bw_items.push_back(n); co.bw_items.push_back(r); }
       co.lvl_nodes.push_back(n);
     }
     co.fw_off.push_back((int)co.fw_items.size() / 2);

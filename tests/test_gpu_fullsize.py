@@ -1,0 +1,151 @@
+"""Full-size checks on the 128 x 128, p = 8 mixed circle/cross lattice, in the
+launch configuration the benchmark times: FP64 assembly, mixed-precision
+setup and solve, ROMs cut to their numerical rank (14 and 11 reduced
+coordinates).
+
+The oracle cannot solve this lattice, so it is compared one cell at a time on
+sampled cells (geometry coefficients, MDEIM vector, stiffness, Schur
+complement, weights, loads) and the solution is checked through properties
+that hold at any size:
+  - the true residual;
+  - the displacement of the FP64 and mixed paths agree;
+  - the compliance equals f^T u with the oracle's load;
+  - repeated solves are bitwise equal.
+
+The ROM is the oracle's, trained once per test session."""
+import numpy as np
+import pytest
+
+from conftest import oracle_roms
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+# cells: clamped corner, clamped column, right edge, interior, top row, random
+SAMPLE = [0, 128, 127, 777, 8191, 16383, 5000, 12345]
+
+
+def _cut_to_rank(rom):
+    nr = max(c["n_used"] for c in rom["clusters"])
+    out = dict(rom, n_r=nr)
+    out["clusters"] = [dict(c, U=c["U"][:, :nr], coeff=c["coeff"][:, :nr]) for c in rom["clusters"]]
+    return out
+
+
+def _oracle_cells(prob, roms, cells):
+    """Oracle Cell objects of selected cells only (the oracle's own cell build,
+    without building the whole lattice)."""
+    from oracle.bddc import Problem
+    from oracle.dofs import Dofs
+    from oracle.geometry import material_tensor
+    P = Problem.__new__(Problem)
+    P.prob, P.p, P.q, P.m = prob, prob["p"], prob["q"], prob["m"]
+    P.nx, P.ny, P.rho, P.moments = prob["nx"], prob["ny"], prob["rho"], prob["moments"]
+    P.dofs = Dofs(P.nx, P.ny, P.p, P.moments)
+    P.Cmat = material_tensor(prob["E"], prob["nu"])
+    P.roms, P.assembly, P.nrhs = roms, "rom", prob["traction"].shape[0]
+    return P, {c: P._build_cell(c) for c in cells}
+
+
+@pytest.fixture(scope="module")
+def full():
+    from gpu_helpers import rom_arrays
+    from paper_2604_09113_amd import lbddc
+    prob = make_problem(3)
+    print("\n[fullsize] training the oracle ROMs", flush=True)
+    roms = {f: _cut_to_rank(r) for f, r in oracle_roms(prob).items()}
+    s = lbddc.Solver(0)
+    for rom in roms.values():
+        s.load_rom(**rom_arrays(rom))
+    s.set_problem(prob["nx"], prob["ny"], prob["p"], prob["q"], prob["m"], prob["ctrl"], prob["family"], prob["t"],
+                  prob["E"], prob["nu"], prob["rho"], prob["moments"], prob["traction"])
+    print("[fullsize] assemble FP64, setup mixed, solve", flush=True)
+    s.assemble(lbddc.FP64)
+    s.setup(lbddc.MIXED)
+    info = s.solve(rtol=1e-10, max_iter=2000)
+    yield prob, roms, s, info
+    s.close()
+
+
+def test_fullsize_sampled_cells(full):
+    from gpu_helpers import rel
+    from oracle.geometry import geometry_coefficients
+    from oracle.rom import stabilised_reduced
+    prob, roms, s, _ = full
+    P, cells = _oracle_cells(prob, roms, SAMPLE)
+    wk = ws = wl = 0.0
+    for c in SAMPLE:
+        cell = cells[c]
+        C, _ = geometry_coefficients(cell.X, prob["q"], P.Cmat)
+        th = s.export(1, c, 1)[0]
+        assert np.abs(th - C).max() <= 1e-13 * np.abs(C).max()
+        _, v = stabilised_reduced(roms[int(prob["family"][c])], float(prob["t"][c]), prob["rho"])
+        it = s.export(2, c, 1)[0]
+        assert np.abs(it[:len(v)] - v).max() <= 1e-13 * max(1.0, np.abs(v).max())
+        wk = max(wk, rel(s.export(0, c, 1)[0], cell.K))
+        a = cell.slot_active
+        ws = max(ws, rel(s.export(3, c, 1)[0][np.ix_(a, a)], cell.S))
+        wl = max(wl, rel(s.export(7, c, 1)[0][:, a].T, cell.f[cell.U_nat]))
+    print(f"[fullsize] sampled cells: K {wk:.2e} S {ws:.2e} load {wl:.2e}")
+    assert wk <= 1e-10 and ws <= 1e-10 and wl <= 1e-13
+
+
+def test_fullsize_weights(full):
+    """D of an interior cell from the oracle's diagonals of it and its 8 neighbours."""
+    from gpu_helpers import rel
+    prob, roms, s, _ = full
+    nx = prob["nx"]
+    c0 = 64 * nx + 64
+    nb = [c0 + dy * nx + dx for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    P, cells = _oracle_cells(prob, roms, nb)
+    tot = {}
+    for c in nb:
+        cell = cells[c]
+        for g, kd in zip(cell.U_glob, np.diag(cell.K)[cell.U_nat]):
+            tot[int(g)] = tot.get(int(g), 0.0) + kd
+    cell = cells[c0]
+    Do = np.array([kd / tot[int(g)] for g, kd in zip(cell.U_glob, np.diag(cell.K)[cell.U_nat])])
+    D = s.export(4, c0, 1)[0][cell.slot_active]
+    print(f"[fullsize] weights of cell {c0}: {rel(D, Do):.2e}")
+    assert rel(D, Do) <= 1e-12
+
+
+def test_fullsize_solution_properties(full):
+    from paper_2604_09113_amd import lbddc
+    prob, roms, s, info = full
+    print(f"[fullsize] mixed: {info[0]['iters']} iterations, rel_res {info[0]['rel_res']:.2e}, "
+          f"true {info[0]['true_rel_res']:.2e}")
+    assert info[0]["rel_res"] <= 1e-10 and info[0]["true_rel_res"] <= 1e-9
+    u_mixed = s.displacement(0)
+    # a repeated solve is bitwise equal (fixed-order reductions, no float atomics)
+    info_r = s.solve(rtol=1e-10, max_iter=2000)
+    assert info_r[0]["iters"] == info[0]["iters"]
+    assert np.array_equal(s.displacement(0), u_mixed)
+    # FP64 preconditioner: same solution to the solver tolerance
+    s.setup(lbddc.FP64)
+    info64 = s.solve(rtol=1e-10, max_iter=2000)
+    u64 = s.displacement(0)
+    d = np.abs(u64 - u_mixed).max() / np.abs(u64).max()
+    print(f"[fullsize] fp64: {info64[0]['iters']} iterations; |u_fp64 - u_mixed| / |u| = {d:.2e}")
+    assert d <= 1e-8
+
+
+def test_fullsize_compliance_is_load_times_displacement(full):
+    """J from the adjoint kernels equals f^T u with the oracle's traction load
+    on the right-edge cells and the GPU displacement."""
+    from oracle.bddc import traction_load
+    from oracle.dofs import edge_nodes_local
+    from oracle.geometry import cell_control_points
+    prob, roms, s, _ = full
+    s.solve(rtol=1e-10, max_iter=2000)
+    J, _, _ = s.compliance_gradient()
+    u = s.displacement(0)
+    p, nx, ny, m = prob["p"], prob["nx"], prob["ny"], prob["m"]
+    Jo = 0.0
+    for iy in range(ny):
+        X = cell_control_points(prob["ctrl"], m, nx - 1, iy)
+        fe = traction_load(X, p, prob["traction"][0, iy])
+        for n, (a, b) in enumerate(edge_nodes_local(p, "right")):
+            Jo += fe[n] @ u[p * iy + b, p * (nx - 1) + a]
+    print(f"[fullsize] J {J[0]:.12e} f^T u {Jo:.12e}")
+    assert abs(J[0] - Jo) <= 1e-12 * abs(Jo)
