@@ -78,6 +78,17 @@ struct NDNodeH {
   int parent = -1, level = 0;
 };
 
+// One work item of a coarse solve sweep: the node data the item needs, so a
+// workgroup starts with a single load.  first = first boundary column
+// (forward) or first own row (backward).  Own dofs of a node are the coarse
+// dofs [own_off, own_off + ns) (coarse dofs are numbered in tree order).
+struct NDItem {
+  long long foff;
+  int ns, nb, own_off, bnd_off, up_off, first;
+  int child_up_off[2], child_nb[2], cmap_off[2];
+  int pad[2];
+};
+
 struct CoarseLayout {
   std::vector<int> sb_off, sb_size;   // coarse numbering by grid lines (offset, size)
   // unique entries of S_C: entry e sums contributions [cstart[e], cstart[e+1]) into dest[e]
@@ -86,13 +97,14 @@ struct CoarseLayout {
   std::vector<int> contrib;           // index into ScLoc (cell*nCp + packed)
   // nested dissection
   std::vector<NDNodeH> nd_nodes;
-  std::vector<int> nd_own, nd_bnd, nd_cmap;
+  std::vector<int> nd_own, nd_bnd, nd_cmap;  // own/boundary coarse ids per node (tree-order numbering)
   std::vector<std::vector<int>> nd_levels;   // node ids per depth (0 = root)
   long long nd_front_total = 0;
   int nd_up_total = 0, nd_beff_total = 0, nd_nfmax = 0, nd_nsmax = 0;
   long long nd_cp_total = 0;  // panel scratch of the largest blocked level
   // per-level work lists of the solve sweeps: (node, first row) items
-  std::vector<int> fw_items, bw_items, lvl_nodes;
+  std::vector<NDItem> fw_items, bw_items;
+  std::vector<int> lvl_nodes;
   std::vector<int> fw_off, bw_off, lvl_off;
   std::vector<int> lvl_nfmax, lvl_nsmax;  // largest front and own-block size per level
 };
@@ -146,8 +158,9 @@ struct Ctx {
   int* d_net_own = nullptr;    // cell*(m+1)^2 + local control point
   int* d_cstart = nullptr; int* d_contrib = nullptr; long long* d_dest = nullptr;
   NDNodeH* d_nd_nodes = nullptr;
-  int *d_nd_own = nullptr, *d_nd_bnd = nullptr, *d_nd_cmap = nullptr;
-  int *d_fw_items = nullptr, *d_bw_items = nullptr, *d_lvl_nodes = nullptr;
+  int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr;
+  NDItem *d_fw_items = nullptr, *d_bw_items = nullptr;
+  int* d_lvl_nodes = nullptr;
   int* d_flags = nullptr;      // device error flags [8]
   int* h_flags = nullptr;      // pinned host mirror
 

@@ -105,14 +105,17 @@ __global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ n
     double piv = rowl[l];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
     const double pinv = 1.0 / piv;
+    // every candidate is formed and one is selected: no per-element branch
     for (int i = wave; i < nf; i += 4) {
       const double ci = coll[i] * pinv;
+      const bool prow = i == l;
       for (int j = lane; j < nf; j += 64) {
-        double v;
-        if (i == l) v = (j == l) ? pinv : rowl[j] * pinv;
-        else if (j == l) v = -ci;
-        else v = S[i * ld + j] - ci * rowl[j];
-        S[i * ld + j] = v;
+        const double s = S[i * ld + j], r = rowl[j];
+        const bool pcol = j == l;
+        const double vrow = pcol ? pinv : r * pinv;
+        const double vcol = -ci;
+        const double vgen = s - ci * r;
+        S[i * ld + j] = prow ? vrow : (pcol ? vcol : vgen);
       }
     }
     __syncthreads();
@@ -165,17 +168,22 @@ __global__ __launch_bounds__(256) void k_lv_diag(const NDNodeH* __restrict__ nod
     double piv = rowb[buf][l];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
     const double pinv = 1.0 / piv;
+    double cs[4], rr[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) cs[a] = colb[buf][tr + 16 * a] * pinv;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rr[b] = rowb[buf][tc + 16 * b];
+    // every candidate is formed and one is selected: no per-element branch
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int i = tr + 16 * a, j = tc + 16 * b;
-        double v = B[a][b];
-        if (i == l && j == l) v = pinv;
-        else if (i == l) v = v * pinv;
-        else if (j == l) v = -v * pinv;
-        else v = v - colb[buf][i] * rowb[buf][j] * pinv;
-        B[a][b] = v;
+        const bool prow = tr + 16 * a == l, pcol = tc + 16 * b == l;
+        const double v = B[a][b];
+        const double vrow = pcol ? pinv : v * pinv;
+        const double vcol = -v * pinv;
+        const double vgen = v - cs[a] * rr[b];
+        B[a][b] = prow ? vrow : (pcol ? vcol : vgen);
       }
     buf ^= 1;
   }
@@ -338,80 +346,84 @@ hipError_t launch_coarse_factor(Ctx* c) {
 //   b_eff = b_s + (children's contributions to the own dofs),
 //   up[r] = w_b[r] - sum_k b_eff[k] M^T[k][r]   for r in [r0, r0 + 64)
 // lane = column r (coalesced rows of M^T), the four waves interleave the rows k
-// and their partial sums are added in a fixed order.  LDS: nf + ns + 256 doubles.
-__device__ void nd_forward_item(const NDNodeH& d, int r0, const NDNodeH* __restrict__ nodes,
-                                const int* __restrict__ own, const int* __restrict__ cmap,
-                                const double* __restrict__ F, const double* __restrict__ b,
-                                double* __restrict__ up, double* __restrict__ beff, double* sh) {
+// and their partial sums are added in a fixed order.  The first 32 rows of M^T
+// are requested before the right-hand side is gathered, so the loads overlap.
+// LDS: nf + 256 doubles.
+__global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int* __restrict__ cmap,
+                                                const double* __restrict__ F, const double* __restrict__ b,
+                                                double* __restrict__ up, double* __restrict__ beff) {
+  extern __shared__ double sh[];
+  const NDItem d = items[blockIdx.x];
   const int nf = d.ns + d.nb, t = threadIdx.x;
-  double* w = sh;          // [nf] children's contributions
-  double* be = sh + nf;    // [ns]
-  double* pr = be + d.ns;  // [4][64] wave partials
-  for (int i = t; i < nf; i += 256) w[i] = 0.0;
+  const int lane = t & 63, wv = t >> 6, r = d.first + lane;
+  const bool col_ok = r < d.nb;
+  const double* col = F + d.foff + d.ns + (col_ok ? r : 0);
+  const long long st = 4LL * nf;
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = (col_ok && wv + 4 * u < d.ns) ? col[(long long)(wv + 4 * u) * nf] : 0.0;
+  double* w = sh;        // [nf]: b_eff on the own positions, w_b on the boundary positions
+  double* pr = sh + nf;  // [4][64] wave partials
+  for (int i = t; i < nf; i += 256) w[i] = i < d.ns ? b[d.own_off + i] : 0.0;
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
-    const int ch = d.child[s];
-    if (ch >= 0) {
-      const NDNodeH c = nodes[ch];
-      const int* map = cmap + d.cmap_off[s];
-      for (int i = t; i < c.nb; i += 256) w[map[i]] += up[c.up_off + i];
-    }
+    const int* map = cmap + d.cmap_off[s];
+    for (int i = t; i < d.child_nb[s]; i += 256) w[map[i]] += up[d.child_up_off[s] + i];
     __syncthreads();
   }
-  for (int i = t; i < d.ns; i += 256) {
-    const double v = b[own[d.own_off + i]] + w[i];
-    be[i] = v;
-    if (r0 == 0) beff[d.beff_off + i] = v;
-  }
-  __syncthreads();
-  const int lane = t & 63, wv = t >> 6, r = r0 + lane;
+  if (d.first == 0)
+    for (int i = t; i < d.ns; i += 256) beff[d.own_off + i] = w[i];
   double s = 0.0;
-  if (r < d.nb) {
-    const double* col = F + d.foff + d.ns + r;
-    const long long st = 4LL * nf;
-    int k = wv;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s += a[u] * (wv + 4 * u < d.ns ? w[wv + 4 * u] : 0.0);
+  if (col_ok) {
+    int k = wv + 32;
     for (; k + 28 < d.ns; k += 32) {
       const double* c0 = col + (long long)k * nf;
-      double a[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) a[u] = c0[u * st];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s += a[u] * be[k + 4 * u];
+      for (int u = 0; u < 8; ++u) s += a[u] * w[k + 4 * u];
     }
-    for (; k < d.ns; k += 4) s += col[(long long)k * nf] * be[k];
+    for (; k < d.ns; k += 4) s += col[(long long)k * nf] * w[k];
   }
   pr[wv * 64 + lane] = s;
   __syncthreads();
-  if (wv == 0 && r < d.nb)
+  if (wv == 0 && col_ok)
     up[d.up_off + r] = w[d.ns + r] - (((pr[lane] + pr[64 + lane]) + pr[128 + lane]) + pr[192 + lane]);
 }
 
 // Backward item (node, first own row k0): rows [k0, k0 + ND_BW_ROWS) of
 // g_s = [F_ss^-1 | M^T] [b_eff; -g_b]; wave wv takes rows k0 + wv + 4q, lanes
-// run along the row, a butterfly sums each row.  LDS: nf doubles.
-__device__ void nd_backward_item(const NDNodeH& d, int k0, const int* __restrict__ own,
-                                 const int* __restrict__ bnd, const double* __restrict__ F,
-                                 const double* __restrict__ beff, double* __restrict__ x, double* sh) {
+// run along the row, a butterfly sums each row.  The first 64 columns of the
+// rows are requested before the vector is gathered.  LDS: nf doubles.
+__global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items, const int* __restrict__ bnd,
+                                                const double* __restrict__ F, const double* __restrict__ beff,
+                                                double* __restrict__ x) {
+  extern __shared__ double sh[];
+  const NDItem d = items[blockIdx.x];
   const int nf = d.ns + d.nb;
-  for (int i = threadIdx.x; i < nf; i += 256)
-    sh[i] = i < d.ns ? beff[d.beff_off + i] : -x[bnd[d.bnd_off + i - d.ns]];
-  __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   constexpr int Q = ND_BW_ROWS / 4;
   const double* rows[Q];
   bool ok[Q];
+  double a[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    const int k = k0 + wv + 4 * q;
+    const int k = d.first + wv + 4 * q;
     ok[q] = k < d.ns;
     rows[q] = F + d.foff + (long long)(ok[q] ? k : 0) * nf;
+    a[q] = (ok[q] && lane < nf) ? rows[q][lane] : 0.0;
   }
+  for (int i = threadIdx.x; i < nf; i += 256)
+    sh[i] = i < d.ns ? beff[d.own_off + i] : -x[bnd[d.bnd_off + i - d.ns]];
+  __syncthreads();
   double s[Q];
+  const double v0 = lane < nf ? sh[lane] : 0.0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) s[q] = 0.0;
-  for (int j = lane; j < nf; j += 64) {
+  for (int q = 0; q < Q; ++q) s[q] = a[q] * v0;
+  for (int j = lane + 64; j < nf; j += 64) {
     const double vj = sh[j];
-    double a[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) a[q] = ok[q] ? rows[q][j] : 0.0;
 #pragma unroll
@@ -421,27 +433,8 @@ __device__ void nd_backward_item(const NDNodeH& d, int k0, const int* __restrict
   for (int q = 0; q < Q; ++q) {
     double v = s[q];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0 && ok[q]) x[own[d.own_off + k0 + wv + 4 * q]] = v;
+    if (lane == 0 && ok[q]) x[d.own_off + d.first + wv + 4 * q] = v;
   }
-}
-
-// one launch per tree level and direction (a level's items are independent)
-__global__ __launch_bounds__(256) void k_nd_fwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
-                                                const int* __restrict__ own, const int* __restrict__ cmap,
-                                                const double* __restrict__ F, const double* __restrict__ b,
-                                                double* __restrict__ up, double* __restrict__ beff) {
-  extern __shared__ double sh[];
-  const NDNodeH d = nodes[items[2 * blockIdx.x]];
-  nd_forward_item(d, items[2 * blockIdx.x + 1], nodes, own, cmap, F, b, up, beff, sh);
-}
-
-__global__ __launch_bounds__(256) void k_nd_bwd(const NDNodeH* __restrict__ nodes, const int* __restrict__ items,
-                                                const int* __restrict__ own, const int* __restrict__ bnd,
-                                                const double* __restrict__ F, const double* __restrict__ beff,
-                                                double* __restrict__ x) {
-  extern __shared__ double sh[];
-  const NDNodeH d = nodes[items[2 * blockIdx.x]];
-  nd_backward_item(d, items[2 * blockIdx.x + 1], own, bnd, F, beff, x, sh);
 }
 
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x) {
@@ -450,17 +443,17 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x) {
   // LDS sized per level, so the many small fronts of the lower levels all fit on the chip
   for (int l = L - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
-    const size_t lds = (size_t)(co.lvl_nfmax[l] + co.lvl_nsmax[l] + 256) * sizeof(double);
+    const size_t lds = (size_t)(co.lvl_nfmax[l] + 256) * sizeof(double);
     if (ni > 0)
-      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), lds, c->stream, c->d_nd_nodes, c->d_fw_items + 2 * i0,
-                         c->d_nd_own, c->d_nd_cmap, c->d_coarse, rhs, c->d_up, c->d_beff);
+      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), lds, c->stream, c->d_fw_items + i0, c->d_nd_cmap,
+                         c->d_coarse, rhs, c->d_up, c->d_beff);
   }
   for (int l = 0; l < L; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
     const size_t lds = (size_t)std::max(1, co.lvl_nfmax[l]) * sizeof(double);
     if (ni > 0)
-      hipLaunchKernelGGL(k_nd_bwd, dim3(ni), dim3(256), lds, c->stream, c->d_nd_nodes, c->d_bw_items + 2 * i0,
-                         c->d_nd_own, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      hipLaunchKernelGGL(k_nd_bwd, dim3(ni), dim3(256), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd,
+                         c->d_coarse, c->d_beff, x);
   }
   return hipGetLastError();
 }

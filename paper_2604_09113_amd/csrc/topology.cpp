@@ -153,7 +153,19 @@ bool build_topology(Ctx* c) {
     }
   }
   if (!build_nested_dissection(c, ent_g1, ent_g2)) return false;
-  // solve work lists: forward rows = boundary rows (at least one item per node), backward rows = own rows
+  // renumber the coarse dofs in tree order (node by node, own dofs in the
+  // order of the node's own list), so a node's own dofs are a contiguous range
+  {
+    std::vector<int> newid(c->NC, -1);
+    for (size_t i = 0; i < co.nd_own.size(); ++i) newid[co.nd_own[i]] = (int)i;
+    for (int& r : c->RC)
+      if (r >= 0) r = newid[r];
+    for (int& g : co.nd_bnd) g = newid[g];
+    for (size_t i = 0; i < co.nd_own.size(); ++i) co.nd_own[i] = (int)i;
+    owners(c->RC, c->NC, cptr, cown);
+  }
+  // solve work lists: forward items = 64-column chunks of the boundary (at
+  // least one per node), backward items = ND_BW_ROWS own rows
   co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear();
   co.fw_off.assign(1, 0); co.bw_off.assign(1, 0); co.lvl_off.assign(1, 0);
   co.lvl_nfmax.assign(co.nd_levels.size(), 0);
@@ -163,12 +175,31 @@ bool build_topology(Ctx* c) {
       const NDNodeH& d = co.nd_nodes[n];
       co.lvl_nfmax[l] = std::max(co.lvl_nfmax[l], d.ns + d.nb);
       co.lvl_nsmax[l] = std::max(co.lvl_nsmax[l], d.ns);
-      for (int r = 0; r < std::max(1, d.nb); r += 64) { co.fw_items.push_back(n); co.fw_items.push_back(r); }
-      for (int r = 0; r < std::max(1, d.ns); r += ND_BW_ROWS) { co.bw_items.push_back(n); co.bw_items.push_back(r); }
+      NDItem it{};
+      it.foff = d.foff;
+      it.ns = d.ns;
+      it.nb = d.nb;
+      it.own_off = d.own_off;
+      it.bnd_off = d.bnd_off;
+      it.up_off = d.up_off;
+      for (int s = 0; s < 2; ++s) {
+        const int ch = d.child[s];
+        it.child_up_off[s] = ch >= 0 ? co.nd_nodes[ch].up_off : 0;
+        it.child_nb[s] = ch >= 0 ? co.nd_nodes[ch].nb : 0;
+        it.cmap_off[s] = ch >= 0 ? d.cmap_off[s] : 0;
+      }
+      for (int r = 0; r < std::max(1, d.nb); r += 64) {
+        it.first = r;
+        co.fw_items.push_back(it);
+      }
+      for (int r = 0; r < std::max(1, d.ns); r += ND_BW_ROWS) {
+        it.first = r;
+        co.bw_items.push_back(it);
+      }
       co.lvl_nodes.push_back(n);
     }
-    co.fw_off.push_back((int)co.fw_items.size() / 2);
-    co.bw_off.push_back((int)co.bw_items.size() / 2);
+    co.fw_off.push_back((int)co.fw_items.size());
+    co.bw_off.push_back((int)co.bw_items.size());
     co.lvl_off.push_back((int)co.lvl_nodes.size());
   }
 
@@ -209,7 +240,7 @@ bool build_topology(Ctx* c) {
          up(&c->d_RC, c->RC) && up(&c->d_uown_ptr, uptr) && up(&c->d_uown, uown) && up(&c->d_cown_ptr, cptr) &&
          up(&c->d_cown, cown) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
-         up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) && up(&c->d_nd_own, co.nd_own) &&
+         up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) &&
          up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_fw_items, co.fw_items) &&
          up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes);
 }
