@@ -177,7 +177,9 @@ enum {
   /* bytes of coarse-factor data one coarse solve reads (both sweeps) */
   LBDDC_Q_COARSE_SOLVE_BYTES = 11,
   /* number of levels of the nested-dissection tree of the coarse problem */
-  LBDDC_Q_COARSE_LEVELS = 12
+  LBDDC_Q_COARSE_LEVELS = 12,
+  /* bytes of coarse-factor data the forward sweep of one coarse solve reads */
+  LBDDC_Q_COARSE_FWD_BYTES = 13
 };
 lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
 
@@ -212,8 +214,10 @@ lbddc_status lbddc_export_cells(lbddc_ctx* ctx, int32_t which, int32_t first, in
  *   [3] whole setup, [4] coarse factorization, [5] whole solve (all load cases),
  *   [6] PCG operator kernel (mean per launch), [7] preconditioner local kernel
  *   (mean per launch), [8] coarse solve (mean per application), [9] recovery,
- *   [10] gradient, [11] adjoint contraction kernel.
- * `n` entries are written (n <= 12). */
+ *   [10] gradient, [11] adjoint contraction kernel, [12] forward sweep of the
+ *   coarse solve (mean per application; one launch per tree level), [13] its
+ *   backward sweep (same).
+ * `n` entries are written (n <= 14). */
 lbddc_status lbddc_phase_times(lbddc_ctx* ctx, double* ms, int32_t n);
 
 #ifdef __cplusplus

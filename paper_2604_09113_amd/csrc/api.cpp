@@ -30,6 +30,8 @@ bool dalloc(Ctx* c, void** p, size_t bytes) {
 }  // namespace lbddc
 
 static void free_problem(Ctx* c) {
+  if (c->h_red) hipHostFree(c->h_red);
+  c->h_red = nullptr;
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
   c->dev_bytes = 0;
@@ -39,7 +41,7 @@ static void free_problem(Ctx* c) {
   fresh.stream = c->stream;
   fresh.own_stream = c->own_stream;
   fresh.roms = std::move(c->roms);
-  for (int i = 0; i < 8; ++i) fresh.ev[i] = c->ev[i];
+  for (int i = 0; i < Ctx::kNumEv; ++i) fresh.ev[i] = c->ev[i];
   fresh.h_flags = c->h_flags;
   fresh.h_scal = c->h_scal;
   fresh.err = c->err;
@@ -105,7 +107,7 @@ lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out) {
     if (hipStreamCreate(&c->stream) != hipSuccess) { delete x; return LBDDC_E_HIP; }
     c->own_stream = true;
   }
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < Ctx::kNumEv; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete x; return LBDDC_E_HIP; }
   if (hipHostMalloc((void**)&c->h_flags, 128 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void**)&c->h_scal, 32 * sizeof(double)) != hipSuccess) {
@@ -128,10 +130,11 @@ void lbddc_destroy(lbddc_ctx* x) {
     for (auto p : kv.second.ucol64) hipFree(p);
     if (kv.second.coeff) hipFree(kv.second.coeff);
   }
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < Ctx::kNumEv; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
   if (c->h_flags) hipHostFree(c->h_flags);
   if (c->h_scal) hipHostFree(c->h_scal);
+  if (c->h_red) hipHostFree(c->h_red);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete x;
 }
@@ -324,6 +327,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
             dalloc_t(c, &c->d_zc, NC) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC) &&
             dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 16)) && dalloc_t(c, &c->d_scal, 32) &&
+            dalloc_t(c, &c->d_vred, (size_t)3 * (NU / 256 + 16)) &&
             dalloc_t(c, &c->d_u, (size_t)c->nrhs * c->Gx * c->Gy * 2) &&
             dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&
             dalloc_t(c, &c->d_H, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_G, (size_t)ncell * c->ns * 4) &&
@@ -332,6 +336,11 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
             dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8) &&
             dalloc_t(c, &c->d_pairs, (size_t)2 * c->npair);
+  if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(c->NU / 1024 + 16) * sizeof(double)) != hipSuccess) {
+    c->h_red = nullptr;
+    c->err = "pinned host allocation failed";
+    ok = false;
+  }
   if (!ok) { free_problem(c); return LBDDC_E_NOMEM; }
   // family -> slot table after the 8 flag words
   std::vector<int> flags(128, 0);
@@ -442,7 +451,7 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
   c->solved = false;
   const bool fp32 = c->setup_prec == LBDDC_MIXED;
   c->info.assign(c->nrhs, lbddc_solve_info{0, 0, 0});
-  double t_op = 0, t_pre = 0, t_coarse = 0;
+  double t_op = 0, t_pre = 0, t_coarse = 0, t_cf = 0, t_cb = 0;
   int napp = 0, nop = 0;
   float ms = 0;
   double t_rec = 0;
@@ -455,7 +464,7 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
     // right-hand side: gather-sum of the cell loads (f_I = 0 for edge tractions)
     HIPCHK(gather_rhs(c, r), "solve rhs");
     lbddc_solve_info inf{0, 0, 0};
-    hipError_t e = pcg_solve(c, r, rtol, max_iter, &inf, fp32, &t_op, &t_pre, &t_coarse, &napp);
+    hipError_t e = pcg_solve(c, r, rtol, max_iter, &inf, fp32, &t_op, &t_pre, &t_coarse, &t_cf, &t_cb, &napp);
     nop += inf.iters;
     if (e == hipErrorUnknown) {
       c->info[r] = inf;
@@ -486,6 +495,8 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
   c->phase_ms[6] = nop ? t_op / nop : 0;
   c->phase_ms[7] = napp ? t_pre / napp : 0;
   c->phase_ms[8] = napp ? t_coarse / napp : 0;
+  c->phase_ms[12] = napp ? t_cf / napp : 0;
+  c->phase_ms[13] = napp ? t_cb / napp : 0;
   c->phase_ms[9] = t_rec;
   {
     lbddc_status fs = check_flags(c, "solve");
@@ -542,13 +553,19 @@ lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
       break;
     }
     case LBDDC_Q_COARSE_LEVELS: *v = (int64_t)c->co.nd_levels.size(); break;
+    case LBDDC_Q_COARSE_FWD_BYTES: {
+      int64_t b = 0;
+      for (const NDNodeH& d : c->co.nd_nodes) b += 8LL * d.ns * d.nb;
+      *v = b;
+      break;
+    }
     default: return LBDDC_E_ARG;
   }
   return LBDDC_OK;
 }
 
 lbddc_status lbddc_phase_times(lbddc_ctx* x, double* ms, int32_t n) {
-  if (!x || !ms || n < 0 || n > 12) return LBDDC_E_ARG;
+  if (!x || !ms || n < 0 || n > 14) return LBDDC_E_ARG;
   for (int i = 0; i < n; ++i) ms[i] = x->c.phase_ms[i];
   return LBDDC_OK;
 }

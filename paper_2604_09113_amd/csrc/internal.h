@@ -204,6 +204,8 @@ struct Ctx {
   double* d_red = nullptr;     // reduction partials [kRedSlots][kMaxBlocks]
   double* d_scal = nullptr;    // scalars
   double* h_scal = nullptr;    // pinned
+  double* d_vred = nullptr;    // interface-vector partials: p.q, r.z, r.r [3][NU / 256 + 16]
+  double* h_red = nullptr;     // pinned copy of the r.r partials
   double* d_u = nullptr;       // [nrhs][Gy][Gx][2]
   std::vector<lbddc_solve_info> info;
 
@@ -220,8 +222,9 @@ struct Ctx {
   std::vector<int> group_counts;
   double* d_ucell = nullptr;   // [ncell][ndof] local displacement (permuted)
 
-  double phase_ms[12] = {0};
-  hipEvent_t ev[8] = {};
+  double phase_ms[14] = {0};
+  static constexpr int kNumEv = 9;
+  hipEvent_t ev[kNumEv] = {};
   size_t dev_bytes = 0;
   std::vector<void*> allocs;   // everything allocated for the problem
 };
@@ -245,9 +248,10 @@ hipError_t launch_weights(Ctx* c);           // A7 (gather of stiffness diagonal
 hipError_t launch_precond(Ctx* c, bool fp32); // A5, A6, A7
 hipError_t launch_coarse_assemble(Ctx* c);   // A8 assembly of S_C blocks
 hipError_t launch_coarse_factor(Ctx* c);     // A8 nested-dissection FP64 factorization
-hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x);  // A8 solve
+hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid = nullptr);  // A8 solve
 hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32,
-                     double* t_op, double* t_pre, double* t_coarse, int* n_apply);  // A9
+                     double* t_op, double* t_pre, double* t_coarse, double* t_cfwd, double* t_cbwd,
+                     int* n_apply);  // A9
 hipError_t pcg_true_residual(Ctx* c, int rhs, double* out);
 hipError_t gather_rhs(Ctx* c, int rhs);
 hipError_t launch_recover(Ctx* c, int rhs);  // A10

@@ -50,12 +50,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
   const double* ut = utg[td.x];
   const double* ut2 = ut2g[td.x];
   __syncthreads();
-  for (int pt = wave; pt < NPT; pt += 4) {
-    double uu[4][4];
+  // products w_P u[n1, i1] u[n2, i2] of the pair rows this lane feeds (4 pairs x 4 components)
+  auto pair_products = [&](int pt, double (&uu)[4][4]) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int P = pt * 16 + 4 * grp + v;
-      if (P < npair && valid) {
+      if (pt < NPT && P < npair && valid) {
         const int2 nn = pairs[P];
         const double w = nn.x == nn.y ? 1.0 : 2.0;
         const double a0 = uc[2 * nn.x], a1 = uc[2 * nn.x + 1], c0 = uc[2 * nn.y], c1 = uc[2 * nn.y + 1];
@@ -64,12 +64,46 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
         uu[v][0] = uu[v][1] = uu[v][2] = uu[v][3] = 0.0;
       }
     }
+  };
+  dbl4 hacc2[RB];  // second accumulator chain of H (odd kk), added in a fixed order at the end
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) hacc2[rb] = dbl4{0, 0, 0, 0};
+  double uu[4][4], un[4][4];
+  pair_products(wave, uu);
+  for (int pt = wave; pt < NPT; pt += 4) {
+    pair_products(pt + 4, un);  // next pair tile: loads overlap this tile's work
     const double* ap = ut + (size_t)pt * ns * KC * 64 + lane;
     const double* ap2 = ut2 + (size_t)pt * ns * RB * 4 * 64 + lane;
+    // operands of step s are requested one step ahead
+    double a[KC], a2[RB][4];
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) a[kc] = ap[kc * 64];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) a2[rb][kk] = ap2[(rb * 4 + kk) * 64];
     for (int s = 0; s < ns; ++s) {
+      const int sn = s + 1 < ns ? s + 1 : s;
+      double an[KC], an2[RB][4];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) an[kc] = ap[(sn * KC + kc) * 64];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) an2[rb][kk] = ap2[((sn * RB + rb) * 4 + kk) * 64];
       dbl4 d = dbl4{0, 0, 0, 0};
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) d = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(s * KC + kc) * 64], b[kc], d, 0, 0, 0);
+      for (int kc = 0; kc < KC; ++kc) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], b[kc], d, 0, 0, 0);
+      const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + s * 4);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          if (kk & 1) hacc2[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc2[rb], 0, 0, 0);
+          else hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc[rb], 0, 0, 0);
+        }
+      }
       double g[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
@@ -80,16 +114,20 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
       }
       const double gm = grp == 0 ? g[0] : grp == 1 ? g[1] : grp == 2 ? g[2] : g[3];
       Gw[(col * ns + s) * 4 + grp] += gm;
-      const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + s * 4);
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
+      for (int kc = 0; kc < KC; ++kc) a[kc] = an[kc];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap2[((s * RB + rb) * 4 + kk) * 64], z, hacc[rb], 0, 0, 0);
-      }
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) a2[rb][kk] = an2[rb][kk];
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) uu[v][e] = un[v][e];
   }
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) hacc[rb] += hacc2[rb];
   __syncthreads();
   // G: sum the four waves in a fixed order and write
   for (int i = threadIdx.x; i < GW; i += 256) {

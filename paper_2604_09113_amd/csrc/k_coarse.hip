@@ -146,7 +146,8 @@ __global__ __launch_bounds__(256) void k_lv_diag(const NDNodeH* __restrict__ nod
     }
   int buf = 0;
   bool bad = false;
-  for (int l = 0; l < GJB; ++l) {
+  // padding pivots (l >= kn) would leave the identity padding unchanged: skipped
+  for (int l = 0; l < kn; ++l) {
     const int la = l >> 4, lb = l & 15;
     if (tr == lb) {
 #pragma unroll
@@ -289,6 +290,49 @@ __global__ __launch_bounds__(256) void k_lv_update(const NDNodeH* __restrict__ n
     }
 }
 
+// Same update as k_lv_update, one workgroup per 64-row strip of a front: the
+// strip's old pivot-column block is staged once and the column tiles are
+// streamed, so every entry of the front is read and written once per pivot
+// block (the pivot rows come from L2).  grid (row strips, fronts).
+__global__ __launch_bounds__(256) void k_lv_update_rows(const NDNodeH* __restrict__ nodes,
+                                                        const int* __restrict__ lvl, double* __restrict__ F, int k0,
+                                                        const double* __restrict__ Cp) {
+  __shared__ double Ct[GJB][GJB + 1];  // Ct[q][r] = Cp[i0 + r][q]
+  __shared__ double Rs[GJB][GJB];      // Rs[q][b] = F[k0 + q][j0 + b]
+  const NDNodeH d = nodes[lvl[blockIdx.y]];
+  const int nf = d.ns + d.nb, i0 = blockIdx.x * GJB;
+  if (k0 >= d.ns || i0 >= nf) return;
+  const int kn = min(GJB, d.ns - k0);
+  if (i0 == k0 && kn == GJB) return;  // pivot rows only
+  double* A = F + d.foff;
+  const double* cp = Cp + d.cp_off;
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  for (int idx = t; idx < GJB * GJB; idx += 256) {
+    const int r = idx >> 6, q = idx & 63, i = i0 + r;
+    Ct[q][r] = (i < nf && q < kn && (i < k0 || i >= k0 + kn)) ? cp[(long long)i * GJB + q] : 0.0;
+  }
+  for (int j0 = 0; j0 < nf; j0 += GJB) {
+    for (int idx = t; idx < GJB * GJB; idx += 256) {
+      const int r = idx >> 6, q = idx & 63, j = j0 + q;
+      Rs[r][q] = (r < kn && j < nf) ? A[(long long)(k0 + r) * nf + j] : 0.0;
+    }
+    __syncthreads();
+    double acc[4][4];
+    tile_product(Ct, Rs, kn, acc);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+        if (i >= nf || j >= nf || (i >= k0 && i < k0 + kn)) continue;
+        double* e = A + (long long)i * nf + j;
+        if (j >= k0 && j < k0 + kn) *e = -acc[a][b];
+        else *e -= acc[a][b];
+      }
+    __syncthreads();
+  }
+}
+
 hipError_t launch_coarse_assemble(Ctx* c) {
   const CoarseLayout& co = c->co;
   hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, c->stream, c->d_coarse, co.nd_front_total, 0.0);
@@ -331,8 +375,12 @@ hipError_t launch_coarse_factor(Ctx* c) {
                          c->d_flags);
       hipLaunchKernelGGL(k_lv_panel, dim3(nt, nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse, k0,
                          c->d_gjC);
-      hipLaunchKernelGGL(k_lv_update, dim3(nt, nt, nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse,
-                         k0, c->d_gjC);
+      if (nn >= 32)  // enough fronts to fill the chip with row strips
+        hipLaunchKernelGGL(k_lv_update_rows, dim3(nt, nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl,
+                           c->d_coarse, k0, c->d_gjC);
+      else
+        hipLaunchKernelGGL(k_lv_update, dim3(nt, nt, nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse,
+                           k0, c->d_gjC);
     }
   }
   return hipGetLastError();
@@ -437,7 +485,7 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
   }
 }
 
-hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x) {
+hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
   // LDS sized per level, so the many small fronts of the lower levels all fit on the chip
@@ -448,6 +496,7 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x) {
       hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), lds, c->stream, c->d_fw_items + i0, c->d_nd_cmap,
                          c->d_coarse, rhs, c->d_up, c->d_beff);
   }
+  if (mid) hipEventRecord(mid, c->stream);
   for (int l = 0; l < L; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
     const size_t lds = (size_t)std::max(1, co.lvl_nfmax[l]) * sizeof(double);

@@ -215,6 +215,76 @@ __global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z,
   p[g] = init ? z[g] : z[g] + scal[5] * p[g];
 }
 
+// ---- interface-vector kernels of the iteration: kVec entries per thread ----
+constexpr int kVec = 4;
+constexpr int kVB = kBlk * kVec;  // entries per workgroup
+
+// fixed-order sum of red[0, n) by one workgroup; every workgroup that calls it
+// on the same data gets the same value
+__device__ inline double wg_sum(const double* __restrict__ red, int n, double* sh) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlk) s += red[i];
+  s = block_sum(s, sh);
+  __syncthreads();
+  return s;
+}
+
+// alpha = rz / (p.q) from the p.q partials (each workgroup sums them in the same
+// order); x += alpha p; r -= alpha q; partial r.r per workgroup.  Workgroup 0
+// records p.q and alpha and flags p.q <= 0 in scal[7].
+__global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, double* __restrict__ r,
+                                                     const double* __restrict__ p, const double* __restrict__ q,
+                                                     double* __restrict__ scal, int N,
+                                                     const double* __restrict__ red_pq, int nred, int rz_slot,
+                                                     double* __restrict__ red_rr) {
+  __shared__ double sh[kBlk];
+  const double pq = wg_sum(red_pq, nred, sh);
+  const double alpha = scal[rz_slot] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[1] = pq;
+    scal[2] = alpha;
+    if (!(pq > 0.0)) scal[7] = 1.0;
+  }
+  const int g0 = blockIdx.x * kVB + threadIdx.x;
+  double d = 0.0;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const int g = g0 + j * kBlk;
+    if (g < N) {
+      x[g] += alpha * p[g];
+      const double rv = r[g] - alpha * q[g];
+      r[g] = rv;
+      d += rv * rv;
+    }
+  }
+  d = block_sum(d, sh);
+  if (threadIdx.x == 0) red_rr[blockIdx.x] = d;
+}
+
+// rz_new from the r.z partials; p = z (init) or z + beta p with
+// beta = rz_new / scal[old_slot]; workgroup 0 stores rz_new in scal[new_slot]
+// (a different slot, so no workgroup reads a value being replaced) and flags
+// rz_new <= 0 in scal[7].
+__global__ __launch_bounds__(kBlk) void k_update_p4(double* __restrict__ p, const double* __restrict__ z,
+                                                    double* __restrict__ scal, int N,
+                                                    const double* __restrict__ red_rz, int nred, int old_slot,
+                                                    int new_slot, int init) {
+  __shared__ double sh[kBlk];
+  const double rz = wg_sum(red_rz, nred, sh);
+  const double beta = init ? 0.0 : rz / scal[old_slot];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[new_slot] = rz;
+    scal[5] = beta;
+    if (!(rz > 0.0)) scal[7] = 1.0;
+  }
+  const int g0 = blockIdx.x * kVB + threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const int g = g0 + j * kBlk;
+    if (g < N) p[g] = init ? z[g] : z[g] + beta * p[g];
+  }
+}
+
 __global__ void k_copy(double* __restrict__ dst, const double* __restrict__ src, int N) {
   int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g < N) dst[g] = src[g];
@@ -331,7 +401,7 @@ static void prolong(Ctx* c, bool fp32) {
 }
 
 // z = S_BDDC^-1 r (Alg. 1), with the partial dot r.z into red
-static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red, double* t_pre, double* t_coarse) {
+static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red) {
   const int nbU = (c->NU + kBlk - 1) / kBlk, nbC = (c->NC + kBlk - 1) / kBlk;
   hipEventRecord(c->ev[2], c->stream);
   pre_local(c, fp32, r);
@@ -339,40 +409,44 @@ static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double*
   hipLaunchKernelGGL(k_gather_dot, dim3(nbC), dim3(kBlk), 0, c->stream, c->d_partC, c->d_cown_ptr, c->d_cown,
                      c->d_zc, c->NC, (const double*)nullptr, (double*)nullptr);
   hipEventRecord(c->ev[4], c->stream);
-  hipError_t e = launch_coarse_solve(c, c->d_zc, c->d_xc);
+  hipError_t e = launch_coarse_solve(c, c->d_zc, c->d_xc, c->ev[8]);
   if (e != hipSuccess) return e;
   hipEventRecord(c->ev[5], c->stream);
   prolong(c, fp32);
   hipLaunchKernelGGL(k_gather_dot, dim3(nbU), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, z,
                      c->NU, r, red);
-  (void)t_pre; (void)t_coarse;
   return hipGetLastError();
 }
 
 hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32, double* t_op,
-                     double* t_pre, double* t_coarse, int* n_apply) {
-  const int N = c->NU, nb = (N + kBlk - 1) / kBlk;
+                     double* t_pre, double* t_coarse, double* t_cfwd, double* t_cbwd, int* n_apply) {
+  const int N = c->NU, nb = (N + kBlk - 1) / kBlk, nv = (N + kVB - 1) / kVB;
   double* f = c->d_f + (size_t)rhs * N;
   double* x = c->d_x + (size_t)rhs * N;
   double *r = c->d_r, *z = c->d_z, *p = c->d_p, *q = c->d_q;
   double* red = c->d_red;
+  // partials: p.q and r.z per gather workgroup (nb), r.r per update workgroup (nv)
+  double *red_pq = c->d_vred, *red_rz = c->d_vred + nb, *red_rr = c->d_vred + 2 * nb;
   double* scal = c->d_scal;
+  // scalar slots: 1 p.q, 2 alpha, 5 beta, 6 f.f, 7 breakdown flag, 10/11 r.z (alternating)
   hipLaunchKernelGGL(k_fill_p, dim3(256), dim3(256), 0, c->stream, x, (long long)N, 0.0);
   hipLaunchKernelGGL(k_fill_p, dim3(1), dim3(64), 0, c->stream, scal, 16LL, 0.0);
   hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kBlk), 0, c->stream, r, f, N);
   hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlk), 0, c->stream, f, f, N, red);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 6, 0);
   float ms = 0;
-  double acc_pre = 0, acc_coarse = 0, acc_op = 0;
+  double acc_pre = 0, acc_coarse = 0, acc_op = 0, acc_cf = 0, acc_cb = 0;
   int napp = 0;
-  hipError_t e = apply_M(c, fp32, r, z, red, t_pre, t_coarse);
+  int slot = 10;
+  hipError_t e = apply_M(c, fp32, r, z, red_rz);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 0, 0);  // rz
-  hipLaunchKernelGGL(k_update_p, dim3(nb), dim3(kBlk), 0, c->stream, p, z, scal, N, 1);
+  hipLaunchKernelGGL(k_update_p4, dim3(nv), dim3(kBlk), 0, c->stream, p, z, scal, N, red_rz, nb, slot, slot, 1);
   napp++;
   hipEventSynchronize(c->ev[5]);
   if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) acc_pre += ms;
   if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) acc_coarse += ms;
+  if (hipEventElapsedTime(&ms, c->ev[4], c->ev[8]) == hipSuccess) acc_cf += ms;
+  if (hipEventElapsedTime(&ms, c->ev[8], c->ev[5]) == hipSuccess) acc_cb += ms;
   e = hipMemcpyAsync(c->h_scal, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(c->stream);
@@ -383,23 +457,26 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   info->iters = 0;
   info->rel_res = ff > 0 ? 1.0 : 0.0;
   if (!(ff > 0)) return hipSuccess;
+  if (c->h_scal[7] != 0.0) return hipErrorUnknown;  // breakdown, reported by the caller
   while (it < max_iter) {
     hipEventRecord(c->ev[0], c->stream);
     op_local(c, p);
     hipEventRecord(c->ev[1], c->stream);
     hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, q, N,
-                       p, red);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 1, 1);  // pq, alpha
-    hipLaunchKernelGGL(k_update_xr, dim3(nb), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 3, 0);  // rr
+                       p, red_pq);
+    hipLaunchKernelGGL(k_update_xr4, dim3(nv), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red_pq, nb, slot,
+                       red_rr);
+    e = hipMemcpyAsync(c->h_red, red_rr, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return e;
     e = hipMemcpyAsync(c->h_scal, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return e;
     hipEventRecord(c->ev[6], c->stream);
-    // speculatively enqueue the preconditioner of the next iteration
-    e = apply_M(c, fp32, r, z, red, t_pre, t_coarse);
+    // speculatively enqueue the preconditioner and the direction update of the next iteration
+    e = apply_M(c, fp32, r, z, red_rz);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 4, 2);  // rz_new, beta
-    hipLaunchKernelGGL(k_update_p, dim3(nb), dim3(kBlk), 0, c->stream, p, z, scal, N, 0);
+    const int next = slot == 10 ? 11 : 10;
+    hipLaunchKernelGGL(k_update_p4, dim3(nv), dim3(kBlk), 0, c->stream, p, z, scal, N, red_rz, nb, slot, next, 0);
+    slot = next;
     e = hipEventSynchronize(c->ev[6]);
     if (e != hipSuccess) return e;
     ++it;
@@ -407,14 +484,18 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
     if (c->h_scal[7] != 0.0) {
       hipStreamSynchronize(c->stream);
       info->iters = it;
-      info->rel_res = sqrt(c->h_scal[3] / ff);
+      info->rel_res = rel;
       return hipErrorUnknown;  // breakdown, reported by the caller
     }
-    rel = sqrt(c->h_scal[3] / ff);
+    double rr = 0.0;  // r.r: the workgroup partials summed on the host in fixed order
+    for (int i = 0; i < nv; ++i) rr += c->h_red[i];
+    rel = sqrt(rr / ff);
     if (rel <= rtol) break;
     hipEventSynchronize(c->ev[5]);
     if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) acc_pre += ms;
     if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) acc_coarse += ms;
+    if (hipEventElapsedTime(&ms, c->ev[4], c->ev[8]) == hipSuccess) acc_cf += ms;
+    if (hipEventElapsedTime(&ms, c->ev[8], c->ev[5]) == hipSuccess) acc_cb += ms;
     napp++;
   }
   e = hipStreamSynchronize(c->stream);
@@ -423,6 +504,8 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   if (t_op) *t_op += acc_op;
   if (t_pre) *t_pre += acc_pre;
   if (t_coarse) *t_coarse += acc_coarse;
+  if (t_cfwd) *t_cfwd += acc_cf;
+  if (t_cbwd) *t_cbwd += acc_cb;
   if (n_apply) *n_apply += napp;
   return e;
 }
