@@ -80,6 +80,28 @@ def kernel_bytes(prob, roms, nC):
     return out
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter record (profiles/lattice128_p8_hbm_traffic.md), or None when there is
+    no record for it or its source file has changed since the counters were taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "lattice128_p8_hbm_traffic.md")
+    try:
+        for line in open(path):
+            if line.startswith("traffic-record:"):
+                rec = json.loads(line.split(":", 1)[1])
+                if rec["kernel"] != kernel:
+                    return None
+                src = open(os.path.join(root, rec["source"]), "rb").read()
+                if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+                    return None
+                return (rec["fetch_bytes_per_solve"] + rec["write_bytes_per_solve"]) / rec["launches_per_solve"]
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
 def cpu_baseline(prob_full, roms, solver):
     """The CPU oracle on a bounded sample of the same workload: the 12 x 12
     sub-lattice drawn with the same recipe (the oracle's online phase: ROM
@@ -134,6 +156,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--quick", action="store_true",
+                    help="one mixed-precision step at rtol 1e-8 only (no calibration, no FP64 or FP32-contraction "
+                         "legs): for counter runs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first copy a device buffer of this many MiB (a plain copy of known size that scales "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -145,6 +173,15 @@ def main():
         sys.exit(1)
     from workloads import make_problem
     from paper_2604_09113_amd import lbddc
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read, {args.copy_probe_mib} MiB written")
+        del src, dst
     prob = make_problem(args.config)
     ncell = prob["nx"] * prob["ny"]
     log(f"[bench] workload {prob['nx']}x{prob['ny']} p={prob['p']} m={prob['m']} cells={ncell}")
@@ -159,6 +196,16 @@ def main():
     log(f"[bench] N={s.query(lbddc.Q_NDOF_FREE)} N_U={s.query(lbddc.Q_N_SKELETON)} N_C={s.query(lbddc.Q_N_COARSE)} "
         f"device MB={s.query(lbddc.Q_DEVICE_BYTES) / 1e6:.0f}")
 
+    if args.quick:
+        for _ in range(args.warmup + args.steps):
+            s.assemble(lbddc.FP64)
+            s.setup(lbddc.MIXED)
+            inf = s.solve(rtol=1e-8, max_iter=3000)
+            s.compliance_gradient()
+        torch.cuda.synchronize()
+        log(f"[bench] quick: mixed step, {inf[0]['iters']} iterations, phases {json.dumps(s.phase_times())}")
+        s.close()
+        return
     # reference: FP64 path converged hard (untimed calibration)
     s.assemble(lbddc.FP64)
     s.setup(lbddc.FP64)
@@ -267,7 +314,7 @@ def main():
         roof["launches_per_solve"] = levels
         roof["note"] = ("per-launch average = event-timed sweep of the back-to-back level launches / levels; "
                         "algorithmic bytes per launch = sweep bytes / levels")
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
     value = ncell / (mixed["ms_per_step"] * 1e-3)
     out = {
         "metric": METRIC, "value": value, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
