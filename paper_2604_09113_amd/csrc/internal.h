@@ -86,8 +86,17 @@ struct NDItem {
   long long foff;
   int ns, nb, own_off, bnd_off, up_off, first;
   int child_up_off[2], child_nb[2], cmap_off[2];
+  int kpart, kparts;     // forward: this item's own-row part and the node's number of parts
+  int child_kparts[2];
   int pad[2];
 };
+
+// Forward items of nodes on levels with fewer than ND_SPLIT_NODES nodes split
+// the own rows into parts of ND_KPART rows, and backward items of those levels
+// take 4 rows each, so the few large fronts of the upper tree levels are spread
+// over more workgroups.
+constexpr int ND_SPLIT_NODES = 64;
+constexpr int ND_KPART = 64;
 
 struct CoarseLayout {
   std::vector<int> sb_off, sb_size;   // coarse numbering by grid lines (offset, size)
@@ -107,6 +116,7 @@ struct CoarseLayout {
   std::vector<int> lvl_nodes;
   std::vector<int> fw_off, bw_off, lvl_off;
   std::vector<int> lvl_nfmax, lvl_nsmax;  // largest front and own-block size per level
+  std::vector<int> lvl_bw_rows;           // own rows per backward item on each level (4 or ND_BW_ROWS)
 };
 
 

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ n
     __syncthreads();
   }
   bool bad = false;
+  constexpr int NJ = (NF + 63) / 64;  // row chunks of 64 columns
   for (int l = 0; l < d.ns; ++l) {
     for (int j = threadIdx.x; j < nf; j += 256) {
       rowl[j] = S[l * ld + j];
@@ -105,17 +106,27 @@ __global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ n
     double piv = rowl[l];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
     const double pinv = 1.0 / piv;
-    // every candidate is formed and one is selected: no per-element branch
+    double rv[NJ];  // this lane's columns of the pivot row
+#pragma unroll
+    for (int c = 0; c < NJ; ++c) rv[c] = lane + 64 * c < nf ? rowl[lane + 64 * c] : 0.0;
     for (int i = wave; i < nf; i += 4) {
-      const double ci = coll[i] * pinv;
-      const bool prow = i == l;
-      for (int j = lane; j < nf; j += 64) {
-        const double s = S[i * ld + j], r = rowl[j];
-        const bool pcol = j == l;
-        const double vrow = pcol ? pinv : r * pinv;
-        const double vcol = -ci;
-        const double vgen = s - ci * r;
-        S[i * ld + j] = prow ? vrow : (pcol ? vcol : vgen);
+      double* srow = S + i * ld;
+      if (i == l) {  // pivot row (wave-uniform): scaled by 1/p, 1/p on the diagonal
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) {
+          const int j = lane + 64 * c;
+          if (j < nf) srow[j] = j == l ? pinv : rv[c] * pinv;
+        }
+      } else {  // other rows: s - (c_i / p) r_j, and -c_i / p in the pivot column
+        const double ci = coll[i] * pinv;
+        double sv[NJ];
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) sv[c] = lane + 64 * c < nf ? srow[lane + 64 * c] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NJ; ++c) {
+          const int j = lane + 64 * c;
+          if (j < nf) srow[j] = j == l ? -ci : sv[c] - ci * rv[c];
+        }
       }
     }
     __syncthreads();
@@ -174,18 +185,27 @@ __global__ __launch_bounds__(256) void k_lv_diag(const NDNodeH* __restrict__ nod
     for (int a = 0; a < 4; ++a) cs[a] = colb[buf][tr + 16 * a] * pinv;
 #pragma unroll
     for (int b = 0; b < 4; ++b) rr[b] = rowb[buf][tc + 16 * b];
-    // every candidate is formed and one is selected: no per-element branch
+    // 1. every element: v - (c_i / p) r_j, with the pivot row left unchanged
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+      const double ca = tr + 16 * a == l ? 0.0 : cs[a];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const bool prow = tr + 16 * a == l, pcol = tc + 16 * b == l;
-        const double v = B[a][b];
-        const double vrow = pcol ? pinv : v * pinv;
-        const double vcol = -v * pinv;
-        const double vgen = v - cs[a] * rr[b];
-        B[a][b] = prow ? vrow : (pcol ? vcol : vgen);
-      }
+      for (int b = 0; b < 4; ++b) B[a][b] -= ca * rr[b];
+    }
+    // 2. pivot row r_j / p (1 / p on the diagonal) and pivot column -c_i / p,
+    //    held by the threads with tr == l % 16 and tc == l % 16; l / 16 is uniform
+#define GJ_FIX(A_)                                                            \
+  case A_:                                                                    \
+    if (tr == lb) {                                                           \
+      _Pragma("unroll") for (int b = 0; b < 4; ++b) B[A_][b] = rr[b] * pinv;  \
+    }                                                                         \
+    if (tc == lb) {                                                           \
+      _Pragma("unroll") for (int a = 0; a < 4; ++a) B[a][A_] = -cs[a];        \
+    }                                                                         \
+    if (tr == lb && tc == lb) B[A_][A_] = pinv;                               \
+    break;
+    switch (la) { GJ_FIX(0) GJ_FIX(1) GJ_FIX(2) GJ_FIX(3) }
+#undef GJ_FIX
     buf ^= 1;
   }
   if (bad) atomicOr(flags, 32);
@@ -390,12 +410,13 @@ hipError_t launch_coarse_factor(Ctx* c) {
 // (row-major, row stride nf); the lower rows are not needed once the parent
 // has taken U.
 
-// Forward item (node, first boundary column r0):
+// Forward item (node, first boundary column r0, own-row part kp):
 //   b_eff = b_s + (children's contributions to the own dofs),
-//   up[r] = w_b[r] - sum_k b_eff[k] M^T[k][r]   for r in [r0, r0 + 64)
-// lane = column r (coalesced rows of M^T), the four waves interleave the rows k
-// and their partial sums are added in a fixed order.  The first 32 rows of M^T
-// are requested before the right-hand side is gathered, so the loads overlap.
+//   part_kp[r] = [kp == 0] w_b[r] - sum_{k in part kp} b_eff[k] M^T[k][r]
+// for r in [r0, r0 + 64); the node's up vector is the sum of its parts, added
+// in order by the parent.  Lane = column r (coalesced rows of M^T), the four
+// waves interleave the rows and their partial sums are added in a fixed order.
+// The first 32 rows are requested before the right-hand side is gathered.
 // LDS: nf + 256 doubles.
 __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int* __restrict__ cmap,
                                                 const double* __restrict__ F, const double* __restrict__ b,
@@ -404,47 +425,64 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
   const NDItem d = items[blockIdx.x];
   const int nf = d.ns + d.nb, t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6, r = d.first + lane;
+  const int kb = d.kparts > 1 ? d.kpart * ND_KPART : 0;
+  const int ke = d.kparts > 1 ? min(d.ns, kb + ND_KPART) : d.ns;
   const bool col_ok = r < d.nb;
   const double* col = F + d.foff + d.ns + (col_ok ? r : 0);
   const long long st = 4LL * nf;
   double a[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) a[u] = (col_ok && wv + 4 * u < d.ns) ? col[(long long)(wv + 4 * u) * nf] : 0.0;
+  for (int u = 0; u < 8; ++u) {
+    const int k = kb + wv + 4 * u;
+    a[u] = (col_ok && k < ke) ? col[(long long)k * nf] : 0.0;
+  }
   double* w = sh;        // [nf]: b_eff on the own positions, w_b on the boundary positions
   double* pr = sh + nf;  // [4][64] wave partials
   for (int i = t; i < nf; i += 256) w[i] = i < d.ns ? b[d.own_off + i] : 0.0;
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
     const int* map = cmap + d.cmap_off[s];
-    for (int i = t; i < d.child_nb[s]; i += 256) w[map[i]] += up[d.child_up_off[s] + i];
+    const int cnb = d.child_nb[s];
+    const double* cup = up + d.child_up_off[s];
+    for (int i = t; i < cnb; i += 256) {
+      double v = cup[i];
+      for (int kp = 1; kp < d.child_kparts[s]; ++kp) v += cup[kp * cnb + i];
+      w[map[i]] += v;
+    }
     __syncthreads();
   }
-  if (d.first == 0)
+  if (d.first == 0 && d.kpart == 0)
     for (int i = t; i < d.ns; i += 256) beff[d.own_off + i] = w[i];
   double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) s += a[u] * (wv + 4 * u < d.ns ? w[wv + 4 * u] : 0.0);
+  for (int u = 0; u < 8; ++u) {
+    const int k = kb + wv + 4 * u;
+    s += a[u] * (k < ke ? w[k] : 0.0);
+  }
   if (col_ok) {
-    int k = wv + 32;
-    for (; k + 28 < d.ns; k += 32) {
+    int k = kb + wv + 32;
+    for (; k + 28 < ke; k += 32) {
       const double* c0 = col + (long long)k * nf;
 #pragma unroll
       for (int u = 0; u < 8; ++u) a[u] = c0[u * st];
 #pragma unroll
       for (int u = 0; u < 8; ++u) s += a[u] * w[k + 4 * u];
     }
-    for (; k < d.ns; k += 4) s += col[(long long)k * nf] * w[k];
+    for (; k < ke; k += 4) s += col[(long long)k * nf] * w[k];
   }
   pr[wv * 64 + lane] = s;
   __syncthreads();
-  if (wv == 0 && col_ok)
-    up[d.up_off + r] = w[d.ns + r] - (((pr[lane] + pr[64 + lane]) + pr[128 + lane]) + pr[192 + lane]);
+  if (wv == 0 && col_ok) {
+    const double tot = ((pr[lane] + pr[64 + lane]) + pr[128 + lane]) + pr[192 + lane];
+    up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w[d.ns + r] : 0.0) - tot;
+  }
 }
 
-// Backward item (node, first own row k0): rows [k0, k0 + ND_BW_ROWS) of
+// Backward item (node, first own row k0): rows [k0, k0 + 4Q) of
 // g_s = [F_ss^-1 | M^T] [b_eff; -g_b]; wave wv takes rows k0 + wv + 4q, lanes
 // run along the row, a butterfly sums each row.  The first 64 columns of the
 // rows are requested before the vector is gathered.  LDS: nf doubles.
+template <int Q>
 __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items, const int* __restrict__ bnd,
                                                 const double* __restrict__ F, const double* __restrict__ beff,
                                                 double* __restrict__ x) {
@@ -452,7 +490,6 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
   const NDItem d = items[blockIdx.x];
   const int nf = d.ns + d.nb;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  constexpr int Q = ND_BW_ROWS / 4;
   const double* rows[Q];
   bool ok[Q];
   double a[Q];
@@ -488,7 +525,8 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
-  // LDS sized per level, so the many small fronts of the lower levels all fit on the chip
+  // LDS sized per level, so the many small fronts of the lower levels all fit on the chip;
+  // the upper levels' items were split when the work lists were built
   for (int l = L - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
     const size_t lds = (size_t)(co.lvl_nfmax[l] + 256) * sizeof(double);
@@ -500,9 +538,13 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
   for (int l = 0; l < L; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
     const size_t lds = (size_t)std::max(1, co.lvl_nfmax[l]) * sizeof(double);
-    if (ni > 0)
-      hipLaunchKernelGGL(k_nd_bwd, dim3(ni), dim3(256), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd,
+    if (ni == 0) continue;
+    if (co.lvl_bw_rows[l] == 4)
+      hipLaunchKernelGGL(k_nd_bwd<1>, dim3(ni), dim3(256), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd,
                          c->d_coarse, c->d_beff, x);
+    else
+      hipLaunchKernelGGL(k_nd_bwd<ND_BW_ROWS / 4>, dim3(ni), dim3(256), lds, c->stream, c->d_bw_items + i0,
+                         c->d_nd_bnd, c->d_coarse, c->d_beff, x);
   }
   return hipGetLastError();
 }

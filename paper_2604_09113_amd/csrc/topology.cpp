@@ -165,12 +165,30 @@ bool build_topology(Ctx* c) {
     owners(c->RC, c->NC, cptr, cown);
   }
   // solve work lists: forward items = 64-column chunks of the boundary (at
-  // least one per node), backward items = ND_BW_ROWS own rows
+  // least one per node) x own-row parts, backward items = runs of own rows.
+  // The forward result of a node is stored as kparts partial vectors of nb
+  // entries (kp-major), which the parent adds in a fixed order.
+  const int L = (int)co.nd_levels.size();
+  std::vector<int> kparts(co.nd_nodes.size(), 1);
+  for (int l = 0; l < L; ++l)
+    if ((int)co.nd_levels[l].size() < ND_SPLIT_NODES)
+      for (int n : co.nd_levels[l]) kparts[n] = std::max(1, (co.nd_nodes[n].ns + ND_KPART - 1) / ND_KPART);
+  {
+    int uoff = 0;
+    for (size_t n = 0; n < co.nd_nodes.size(); ++n) {
+      co.nd_nodes[n].up_off = uoff;
+      uoff += kparts[n] * co.nd_nodes[n].nb;
+    }
+    co.nd_up_total = uoff;
+  }
   co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear();
   co.fw_off.assign(1, 0); co.bw_off.assign(1, 0); co.lvl_off.assign(1, 0);
-  co.lvl_nfmax.assign(co.nd_levels.size(), 0);
-  co.lvl_nsmax.assign(co.nd_levels.size(), 0);
-  for (size_t l = 0; l < co.nd_levels.size(); ++l) {
+  co.lvl_nfmax.assign(L, 0);
+  co.lvl_nsmax.assign(L, 0);
+  co.lvl_bw_rows.assign(L, ND_BW_ROWS);
+  for (int l = 0; l < L; ++l) {
+    const bool split = (int)co.nd_levels[l].size() < ND_SPLIT_NODES;
+    co.lvl_bw_rows[l] = split ? 4 : ND_BW_ROWS;
     for (int n : co.nd_levels[l]) {
       const NDNodeH& d = co.nd_nodes[n];
       co.lvl_nfmax[l] = std::max(co.lvl_nfmax[l], d.ns + d.nb);
@@ -182,17 +200,22 @@ bool build_topology(Ctx* c) {
       it.own_off = d.own_off;
       it.bnd_off = d.bnd_off;
       it.up_off = d.up_off;
+      it.kparts = kparts[n];
       for (int s = 0; s < 2; ++s) {
         const int ch = d.child[s];
         it.child_up_off[s] = ch >= 0 ? co.nd_nodes[ch].up_off : 0;
         it.child_nb[s] = ch >= 0 ? co.nd_nodes[ch].nb : 0;
+        it.child_kparts[s] = ch >= 0 ? kparts[ch] : 0;
         it.cmap_off[s] = ch >= 0 ? d.cmap_off[s] : 0;
       }
-      for (int r = 0; r < std::max(1, d.nb); r += 64) {
-        it.first = r;
-        co.fw_items.push_back(it);
-      }
-      for (int r = 0; r < std::max(1, d.ns); r += ND_BW_ROWS) {
+      for (int kp = 0; kp < kparts[n]; ++kp)
+        for (int r = 0; r < std::max(1, d.nb); r += 64) {
+          it.first = r;
+          it.kpart = kp;
+          co.fw_items.push_back(it);
+        }
+      it.kpart = 0;
+      for (int r = 0; r < std::max(1, d.ns); r += co.lvl_bw_rows[l]) {
         it.first = r;
         co.bw_items.push_back(it);
       }
