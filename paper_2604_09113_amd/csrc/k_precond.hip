@@ -9,7 +9,9 @@
 //   P = Shat^-1 - X That^-1 X^T,
 // stored D-scaled (D_E P D_E) so that each PCG iteration applies the fine
 // correction of Alg. 1 as one packed symmetric matrix-vector product instead of
-// three dependent triangular solves.
+// three dependent triangular solves.  Shat^-1 and That^-1 are formed by in-place
+// Gauss-Jordan sweeps (both are SPD: no pivoting), whose pivot steps update
+// every entry in parallel; the other steps are small matrix products.
 //
 // The coarse basis (Eq. of the local coarse problems) solves the same saddle
 // problem with right-hand side [0; e_j].  For an edge constraint j that is
@@ -26,32 +28,63 @@
 
 namespace lbddc {
 
+// In-place Gauss-Jordan inverse of the SPD n x n block A (row stride LDA) by
+// the 256 threads of the workgroup: rows go to the waves, columns to the lanes
+// (n <= 64); colp is a length-n scratch.  Sets *bad on a non-positive pivot.
+template <typename T, int LDA>
+__device__ void gj_inverse(T* A, int n, T* colp, int* bad) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int l = 0; l < n; ++l) {
+    if (threadIdx.x < n) colp[threadIdx.x] = A[threadIdx.x * LDA + l];
+    __syncthreads();
+    T piv = colp[l];
+    if (!(piv > (T)0)) { if (threadIdx.x == 0) *bad = 1; piv = (T)1; }
+    const T pinv = (T)1 / piv;
+    const T rl = lane < n ? A[l * LDA + lane] : (T)0;  // pivot row, read before any write below
+    __syncthreads();
+    for (int i = wave; i < n; i += 4) {
+      if (lane >= n) continue;
+      T* a = A + i * LDA + lane;
+      if (i == l) {
+        *a = lane == l ? pinv : rl * pinv;
+      } else {
+        const T ci = colp[i] * pinv;
+        *a = lane == l ? -ci : *a - ci * rl;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, int P, int NCE>
 __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, const double* __restrict__ cons,
                                                  const double* __restrict__ diagK, const double* __restrict__ Ktot,
                                                  const int* __restrict__ RU, int nx, T* __restrict__ Pout,
                                                  T* __restrict__ Psiout, double* __restrict__ Dout,
                                                  double* __restrict__ ScOut, int* __restrict__ flags) {
-  constexpr int NU = 8 * P, NE = NU - 8, NCC = 4 * NCE, NC = 8 + NCC, NR = NE + NCC;
+  constexpr int NU = 8 * P, NE = NU - 8, NCC = 4 * NCE, NC = 8 + NCC;
   constexpr int NSP = NU * (NU + 1) / 2;
+  static_assert(NU <= 64, "one row per lane");
   const int cell = blockIdx.x, tid = threadIdx.x;
   const bool left = (cell % nx) == 0;
-  __shared__ T Sh[NE][NE + 1];
-  __shared__ T Z[NE][NR + 1];
+  __shared__ T A[NE][NE + 1];     // Shat, then Shat^-1, then P
+  __shared__ T X[NE][NCC + 1];    // Shat^-1 Chat^T
+  __shared__ T W2[NE][NCC + 1];   // X That^-1
   __shared__ T Ch[NCC][NE];
   __shared__ T Cc[NCC][8];
-  __shared__ T Tm[NCC][NCC];
-  __shared__ T W2[NE][NCC];
+  __shared__ T Tm[NCC][NCC + 1];  // That, then That^-1
   __shared__ T Scol[NE][8];
+  __shared__ T colp[NE];
   __shared__ double Dv[NU];
-  __shared__ double SPsi[NU * NC];
+  __shared__ double Ps[NU][NC + 1];   // coarse basis (unscaled)
+  __shared__ double SPs[NU][NC + 1];  // S Psi
   __shared__ int bad;
   const double* S = Sg + (size_t)cell * NSP;
   if (tid == 0) bad = 0;
   for (int idx = tid; idx < NE * NE; idx += 256) {
     int i = idx / NE, j = idx % NE, I = 8 + i, J = 8 + j;
     int hi = I > J ? I : J, lo = I > J ? J : I;
-    Sh[i][j] = (T)S[hi * (hi + 1) / 2 + lo];
+    A[i][j] = (T)S[hi * (hi + 1) / 2 + lo];
   }
   for (int idx = tid; idx < NE * 8; idx += 256) {
     int i = idx / 8, j = idx % 8, I = 8 + i;
@@ -80,166 +113,90 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
     }
   }
   __syncthreads();
-  // Cholesky of Shat (right-looking, unscaled trailing update, one barrier per column)
-  for (int k = 0; k < NE; ++k) {
-    const T akk = Sh[k][k];
-    if (tid == 0 && !(akk > (T)0)) bad = 1;
-    const T inv = (T)1 / akk;
-    for (int idx = tid; idx < NE * NE; idx += 256) {
-      int i = idx / NE, j = idx % NE;
-      if (j > k && i >= j) Sh[i][j] -= Sh[i][k] * Sh[j][k] * inv;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < NE * NE; idx += 256) {
-    int i = idx / NE, k = idx % NE;
-    if (i > k) Sh[i][k] = Sh[i][k] / sqrt(Sh[k][k]);
-  }
-  __syncthreads();
-  if (tid < NE) Sh[tid][tid] = sqrt(Sh[tid][tid]);
-  // right-hand sides [I | Chat^T]
-  for (int idx = tid; idx < NE * NR; idx += 256) {
-    int i = idx / NR, j = idx % NR;
-    Z[i][j] = j < NE ? (T)(i == j ? 1 : 0) : Ch[j - NE][i];
-  }
-  __syncthreads();
-  // one thread per right-hand side: forward and backward substitution
-  if (tid < NR) {
-    const int j = tid;
-    for (int k = 0; k < NE; ++k) {
-      T zk = Z[k][j] / Sh[k][k];
-      Z[k][j] = zk;
-      for (int i = k + 1; i < NE; ++i) Z[i][j] -= Sh[i][k] * zk;
-    }
-    for (int k = NE - 1; k >= 0; --k) {
-      T zk = Z[k][j];
-      for (int i = k + 1; i < NE; ++i) zk -= Sh[i][k] * Z[i][j];
-      Z[k][j] = zk / Sh[k][k];
-    }
-  }
-  __syncthreads();
-  // That = Chat X, masked rows get a unit diagonal (they carry no constraint)
-  for (int idx = tid; idx < NCC * NCC; idx += 256) {
-    int a = idx / NCC, b = idx % NCC;
+  // Shat^-1 in place
+  gj_inverse<T, NE + 1>(&A[0][0], NE, colp, &bad);
+  // X = Shat^-1 Chat^T
+  for (int idx = tid; idx < NE * NCC; idx += 256) {
+    const int i = idx / NCC, a = idx % NCC;
     T s = 0;
-    for (int i = 0; i < NE; ++i) s += Ch[a][i] * Z[i][NE + b];
+    for (int k = 0; k < NE; ++k) s += A[i][k] * Ch[a][k];
+    X[i][a] = s;
+  }
+  __syncthreads();
+  // That = Chat X; the clamped edge's rows carry no constraint and get a unit diagonal
+  for (int idx = tid; idx < NCC * NCC; idx += 256) {
+    const int a = idx / NCC, b = idx % NCC;
+    T s = 0;
+    for (int i = 0; i < NE; ++i) s += Ch[a][i] * X[i][b];
     if (left && a == b && a < NCE) s = (T)1;
     Tm[a][b] = s;
   }
   __syncthreads();
-  if (tid == 0) {  // small dense Cholesky of That
-    for (int k = 0; k < NCC; ++k) {
-      T d = Tm[k][k];
-      for (int l = 0; l < k; ++l) d -= Tm[k][l] * Tm[k][l];
-      if (!(d > (T)0)) { bad = 1; d = (T)1; }
-      d = sqrt(d);
-      Tm[k][k] = d;
-      for (int i = k + 1; i < NCC; ++i) {
-        T s = Tm[i][k];
-        for (int l = 0; l < k; ++l) s -= Tm[i][l] * Tm[k][l];
-        Tm[i][k] = s / d;
-      }
-    }
+  gj_inverse<T, NCC + 1>(&Tm[0][0], NCC, colp, &bad);
+  // W2 = X That^-1
+  for (int idx = tid; idx < NE * NCC; idx += 256) {
+    const int i = idx / NCC, a = idx % NCC;
+    T s = 0;
+    for (int b = 0; b < NCC; ++b) s += X[i][b] * Tm[b][a];
+    W2[i][a] = s;
   }
   __syncthreads();
-  // W2 = X That^-1 (row i solves That w = X[i,:]^T)
-  if (tid < NE) {
-    const int i = tid;
-    T w[NCC];
-    for (int a = 0; a < NCC; ++a) {
-      T s = Z[i][NE + a];
-      for (int l = 0; l < a; ++l) s -= Tm[a][l] * w[l];
-      w[a] = s / Tm[a][a];
-    }
-    for (int a = NCC - 1; a >= 0; --a) {
-      T s = w[a];
-      for (int l = a + 1; l < NCC; ++l) s -= Tm[l][a] * w[l];
-      w[a] = s / Tm[a][a];
-    }
-    for (int a = 0; a < NCC; ++a) W2[i][a] = w[a];
-  }
-  __syncthreads();
-  // P = Shat^-1 - W2 X^T (in place in the first NE columns of Z)
+  // P = Shat^-1 - W2 X^T (in place)
   for (int idx = tid; idx < NE * NE; idx += 256) {
-    int i = idx / NE, j = idx % NE;
-    T s = Z[i][j];
-    for (int a = 0; a < NCC; ++a) s -= W2[i][a] * Z[j][NE + a];
-    Sh[i][j] = s;  // Sh is free after the solves; hold P there
+    const int i = idx / NE, j = idx % NE;
+    T s = A[i][j];
+    for (int a = 0; a < NCC; ++a) s -= W2[i][a] * X[j][a];
+    A[i][j] = s;
   }
   __syncthreads();
   // store D_E P D_E packed lower
   T* Pc = Pout + (size_t)cell * (NE * (NE + 1) / 2);
-  for (int idx = tid; idx < NE * (NE + 1) / 2; idx += 256) {
-    int i = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= idx) ++i;
-    while (i * (i + 1) / 2 > idx) --i;
-    int j = idx - i * (i + 1) / 2;
-    Pc[idx] = (T)(Dv[8 + i] * (double)Sh[i][j] * Dv[8 + j]);
-  }
-  // coarse basis Psi (NU x NC), kept in Z[0..NU) rows? Z has NE rows: store edge part in Z, corners implicit
-  __syncthreads();
-  for (int idx = tid; idx < NE * NC; idx += 256) {
-    int i = idx / NC, j = idx % NC;
-    T v;
-    if (j < 8) {
+  for (int i = tid >> 6; i < NE; i += 4)
+    for (int j = tid & 63; j <= i; j += 64)
+      Pc[i * (i + 1) / 2 + j] = (T)(Dv[8 + i] * (double)A[i][j] * Dv[8 + j]);
+  // coarse basis Psi [NU][NC]: corner rows are the identity (masked on the
+  // clamped side); edge rows: corner columns -P S[E, c] - W2 C[:, c], edge
+  // constraint columns W2
+  for (int idx = tid; idx < NU * NC; idx += 256) {
+    const int i = idx / NC, j = idx % NC;
+    const bool cmask = left && (j == 0 || j == 1 || j == 4 || j == 5);
+    double v;
+    if (i < 8) {
+      v = (i == j && !cmask) ? 1.0 : 0.0;
+    } else if (j < 8) {
       T s = 0;
-      for (int k = 0; k < NE; ++k) s -= Sh[i][k] * Scol[k][j];
-      for (int a = 0; a < NCC; ++a) s -= W2[i][a] * Cc[a][j];
-      v = s;
+      for (int k2 = 0; k2 < NE; ++k2) s -= A[i - 8][k2] * Scol[k2][j];
+      for (int a = 0; a < NCC; ++a) s -= W2[i - 8][a] * Cc[a][j];
+      v = cmask ? 0.0 : (double)s;
     } else {
-      v = W2[i][j - 8];
+      const bool emask = left && j < 8 + NCE;
+      v = emask ? 0.0 : (double)W2[i - 8][j - 8];
     }
-    bool masked = left && (j == 0 || j == 1 || j == 4 || j == 5 || (j >= 8 && j < 8 + NCE));
-    Z[i][j] = masked ? (T)0 : v;
+    Ps[i][j] = v;
   }
   __syncthreads();
   T* Pso = Psiout + (size_t)cell * NU * NC;
   for (int idx = tid; idx < NU * NC; idx += 256) {
-    int i = idx / NC, j = idx % NC;
-    double v;
-    if (i < 8) {
-      bool masked = left && (j == 0 || j == 1 || j == 4 || j == 5);
-      v = (i == j && !masked) ? 1.0 : 0.0;
-    } else {
-      v = (double)Z[i - 8][j];
-    }
-    Pso[idx] = (T)(Dv[i] * v);
+    const int i = idx / NC, j = idx % NC;
+    Pso[idx] = (T)(Dv[i] * Ps[i][j]);
   }
   for (int j = tid; j < NU; j += 256) Dout[(size_t)cell * NU + j] = Dv[j];
-  // S Psi in FP64 into W2-sized scratch: reuse Sh (P no longer needed)
-  __syncthreads();
+  // S Psi in FP64 (S packed lower, read through the cache), then Psi^T S Psi
   for (int idx = tid; idx < NU * NC; idx += 256) {
-    int i = idx / NC, j = idx % NC;
+    const int i = idx / NC, j = idx % NC;
+    const int ri = i * (i + 1) / 2;
     double s = 0.0;
-    for (int k = 0; k < NU; ++k) {
-      int hi = i > k ? i : k, lo = i > k ? k : i;
-      double psi;
-      if (k < 8) {
-        bool masked = left && (j == 0 || j == 1 || j == 4 || j == 5);
-        psi = (k == j && !masked) ? 1.0 : 0.0;
-      } else {
-        psi = (double)Z[k - 8][j];
-      }
-      s += S[hi * (hi + 1) / 2 + lo] * psi;
-    }
-    SPsi[idx] = s;
+    for (int k2 = 0; k2 <= i; ++k2) s += S[ri + k2] * Ps[k2][j];
+    for (int k2 = i + 1; k2 < NU; ++k2) s += S[k2 * (k2 + 1) / 2 + i] * Ps[k2][j];
+    SPs[i][j] = s;
   }
   __syncthreads();
   double* Sc = ScOut + (size_t)cell * (NC * (NC + 1) / 2);
   for (int idx = tid; idx < NC * NC; idx += 256) {
-    int a = idx / NC, b = idx % NC;
+    const int a = idx / NC, b = idx % NC;
     if (b > a) continue;
     double s = 0.0;
-    for (int k = 0; k < NU; ++k) {
-      double psi;
-      if (k < 8) {
-        bool masked = left && (a == 0 || a == 1 || a == 4 || a == 5);
-        psi = (k == a && !masked) ? 1.0 : 0.0;
-      } else {
-        psi = (double)Z[k - 8][a];
-      }
-      s += psi * SPsi[k * NC + b];
-    }
+    for (int k2 = 0; k2 < NU; ++k2) s += Ps[k2][a] * SPs[k2][b];
     Sc[a * (a + 1) / 2 + b] = s;
   }
   if (tid == 0 && bad) atomicOr(flags, 16);
