@@ -197,6 +197,7 @@ def main():
         f"device MB={s.query(lbddc.Q_DEVICE_BYTES) / 1e6:.0f}")
 
     if args.quick:
+        s.assemble(lbddc.FP32_CONTRACTION)  # the FP32 MFMA contraction variant, once
         for _ in range(args.warmup + args.steps):
             s.assemble(lbddc.FP64)
             s.setup(lbddc.MIXED)
