@@ -326,7 +326,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
             dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
             dalloc_t(c, &c->d_zc, NC) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC) &&
-            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 16)) && dalloc_t(c, &c->d_scal, 32) &&
+            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 272)) && dalloc_t(c, &c->d_scal, 32) &&
             dalloc_t(c, &c->d_vred, (size_t)3 * (NU / 256 + 16)) &&
             dalloc_t(c, &c->d_u, (size_t)c->nrhs * c->Gx * c->Gy * 2) &&
             dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&

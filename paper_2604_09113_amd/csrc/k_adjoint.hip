@@ -104,15 +104,18 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
           else hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc[rb], 0, 0, 0);
         }
       }
+      // this lane's 4 pairs' contributions to the 4 components e; the 16-lane
+      // groups then reduce-scatter so that group grp holds the total of e = grp:
+      // across 32 lanes each lane keeps the half of e its group ends in, then
+      // across 16 lanes the one component
       double g[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        double t = uu[0][e] * d[0] + uu[1][e] * d[1] + uu[2][e] * d[2] + uu[3][e] * d[3];
-        t += __shfl_xor(t, 16);
-        t += __shfl_xor(t, 32);
-        g[e] = t;
-      }
-      const double gm = grp == 0 ? g[0] : grp == 1 ? g[1] : grp == 2 ? g[2] : g[3];
+      for (int e = 0; e < 4; ++e) g[e] = uu[0][e] * d[0] + uu[1][e] * d[1] + uu[2][e] * d[2] + uu[3][e] * d[3];
+      const int hi = grp >> 1, lo = grp & 1;
+      const double k0 = hi ? g[2] : g[0], k1 = hi ? g[3] : g[1];
+      const double s0 = hi ? g[0] : g[2], s1 = hi ? g[1] : g[3];
+      const double x0 = k0 + __shfl_xor(s0, 32), x1 = k1 + __shfl_xor(s1, 32);
+      const double gm = (lo ? x1 : x0) + __shfl_xor(lo ? x0 : x1, 16);
       Gw[(col * ns + s) * 4 + grp] += gm;
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) a[kc] = an[kc];
@@ -293,11 +296,26 @@ __global__ void k_net_gather(const double* __restrict__ gcell, const int* __rest
   gnet[2 * i + 1] = a1;
 }
 
-// J = f . x over the skeleton (tractions act on skeleton dofs only), one block
-__global__ void k_compliance(const double* __restrict__ f, const double* __restrict__ x, int N, double* __restrict__ J) {
+// J = f . x over the skeleton (tractions act on skeleton dofs only): partial
+// sums per workgroup, then one workgroup adds them in order
+__global__ void k_compliance_part(const double* __restrict__ f, const double* __restrict__ x, int N,
+                                  double* __restrict__ part) {
   __shared__ double sh[256];
   double s = 0.0;
-  for (int i = threadIdx.x; i < N; i += 256) s += f[i] * x[i];
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256) s += f[i] * x[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_compliance(const double* __restrict__ part, int n, double* __restrict__ J) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -390,8 +408,10 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   const int nnet = c->netx * c->nety;
   hipLaunchKernelGGL(k_net_gather, dim3((nnet + 255) / 256), dim3(256), 0, c->stream, c->d_gcell, c->d_net_ptr,
                      c->d_net_own, c->d_gX + (size_t)rhs * nnet * 2, nnet);
-  hipLaunchKernelGGL(k_compliance, dim3(1), dim3(256), 0, c->stream, c->d_f + (size_t)rhs * c->NU,
-                     c->d_x + (size_t)rhs * c->NU, c->NU, c->d_J + rhs);
+  const int nparts = 256;
+  hipLaunchKernelGGL(k_compliance_part, dim3(nparts), dim3(256), 0, c->stream, c->d_f + (size_t)rhs * c->NU,
+                     c->d_x + (size_t)rhs * c->NU, c->NU, c->d_red);
+  hipLaunchKernelGGL(k_compliance, dim3(1), dim3(256), 0, c->stream, c->d_red, nparts, c->d_J + rhs);
   return hipGetLastError();
 }
 
