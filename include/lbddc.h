@@ -220,6 +220,17 @@ lbddc_status lbddc_export_cells(lbddc_ctx* ctx, int32_t which, int32_t first, in
  * `n` entries are written (n <= 14). */
 lbddc_status lbddc_phase_times(lbddc_ctx* ctx, double* ms, int32_t n);
 
+/* PCG phases timed by lbddc_solve (bit mask; LBDDC_TIME_ALL after create):
+ * LBDDC_TIME_OP the operator kernel (phase_times [6]), LBDDC_TIME_PRE the
+ * preconditioner's local kernel ([7]), LBDDC_TIME_COARSE the coarse solve and
+ * its two sweeps ([8], [12], [13]).  Each timed phase records two or three
+ * events per PCG iteration, and an event leaves the device idle for a few
+ * microseconds between kernels; phases that are not timed report 0.  The
+ * assembly, setup, recovery and gradient phases are always timed (a few
+ * events per call).  Returns LBDDC_E_ARG for unknown bits. */
+enum { LBDDC_TIME_OP = 1, LBDDC_TIME_PRE = 2, LBDDC_TIME_COARSE = 4, LBDDC_TIME_ALL = 7 };
+lbddc_status lbddc_set_timing(lbddc_ctx* ctx, int32_t mask);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,9 @@ static void free_problem(Ctx* c) {
   fresh.own_stream = c->own_stream;
   fresh.roms = std::move(c->roms);
   for (int i = 0; i < Ctx::kNumEv; ++i) fresh.ev[i] = c->ev[i];
+  for (int i = 0; i < Ctx::kRing; ++i)
+    for (int k = 0; k < Ctx::kRingEv; ++k) fresh.pev[i][k] = c->pev[i][k];
+  fresh.timing = c->timing;
   fresh.h_flags = c->h_flags;
   fresh.h_scal = c->h_scal;
   fresh.err = c->err;
@@ -109,6 +112,9 @@ lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out) {
   }
   for (int i = 0; i < Ctx::kNumEv; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete x; return LBDDC_E_HIP; }
+  for (int i = 0; i < Ctx::kRing; ++i)
+    for (int k = 0; k < Ctx::kRingEv; ++k)
+      if (hipEventCreate(&c->pev[i][k]) != hipSuccess) { delete x; return LBDDC_E_HIP; }
   if (hipHostMalloc((void**)&c->h_flags, 128 * sizeof(int)) != hipSuccess ||
       hipHostMalloc((void**)&c->h_scal, 32 * sizeof(double)) != hipSuccess) {
     delete x;
@@ -132,6 +138,9 @@ void lbddc_destroy(lbddc_ctx* x) {
   }
   for (int i = 0; i < Ctx::kNumEv; ++i)
     if (c->ev[i]) hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < Ctx::kRing; ++i)
+    for (int k = 0; k < Ctx::kRingEv; ++k)
+      if (c->pev[i][k]) hipEventDestroy(c->pev[i][k]);
   if (c->h_flags) hipHostFree(c->h_flags);
   if (c->h_scal) hipHostFree(c->h_scal);
   if (c->h_red) hipHostFree(c->h_red);
@@ -505,6 +514,13 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
   c->solved = true;
   if (status != LBDDC_OK) c->err = "solve: PCG reached max_iter before rtol";
   return status;
+}
+
+lbddc_status lbddc_set_timing(lbddc_ctx* x, int32_t mask) {
+  if (!x) return LBDDC_E_ARG;
+  if (mask & ~LBDDC_TIME_ALL) return fail(&x->c, LBDDC_E_ARG, "set_timing: unknown phase bits");
+  x->c.timing = mask;
+  return LBDDC_OK;
 }
 
 lbddc_status lbddc_get_displacement(lbddc_ctx* x, int32_t rhs, double* u) {

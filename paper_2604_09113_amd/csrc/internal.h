@@ -85,16 +85,17 @@ struct NDNodeH {
 struct NDItem {
   long long foff;
   int ns, nb, own_off, bnd_off, up_off, first;
-  int child_up_off[2], child_nb[2], cmap_off[2];
+  int child_up_off[2], child_nb[2];
+  int pull_off;          // forward: the node's pull map (int2 per front position), -1 for a leaf
   int kpart, kparts;     // forward: this item's own-row part and the node's number of parts
   int child_kparts[2];
-  int pad[2];
+  int pad[3];
 };
 
-// Forward items of nodes on levels with fewer than ND_SPLIT_NODES nodes split
-// the own rows into parts of ND_KPART rows, and backward items of those levels
-// take 4 rows each, so the few large fronts of the upper tree levels are spread
-// over more workgroups.
+// Forward items split the own rows of every node into parts of ND_KPART rows
+// (one part per workgroup, 16 rows per wave).  Backward items of levels with
+// fewer than ND_SPLIT_NODES nodes take 4 rows each, so the few large fronts of
+// the upper tree levels are spread over more workgroups.
 constexpr int ND_SPLIT_NODES = 64;
 constexpr int ND_KPART = 64;
 
@@ -107,6 +108,10 @@ struct CoarseLayout {
   // nested dissection
   std::vector<NDNodeH> nd_nodes;
   std::vector<int> nd_own, nd_bnd, nd_cmap;  // own/boundary coarse ids per node (tree-order numbering)
+  // pull maps of the forward sweep: for each front position of a node with
+  // children, the index of that position in child 0's and child 1's boundary
+  // (-1 where the child does not touch it); the inverse of nd_cmap
+  std::vector<int> nd_pull;
   std::vector<std::vector<int>> nd_levels;   // node ids per depth (0 = root)
   long long nd_front_total = 0;
   int nd_up_total = 0, nd_beff_total = 0, nd_nfmax = 0, nd_nsmax = 0;
@@ -168,7 +173,7 @@ struct Ctx {
   int* d_net_own = nullptr;    // cell*(m+1)^2 + local control point
   int* d_cstart = nullptr; int* d_contrib = nullptr; long long* d_dest = nullptr;
   NDNodeH* d_nd_nodes = nullptr;
-  int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr;
+  int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr, *d_nd_pull = nullptr;
   NDItem *d_fw_items = nullptr, *d_bw_items = nullptr;
   int* d_lvl_nodes = nullptr;
   int* d_flags = nullptr;      // device error flags [8]
@@ -235,6 +240,13 @@ struct Ctx {
   double phase_ms[14] = {0};
   static constexpr int kNumEv = 9;
   hipEvent_t ev[kNumEv] = {};
+  // events of the timed PCG phases, a ring of kRing iterations read back at the
+  // end of the solve (no host wait inside the loop): per slot [0, 1] operator,
+  // [2, 3] preconditioner local kernel, [4, 5, 6] coarse solve start, between
+  // the sweeps, end
+  static constexpr int kRing = 8, kRingEv = 7;
+  hipEvent_t pev[kRing][kRingEv] = {};
+  int timing = LBDDC_TIME_ALL;  // PCG phases timed (LBDDC_TIME_* mask)
   size_t dev_bytes = 0;
   std::vector<void*> allocs;   // everything allocated for the problem
 };

@@ -410,109 +410,186 @@ hipError_t launch_coarse_factor(Ctx* c) {
 // (row-major, row stride nf); the lower rows are not needed once the parent
 // has taken U.
 
-// Forward item (node, first boundary column r0, own-row part kp):
-//   b_eff = b_s + (children's contributions to the own dofs),
-//   part_kp[r] = [kp == 0] w_b[r] - sum_{k in part kp} b_eff[k] M^T[k][r]
-// for r in [r0, r0 + 64); the node's up vector is the sum of its parts, added
-// in order by the parent.  Lane = column r (coalesced rows of M^T), the four
-// waves interleave the rows and their partial sums are added in a fixed order.
-// The first 32 rows are requested before the right-hand side is gathered.
-// LDS: nf + 256 doubles.
-__global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int* __restrict__ cmap,
+// Sum over a child's parts of entry i of its up vector, in part order, for
+// the two children at once.  i = -1: the child does not touch this front
+// position.  The loads of the first 8 parts of both children are made
+// unconditionally (a position that is not needed reads up[0]) so that all of
+// them are requested before the first add.
+__device__ __forceinline__ void pull_children(const NDItem& d, const double* __restrict__ up, int2 src,
+                                              double& c0, double& c1) {
+  const int n0 = src.x >= 0 ? d.child_kparts[0] : 0, n1 = src.y >= 0 ? d.child_kparts[1] : 0;
+  double t0[8], t1[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double l0 = up[u < n0 ? d.child_up_off[0] + u * d.child_nb[0] + src.x : 0];
+    t0[u] = u < n0 ? l0 : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double l1 = up[u < n1 ? d.child_up_off[1] + u * d.child_nb[1] + src.y : 0];
+    t1[u] = u < n1 ? l1 : 0.0;
+  }
+  c0 = 0.0;
+  c1 = 0.0;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) c0 += t0[u];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) c1 += t1[u];
+  for (int kp = 8; kp < n0; ++kp) c0 += up[d.child_up_off[0] + kp * d.child_nb[0] + src.x];
+  for (int kp = 8; kp < n1; ++kp) c1 += up[d.child_up_off[1] + kp * d.child_nb[1] + src.y];
+}
+
+// Forward item (node, boundary columns [r0, r0 + 64), own-row part kp = rows
+// [kb, ke), ke - kb <= 64):
+//   w_k = b_k + (children's contributions to own row k),          k in [kb, ke)
+//   w_b[r] = children's contributions to boundary position r,       (part 0)
+//   part_kp[r] = [kp == 0] w_b[r] - sum_{k in [kb, ke)} w_k M^T[k][r]
+// The node's up vector is the sum of its parts, added in order by the parent;
+// the children's contributions are pulled through the node's pull map, so an
+// item gathers only the 64 rows and 64 columns it uses.  Lane = column r
+// (coalesced rows of M^T), wave wv takes rows kb + wv + 4u, u < 16, all
+// requested before the right-hand side is gathered; the four wave partials
+// are added in a fixed order.  The items of column block 0 store b_eff of
+// their rows for the backward sweep.
+__global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int2* __restrict__ pull,
                                                 const double* __restrict__ F, const double* __restrict__ b,
                                                 double* __restrict__ up, double* __restrict__ beff) {
-  extern __shared__ double sh[];
+  __shared__ double w[128];  // [0, 64): w on rows kb.., [64, 128): w_b on columns r0..
+  __shared__ double pr[4][64];
   const NDItem d = items[blockIdx.x];
   const int nf = d.ns + d.nb, t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6, r = d.first + lane;
-  const int kb = d.kparts > 1 ? d.kpart * ND_KPART : 0;
-  const int ke = d.kparts > 1 ? min(d.ns, kb + ND_KPART) : d.ns;
+  const int kb = d.kpart * ND_KPART, ke = min(d.ns, kb + ND_KPART);
   const bool col_ok = r < d.nb;
-  const double* col = F + d.foff + d.ns + (col_ok ? r : 0);
-  const long long st = 4LL * nf;
-  double a[8];
+  // front position of threads t < 128: own row kb + t, or boundary column
+  // r0 + t - 64; positions that are not needed read index 0 and are discarded
+  const bool own = t < 64;
+  const bool ok = t < 128 && (own ? kb + t < ke : (d.kpart == 0 && d.first + (t - 64) < d.nb));
+  const int j = ok ? (own ? kb + t : d.ns + d.first + (t - 64)) : 0;
+  // the pull map and b ahead of M^T (the counter is in order); leaves and
+  // positions that are not needed read entry 0 of the maps (never empty)
+  const int2 srcl = pull[d.pull_off >= 0 && ok ? d.pull_off + j : 0];
+  const double bj = b[ok && own ? d.own_off + j : 0];
+  __builtin_amdgcn_sched_barrier(0);
+  // unconditional loads of M^T: rows past ke read row 0 and meet zeros of w,
+  // columns past nb read F[0] and are not stored (factor entries are finite)
+  const double* col = col_ok ? F + d.foff + d.ns + r : F;
+  double a[16];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
+  for (int u = 0; u < 16; ++u) {
     const int k = kb + wv + 4 * u;
-    a[u] = (col_ok && k < ke) ? col[(long long)k * nf] : 0.0;
+    a[u] = col[col_ok && k < ke ? (long long)k * nf : 0];
   }
-  double* w = sh;        // [nf]: b_eff on the own positions, w_b on the boundary positions
-  double* pr = sh + nf;  // [4][64] wave partials
-  for (int i = t; i < nf; i += 256) w[i] = i < d.ns ? b[d.own_off + i] : 0.0;
-  __syncthreads();
-  for (int s = 0; s < 2; ++s) {
-    const int* map = cmap + d.cmap_off[s];
-    const int cnb = d.child_nb[s];
-    const double* cup = up + d.child_up_off[s];
-    for (int i = t; i < cnb; i += 256) {
-      double v = cup[i];
-      for (int kp = 1; kp < d.child_kparts[s]; ++kp) v += cup[kp * cnb + i];
-      w[map[i]] += v;
+  if (t < 128) {
+    double v = own ? bj : 0.0;
+    if (d.pull_off >= 0) {
+      double c0, c1;
+      pull_children(d, up, ok ? srcl : make_int2(-1, -1), c0, c1);
+      v += c0;
+      v += c1;
     }
-    __syncthreads();
+    v = ok ? v : 0.0;
+    if (ok && own && d.first == 0) beff[d.own_off + j] = v;
+    w[t] = v;
   }
-  if (d.first == 0 && d.kpart == 0)
-    for (int i = t; i < d.ns; i += 256) beff[d.own_off + i] = w[i];
+  __syncthreads();
   double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int k = kb + wv + 4 * u;
-    s += a[u] * (k < ke ? w[k] : 0.0);
-  }
-  if (col_ok) {
-    int k = kb + wv + 32;
-    for (; k + 28 < ke; k += 32) {
-      const double* c0 = col + (long long)k * nf;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = c0[u * st];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) s += a[u] * w[k + 4 * u];
-    }
-    for (; k < ke; k += 4) s += col[(long long)k * nf] * w[k];
-  }
-  pr[wv * 64 + lane] = s;
+  for (int u = 0; u < 16; ++u) s += a[u] * w[wv + 4 * u];
+  pr[wv][lane] = s;
   __syncthreads();
   if (wv == 0 && col_ok) {
-    const double tot = ((pr[lane] + pr[64 + lane]) + pr[128 + lane]) + pr[192 + lane];
-    up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w[d.ns + r] : 0.0) - tot;
+    const double tot = ((pr[0][lane] + pr[1][lane]) + pr[2][lane]) + pr[3][lane];
+    up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w[64 + lane] : 0.0) - tot;
   }
 }
 
-// Backward item (node, first own row k0): rows [k0, k0 + 4Q) of
-// g_s = [F_ss^-1 | M^T] [b_eff; -g_b]; wave wv takes rows k0 + wv + 4q, lanes
-// run along the row, a butterfly sums each row.  The first 64 columns of the
-// rows are requested before the vector is gathered.  LDS: nf doubles.
-template <int Q>
+// Backward item (node, own rows [k0, k0 + 4Q)): rows of
+// g_s = [F_ss^-1 | M^T] [b_eff; -g_b].  Wave wv takes rows k0 + wv + 4q;
+// lanes run along a row in passes of NCH chunks of 64 columns, every load of
+// a pass requested before its first use (the first pass before the vector is
+// gathered); a butterfly sums each row.  LDS: nf doubles rounded up to a
+// multiple of 1024.
+template <int Q, int NCH>
 __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items, const int* __restrict__ bnd,
                                                 const double* __restrict__ F, const double* __restrict__ beff,
                                                 double* __restrict__ x) {
   extern __shared__ double sh[];
   const NDItem d = items[blockIdx.x];
-  const int nf = d.ns + d.nb;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (d.ns == 0) return;  // no own rows (the whole workgroup)
+  const int nf = d.ns + d.nb, t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  // boundary indices of the first 1024 front positions (four per thread)
+  int g[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int j = t + 256 * m;
+    g[m] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
+  }
+  // keep the index loads ahead of the row loads (the counter is in order)
+  __builtin_amdgcn_sched_barrier(0);
   const double* rows[Q];
   bool ok[Q];
-  double a[Q];
+  double a[Q][NCH];
+  // row loads are unconditional, so the compiler counts them exactly and the
+  // gather waits for the indices alone: columns past nf read the row's first
+  // entry and meet zeros of the padded vector, rows past ns read the front's
+  // first row and are not stored (factor entries are finite)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int k = d.first + wv + 4 * q;
     ok[q] = k < d.ns;
     rows[q] = F + d.foff + (long long)(ok[q] ? k : 0) * nf;
-    a[q] = (ok[q] && lane < nf) ? rows[q][lane] : 0.0;
   }
-  for (int i = threadIdx.x; i < nf; i += 256)
-    sh[i] = i < d.ns ? beff[d.own_off + i] : -x[bnd[d.bnd_off + i - d.ns]];
+#pragma unroll
+  for (int q = 0; q < Q; ++q)
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int j = lane + 64 * c;
+      a[q][c] = rows[q][j < nf ? j : 0];
+    }
+  // [b_eff; -x_b] into LDS: one load per position through a selected address,
+  // every value stored (the LDS vector is padded to a multiple of 1024); the
+  // first 1024 positions outside the loop, so their loads wait only for the
+  // boundary indices
+  auto gather = [&](int j0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int j = j0 + t + 256 * m;
+      const bool is_b = j >= d.ns && j < nf, is_s = j < d.ns;
+      const double l = *(is_b ? x + g[m] : beff + (is_s ? d.own_off + j : 0));
+      sh[j] = is_b ? -l : (is_s ? l : 0.0);
+    }
+  };
+  gather(0);
+  for (int j0 = 1024; j0 < nf; j0 += 1024) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int j = j0 + t + 256 * m;
+      g[m] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
+    }
+    gather(j0);
+  }
   __syncthreads();
   double s[Q];
-  const double v0 = lane < nf ? sh[lane] : 0.0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) s[q] = a[q] * v0;
-  for (int j = lane + 64; j < nf; j += 64) {
-    const double vj = sh[j];
+  for (int q = 0; q < Q; ++q) s[q] = 0.0;
+  for (int c0 = 0;;) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) a[q] = ok[q] ? rows[q][j] : 0.0;
+    for (int c = 0; c < NCH; ++c) {
+      const double vj = sh[c0 + lane + 64 * c];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) s[q] += a[q] * vj;
+      for (int q = 0; q < Q; ++q) s[q] += a[q][c] * vj;
+    }
+    c0 += 64 * NCH;
+    if (c0 >= nf) break;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const int j = c0 + lane + 64 * c;
+        a[q][c] = rows[q][j < nf ? j : 0];
+      }
   }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
@@ -522,29 +599,42 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
   }
 }
 
+template <int Q>
+static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDItem* items, const int* bnd,
+                       const double* F, const double* beff, double* x) {
+  if (nch <= 2)
+    hipLaunchKernelGGL((k_nd_bwd<Q, 2>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+  else if (nch <= 4)
+    hipLaunchKernelGGL((k_nd_bwd<Q, 4>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+  else if (nch <= 8)
+    hipLaunchKernelGGL((k_nd_bwd<Q, 8>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+  else
+    hipLaunchKernelGGL((k_nd_bwd<Q, 16>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+}
+
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
-  // LDS sized per level, so the many small fronts of the lower levels all fit on the chip;
-  // the upper levels' items were split when the work lists were built
   for (int l = L - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
-    const size_t lds = (size_t)(co.lvl_nfmax[l] + 256) * sizeof(double);
     if (ni > 0)
-      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), lds, c->stream, c->d_fw_items + i0, c->d_nd_cmap,
-                         c->d_coarse, rhs, c->d_up, c->d_beff);
+      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), 0, c->stream, c->d_fw_items + i0,
+                         (const int2*)c->d_nd_pull, c->d_coarse, rhs, c->d_up, c->d_beff);
   }
   if (mid) hipEventRecord(mid, c->stream);
+  // LDS sized per level, so the many small fronts of the lower levels all fit
+  // on the chip; the upper levels' items were split when the lists were built
   for (int l = 0; l < L; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
-    const size_t lds = (size_t)std::max(1, co.lvl_nfmax[l]) * sizeof(double);
     if (ni == 0) continue;
+    const int nf = std::max(1, co.lvl_nfmax[l]);
+    const size_t lds = (size_t)((nf + 1023) / 1024 * 1024) * sizeof(double);
+    const int nch = (nf + 63) / 64;
     if (co.lvl_bw_rows[l] == 4)
-      hipLaunchKernelGGL(k_nd_bwd<1>, dim3(ni), dim3(256), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd,
-                         c->d_coarse, c->d_beff, x);
+      launch_bwd<1>(nch, dim3(ni), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
     else
-      hipLaunchKernelGGL(k_nd_bwd<ND_BW_ROWS / 4>, dim3(ni), dim3(256), lds, c->stream, c->d_bw_items + i0,
-                         c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      launch_bwd<ND_BW_ROWS / 4>(nch, dim3(ni), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd, c->d_coarse,
+                                 c->d_beff, x);
   }
   return hipGetLastError();
 }

@@ -400,18 +400,51 @@ static void prolong(Ctx* c, bool fp32) {
 #undef PLC
 }
 
-// z = S_BDDC^-1 r (Alg. 1), with the partial dot r.z into red
-static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red) {
+// Device times of the timed PCG phases, accumulated from the event ring.
+struct PhaseAcc {
+  double op = 0, pre = 0, coarse = 0, cf = 0, cb = 0;
+};
+
+static double elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0;
+  return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.0;
+}
+
+// read back ring slot `s` of an operator launch / a preconditioner application
+static void harvest_op(Ctx* c, int s, PhaseAcc& a) {
+  if (!(c->timing & LBDDC_TIME_OP)) return;
+  hipEventSynchronize(c->pev[s][1]);
+  a.op += elapsed(c->pev[s][0], c->pev[s][1]);
+}
+static void harvest_apply(Ctx* c, int s, PhaseAcc& a) {
+  hipEvent_t* e = c->pev[s];
+  if (c->timing & LBDDC_TIME_PRE) {
+    hipEventSynchronize(e[3]);
+    a.pre += elapsed(e[2], e[3]);
+  }
+  if (c->timing & LBDDC_TIME_COARSE) {
+    hipEventSynchronize(e[6]);
+    a.coarse += elapsed(e[4], e[6]);
+    a.cf += elapsed(e[4], e[5]);
+    a.cb += elapsed(e[5], e[6]);
+  }
+}
+
+// z = S_BDDC^-1 r (Alg. 1), with the partial dot r.z into red; the timed
+// phases record their events into ring slot `slot`
+static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red, int slot) {
   const int nbU = (c->NU + kBlk - 1) / kBlk, nbC = (c->NC + kBlk - 1) / kBlk;
-  hipEventRecord(c->ev[2], c->stream);
+  hipEvent_t* e = c->pev[slot];
+  const bool tp = c->timing & LBDDC_TIME_PRE, tc = c->timing & LBDDC_TIME_COARSE;
+  if (tp) hipEventRecord(e[2], c->stream);
   pre_local(c, fp32, r);
-  hipEventRecord(c->ev[3], c->stream);
+  if (tp) hipEventRecord(e[3], c->stream);
   hipLaunchKernelGGL(k_gather_dot, dim3(nbC), dim3(kBlk), 0, c->stream, c->d_partC, c->d_cown_ptr, c->d_cown,
                      c->d_zc, c->NC, (const double*)nullptr, (double*)nullptr);
-  hipEventRecord(c->ev[4], c->stream);
-  hipError_t e = launch_coarse_solve(c, c->d_zc, c->d_xc, c->ev[8]);
-  if (e != hipSuccess) return e;
-  hipEventRecord(c->ev[5], c->stream);
+  if (tc) hipEventRecord(e[4], c->stream);
+  hipError_t err = launch_coarse_solve(c, c->d_zc, c->d_xc, tc ? e[5] : nullptr);
+  if (err != hipSuccess) return err;
+  if (tc) hipEventRecord(e[6], c->stream);
   prolong(c, fp32);
   hipLaunchKernelGGL(k_gather_dot, dim3(nbU), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, z,
                      c->NU, r, red);
@@ -434,19 +467,32 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   hipLaunchKernelGGL(k_copy, dim3(nb), dim3(kBlk), 0, c->stream, r, f, N);
   hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kBlk), 0, c->stream, f, f, N, red);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, red, nb, scal, 6, 0);
-  float ms = 0;
-  double acc_pre = 0, acc_coarse = 0, acc_op = 0, acc_cf = 0, acc_cb = 0;
-  int napp = 0;
+  // event ring: an operator launch and a preconditioner application use slot
+  // (count mod kRing); a slot is read back before it is recorded again, by
+  // which time its events completed long ago, and the rest after the loop
+  PhaseAcc acc;
+  int napp = 0, nop = 0;
+  auto apply = [&](void) -> hipError_t {
+    const int sl = napp % Ctx::kRing;
+    if (napp >= Ctx::kRing) harvest_apply(c, sl, acc);
+    ++napp;
+    return apply_M(c, fp32, r, z, red_rz, sl);
+  };
+  auto finish = [&](hipError_t e) {
+    for (int k = std::max(0, napp - Ctx::kRing); k < napp; ++k) harvest_apply(c, k % Ctx::kRing, acc);
+    for (int k = std::max(0, nop - Ctx::kRing); k < nop; ++k) harvest_op(c, k % Ctx::kRing, acc);
+    if (t_op) *t_op += acc.op;
+    if (t_pre) *t_pre += acc.pre;
+    if (t_coarse) *t_coarse += acc.coarse;
+    if (t_cfwd) *t_cfwd += acc.cf;
+    if (t_cbwd) *t_cbwd += acc.cb;
+    if (n_apply) *n_apply += napp;
+    return e;
+  };
   int slot = 10;
-  hipError_t e = apply_M(c, fp32, r, z, red_rz);
+  hipError_t e = apply();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_update_p4, dim3(nv), dim3(kBlk), 0, c->stream, p, z, scal, N, red_rz, nb, slot, slot, 1);
-  napp++;
-  hipEventSynchronize(c->ev[5]);
-  if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) acc_pre += ms;
-  if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) acc_coarse += ms;
-  if (hipEventElapsedTime(&ms, c->ev[4], c->ev[8]) == hipSuccess) acc_cf += ms;
-  if (hipEventElapsedTime(&ms, c->ev[8], c->ev[5]) == hipSuccess) acc_cb += ms;
   e = hipMemcpyAsync(c->h_scal, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e != hipSuccess) return e;
   e = hipStreamSynchronize(c->stream);
@@ -456,12 +502,16 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   int it = 0;
   info->iters = 0;
   info->rel_res = ff > 0 ? 1.0 : 0.0;
-  if (!(ff > 0)) return hipSuccess;
-  if (c->h_scal[7] != 0.0) return hipErrorUnknown;  // breakdown, reported by the caller
+  if (!(ff > 0)) return finish(hipSuccess);
+  if (c->h_scal[7] != 0.0) return finish(hipErrorUnknown);  // breakdown, reported by the caller
+  const bool top = c->timing & LBDDC_TIME_OP;
   while (it < max_iter) {
-    hipEventRecord(c->ev[0], c->stream);
+    const int so = nop % Ctx::kRing;
+    if (nop >= Ctx::kRing) harvest_op(c, so, acc);
+    ++nop;
+    if (top) hipEventRecord(c->pev[so][0], c->stream);
     op_local(c, p);
-    hipEventRecord(c->ev[1], c->stream);
+    if (top) hipEventRecord(c->pev[so][1], c->stream);
     hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, q, N,
                        p, red_pq);
     hipLaunchKernelGGL(k_update_xr4, dim3(nv), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red_pq, nb, slot,
@@ -472,7 +522,7 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
     if (e != hipSuccess) return e;
     hipEventRecord(c->ev[6], c->stream);
     // speculatively enqueue the preconditioner and the direction update of the next iteration
-    e = apply_M(c, fp32, r, z, red_rz);
+    e = apply();
     if (e != hipSuccess) return e;
     const int next = slot == 10 ? 11 : 10;
     hipLaunchKernelGGL(k_update_p4, dim3(nv), dim3(kBlk), 0, c->stream, p, z, scal, N, red_rz, nb, slot, next, 0);
@@ -480,34 +530,21 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
     e = hipEventSynchronize(c->ev[6]);
     if (e != hipSuccess) return e;
     ++it;
-    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) acc_op += ms;
     if (c->h_scal[7] != 0.0) {
       hipStreamSynchronize(c->stream);
       info->iters = it;
       info->rel_res = rel;
-      return hipErrorUnknown;  // breakdown, reported by the caller
+      return finish(hipErrorUnknown);  // breakdown, reported by the caller
     }
     double rr = 0.0;  // r.r: the workgroup partials summed on the host in fixed order
     for (int i = 0; i < nv; ++i) rr += c->h_red[i];
     rel = sqrt(rr / ff);
     if (rel <= rtol) break;
-    hipEventSynchronize(c->ev[5]);
-    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) acc_pre += ms;
-    if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) acc_coarse += ms;
-    if (hipEventElapsedTime(&ms, c->ev[4], c->ev[8]) == hipSuccess) acc_cf += ms;
-    if (hipEventElapsedTime(&ms, c->ev[8], c->ev[5]) == hipSuccess) acc_cb += ms;
-    napp++;
   }
   e = hipStreamSynchronize(c->stream);
   info->iters = it;
   info->rel_res = rel;
-  if (t_op) *t_op += acc_op;
-  if (t_pre) *t_pre += acc_pre;
-  if (t_coarse) *t_coarse += acc_coarse;
-  if (t_cfwd) *t_cfwd += acc_cf;
-  if (t_cbwd) *t_cbwd += acc_cb;
-  if (n_apply) *n_apply += napp;
-  return e;
+  return finish(e);
 }
 
 // ||f - S x||_2 / ||f||_2 recomputed from the iterate

@@ -165,14 +165,39 @@ bool build_topology(Ctx* c) {
     owners(c->RC, c->NC, cptr, cown);
   }
   // solve work lists: forward items = 64-column chunks of the boundary (at
-  // least one per node) x own-row parts, backward items = runs of own rows.
-  // The forward result of a node is stored as kparts partial vectors of nb
-  // entries (kp-major), which the parent adds in a fixed order.
+  // least one per node) x 64-row parts of the own rows, backward items = runs
+  // of own rows.  The forward result of a node is stored as kparts partial
+  // vectors of nb entries (kp-major), which the parent adds in a fixed order.
   const int L = (int)co.nd_levels.size();
   std::vector<int> kparts(co.nd_nodes.size(), 1);
-  for (int l = 0; l < L; ++l)
-    if ((int)co.nd_levels[l].size() < ND_SPLIT_NODES)
-      for (int n : co.nd_levels[l]) kparts[n] = std::max(1, (co.nd_nodes[n].ns + ND_KPART - 1) / ND_KPART);
+  for (size_t n = 0; n < co.nd_nodes.size(); ++n)
+    kparts[n] = std::max(1, (co.nd_nodes[n].ns + ND_KPART - 1) / ND_KPART);
+  // pull maps: inverse of the child maps, two entries per front position
+  std::vector<int> pull_off(co.nd_nodes.size(), -1);
+  co.nd_pull.clear();
+  for (size_t n = 0; n < co.nd_nodes.size(); ++n) {
+    const NDNodeH& d = co.nd_nodes[n];
+    if (d.child[0] < 0 && d.child[1] < 0) continue;
+    const size_t base = co.nd_pull.size();
+    pull_off[n] = (int)(base / 2);
+    co.nd_pull.resize(base + 2 * (size_t)(d.ns + d.nb), -1);
+    for (int s = 0; s < 2; ++s) {
+      const int ch = d.child[s];
+      if (ch < 0) continue;
+      for (int i = 0; i < co.nd_nodes[ch].nb; ++i) {
+        const int pos = co.nd_cmap[d.cmap_off[s] + i];
+        if (pos < 0 || pos >= d.ns + d.nb || co.nd_pull[base + 2 * pos + s] != -1) {
+          c->err = "internal: a child map that is not one-to-one";
+          return false;
+        }
+        co.nd_pull[base + 2 * pos + s] = i;
+      }
+    }
+  }
+  // one spare position, so the maps are never empty: the forward sweep reads
+  // entry 0 for leaves and for positions it does not need
+  co.nd_pull.push_back(-1);
+  co.nd_pull.push_back(-1);
   {
     int uoff = 0;
     for (size_t n = 0; n < co.nd_nodes.size(); ++n) {
@@ -206,8 +231,8 @@ bool build_topology(Ctx* c) {
         it.child_up_off[s] = ch >= 0 ? co.nd_nodes[ch].up_off : 0;
         it.child_nb[s] = ch >= 0 ? co.nd_nodes[ch].nb : 0;
         it.child_kparts[s] = ch >= 0 ? kparts[ch] : 0;
-        it.cmap_off[s] = ch >= 0 ? d.cmap_off[s] : 0;
       }
+      it.pull_off = pull_off[n];
       for (int kp = 0; kp < kparts[n]; ++kp)
         for (int r = 0; r < std::max(1, d.nb); r += 64) {
           it.first = r;
@@ -264,7 +289,7 @@ bool build_topology(Ctx* c) {
          up(&c->d_cown, cown) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
          up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) &&
-         up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_fw_items, co.fw_items) &&
+         up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_nd_pull, co.nd_pull) && up(&c->d_fw_items, co.fw_items) &&
          up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes);
 }
 

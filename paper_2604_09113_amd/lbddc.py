@@ -21,6 +21,7 @@ FP64, MIXED, FP32_CONTRACTION = 0, 1, 2
 X_K, X_THETA, X_ITIL, X_S, X_D, X_PSI, X_SC, X_LOAD, X_FINE = range(9)
 Q_NCELL, Q_NDOF_FREE, Q_N_SKELETON, Q_N_INTERIOR, Q_N_COARSE, Q_N_I_ROM, Q_NU_CELL, Q_NC_CELL, Q_NRHS, \
     Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES = range(14)
+TIME_OP, TIME_PRE, TIME_COARSE, TIME_ALL = 1, 2, 4, 7
 PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor", "solve", "op_kernel",
           "pre_kernel", "coarse_solve", "recovery", "gradient", "adjoint_kernel", "coarse_fwd_sweep",
           "coarse_bwd_sweep"]
@@ -28,7 +29,8 @@ PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor
 FUNCTIONS = ["lbddc_create", "lbddc_destroy", "lbddc_last_error", "lbddc_version", "lbddc_load_rom",
              "lbddc_set_problem", "lbddc_set_geometry_device", "lbddc_assemble", "lbddc_setup", "lbddc_solve",
              "lbddc_get_displacement", "lbddc_get_displacement_device", "lbddc_compliance_gradient",
-             "lbddc_compliance_gradient_device", "lbddc_query", "lbddc_export_cells", "lbddc_phase_times"]
+             "lbddc_compliance_gradient_device", "lbddc_query", "lbddc_export_cells", "lbddc_phase_times",
+             "lbddc_set_timing"]
 
 
 class LbddcError(RuntimeError):
@@ -85,6 +87,7 @@ def library():
         "lbddc_query": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64)]),
         "lbddc_export_cells": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, dp]),
         "lbddc_phase_times": (C.c_int, [P, dp, C.c_int32]),
+        "lbddc_set_timing": (C.c_int, [P, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -196,6 +199,10 @@ class Solver:
         out = np.zeros((count,) + per)
         self._check(self.lib.lbddc_export_cells(self.ctx, which, first, count, _dptr(out)))
         return out
+
+    def set_timing(self, mask):
+        """PCG phases timed by solve (TIME_OP | TIME_PRE | TIME_COARSE; TIME_ALL after creation)."""
+        self._check(self.lib.lbddc_set_timing(self.ctx, int(mask)))
 
     def phase_times(self):
         out = np.zeros(len(PHASES))
