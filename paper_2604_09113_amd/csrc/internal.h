@@ -122,6 +122,8 @@ struct CoarseLayout {
   std::vector<int> fw_off, bw_off, lvl_off;
   std::vector<int> lvl_nfmax, lvl_nsmax;  // largest front and own-block size per level
   std::vector<int> lvl_bw_rows;           // own rows per backward item on each level (4 or ND_BW_ROWS)
+  std::vector<int> lvl_fw_rows;           // largest own-row part of a forward item on each level
+  std::vector<int> lvl_child_kparts;      // largest number of row parts of a child on each level
 };
 
 

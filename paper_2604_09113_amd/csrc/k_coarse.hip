@@ -412,31 +412,37 @@ hipError_t launch_coarse_factor(Ctx* c) {
 
 // Sum over a child's parts of entry i of its up vector, in part order, for
 // the two children at once.  i = -1: the child does not touch this front
-// position.  The loads of the first 8 parts of both children are made
-// unconditionally (a position that is not needed reads up[0]) so that all of
-// them are requested before the first add.
-__device__ __forceinline__ void pull_children(const NDItem& d, const double* __restrict__ up, int2 src,
-                                              double& c0, double& c1) {
-  const int n0 = src.x >= 0 ? d.child_kparts[0] : 0, n1 = src.y >= 0 ? d.child_kparts[1] : 0;
-  double t0[8], t1[8];
+// position.  pull_load requests the first CK parts of both children
+// unconditionally (a position that is not needed reads up[0]), so that the
+// loads of several positions can all be in flight before pull_sum adds them;
+// pull_sum adds any further parts in a loop.
+template <int CK>
+struct Pulled {
+  double t0[CK], t1[CK];
+  int n0, n1;
+};
+template <int CK>
+__device__ __forceinline__ Pulled<CK> pull_load(const NDItem& d, const double* __restrict__ up, int2 src) {
+  Pulled<CK> p;
+  p.n0 = src.x >= 0 ? d.child_kparts[0] : 0;
+  p.n1 = src.y >= 0 ? d.child_kparts[1] : 0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const double l0 = up[u < n0 ? d.child_up_off[0] + u * d.child_nb[0] + src.x : 0];
-    t0[u] = u < n0 ? l0 : 0.0;
-  }
+  for (int u = 0; u < CK; ++u) p.t0[u] = up[u < p.n0 ? d.child_up_off[0] + u * d.child_nb[0] + src.x : 0];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const double l1 = up[u < n1 ? d.child_up_off[1] + u * d.child_nb[1] + src.y : 0];
-    t1[u] = u < n1 ? l1 : 0.0;
-  }
+  for (int u = 0; u < CK; ++u) p.t1[u] = up[u < p.n1 ? d.child_up_off[1] + u * d.child_nb[1] + src.y : 0];
+  return p;
+}
+template <int CK>
+__device__ __forceinline__ void pull_sum(const NDItem& d, const double* __restrict__ up, int2 src,
+                                         const Pulled<CK>& p, double& c0, double& c1) {
   c0 = 0.0;
   c1 = 0.0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) c0 += t0[u];
+  for (int u = 0; u < CK; ++u) c0 += u < p.n0 ? p.t0[u] : 0.0;
 #pragma unroll
-  for (int u = 0; u < 8; ++u) c1 += t1[u];
-  for (int kp = 8; kp < n0; ++kp) c0 += up[d.child_up_off[0] + kp * d.child_nb[0] + src.x];
-  for (int kp = 8; kp < n1; ++kp) c1 += up[d.child_up_off[1] + kp * d.child_nb[1] + src.y];
+  for (int u = 0; u < CK; ++u) c1 += u < p.n1 ? p.t1[u] : 0.0;
+  for (int kp = CK; kp < p.n0; ++kp) c0 += up[d.child_up_off[0] + kp * d.child_nb[0] + src.x];
+  for (int kp = CK; kp < p.n1; ++kp) c1 += up[d.child_up_off[1] + kp * d.child_nb[1] + src.y];
 }
 
 // Forward item (node, boundary columns [r0, r0 + 64), own-row part kp = rows
@@ -484,7 +490,8 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
     double v = own ? bj : 0.0;
     if (d.pull_off >= 0) {
       double c0, c1;
-      pull_children(d, up, ok ? srcl : make_int2(-1, -1), c0, c1);
+      const int2 src = ok ? srcl : make_int2(-1, -1);
+      pull_sum<8>(d, up, src, pull_load<8>(d, up, src), c0, c1);
       v += c0;
       v += c1;
     }
@@ -599,6 +606,141 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
   }
 }
 
+// Lane l's copy of a double held by lane `src` (wave-uniform src), through
+// two scalar reads.
+__device__ __forceinline__ double read_lane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// Forward items of the lower tree levels (many small fronts), one per wave,
+// four per workgroup: the same item as k_nd_fwd with at most R own rows.
+// Lane l pulls front position kb + l (own row) and boundary column r0 + l,
+// reads the R rows of M^T in its column, and takes w_k from lane k - kb.
+template <int R, int CK>
+__global__ __launch_bounds__(256) void k_nd_fwd_w(const NDItem* __restrict__ items, int nitems,
+                                                  const int2* __restrict__ pull, const double* __restrict__ F,
+                                                  const double* __restrict__ b, double* __restrict__ up,
+                                                  double* __restrict__ beff) {
+  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (it >= nitems) return;  // the whole wave
+  const NDItem d = items[it];
+  const int lane = threadIdx.x & 63, nf = d.ns + d.nb, r = d.first + lane;
+  const int kb = d.kpart * ND_KPART, ke = min(d.ns, kb + R);
+  const bool col_ok = r < d.nb;
+  const bool ok1 = kb + lane < ke, ok2 = d.kpart == 0 && col_ok;
+  const int j1 = ok1 ? kb + lane : 0, j2 = ok2 ? d.ns + r : 0;
+  const bool has_ch = d.pull_off >= 0;
+  const int2 s1 = pull[has_ch && ok1 ? d.pull_off + j1 : 0];
+  const int2 s2 = pull[has_ch && ok2 ? d.pull_off + j2 : 0];
+  const double b1 = b[ok1 ? d.own_off + j1 : 0];
+  __builtin_amdgcn_sched_barrier(0);  // indices ahead of M^T (the counter is in order)
+  // rows past ke read row 0 and meet w = 0; columns past nb are not stored
+  const double* col = col_ok ? F + d.foff + d.ns + r : F;
+  double a[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) a[u] = col[col_ok && kb + u < ke ? (long long)(kb + u) * nf : 0];
+  double w1 = b1, w2 = 0.0;
+  if (has_ch) {
+    double c0, c1, e0, e1;
+    const int2 p1 = ok1 ? s1 : make_int2(-1, -1), p2 = ok2 ? s2 : make_int2(-1, -1);
+    const Pulled<CK> l1 = pull_load<CK>(d, up, p1);
+    const Pulled<CK> l2 = pull_load<CK>(d, up, p2);
+    pull_sum<CK>(d, up, p1, l1, c0, c1);
+    pull_sum<CK>(d, up, p2, l2, e0, e1);
+    w1 += c0;
+    w1 += c1;
+    w2 += e0;
+    w2 += e1;
+  }
+  w1 = ok1 ? w1 : 0.0;
+  if (ok1 && d.first == 0) beff[d.own_off + j1] = w1;
+  double acc = 0.0;
+#pragma unroll
+  for (int u = 0; u < R; ++u) acc += a[u] * read_lane(w1, u);
+  if (col_ok) up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w2 : 0.0) - acc;
+}
+
+// Backward items of the lower tree levels, one per wave, four per
+// workgroup: 16 own rows [k0, k0 + 16) of g_s = [F_ss^-1 | M^T] [b_eff; -g_b]
+// with nf <= 64 NCH.  Lane l owns columns l + 64c and gathers their vector
+// entries itself (no LDS); a reduce-scatter over the lanes leaves row
+// 8 b5 + 4 b4 + 2 b3 + b2 (bits of the lane id) in lanes with b1 = b0 = 0.
+static_assert(ND_BW_ROWS == 16, "k_nd_bwd_w takes items of 16 rows");
+template <int NCH>
+__global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ items, int nitems,
+                                                  const int* __restrict__ bnd, const double* __restrict__ F,
+                                                  const double* __restrict__ beff, double* __restrict__ x) {
+  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (it >= nitems) return;  // the whole wave
+  const NDItem d = items[it];
+  if (d.ns == 0) return;
+  const int lane = threadIdx.x & 63, nf = d.ns + d.nb;
+  int g[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int j = lane + 64 * c;
+    g[c] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
+  }
+  __builtin_amdgcn_sched_barrier(0);  // indices ahead of the rows (the counter is in order)
+  // rows past ns read row 0 and are not stored; columns past nf meet v = 0
+  double a[16][NCH];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int k = d.first + q;
+    const double* row = F + d.foff + (long long)(k < d.ns ? k : 0) * nf;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const int j = lane + 64 * c;
+      a[q][c] = row[j < nf ? j : 0];
+    }
+  }
+  double v[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int j = lane + 64 * c;
+    const bool is_b = j >= d.ns && j < nf, is_s = j < d.ns;
+    const double l = *(is_b ? x + g[c] : beff + (is_s ? d.own_off + j : 0));
+    v[c] = is_b ? -l : (is_s ? l : 0.0);
+  }
+  double s[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    s[q] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) s[q] += a[q][c] * v[c];
+  }
+  // reduce-scatter: at each step a lane keeps the half of its rows selected by
+  // one bit of its id and adds the partner's copy of that half
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+  double t8[8], t4[4], t2[2];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double keep = b5 ? s[8 + i] : s[i], send = b5 ? s[i] : s[8 + i];
+    t8[i] = keep + __shfl_xor(send, 32);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = b4 ? t8[4 + i] : t8[i], send = b4 ? t8[i] : t8[4 + i];
+    t4[i] = keep + __shfl_xor(send, 16);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = b3 ? t4[2 + i] : t4[i], send = b3 ? t4[i] : t4[2 + i];
+    t2[i] = keep + __shfl_xor(send, 8);
+  }
+  double t1;
+  {
+    const double keep = b2 ? t2[1] : t2[0], send = b2 ? t2[0] : t2[1];
+    t1 = keep + __shfl_xor(send, 4);
+  }
+  t1 += __shfl_xor(t1, 2);
+  t1 += __shfl_xor(t1, 1);
+  const int q = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
+  if ((lane & 3) == 0 && d.first + q < d.ns) x[d.own_off + d.first + q] = t1;
+}
+
 template <int Q>
 static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDItem* items, const int* bnd,
                        const double* F, const double* beff, double* x) {
@@ -612,14 +754,41 @@ static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDI
     hipLaunchKernelGGL((k_nd_bwd<Q, 16>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
 }
 
+// Levels with at least this many items take the one-item-per-wave kernels.
+constexpr int ND_WAVE_ITEMS = 512;
+
+template <int R>
+static void launch_fwd_w(int ck, int ni, hipStream_t st, const NDItem* items, const int2* pull, const double* F,
+                         const double* b, double* up, double* beff) {
+  const dim3 grid((ni + 3) / 4);
+  if (ck <= 1)
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 1>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
+  else if (ck <= 2)
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 2>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
+  else
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 8>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
+}
+
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
+  const int2* pull = (const int2*)c->d_nd_pull;
   for (int l = L - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
-    if (ni > 0)
-      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), 0, c->stream, c->d_fw_items + i0,
-                         (const int2*)c->d_nd_pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+    if (ni == 0) continue;
+    const NDItem* it = c->d_fw_items + i0;
+    const int rows = co.lvl_fw_rows[l], ck = co.lvl_child_kparts[l];
+    if (ni >= ND_WAVE_ITEMS && rows <= 48) {
+      if (rows <= 16)
+        launch_fwd_w<16>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+      else if (rows <= 32)
+        launch_fwd_w<32>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+      else
+        launch_fwd_w<48>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+    } else {
+      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), 0, c->stream, it, pull, c->d_coarse, rhs, c->d_up,
+                         c->d_beff);
+    }
   }
   if (mid) hipEventRecord(mid, c->stream);
   // LDS sized per level, so the many small fronts of the lower levels all fit
@@ -627,14 +796,27 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
   for (int l = 0; l < L; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
     if (ni == 0) continue;
+    const NDItem* it = c->d_bw_items + i0;
     const int nf = std::max(1, co.lvl_nfmax[l]);
-    const size_t lds = (size_t)((nf + 1023) / 1024 * 1024) * sizeof(double);
     const int nch = (nf + 63) / 64;
+    if (co.lvl_bw_rows[l] == 16 && ni >= ND_WAVE_ITEMS && nch <= 4) {
+      const dim3 grid((ni + 3) / 4);
+      if (nch <= 2)
+        hipLaunchKernelGGL(k_nd_bwd_w<2>, grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
+                           c->d_beff, x);
+      else if (nch <= 3)
+        hipLaunchKernelGGL(k_nd_bwd_w<3>, grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
+                           c->d_beff, x);
+      else
+        hipLaunchKernelGGL(k_nd_bwd_w<4>, grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
+                           c->d_beff, x);
+      continue;
+    }
+    const size_t lds = (size_t)((nf + 1023) / 1024 * 1024) * sizeof(double);
     if (co.lvl_bw_rows[l] == 4)
-      launch_bwd<1>(nch, dim3(ni), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      launch_bwd<1>(nch, dim3(ni), lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
     else
-      launch_bwd<ND_BW_ROWS / 4>(nch, dim3(ni), lds, c->stream, c->d_bw_items + i0, c->d_nd_bnd, c->d_coarse,
-                                 c->d_beff, x);
+      launch_bwd<ND_BW_ROWS / 4>(nch, dim3(ni), lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
   }
   return hipGetLastError();
 }

@@ -211,6 +211,8 @@ bool build_topology(Ctx* c) {
   co.lvl_nfmax.assign(L, 0);
   co.lvl_nsmax.assign(L, 0);
   co.lvl_bw_rows.assign(L, ND_BW_ROWS);
+  co.lvl_fw_rows.assign(L, 0);
+  co.lvl_child_kparts.assign(L, 0);
   for (int l = 0; l < L; ++l) {
     const bool split = (int)co.nd_levels[l].size() < ND_SPLIT_NODES;
     co.lvl_bw_rows[l] = split ? 4 : ND_BW_ROWS;
@@ -218,6 +220,9 @@ bool build_topology(Ctx* c) {
       const NDNodeH& d = co.nd_nodes[n];
       co.lvl_nfmax[l] = std::max(co.lvl_nfmax[l], d.ns + d.nb);
       co.lvl_nsmax[l] = std::max(co.lvl_nsmax[l], d.ns);
+      co.lvl_fw_rows[l] = std::max(co.lvl_fw_rows[l], std::min(d.ns, ND_KPART));
+      for (int s = 0; s < 2; ++s)
+        if (d.child[s] >= 0) co.lvl_child_kparts[l] = std::max(co.lvl_child_kparts[l], kparts[d.child[s]]);
       NDItem it{};
       it.foff = d.foff;
       it.ns = d.ns;
