@@ -98,6 +98,12 @@ struct NDItem {
 // the upper tree levels are spread over more workgroups.
 constexpr int ND_SPLIT_NODES = 64;
 constexpr int ND_KPART = 64;
+// The bottom ND_SUB_LEVELS levels of the tree are swept one subtree per
+// workgroup (one launch per sweep), when their top level has at least
+// ND_SUB_MIN_ROOTS nodes and their fronts fit the per-wave kernels.
+constexpr int ND_SUB_LEVELS = 3;
+constexpr int ND_SUB_MIN_ROOTS = 256;
+constexpr int ND_SUB_MAX_NF = 256;
 
 struct CoarseLayout {
   std::vector<int> sb_off, sb_size;   // coarse numbering by grid lines (offset, size)
@@ -124,6 +130,12 @@ struct CoarseLayout {
   std::vector<int> lvl_bw_rows;           // own rows per backward item on each level (4 or ND_BW_ROWS)
   std::vector<int> lvl_fw_rows;           // largest own-row part of a forward item on each level
   std::vector<int> lvl_child_kparts;      // largest number of row parts of a child on each level
+  // bottom levels [sub_level, L) swept one subtree per workgroup (sub_level = L: none):
+  // items of subtree t, stage s in [off[t (nst + 1) + s], off[t (nst + 1) + s + 1])
+  int sub_level = 0, sub_nst = 0, sub_count = 0;
+  int sub_fw_rows = 0, sub_child_kparts = 0, sub_nfmax = 0;
+  std::vector<NDItem> sub_fw_items, sub_bw_items;
+  std::vector<int> sub_fw_off, sub_bw_off;
 };
 
 
@@ -177,6 +189,8 @@ struct Ctx {
   NDNodeH* d_nd_nodes = nullptr;
   int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr, *d_nd_pull = nullptr;
   NDItem *d_fw_items = nullptr, *d_bw_items = nullptr;
+  NDItem *d_sub_fw_items = nullptr, *d_sub_bw_items = nullptr;
+  int *d_sub_fw_off = nullptr, *d_sub_bw_off = nullptr;
   int* d_lvl_nodes = nullptr;
   int* d_flags = nullptr;      // device error flags [8]
   int* h_flags = nullptr;      // pinned host mirror

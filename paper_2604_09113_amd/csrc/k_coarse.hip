@@ -614,18 +614,14 @@ __device__ __forceinline__ double read_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// Forward items of the lower tree levels (many small fronts), one per wave,
-// four per workgroup: the same item as k_nd_fwd with at most R own rows.
-// Lane l pulls front position kb + l (own row) and boundary column r0 + l,
-// reads the R rows of M^T in its column, and takes w_k from lane k - kb.
+// Forward item with at most R own rows, taken by one wave: the item of
+// k_nd_fwd.  Lane l pulls front position kb + l (own row) and boundary
+// column r0 + l, reads the R rows of M^T in its column, and takes w_k from
+// lane k - kb.
 template <int R, int CK>
-__global__ __launch_bounds__(256) void k_nd_fwd_w(const NDItem* __restrict__ items, int nitems,
-                                                  const int2* __restrict__ pull, const double* __restrict__ F,
-                                                  const double* __restrict__ b, double* __restrict__ up,
-                                                  double* __restrict__ beff) {
-  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (it >= nitems) return;  // the whole wave
-  const NDItem d = items[it];
+__device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict__ pull,
+                                         const double* __restrict__ F, const double* __restrict__ b,
+                                         double* __restrict__ up, double* __restrict__ beff) {
   const int lane = threadIdx.x & 63, nf = d.ns + d.nb, r = d.first + lane;
   const int kb = d.kpart * ND_KPART, ke = min(d.ns, kb + R);
   const bool col_ok = r < d.nb;
@@ -662,19 +658,15 @@ __global__ __launch_bounds__(256) void k_nd_fwd_w(const NDItem* __restrict__ ite
   if (col_ok) up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w2 : 0.0) - acc;
 }
 
-// Backward items of the lower tree levels, one per wave, four per
-// workgroup: 16 own rows [k0, k0 + 16) of g_s = [F_ss^-1 | M^T] [b_eff; -g_b]
-// with nf <= 64 NCH.  Lane l owns columns l + 64c and gathers their vector
-// entries itself (no LDS); a reduce-scatter over the lanes leaves row
-// 8 b5 + 4 b4 + 2 b3 + b2 (bits of the lane id) in lanes with b1 = b0 = 0.
-static_assert(ND_BW_ROWS == 16, "k_nd_bwd_w takes items of 16 rows");
+// Backward item of 16 own rows [k0, k0 + 16) taken by one wave: rows of
+// g_s = [F_ss^-1 | M^T] [b_eff; -g_b] with nf <= 64 NCH.  Lane l owns columns
+// l + 64c and gathers their vector entries itself (no LDS); a reduce-scatter
+// over the lanes leaves row 8 b5 + 4 b4 + 2 b3 + b2 (bits of the lane id) in
+// the lanes with b1 = b0 = 0.
+static_assert(ND_BW_ROWS == 16, "bwd_task takes items of 16 rows");
 template <int NCH>
-__global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ items, int nitems,
-                                                  const int* __restrict__ bnd, const double* __restrict__ F,
-                                                  const double* __restrict__ beff, double* __restrict__ x) {
-  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (it >= nitems) return;  // the whole wave
-  const NDItem d = items[it];
+__device__ __forceinline__ void bwd_task(const NDItem& d, const int* __restrict__ bnd, const double* __restrict__ F,
+                                         const double* __restrict__ beff, double* __restrict__ x) {
   if (d.ns == 0) return;
   const int lane = threadIdx.x & 63, nf = d.ns + d.nb;
   int g[NCH];
@@ -741,6 +733,57 @@ __global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ ite
   if ((lane & 3) == 0 && d.first + q < d.ns) x[d.own_off + d.first + q] = t1;
 }
 
+// Items of the lower tree levels (many small fronts): one per wave, four
+// per workgroup.
+template <int R, int CK>
+__global__ __launch_bounds__(256) void k_nd_fwd_w(const NDItem* __restrict__ items, int nitems,
+                                                  const int2* __restrict__ pull, const double* __restrict__ F,
+                                                  const double* __restrict__ b, double* __restrict__ up,
+                                                  double* __restrict__ beff) {
+  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (it < nitems) fwd_task<R, CK>(items[it], pull, F, b, up, beff);
+}
+template <int NCH>
+__global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ items, int nitems,
+                                                  const int* __restrict__ bnd, const double* __restrict__ F,
+                                                  const double* __restrict__ beff, double* __restrict__ x) {
+  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (it < nitems) bwd_task<NCH>(items[it], bnd, F, beff, x);
+}
+
+// The bottom levels of the tree in one launch per sweep: workgroup = one
+// subtree, processed in nst stages (forward: deepest level first; backward:
+// the subtree root first), the stage's items taken by the four waves in turn.
+// The items of a stage read what the previous stages of the same workgroup
+// wrote to global memory (up vectors, solution entries): the barrier between
+// stages orders them at workgroup scope.  stage_off[(sub) (nst + 1) + s] is
+// the first item of stage s of subtree `sub`.
+template <int R, int CK>
+__global__ __launch_bounds__(256) void k_nd_fwd_sub(const NDItem* __restrict__ items,
+                                                    const int* __restrict__ stage_off, int nst,
+                                                    const int2* __restrict__ pull, const double* __restrict__ F,
+                                                    const double* __restrict__ b, double* __restrict__ up,
+                                                    double* __restrict__ beff) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* so = stage_off + (long long)blockIdx.x * (nst + 1);
+  for (int st = 0; st < nst; ++st) {
+    for (int it = so[st] + wv; it < so[st + 1]; it += 4) fwd_task<R, CK>(items[it], pull, F, b, up, beff);
+    __syncthreads();
+  }
+}
+template <int NCH>
+__global__ __launch_bounds__(256) void k_nd_bwd_sub(const NDItem* __restrict__ items,
+                                                    const int* __restrict__ stage_off, int nst,
+                                                    const int* __restrict__ bnd, const double* __restrict__ F,
+                                                    const double* __restrict__ beff, double* __restrict__ x) {
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* so = stage_off + (long long)blockIdx.x * (nst + 1);
+  for (int st = 0; st < nst; ++st) {
+    for (int it = so[st] + wv; it < so[st + 1]; it += 4) bwd_task<NCH>(items[it], bnd, F, beff, x);
+    __syncthreads();
+  }
+}
+
 template <int Q>
 static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDItem* items, const int* bnd,
                        const double* F, const double* beff, double* x) {
@@ -769,11 +812,40 @@ static void launch_fwd_w(int ck, int ni, hipStream_t st, const NDItem* items, co
     hipLaunchKernelGGL((k_nd_fwd_w<R, 8>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
 }
 
+template <int R>
+static void launch_fwd_sub(const Ctx* c, const double* rhs) {
+  const CoarseLayout& co = c->co;
+  const int ck = co.sub_child_kparts;
+  const dim3 grid(co.sub_count);
+  const int2* pull = (const int2*)c->d_nd_pull;
+  if (ck <= 1)
+    hipLaunchKernelGGL((k_nd_fwd_sub<R, 1>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
+                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+  else if (ck <= 2)
+    hipLaunchKernelGGL((k_nd_fwd_sub<R, 2>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
+                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+  else
+    hipLaunchKernelGGL((k_nd_fwd_sub<R, 8>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
+                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+}
+
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
   const int2* pull = (const int2*)c->d_nd_pull;
-  for (int l = L - 1; l >= 0; --l) {
+  // forward: the subtrees of the bottom levels, then the upper levels one launch each
+  if (co.sub_level < L) {
+    const int rows = co.sub_fw_rows;
+    if (rows <= 16)
+      launch_fwd_sub<16>(c, rhs);
+    else if (rows <= 32)
+      launch_fwd_sub<32>(c, rhs);
+    else if (rows <= 48)
+      launch_fwd_sub<48>(c, rhs);
+    else
+      launch_fwd_sub<64>(c, rhs);
+  }
+  for (int l = co.sub_level - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
     if (ni == 0) continue;
     const NDItem* it = c->d_fw_items + i0;
@@ -791,9 +863,9 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
     }
   }
   if (mid) hipEventRecord(mid, c->stream);
-  // LDS sized per level, so the many small fronts of the lower levels all fit
-  // on the chip; the upper levels' items were split when the lists were built
-  for (int l = 0; l < L; ++l) {
+  // backward: the upper levels one launch each (LDS sized per level; the upper
+  // levels' items were split when the lists were built), then the subtrees
+  for (int l = 0; l < co.sub_level; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
     if (ni == 0) continue;
     const NDItem* it = c->d_bw_items + i0;
@@ -817,6 +889,19 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
       launch_bwd<1>(nch, dim3(ni), lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
     else
       launch_bwd<ND_BW_ROWS / 4>(nch, dim3(ni), lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+  }
+  if (co.sub_level < L) {
+    const int nch = (std::max(1, co.sub_nfmax) + 63) / 64;
+    const dim3 grid(co.sub_count);
+    if (nch <= 2)
+      hipLaunchKernelGGL(k_nd_bwd_sub<2>, grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
+                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+    else if (nch <= 3)
+      hipLaunchKernelGGL(k_nd_bwd_sub<3>, grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
+                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+    else
+      hipLaunchKernelGGL(k_nd_bwd_sub<4>, grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
+                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
   }
   return hipGetLastError();
 }

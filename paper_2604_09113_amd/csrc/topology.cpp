@@ -206,6 +206,42 @@ bool build_topology(Ctx* c) {
     }
     co.nd_up_total = uoff;
   }
+  auto make_item = [&](int n) {
+    const NDNodeH& d = co.nd_nodes[n];
+    NDItem it{};
+    it.foff = d.foff;
+    it.ns = d.ns;
+    it.nb = d.nb;
+    it.own_off = d.own_off;
+    it.bnd_off = d.bnd_off;
+    it.up_off = d.up_off;
+    it.kparts = kparts[n];
+    for (int s = 0; s < 2; ++s) {
+      const int ch = d.child[s];
+      it.child_up_off[s] = ch >= 0 ? co.nd_nodes[ch].up_off : 0;
+      it.child_nb[s] = ch >= 0 ? co.nd_nodes[ch].nb : 0;
+      it.child_kparts[s] = ch >= 0 ? kparts[ch] : 0;
+    }
+    it.pull_off = pull_off[n];
+    return it;
+  };
+  auto push_fw = [&](int n, std::vector<NDItem>& out) {
+    NDItem it = make_item(n);
+    for (int kp = 0; kp < kparts[n]; ++kp)
+      for (int r = 0; r < std::max(1, co.nd_nodes[n].nb); r += 64) {
+        it.first = r;
+        it.kpart = kp;
+        out.push_back(it);
+      }
+  };
+  auto push_bw = [&](int n, int rows, std::vector<NDItem>& out) {
+    NDItem it = make_item(n);
+    it.kpart = 0;
+    for (int r = 0; r < std::max(1, co.nd_nodes[n].ns); r += rows) {
+      it.first = r;
+      out.push_back(it);
+    }
+  };
   co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear();
   co.fw_off.assign(1, 0); co.bw_off.assign(1, 0); co.lvl_off.assign(1, 0);
   co.lvl_nfmax.assign(L, 0);
@@ -223,37 +259,57 @@ bool build_topology(Ctx* c) {
       co.lvl_fw_rows[l] = std::max(co.lvl_fw_rows[l], std::min(d.ns, ND_KPART));
       for (int s = 0; s < 2; ++s)
         if (d.child[s] >= 0) co.lvl_child_kparts[l] = std::max(co.lvl_child_kparts[l], kparts[d.child[s]]);
-      NDItem it{};
-      it.foff = d.foff;
-      it.ns = d.ns;
-      it.nb = d.nb;
-      it.own_off = d.own_off;
-      it.bnd_off = d.bnd_off;
-      it.up_off = d.up_off;
-      it.kparts = kparts[n];
-      for (int s = 0; s < 2; ++s) {
-        const int ch = d.child[s];
-        it.child_up_off[s] = ch >= 0 ? co.nd_nodes[ch].up_off : 0;
-        it.child_nb[s] = ch >= 0 ? co.nd_nodes[ch].nb : 0;
-        it.child_kparts[s] = ch >= 0 ? kparts[ch] : 0;
-      }
-      it.pull_off = pull_off[n];
-      for (int kp = 0; kp < kparts[n]; ++kp)
-        for (int r = 0; r < std::max(1, d.nb); r += 64) {
-          it.first = r;
-          it.kpart = kp;
-          co.fw_items.push_back(it);
-        }
-      it.kpart = 0;
-      for (int r = 0; r < std::max(1, d.ns); r += co.lvl_bw_rows[l]) {
-        it.first = r;
-        co.bw_items.push_back(it);
-      }
+      push_fw(n, co.fw_items);
+      push_bw(n, co.lvl_bw_rows[l], co.bw_items);
       co.lvl_nodes.push_back(n);
     }
     co.fw_off.push_back((int)co.fw_items.size());
     co.bw_off.push_back((int)co.bw_items.size());
     co.lvl_off.push_back((int)co.lvl_nodes.size());
+  }
+  // subtree sweeps of the bottom levels
+  co.sub_level = L;
+  co.sub_nst = 0;
+  co.sub_count = 0;
+  co.sub_fw_items.clear(); co.sub_bw_items.clear(); co.sub_fw_off.clear(); co.sub_bw_off.clear();
+  {
+    const int ls = L - ND_SUB_LEVELS;
+    bool use = ls >= 1 && (int)co.nd_levels[ls].size() >= ND_SUB_MIN_ROOTS;
+    for (int l = std::max(ls, 0); use && l < L; ++l) use = co.lvl_nfmax[l] <= ND_SUB_MAX_NF;
+    if (use) {
+      co.sub_level = ls;
+      co.sub_nst = L - ls;
+      co.sub_count = (int)co.nd_levels[ls].size();
+      co.sub_fw_rows = co.sub_child_kparts = co.sub_nfmax = 0;
+      for (int l = ls; l < L; ++l) {
+        co.sub_fw_rows = std::max(co.sub_fw_rows, co.lvl_fw_rows[l]);
+        co.sub_child_kparts = std::max(co.sub_child_kparts, co.lvl_child_kparts[l]);
+        co.sub_nfmax = std::max(co.sub_nfmax, co.lvl_nfmax[l]);
+      }
+      for (int root : co.nd_levels[ls]) {
+        // nodes of the subtree by level
+        std::vector<std::vector<int>> by(co.sub_nst);
+        std::vector<int> stack{root};
+        while (!stack.empty()) {
+          const int n = stack.back();
+          stack.pop_back();
+          by[co.nd_nodes[n].level - ls].push_back(n);
+          for (int s2 = 1; s2 >= 0; --s2)
+            if (co.nd_nodes[n].child[s2] >= 0) stack.push_back(co.nd_nodes[n].child[s2]);
+        }
+        for (auto& v : by) std::sort(v.begin(), v.end());
+        for (int st = 0; st < co.sub_nst; ++st) {
+          co.sub_fw_off.push_back((int)co.sub_fw_items.size());
+          for (int n : by[co.sub_nst - 1 - st]) push_fw(n, co.sub_fw_items);
+        }
+        co.sub_fw_off.push_back((int)co.sub_fw_items.size());
+        for (int st = 0; st < co.sub_nst; ++st) {
+          co.sub_bw_off.push_back((int)co.sub_bw_items.size());
+          for (int n : by[st]) push_bw(n, ND_BW_ROWS, co.sub_bw_items);
+        }
+        co.sub_bw_off.push_back((int)co.sub_bw_items.size());
+      }
+    }
   }
 
   // net owners for the gradient gather
@@ -295,6 +351,8 @@ bool build_topology(Ctx* c) {
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
          up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) &&
          up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_nd_pull, co.nd_pull) && up(&c->d_fw_items, co.fw_items) &&
+         up(&c->d_sub_fw_items, co.sub_fw_items) && up(&c->d_sub_bw_items, co.sub_bw_items) &&
+         up(&c->d_sub_fw_off, co.sub_fw_off) && up(&c->d_sub_bw_off, co.sub_bw_off) &&
          up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes);
 }
 
