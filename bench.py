@@ -239,6 +239,7 @@ def main():
     flops = assembly_flops(prob, roms)
     kb = kernel_bytes(prob, roms, nC)
     levels = s.query(lbddc.Q_COARSE_LEVELS)
+    launches = s.query(lbddc.Q_COARSE_SWEEP_LAUNCHES)  # per sweep
     fwd_bytes = s.query(lbddc.Q_COARSE_FWD_BYTES)
     bwd_bytes = s.query(lbddc.Q_COARSE_SOLVE_BYTES) - fwd_bytes
 
@@ -263,13 +264,13 @@ def main():
             e = hbm(kb["pre"](4), ph["pre_kernel"])
         elif name == "coarse_solve":
             # both nested-dissection sweeps read [F_ss^-1 | M^T] of every front: 8 ns (ns + 2 nb) bytes
-            e = dict(hbm(s.query(lbddc.Q_COARSE_SOLVE_BYTES), ph["coarse_solve"]), launches=2 * levels)
+            e = dict(hbm(s.query(lbddc.Q_COARSE_SOLVE_BYTES), ph["coarse_solve"]), launches=2 * launches, tree_levels=levels)
         elif name == "k_nd_fwd":
             # forward sweep (one launch per tree level): M^T of every front, 8 ns nb bytes
-            e = dict(hbm(fwd_bytes, ph["coarse_fwd_sweep"]), launches_per_solve=levels)
+            e = dict(hbm(fwd_bytes, ph["coarse_fwd_sweep"]), launches_per_solve=launches)
         elif name == "k_nd_bwd":
             # backward sweep: [F_ss^-1 | M^T] of every front, 8 ns (ns + nb) bytes
-            e = dict(hbm(bwd_bytes, ph["coarse_bwd_sweep"]), launches_per_solve=levels)
+            e = dict(hbm(bwd_bytes, ph["coarse_bwd_sweep"]), launches_per_solve=launches)
         else:
             raise KeyError(name)
         e["frac"] = e["achieved"] / e["peak"]
@@ -341,9 +342,10 @@ def main():
     roof["kernel"] = dom
     roof["ms_per_step"] = per_step_ms(timed, mixed["iters"])[dom]
     if dom in ("k_nd_fwd", "k_nd_bwd"):
-        roof["launches_per_solve"] = levels
-        roof["note"] = ("per-launch average = event-timed sweep of the back-to-back level launches / levels; "
-                        "algorithmic bytes per launch = sweep bytes / levels")
+        roof["launches_per_solve"] = launches
+        roof["note"] = ("the sweep is one launch per upper tree level plus one for the bottom-level subtrees "
+                        "(k_nd_*, k_nd_*_w, k_nd_*_sub); per-launch average = event-timed sweep / launches; "
+                        "algorithmic bytes per launch = sweep bytes / launches")
     roof["traffic"] = measured_traffic(dom)
     value = ncell / (mixed["ms_per_step"] * 1e-3)
     out = {

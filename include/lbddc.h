@@ -179,7 +179,11 @@ enum {
   /* number of levels of the nested-dissection tree of the coarse problem */
   LBDDC_Q_COARSE_LEVELS = 12,
   /* bytes of coarse-factor data the forward sweep of one coarse solve reads */
-  LBDDC_Q_COARSE_FWD_BYTES = 13
+  LBDDC_Q_COARSE_FWD_BYTES = 13,
+  /* kernel launches of one sweep of a coarse solve: one per tree level above
+   * the bottom levels that are swept one subtree per workgroup, plus one for
+   * those (equal to the number of levels when no subtree sweep is used) */
+  LBDDC_Q_COARSE_SWEEP_LAUNCHES = 14
 };
 lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
 

@@ -575,6 +575,12 @@ lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
       *v = b;
       break;
     }
+    case LBDDC_Q_COARSE_SWEEP_LAUNCHES: {
+      // levels above the subtree levels one launch each, the subtrees one
+      const int L = (int)c->co.nd_levels.size();
+      *v = c->co.sub_level < L ? c->co.sub_level + 1 : L;
+      break;
+    }
     default: return LBDDC_E_ARG;
   }
   return LBDDC_OK;

@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE",
 FP64, MIXED, FP32_CONTRACTION = 0, 1, 2
 X_K, X_THETA, X_ITIL, X_S, X_D, X_PSI, X_SC, X_LOAD, X_FINE = range(9)
 Q_NCELL, Q_NDOF_FREE, Q_N_SKELETON, Q_N_INTERIOR, Q_N_COARSE, Q_N_I_ROM, Q_NU_CELL, Q_NC_CELL, Q_NRHS, \
-    Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES = range(14)
+    Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES, \
+    Q_COARSE_SWEEP_LAUNCHES = range(15)
 TIME_OP, TIME_PRE, TIME_COARSE, TIME_ALL = 1, 2, 4, 7
 PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor", "solve", "op_kernel",
           "pre_kernel", "coarse_solve", "recovery", "gradient", "adjoint_kernel", "coarse_fwd_sweep",
