@@ -82,21 +82,22 @@ def kernel_bytes(prob, roms, nC):
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
-    counter record (profiles/lattice128_p8_hbm_traffic.md), or None when there is
+    counter records (profiles/lattice128_p8_hbm_traffic.md), or None when there is
     no record for it or its source file has changed since the counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "lattice128_p8_hbm_traffic.md")
     try:
         for line in open(path):
-            if line.startswith("traffic-record:"):
-                rec = json.loads(line.split(":", 1)[1])
-                if rec["kernel"] != kernel:
-                    return None
-                src = open(os.path.join(root, rec["source"]), "rb").read()
-                if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
-                    return None
-                return (rec["fetch_bytes_per_solve"] + rec["write_bytes_per_solve"]) / rec["launches_per_solve"]
+            if not line.startswith("traffic-record:"):
+                continue
+            rec = json.loads(line.split(":", 1)[1])
+            if rec["kernel"] != kernel:
+                continue
+            src = open(os.path.join(root, rec["source"]), "rb").read()
+            if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+                return None
+            return (rec["fetch_bytes_per_solve"] + rec["write_bytes_per_solve"]) / rec["launches_per_solve"]
     except (OSError, ValueError, KeyError):
         return None
     return None
