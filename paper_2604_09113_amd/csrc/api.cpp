@@ -319,6 +319,8 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_itil, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_itil32, (size_t)ncell * 4 * c->KC) &&
             dalloc_t(c, &c->d_cluster, ncell) && dalloc_t(c, &c->d_sorted, ncell) &&
             dalloc_t(c, &c->d_tiles, (size_t)4 * (ncell / 16 + 64) + 64) &&
+            dalloc_t(c, &c->d_theta_t, (size_t)(ncell / 128 + 17) * c->ns * 512) &&
+            dalloc_t(c, &c->d_theta_t32, (size_t)(ncell / 128 + 17) * c->ns * 512) &&
             dalloc_t(c, &c->d_K, (size_t)ncell * c->npair * 4) &&
             dalloc_t(c, &c->d_load, (size_t)c->nrhs * ncell * nU) &&
             dalloc_t(c, &c->d_cons, (size_t)ncell * 4 * c->nce * (c->p + 1) * 2) &&

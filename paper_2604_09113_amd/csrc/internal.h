@@ -202,6 +202,10 @@ struct Ctx {
   float* d_itil32 = nullptr;
   int* d_cluster = nullptr;    // [ncell] group id
   int* d_sorted = nullptr;     // [ncell] cells sorted by group
+  // theta of the cells of each contraction tile, step-major: [tile][ns][128][4]
+  // (one 16-cell block of one step is 16 consecutive entries)
+  double* d_theta_t = nullptr;
+  float* d_theta_t32 = nullptr;
   int* d_tiles = nullptr;      // [ntiles][4]: group, start, count, -
   int ntiles = 0;
   double* d_K = nullptr;       // [ncell][npair][4]

@@ -15,6 +15,10 @@
 // Workgroup: 4 waves x 32 cells on one 16-pair tile; consecutive workgroups
 // walk the cells of one (family, cluster) group, so a pair tile of Uhat is
 // streamed from L2 by every workgroup on an XCD at about the same time.
+// The geometry coefficients are read from a copy in tile order
+// ([tile][s][128 cells][4], k_theta_tile): the 16 cells of a block at one step
+// are one contiguous 256 B (FP32) segment, where the cell-major array would
+// touch 16 cache lines per load, re-read for every one of the ~208 pair tiles.
 #include "internal.h"
 
 namespace lbddc {
@@ -30,8 +34,24 @@ __device__ inline dbl4 mfma(double a, double b, dbl4 c) { return __builtin_amdgc
 __device__ inline flt4 mfma(float a, float b, flt4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 
 // tiles[i] = {group, first position in `sorted`, number of cells, unused}
+// theta_t[tile][s][o][e] = theta[sorted[start + o]][s][e] for the tile's
+// cells o < count, zero for the unused slots of a partial tile
+template <typename T>
+__global__ __launch_bounds__(256) void k_theta_tile(const T* __restrict__ theta, const int* __restrict__ sorted,
+                                                    const int4* __restrict__ tiles, int ns, T* __restrict__ theta_t) {
+  typedef typename V4<T>::type v4;
+  const int4 td = tiles[blockIdx.x];
+  T* out = theta_t + (size_t)blockIdx.x * ns * 512;
+  for (int i = threadIdx.x; i < ns * 128; i += 256) {
+    const int st = i >> 7, o = i & 127;
+    v4 v = v4{0, 0, 0, 0};
+    if (o < td.z) v = *reinterpret_cast<const v4*>(theta + ((size_t)sorted[td.y + o] * ns + st) * 4);
+    *reinterpret_cast<v4*>(out + (size_t)i * 4) = v;
+  }
+}
+
 template <typename T, int KC>
-__global__ __launch_bounds__(256) void k_assemble(const T* const* __restrict__ utg, const T* __restrict__ theta,
+__global__ __launch_bounds__(256) void k_assemble(const T* const* __restrict__ utg, const T* __restrict__ theta_t,
                                                   const T* __restrict__ itil, const int* __restrict__ sorted,
                                                   const int4* __restrict__ tiles, T* __restrict__ K, int ns,
                                                   int npair, int itil_stride) {
@@ -58,32 +78,45 @@ __global__ __launch_bounds__(256) void k_assemble(const T* const* __restrict__ u
   for (int bk = 0; bk < 2; ++bk)
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[bk][e] = v4{0, 0, 0, 0};
-  const T* ap = utg[td.x] + (size_t)pt * ns * KC * 64 + lane;
-  const T* th0 = theta + (size_t)cidx[0] * ns * 4;
-  const T* th1 = theta + (size_t)cidx[1] * ns * 4;
-  T a[KC];
+  // The group's Uhat is read through a pointer loaded from memory: say that it
+  // is global memory, so the loads are global loads (a flat load would also be
+  // counted by the LDS/scalar counter, whose waits would then drain the
+  // prefetch).  Two register sets take the steps of s in turn, each reloaded
+  // (for s + 2) right after the step that used it, without copies between
+  // them, so every load has a whole step of MFMA work to arrive.
+  typedef const T __attribute__((address_space(1)))* GP;
+  const GP ap = (GP)utg[td.x] + (size_t)pt * ns * KC * 64 + lane;
+  const T* th0 = theta_t + ((size_t)blockIdx.x * ns * 128 + wave * 32 + col) * 4;
+  const T* th1 = th0 + 16 * 4;
+  T aA[KC], aB[KC];
+  v4 tA0, tA1, tB0, tB1;
+  auto load = [&](int sl, T (&a)[KC], v4& t0, v4& t1) {
+    sl = sl < ns ? sl : ns - 1;  // past the end: a valid step, not used
 #pragma unroll
-  for (int kc = 0; kc < KC; ++kc) a[kc] = ap[kc * 64];
-  for (int s = 0; s < ns; ++s) {
-    T an[KC];
-    const int sn = s + 1 < ns ? s + 1 : s;
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) an[kc] = ap[((size_t)sn * KC + kc) * 64];
+    for (int kc = 0; kc < KC; ++kc) a[kc] = ap[((size_t)sl * KC + kc) * 64];
+    t0 = *reinterpret_cast<const v4*>(th0 + (size_t)sl * 512);
+    t1 = *reinterpret_cast<const v4*>(th1 + (size_t)sl * 512);
+  };
+  auto step = [&](const T (&a)[KC], const v4& t0, const v4& t1) {
     v4 d0 = v4{0, 0, 0, 0}, d1 = v4{0, 0, 0, 0};
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       d0 = mfma(a[kc], b[0][kc], d0);
       d1 = mfma(a[kc], b[1][kc], d1);
     }
-    const v4 t0 = *reinterpret_cast<const v4*>(th0 + s * 4);
-    const v4 t1 = *reinterpret_cast<const v4*>(th1 + s * 4);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       acc[0][e] += t0[e] * d0;
       acc[1][e] += t1[e] * d1;
     }
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) a[kc] = an[kc];
+  };
+  load(0, aA, tA0, tA1);
+  load(1, aB, tB0, tB1);
+  for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
+    step(aA, tA0, tA1);
+    load(s + 2, aA, tA0, tA1);
+    step(aB, tB0, tB1);
+    load(s + 3, aB, tB0, tB1);
   }
   // lane (grp, col) holds pairs 4*grp + v of its cell
 #pragma unroll
@@ -140,6 +173,7 @@ static hipError_t launch_family(Ctx* c, const T* const* d_utg, int KC, const T* 
                                 const int4* tiles, int ntiles, T* K) {
   dim3 grid(ntiles, c->NPT), block(256);
   const int st = 4 * c->KC;
+  if (c->ns % 2 != 0) return hipErrorInvalidValue;  // the kernel takes the steps of s in pairs
 #define LB_CASE(kc)                                                                                       \
   case kc:                                                                                                \
     hipLaunchKernelGGL((k_assemble<T, kc>), grid, block, 0, c->stream, d_utg, theta, itil, c->d_sorted, \
@@ -208,15 +242,26 @@ hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
   void** d_ptrs = (void**)(c->d_tiles + 4 * (c->ncell / 16 + 64));
   e = hipMemcpyAsync(d_ptrs, ptrs.data(), G * sizeof(void*), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
+  if (c->ntiles > c->ncell / 128 + 17) return hipErrorInvalidValue;  // size of the tile-ordered theta
   if (e0) hipEventRecord(e0, c->stream);
+  const int4* d_tl = reinterpret_cast<const int4*>(c->d_tiles);
+  if (fp32)
+    hipLaunchKernelGGL(k_theta_tile<float>, dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta32, c->d_sorted, d_tl,
+                       c->ns, c->d_theta_t32);
+  else
+    hipLaunchKernelGGL(k_theta_tile<double>, dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta, c->d_sorted, d_tl,
+                       c->ns, c->d_theta_t);
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     if (fam_n[s] == 0) continue;
-    const int4* tl = reinterpret_cast<const int4*>(c->d_tiles) + fam_first[s];
+    const int4* tl = d_tl + fam_first[s];
+    const size_t toff = (size_t)fam_first[s] * c->ns * 512;
     const int KC = c->roms[c->fam_ids[s]].KC;
     if (fp32)
-      e = launch_family<float>(c, (const float* const*)d_ptrs, KC, c->d_theta32, c->d_itil32, tl, fam_n[s], c->d_K32);
+      e = launch_family<float>(c, (const float* const*)d_ptrs, KC, c->d_theta_t32 + toff, c->d_itil32, tl, fam_n[s],
+                               c->d_K32);
     else
-      e = launch_family<double>(c, (const double* const*)d_ptrs, KC, c->d_theta, c->d_itil, tl, fam_n[s], c->d_K);
+      e = launch_family<double>(c, (const double* const*)d_ptrs, KC, c->d_theta_t + toff, c->d_itil, tl, fam_n[s],
+                                c->d_K);
     if (e != hipSuccess) return e;
   }
   if (e1) hipEventRecord(e1, c->stream);
