@@ -47,8 +47,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
   for (int rb = 0; rb < RB; ++rb) hacc[rb] = dbl4{0, 0, 0, 0};
   const double* uc = ucell + (size_t)cell * ndof;
   const double* th = theta + (size_t)cell * ns * 4;
-  const double* ut = utg[td.x];
-  const double* ut2 = ut2g[td.x];
+  // the group's Uhat tiles are read through pointers loaded from memory: say
+  // that they are global memory (a flat load would also be counted by the
+  // LDS/scalar counter, whose waits drain the prefetch)
+  typedef const double __attribute__((address_space(1)))* GP;
+  const GP ut = (GP)utg[td.x];
+  const GP ut2 = (GP)ut2g[td.x];
   __syncthreads();
   // products w_P u[n1, i1] u[n2, i2] of the pair rows this lane feeds (4 pairs x 4 components)
   auto pair_products = [&](int pt, double (&uu)[4][4]) {
@@ -68,61 +72,66 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
   dbl4 hacc2[RB];  // second accumulator chain of H (odd kk), added in a fixed order at the end
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) hacc2[rb] = dbl4{0, 0, 0, 0};
-  double uu[4][4], un[4][4];
-  pair_products(wave, uu);
-  for (int pt = wave; pt < NPT; pt += 4) {
-    pair_products(pt + 4, un);  // next pair tile: loads overlap this tile's work
-    const double* ap = ut + (size_t)pt * ns * KC * 64 + lane;
-    const double* ap2 = ut2 + (size_t)pt * ns * RB * 4 * 64 + lane;
-    // operands of step s are requested one step ahead
-    double a[KC], a2[RB][4];
+  // MFMA operands of step s of pair tile pt; steps past the end belong to the
+  // wave's next tile (pt + 4), and past the last tile to any valid address
+  auto load = [&](int ptl, int sl, double (&a)[KC], double (&a2)[RB][4]) {
+    if (sl >= ns) {
+      sl -= ns;
+      ptl += 4;
+    }
+    if (ptl >= NPT) ptl = NPT - 1;
+    const GP ap = ut + ((size_t)ptl * ns + sl) * KC * 64 + lane;
+    const GP ap2 = ut2 + ((size_t)ptl * ns + sl) * RB * 4 * 64 + lane;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) a[kc] = ap[kc * 64];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) a2[rb][kk] = ap2[(rb * 4 + kk) * 64];
-    for (int s = 0; s < ns; ++s) {
-      const int sn = s + 1 < ns ? s + 1 : s;
-      double an[KC], an2[RB][4];
+  };
+  double uu[4][4], un[4][4];
+  // one step: Ihat of the 16 pairs x 16 cells on MFMA, H += Uhat2^T Z, G += u u Ihat
+  auto step = [&](int s, const double (&a)[KC], const double (&a2)[RB][4]) {
+    dbl4 d = dbl4{0, 0, 0, 0};
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) an[kc] = ap[(sn * KC + kc) * 64];
+    for (int kc = 0; kc < KC; ++kc) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], b[kc], d, 0, 0, 0);
+    const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + s * 4);
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+    for (int kk = 0; kk < 4; ++kk) {
+      const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) an2[rb][kk] = ap2[((sn * RB + rb) * 4 + kk) * 64];
-      dbl4 d = dbl4{0, 0, 0, 0};
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], b[kc], d, 0, 0, 0);
-      const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + s * 4);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          if (kk & 1) hacc2[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc2[rb], 0, 0, 0);
-          else hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc[rb], 0, 0, 0);
-        }
+      for (int rb = 0; rb < RB; ++rb) {
+        if (kk & 1) hacc2[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc2[rb], 0, 0, 0);
+        else hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc[rb], 0, 0, 0);
       }
-      // this lane's 4 pairs' contributions to the 4 components e; the 16-lane
-      // groups then reduce-scatter so that group grp holds the total of e = grp:
-      // across 32 lanes each lane keeps the half of e its group ends in, then
-      // across 16 lanes the one component
-      double g[4];
+    }
+    // this lane's 4 pairs' contributions to the 4 components e; the 16-lane
+    // groups then reduce-scatter so that group grp holds the total of e = grp:
+    // across 32 lanes each lane keeps the half of e its group ends in, then
+    // across 16 lanes the one component
+    double g[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) g[e] = uu[0][e] * d[0] + uu[1][e] * d[1] + uu[2][e] * d[2] + uu[3][e] * d[3];
-      const int hi = grp >> 1, lo = grp & 1;
-      const double k0 = hi ? g[2] : g[0], k1 = hi ? g[3] : g[1];
-      const double s0 = hi ? g[0] : g[2], s1 = hi ? g[1] : g[3];
-      const double x0 = k0 + __shfl_xor(s0, 32), x1 = k1 + __shfl_xor(s1, 32);
-      const double gm = (lo ? x1 : x0) + __shfl_xor(lo ? x0 : x1, 16);
-      Gw[(col * ns + s) * 4 + grp] += gm;
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) a[kc] = an[kc];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) a2[rb][kk] = an2[rb][kk];
+    for (int e = 0; e < 4; ++e) g[e] = uu[0][e] * d[0] + uu[1][e] * d[1] + uu[2][e] * d[2] + uu[3][e] * d[3];
+    const int hi = grp >> 1, lo = grp & 1;
+    const double k0 = hi ? g[2] : g[0], k1 = hi ? g[3] : g[1];
+    const double s0 = hi ? g[0] : g[2], s1 = hi ? g[1] : g[3];
+    const double x0 = k0 + __shfl_xor(s0, 32), x1 = k1 + __shfl_xor(s1, 32);
+    const double gm = (lo ? x1 : x0) + __shfl_xor(lo ? x0 : x1, 16);
+    Gw[(col * ns + s) * 4 + grp] += gm;
+  };
+  // two operand sets take the steps in turn, each reloaded (two steps ahead)
+  // right after the step that used it, without copies between them
+  double aA[KC], a2A[RB][4], aB[KC], a2B[RB][4];
+  load(wave, 0, aA, a2A);
+  load(wave, 1, aB, a2B);
+  pair_products(wave, uu);
+  for (int pt = wave; pt < NPT; pt += 4) {
+    pair_products(pt + 4, un);  // next pair tile: loads overlap this tile's work
+    for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
+      step(s, aA, a2A);
+      load(pt, s + 2, aA, a2A);
+      step(s + 1, aB, a2B);
+      load(pt, s + 3, aB, a2B);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -329,6 +338,7 @@ template <int KC>
 static void launch_adj(Ctx* c, const double* const* pu, const double* const* pu2, const int4* tiles, int ntiles,
                        const int2* pairs, const double* ucell) {
   constexpr int RB = (4 * KC + 15) / 16;
+  if (c->ns % 2 != 0) return;  // the kernel takes the steps of s in pairs (ns = 4 (q + 1)^2)
   const size_t lds = (size_t)4 * 16 * c->ns * 4 * sizeof(double);
   hipLaunchKernelGGL((k_adjoint<KC, RB>), dim3(ntiles), dim3(256), lds, c->stream, pu, pu2, c->d_theta, c->d_itil,
                      ucell, c->d_sorted, tiles, pairs, c->d_H, c->d_G, c->ns, c->npair, c->NPT, 4 * c->KC,
