@@ -203,7 +203,8 @@ struct Ctx {
   int* d_cluster = nullptr;    // [ncell] group id
   int* d_sorted = nullptr;     // [ncell] cells sorted by group
   // theta of the cells of each contraction tile, step-major: [tile][ns][128][4]
-  // (one 16-cell block of one step is 16 consecutive entries)
+  // (one 16-cell block of one step is 16 consecutive entries); the gradient
+  // reuses the FP64 buffer for its 16-cell tiles ([tile][ns][16][4])
   double* d_theta_t = nullptr;
   float* d_theta_t32 = nullptr;
   int* d_tiles = nullptr;      // [ntiles][4]: group, start, count, -
@@ -285,6 +286,7 @@ void build_tables(Ctx* c, std::vector<double>& tab);
 hipError_t launch_geometry(Ctx* c);          // theta, det check, MDEIM eval (A1, A2)
 hipError_t launch_constraints_loads(Ctx* c); // edge constraint rows and loads
 hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1);  // A3
+hipError_t launch_theta_tile16(Ctx* c, const int4* tiles, int ntiles, double* out);  // A11 (theta in tile order)
 hipError_t launch_schur(Ctx* c);             // A4
 hipError_t launch_weights(Ctx* c);           // A7 (gather of stiffness diagonals)
 hipError_t launch_precond(Ctx* c, bool fp32); // A5, A6, A7

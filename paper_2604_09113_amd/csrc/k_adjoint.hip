@@ -46,7 +46,9 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) hacc[rb] = dbl4{0, 0, 0, 0};
   const double* uc = ucell + (size_t)cell * ndof;
-  const double* th = theta + (size_t)cell * ns * 4;
+  // theta in tile order ([tile][s][16 cells][4]): one step of the tile's 16
+  // cells is one contiguous 512 B segment
+  const double* th = theta + ((size_t)blockIdx.x * ns * 16 + col) * 4;
   // the group's Uhat tiles are read through pointers loaded from memory: say
   // that they are global memory (a flat load would also be counted by the
   // LDS/scalar counter, whose waits drain the prefetch)
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
     dbl4 d = dbl4{0, 0, 0, 0};
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc], b[kc], d, 0, 0, 0);
-    const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + s * 4);
+    const dbl4 t4 = *reinterpret_cast<const dbl4*>(th + (size_t)s * 64);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
@@ -336,11 +338,11 @@ __global__ void k_compliance(const double* __restrict__ part, int n, double* __r
 
 template <int KC>
 static void launch_adj(Ctx* c, const double* const* pu, const double* const* pu2, const int4* tiles, int ntiles,
-                       const int2* pairs, const double* ucell) {
+                       const int2* pairs, const double* ucell, const double* theta16) {
   constexpr int RB = (4 * KC + 15) / 16;
   if (c->ns % 2 != 0) return;  // the kernel takes the steps of s in pairs (ns = 4 (q + 1)^2)
   const size_t lds = (size_t)4 * 16 * c->ns * 4 * sizeof(double);
-  hipLaunchKernelGGL((k_adjoint<KC, RB>), dim3(ntiles), dim3(256), lds, c->stream, pu, pu2, c->d_theta, c->d_itil,
+  hipLaunchKernelGGL((k_adjoint<KC, RB>), dim3(ntiles), dim3(256), lds, c->stream, pu, pu2, theta16, c->d_itil,
                      ucell, c->d_sorted, tiles, pairs, c->d_H, c->d_G, c->ns, c->npair, c->NPT, 4 * c->KC,
                      c->ndof);
 }
@@ -377,23 +379,26 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   if (e != hipSuccess) return e;
   const double* const* pu = (const double* const*)c->d_adj_ptrs;
   hipEventRecord(c->ev[0], c->stream);
+  e = launch_theta_tile16(c, reinterpret_cast<const int4*>(c->d_adj_tiles), (int)tiles.size() / 4, c->d_theta_t);
+  if (e != hipSuccess) return e;
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     if (fam_n[s] == 0) continue;
     const int4* tl = reinterpret_cast<const int4*>(c->d_adj_tiles) + fam_first[s];
     const int2* pr = reinterpret_cast<const int2*>(c->d_pairs);
     const double* uc = c->d_ucell + (size_t)rhs * c->ncell * c->ndof;
+    const double* th = c->d_theta_t + (size_t)fam_first[s] * c->ns * 64;
     switch (c->roms[c->fam_ids[s]].KC) {
-      case 1: launch_adj<1>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 2: launch_adj<2>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 3: launch_adj<3>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 4: launch_adj<4>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 5: launch_adj<5>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 6: launch_adj<6>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 7: launch_adj<7>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 8: launch_adj<8>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 9: launch_adj<9>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 10: launch_adj<10>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
-      case 11: launch_adj<11>(c, pu, pu + G, tl, fam_n[s], pr, uc); break;
+      case 1: launch_adj<1>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 2: launch_adj<2>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 3: launch_adj<3>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 4: launch_adj<4>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 5: launch_adj<5>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 6: launch_adj<6>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 7: launch_adj<7>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 8: launch_adj<8>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 9: launch_adj<9>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 10: launch_adj<10>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 11: launch_adj<11>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
       default: return hipErrorInvalidValue;
     }
     e = hipGetLastError();

@@ -35,19 +35,27 @@ __device__ inline flt4 mfma(float a, float b, flt4 c) { return __builtin_amdgcn_
 
 // tiles[i] = {group, first position in `sorted`, number of cells, unused}
 // theta_t[tile][s][o][e] = theta[sorted[start + o]][s][e] for the tile's
-// cells o < count, zero for the unused slots of a partial tile
-template <typename T>
+// cells o < count (TS cells per tile), zero for the unused slots of a partial tile
+template <typename T, int TS>
 __global__ __launch_bounds__(256) void k_theta_tile(const T* __restrict__ theta, const int* __restrict__ sorted,
                                                     const int4* __restrict__ tiles, int ns, T* __restrict__ theta_t) {
   typedef typename V4<T>::type v4;
   const int4 td = tiles[blockIdx.x];
-  T* out = theta_t + (size_t)blockIdx.x * ns * 512;
-  for (int i = threadIdx.x; i < ns * 128; i += 256) {
-    const int st = i >> 7, o = i & 127;
+  T* out = theta_t + (size_t)blockIdx.x * ns * TS * 4;
+  for (int i = threadIdx.x; i < ns * TS; i += 256) {
+    const int st = i / TS, o = i % TS;
     v4 v = v4{0, 0, 0, 0};
     if (o < td.z) v = *reinterpret_cast<const v4*>(theta + ((size_t)sorted[td.y + o] * ns + st) * 4);
     *reinterpret_cast<v4*>(out + (size_t)i * 4) = v;
   }
+}
+
+// the FP64 coefficients in the order of 16-cell tiles (the adjoint's tiles)
+hipError_t launch_theta_tile16(Ctx* c, const int4* tiles, int ntiles, double* out) {
+  if ((size_t)ntiles * 16 > (size_t)(c->ncell / 128 + 17) * 128) return hipErrorInvalidValue;  // buffer size
+  hipLaunchKernelGGL((k_theta_tile<double, 16>), dim3(ntiles), dim3(256), 0, c->stream, c->d_theta, c->d_sorted,
+                     tiles, c->ns, out);
+  return hipGetLastError();
 }
 
 template <typename T, int KC>
@@ -246,10 +254,10 @@ hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
   if (e0) hipEventRecord(e0, c->stream);
   const int4* d_tl = reinterpret_cast<const int4*>(c->d_tiles);
   if (fp32)
-    hipLaunchKernelGGL(k_theta_tile<float>, dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta32, c->d_sorted, d_tl,
+    hipLaunchKernelGGL((k_theta_tile<float, 128>), dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta32, c->d_sorted, d_tl,
                        c->ns, c->d_theta_t32);
   else
-    hipLaunchKernelGGL(k_theta_tile<double>, dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta, c->d_sorted, d_tl,
+    hipLaunchKernelGGL((k_theta_tile<double, 128>), dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta, c->d_sorted, d_tl,
                        c->ns, c->d_theta_t);
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     if (fam_n[s] == 0) continue;
