@@ -21,6 +21,12 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wno-unused-result", "-I" + os.path.join(HERE, "..", "include")]
 
 
+# Per-file flags.  The stiffness contraction reads every MFMA result with
+# ordinary VALU instructions right away, so its MFMAs write VGPRs directly
+# instead of accumulation registers that would first have to be copied out.
+EXTRA = {"k_assembly.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def sources():
     return sorted(f for f in os.listdir(SRC) if f.endswith((".hip", ".cpp")))
 
@@ -28,9 +34,9 @@ def sources():
 def _compile(name):
     src = os.path.join(SRC, name)
     obj = os.path.join(OUT, name + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA.get(name, []) + ["-c", src, "-o", obj]
     if name.endswith(".cpp"):
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
+        cmd = [HIPCC] + FLAGS + EXTRA.get(name, []) + ["-x", "hip", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     errs = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     return name, r.returncode, errs, obj
