@@ -337,7 +337,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
             dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
             dalloc_t(c, &c->d_zc, NC) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC) &&
-            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 272)) && dalloc_t(c, &c->d_scal, 32) &&
+            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 272)) && dalloc_t(c, &c->d_scal, (size_t)(32 + NU / 1024 + 16)) &&
             dalloc_t(c, &c->d_vred, (size_t)3 * (NU / 256 + 16)) &&
             dalloc_t(c, &c->d_u, (size_t)c->nrhs * c->Gx * c->Gy * 2) &&
             dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&
@@ -347,7 +347,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
             dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8) &&
             dalloc_t(c, &c->d_pairs, (size_t)2 * c->npair);
-  if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(c->NU / 1024 + 16) * sizeof(double)) != hipSuccess) {
+  if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(32 + c->NU / 1024 + 16) * sizeof(double)) != hipSuccess) {
     c->h_red = nullptr;
     c->err = "pinned host allocation failed";
     ok = false;

@@ -182,6 +182,10 @@ struct Ctx {
   int* d_uown = nullptr;       // owner slot ids cell*nU + slot
   int* d_cown_ptr = nullptr;   // [NC+1]
   int* d_cown = nullptr;
+  // the same owner lists at a fixed width of 4 (-1: none; a skeleton or coarse
+  // dof belongs to at most the 4 cells around a vertex), for one-load gathers
+  int4* d_uown4 = nullptr;     // [NU]
+  int4* d_cown4 = nullptr;     // [NC]
   int* d_skel_node = nullptr;  // [NU/2] node lattice index of each skeleton node
   int* d_net_ptr = nullptr;    // [netx*nety+1]
   int* d_net_own = nullptr;    // cell*(m+1)^2 + local control point

@@ -150,14 +150,22 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // out[g] = sum of owners' partials; optional partial dot out . w per block
-__global__ __launch_bounds__(kBlk) void k_gather_dot(const double* __restrict__ part, const int* __restrict__ ptr,
-                                                     const int* __restrict__ own, double* __restrict__ out, int N,
-                                                     const double* __restrict__ w, double* __restrict__ red) {
+__global__ __launch_bounds__(kBlk) void k_gather_dot(const double* __restrict__ part, const int4* __restrict__ own4,
+                                                     double* __restrict__ out, int N, const double* __restrict__ w,
+                                                     double* __restrict__ red) {
   __shared__ double sh[kBlk];
   int g = blockIdx.x * kBlk + threadIdx.x;
   double s = 0.0;
   if (g < N) {
-    for (int o = ptr[g]; o < ptr[g + 1]; ++o) s += part[own[o]];
+    // the owners in increasing cell order, all four values requested at once
+    // (a missing owner reads entry 0 and adds nothing)
+    const int4 o = own4[g];
+    const double v0 = part[o.x >= 0 ? o.x : 0], v1 = part[o.y >= 0 ? o.y : 0];
+    const double v2 = part[o.z >= 0 ? o.z : 0], v3 = part[o.w >= 0 ? o.w : 0];
+    if (o.x >= 0) s += v0;
+    if (o.y >= 0) s += v1;
+    if (o.z >= 0) s += v2;
+    if (o.w >= 0) s += v3;
     out[g] = s;
   }
   if (red) {
@@ -439,14 +447,14 @@ static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double*
   if (tp) hipEventRecord(e[2], c->stream);
   pre_local(c, fp32, r);
   if (tp) hipEventRecord(e[3], c->stream);
-  hipLaunchKernelGGL(k_gather_dot, dim3(nbC), dim3(kBlk), 0, c->stream, c->d_partC, c->d_cown_ptr, c->d_cown,
+  hipLaunchKernelGGL(k_gather_dot, dim3(nbC), dim3(kBlk), 0, c->stream, c->d_partC, c->d_cown4,
                      c->d_zc, c->NC, (const double*)nullptr, (double*)nullptr);
   if (tc) hipEventRecord(e[4], c->stream);
   hipError_t err = launch_coarse_solve(c, c->d_zc, c->d_xc, tc ? e[5] : nullptr);
   if (err != hipSuccess) return err;
   if (tc) hipEventRecord(e[6], c->stream);
   prolong(c, fp32);
-  hipLaunchKernelGGL(k_gather_dot, dim3(nbU), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, z,
+  hipLaunchKernelGGL(k_gather_dot, dim3(nbU), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown4, z,
                      c->NU, r, red);
   return hipGetLastError();
 }
@@ -458,8 +466,9 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   double* x = c->d_x + (size_t)rhs * N;
   double *r = c->d_r, *z = c->d_z, *p = c->d_p, *q = c->d_q;
   double* red = c->d_red;
-  // partials: p.q and r.z per gather workgroup (nb), r.r per update workgroup (nv)
-  double *red_pq = c->d_vred, *red_rz = c->d_vred + nb, *red_rr = c->d_vred + 2 * nb;
+  // partials: p.q and r.z per gather workgroup (nb); r.r per update workgroup
+  // (nv) right after the scalar slots, so that one copy brings both to the host
+  double *red_pq = c->d_vred, *red_rz = c->d_vred + nb, *red_rr = c->d_scal + 32;
   double* scal = c->d_scal;
   // scalar slots: 1 p.q, 2 alpha, 5 beta, 6 f.f, 7 breakdown flag, 10/11 r.z (alternating)
   hipLaunchKernelGGL(k_fill_p, dim3(256), dim3(256), 0, c->stream, x, (long long)N, 0.0);
@@ -512,13 +521,11 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
     if (top) hipEventRecord(c->pev[so][0], c->stream);
     op_local(c, p);
     if (top) hipEventRecord(c->pev[so][1], c->stream);
-    hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, q, N,
+    hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown4, q, N,
                        p, red_pq);
     hipLaunchKernelGGL(k_update_xr4, dim3(nv), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red_pq, nb, slot,
                        red_rr);
-    e = hipMemcpyAsync(c->h_red, red_rr, nv * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(c->h_scal, scal, 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(c->h_red, scal, (32 + nv) * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return e;
     hipEventRecord(c->ev[6], c->stream);
     // speculatively enqueue the preconditioner and the direction update of the next iteration
@@ -530,14 +537,14 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
     e = hipEventSynchronize(c->ev[6]);
     if (e != hipSuccess) return e;
     ++it;
-    if (c->h_scal[7] != 0.0) {
+    if (c->h_red[7] != 0.0) {
       hipStreamSynchronize(c->stream);
       info->iters = it;
       info->rel_res = rel;
       return finish(hipErrorUnknown);  // breakdown, reported by the caller
     }
     double rr = 0.0;  // r.r: the workgroup partials summed on the host in fixed order
-    for (int i = 0; i < nv; ++i) rr += c->h_red[i];
+    for (int i = 0; i < nv; ++i) rr += c->h_red[32 + i];
     rel = sqrt(rr / ff);
     if (rel <= rtol) break;
   }
@@ -553,7 +560,7 @@ hipError_t pcg_true_residual(Ctx* c, int rhs, double* out) {
   const double* f = c->d_f + (size_t)rhs * N;
   const double* x = c->d_x + (size_t)rhs * N;
   op_local(c, x);
-  hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown_ptr, c->d_uown, c->d_q,
+  hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown4, c->d_q,
                      N, (const double*)nullptr, (double*)nullptr);
   hipLaunchKernelGGL(k_diff_dot, dim3(nb), dim3(kBlk), 0, c->stream, f, c->d_q, N, c->d_red);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlk), 0, c->stream, c->d_red, nb, c->d_scal, 8, 0);
@@ -570,7 +577,7 @@ hipError_t pcg_true_residual(Ctx* c, int rhs, double* out) {
 hipError_t gather_rhs(Ctx* c, int rhs) {
   const int N = c->NU;
   hipLaunchKernelGGL(k_gather_dot, dim3((N + kBlk - 1) / kBlk), dim3(kBlk), 0, c->stream,
-                     c->d_load + (size_t)rhs * c->ncell * c->nU, c->d_uown_ptr, c->d_uown, c->d_f + (size_t)rhs * N,
+                     c->d_load + (size_t)rhs * c->ncell * c->nU, c->d_uown4, c->d_f + (size_t)rhs * N,
                      N, (const double*)nullptr, (double*)nullptr);
   return hipGetLastError();
 }

@@ -312,6 +312,24 @@ bool build_topology(Ctx* c) {
     }
   }
 
+  // fixed-width owner tables (taken after the coarse renumbering)
+  auto owners4 = [&](const std::vector<int>& ptr, const std::vector<int>& own, int N, std::vector<int4>& out) {
+    out.assign(N, make_int4(-1, -1, -1, -1));
+    for (int g = 0; g < N; ++g) {
+      const int n = ptr[g + 1] - ptr[g];
+      if (n > 4) return false;
+      int v[4] = {-1, -1, -1, -1};
+      for (int k = 0; k < n; ++k) v[k] = own[ptr[g] + k];
+      out[g] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+    return true;
+  };
+  std::vector<int4> uown4, cown4;
+  if (!owners4(uptr, uown, c->NU, uown4) || !owners4(cptr, cown, c->NC, cown4)) {
+    c->err = "internal: a dof with more than 4 owning cells";
+    return false;
+  }
+
   // net owners for the gradient gather
   const int m = c->m, np1 = (m + 1) * (m + 1);
   std::vector<int> nptr((size_t)c->netx * c->nety + 1, 0), nown;
@@ -347,7 +365,7 @@ bool build_topology(Ctx* c) {
   };
   return up(&c->d_perm, c->perm_nat) && up(&c->d_dirmask, c->dirmask) && up(&c->d_RU, c->RU) &&
          up(&c->d_RC, c->RC) && up(&c->d_uown_ptr, uptr) && up(&c->d_uown, uown) && up(&c->d_cown_ptr, cptr) &&
-         up(&c->d_cown, cown) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
+         up(&c->d_cown, cown) && up(&c->d_uown4, uown4) && up(&c->d_cown4, cown4) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
          up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) &&
          up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_nd_pull, co.nd_pull) && up(&c->d_fw_items, co.fw_items) &&
