@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   const bool left = (cell % nx) == 0;
   __shared__ double colbuf[2][256];
+  __shared__ double pv[2][2];
   __shared__ double sst[NSP];
   __shared__ int msk[NU];
   for (int i = tid; i < NU; i += 256) msk[i] = left ? dirmask[i] : 0;
@@ -60,6 +61,12 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
   bool bad = false;
   double* Lc = L + (size_t)cell * (NI * (NI + 1) / 2);
   double* Yc = Y + (size_t)cell * NI * NU;
+  // colbuf[buf][I] = column k below the pivot (zero for I <= k and past NDOF),
+  // pv[buf] = {pivot, 1/sqrt(pivot)}: the updates below then need no masks
+  // (rows and columns at or above the pivot meet zeros; the eliminated
+  // columns, already stored as L and Y, are not read again)
+  for (int i = tid; i < 2 * 256; i += 256) (&colbuf[0][0])[i] = 0.0;
+  __syncthreads();
 #pragma unroll
   for (int ph = 0; ph < NPH; ++ph) {
     for (int kk = 0; kk < 16; ++kk) {
@@ -69,24 +76,26 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
 #pragma unroll
         for (int a = ph; a < NA; ++a) {
           const int I = tr + 16 * a;
-          if (I >= k && I < NDOF) colbuf[buf][I] = A[a][ph];
+          if (I < NDOF) colbuf[buf][I] = I > k ? A[a][ph] : 0.0;
+        }
+        if (tr == kk) {
+          double p0 = A[ph][ph];
+          if (!(p0 > 0.0)) { bad = true; p0 = 1.0; }
+          pv[buf][0] = p0;
+          pv[buf][1] = 1.0 / sqrt(p0);
         }
       }
       __syncthreads();
-      double piv = colbuf[buf][k];
-      if (!(piv > 0.0)) { bad = true; piv = 1.0; }
-      const double rinv = 1.0 / sqrt(piv);
+      const double rinv = pv[buf][1];
       if (tid >= k && tid < NDOF) {
-        const double l = colbuf[buf][tid] * rinv;
-        if (tid < NI) Lc[k * NI - k * (k - 1) / 2 + (tid - k)] = (tid == k) ? sqrt(piv) : l;
-        else Yc[(size_t)k * NU + (tid - NI)] = l;
+        if (tid < NI) Lc[k * NI - k * (k - 1) / 2 + (tid - k)] = tid == k ? sqrt(pv[buf][0]) : colbuf[buf][tid] * rinv;
+        else Yc[(size_t)k * NU + (tid - NI)] = colbuf[buf][tid] * rinv;
       }
       double lr[NA], lcv[NA];
 #pragma unroll
       for (int a = ph; a < NA; ++a) {
-        const int I = tr + 16 * a, J = tc + 16 * a;
-        lr[a] = (I > k && I < NDOF) ? colbuf[buf][I] * rinv : 0.0;
-        lcv[a] = (J > k && J < NDOF) ? colbuf[buf][J] * rinv : 0.0;
+        lr[a] = colbuf[buf][tr + 16 * a] * rinv;
+        lcv[a] = colbuf[buf][tc + 16 * a] * rinv;
       }
 #pragma unroll
       for (int a = ph; a < NA; ++a)
