@@ -56,6 +56,55 @@ __device__ void gj_inverse(T* A, int n, T* colp, int* bad) {
   }
 }
 
+typedef float flt4m __attribute__((ext_vector_type(4)));
+typedef double dbl4m __attribute__((ext_vector_type(4)));
+
+// MFMA 16x16x4 in the precision T.  Operands: lane l gives A[m = l % 16][k = l / 16]
+// and B[k = l / 16][n = l % 16]; value v of the result sits at column l % 16 and
+// row row(l, v).
+template <typename T> struct Mf;
+template <> struct Mf<float> {
+  typedef flt4m v4;
+  static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <> struct Mf<double> {
+  typedef dbl4m v4;
+  static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
+// C = A B (M x N, depth K) on MFMA by the workgroup's four waves, one 16 x 16
+// output tile per wave at a time (operands past M, N, K are zero):
+// a(i, k) and b(k, j) read the operands, out(i, j, value) takes each result.
+template <typename T, int M, int N, int K, typename FA, typename FB, typename FO>
+__device__ __forceinline__ void mfma_mm(FA a, FB b, FO out) {
+  typedef typename Mf<T>::v4 v4;
+  constexpr int TM = (M + 15) / 16, TN = (N + 15) / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, kl = lane >> 4;
+  for (int t = wave; t < TM * TN; t += 4) {
+    const int r0 = (t / TN) * 16, c0 = (t % TN) * 16;
+    v4 acc = v4{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + kl;
+      const T av = (r0 + l16 < M && k < K) ? a(r0 + l16, k) : (T)0;
+      const T bv = (k < K && c0 + l16 < N) ? b(k, c0 + l16) : (T)0;
+      acc = Mf<T>::op(av, bv, acc);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + Mf<T>::row(lane, v), j = c0 + l16;
+      if (i < M && j < N) out(i, j, acc[v]);
+    }
+  }
+}
+
 template <typename T, int P, int NCE>
 __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, const double* __restrict__ cons,
                                                  const double* __restrict__ diagK, const double* __restrict__ Ktot,
@@ -67,18 +116,32 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   static_assert(NU <= 64, "one row per lane");
   const int cell = blockIdx.x, tid = threadIdx.x;
   const bool left = (cell % nx) == 0;
-  __shared__ T A[NE][NE + 1];     // Shat, then Shat^-1, then P
-  __shared__ T X[NE][NCC + 1];    // Shat^-1 Chat^T
-  __shared__ T W2[NE][NCC + 1];   // X That^-1
-  __shared__ T Ch[NCC][NE];
-  __shared__ T Cc[NCC][8];
-  __shared__ T Tm[NCC][NCC + 1];  // That, then That^-1
-  __shared__ T Scol[NE][8];
+  // the first-stage arrays are dead once Psi is formed; S Psi takes their space
+  struct Stage1 {
+    T A[NE][NE + 1];     // Shat, then Shat^-1, then P
+    T X[NE][NCC + 1];    // Shat^-1 Chat^T
+    T W2[NE][NCC + 1];   // X That^-1
+    T Ch[NCC][NE];
+    T Cc[NCC][8];
+    T Tm[NCC][NCC + 1];  // That, then That^-1
+    T Scol[NE][8];
+  };
+  union Work {
+    Stage1 s;
+    double SPs[NU][NC + 1];  // S Psi
+  };
+  __shared__ Work wk;
   __shared__ T colp[NE];
   __shared__ double Dv[NU];
-  __shared__ double Ps[NU][NC + 1];   // coarse basis (unscaled)
-  __shared__ double SPs[NU][NC + 1];  // S Psi
+  __shared__ double Ps[NU][NC + 1];  // coarse basis (unscaled)
   __shared__ int bad;
+  auto& A = wk.s.A;
+  auto& X = wk.s.X;
+  auto& W2 = wk.s.W2;
+  auto& Ch = wk.s.Ch;
+  auto& Cc = wk.s.Cc;
+  auto& Tm = wk.s.Tm;
+  auto& Scol = wk.s.Scol;
   const double* S = Sg + (size_t)cell * NSP;
   if (tid == 0) bad = 0;
   for (int idx = tid; idx < NE * NE; idx += 256) {
@@ -116,38 +179,21 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   // Shat^-1 in place
   gj_inverse<T, NE + 1>(&A[0][0], NE, colp, &bad);
   // X = Shat^-1 Chat^T
-  for (int idx = tid; idx < NE * NCC; idx += 256) {
-    const int i = idx / NCC, a = idx % NCC;
-    T s = 0;
-    for (int k = 0; k < NE; ++k) s += A[i][k] * Ch[a][k];
-    X[i][a] = s;
-  }
+  mfma_mm<T, NE, NCC, NE>([&](int i, int k) { return A[i][k]; }, [&](int k, int a) { return Ch[a][k]; },
+                          [&](int i, int a, T v) { X[i][a] = v; });
   __syncthreads();
   // That = Chat X; the clamped edge's rows carry no constraint and get a unit diagonal
-  for (int idx = tid; idx < NCC * NCC; idx += 256) {
-    const int a = idx / NCC, b = idx % NCC;
-    T s = 0;
-    for (int i = 0; i < NE; ++i) s += Ch[a][i] * X[i][b];
-    if (left && a == b && a < NCE) s = (T)1;
-    Tm[a][b] = s;
-  }
+  mfma_mm<T, NCC, NCC, NE>([&](int a, int i) { return Ch[a][i]; }, [&](int i, int b) { return X[i][b]; },
+                           [&](int a, int b, T v) { Tm[a][b] = (left && a == b && a < NCE) ? (T)1 : v; });
   __syncthreads();
   gj_inverse<T, NCC + 1>(&Tm[0][0], NCC, colp, &bad);
   // W2 = X That^-1
-  for (int idx = tid; idx < NE * NCC; idx += 256) {
-    const int i = idx / NCC, a = idx % NCC;
-    T s = 0;
-    for (int b = 0; b < NCC; ++b) s += X[i][b] * Tm[b][a];
-    W2[i][a] = s;
-  }
+  mfma_mm<T, NE, NCC, NCC>([&](int i, int b) { return X[i][b]; }, [&](int b, int a) { return Tm[b][a]; },
+                           [&](int i, int a, T v) { W2[i][a] = v; });
   __syncthreads();
-  // P = Shat^-1 - W2 X^T (in place)
-  for (int idx = tid; idx < NE * NE; idx += 256) {
-    const int i = idx / NE, j = idx % NE;
-    T s = A[i][j];
-    for (int a = 0; a < NCC; ++a) s -= W2[i][a] * X[j][a];
-    A[i][j] = s;
-  }
+  // P = Shat^-1 - W2 X^T in place (each tile of A is read and written by one wave)
+  mfma_mm<T, NE, NE, NCC>([&](int i, int a) { return W2[i][a]; }, [&](int a, int j) { return X[j][a]; },
+                          [&](int i, int j, T v) { A[i][j] -= v; });
   __syncthreads();
   // store D_E P D_E packed lower
   T* Pc = Pout + (size_t)cell * (NE * (NE + 1) / 2);
@@ -155,25 +201,24 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
     for (int j = tid & 63; j <= i; j += 64)
       Pc[i * (i + 1) / 2 + j] = (T)(Dv[8 + i] * (double)A[i][j] * Dv[8 + j]);
   // coarse basis Psi [NU][NC]: corner rows are the identity (masked on the
-  // clamped side); edge rows: corner columns -P S[E, c] - W2 C[:, c], edge
-  // constraint columns W2
+  // clamped side); edge rows: edge constraint columns W2, corner columns
+  // -P S[E, c] - W2 C[:, c] (one product of depth NE + NCC)
   for (int idx = tid; idx < NU * NC; idx += 256) {
     const int i = idx / NC, j = idx % NC;
     const bool cmask = left && (j == 0 || j == 1 || j == 4 || j == 5);
-    double v;
     if (i < 8) {
-      v = (i == j && !cmask) ? 1.0 : 0.0;
-    } else if (j < 8) {
-      T s = 0;
-      for (int k2 = 0; k2 < NE; ++k2) s -= A[i - 8][k2] * Scol[k2][j];
-      for (int a = 0; a < NCC; ++a) s -= W2[i - 8][a] * Cc[a][j];
-      v = cmask ? 0.0 : (double)s;
-    } else {
+      Ps[i][j] = (i == j && !cmask) ? 1.0 : 0.0;
+    } else if (j >= 8) {
       const bool emask = left && j < 8 + NCE;
-      v = emask ? 0.0 : (double)W2[i - 8][j - 8];
+      Ps[i][j] = emask ? 0.0 : (double)W2[i - 8][j - 8];
     }
-    Ps[i][j] = v;
   }
+  mfma_mm<T, NE, 8, NE + NCC>([&](int i, int k) { return k < NE ? A[i][k] : W2[i][k - NE]; },
+                              [&](int k, int j) { return k < NE ? Scol[k][j] : Cc[k - NE][j]; },
+                              [&](int i, int j, T v) {
+                                const bool cmask = left && (j == 0 || j == 1 || j == 4 || j == 5);
+                                Ps[8 + i][j] = cmask ? 0.0 : -(double)v;
+                              });
   __syncthreads();
   T* Pso = Psiout + (size_t)cell * NU * NC;
   for (int idx = tid; idx < NU * NC; idx += 256) {
@@ -181,24 +226,21 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
     Pso[idx] = (T)(Dv[i] * Ps[i][j]);
   }
   for (int j = tid; j < NU; j += 256) Dout[(size_t)cell * NU + j] = Dv[j];
-  // S Psi in FP64 (S packed lower, read through the cache), then Psi^T S Psi
-  for (int idx = tid; idx < NU * NC; idx += 256) {
-    const int i = idx / NC, j = idx % NC;
-    const int ri = i * (i + 1) / 2;
-    double s = 0.0;
-    for (int k2 = 0; k2 <= i; ++k2) s += S[ri + k2] * Ps[k2][j];
-    for (int k2 = i + 1; k2 < NU; ++k2) s += S[k2 * (k2 + 1) / 2 + i] * Ps[k2][j];
-    SPs[i][j] = s;
-  }
+  // S Psi in FP64 (S packed lower, read through the cache), then Psi^T S Psi;
+  // S Psi overwrites the first-stage arrays (all reads of them ended at the
+  // barrier above)
+  mfma_mm<double, NU, NC, NU>(
+      [&](int i, int k) {
+        const int hi = i > k ? i : k, lo = i > k ? k : i;
+        return S[hi * (hi + 1) / 2 + lo];
+      },
+      [&](int k, int j) { return Ps[k][j]; }, [&](int i, int j, double v) { wk.SPs[i][j] = v; });
   __syncthreads();
   double* Sc = ScOut + (size_t)cell * (NC * (NC + 1) / 2);
-  for (int idx = tid; idx < NC * NC; idx += 256) {
-    const int a = idx / NC, b = idx % NC;
-    if (b > a) continue;
-    double s = 0.0;
-    for (int k2 = 0; k2 < NU; ++k2) s += Ps[k2][a] * SPs[k2][b];
-    Sc[a * (a + 1) / 2 + b] = s;
-  }
+  mfma_mm<double, NC, NC, NU>([&](int a, int k) { return Ps[k][a]; }, [&](int k, int b) { return wk.SPs[k][b]; },
+                              [&](int a, int b, double v) {
+                                if (b <= a) Sc[a * (a + 1) / 2 + b] = v;
+                              });
   if (tid == 0 && bad) atomicOr(flags, 16);
 }
 
