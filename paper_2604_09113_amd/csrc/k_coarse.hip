@@ -69,17 +69,18 @@ __global__ __launch_bounds__(256) void k_extend_add(const NDNodeH* __restrict__ 
 // which is the same elimination as the pivot-by-pivot sweep, regrouped.
 constexpr int GJB = 64;
 
-template <int NF>
-__global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
-                                                   const int* __restrict__ cmap, double* __restrict__ F,
-                                                   int* __restrict__ flags) {
+template <int NF, int NT>
+__global__ __launch_bounds__(NT) void k_front_lds(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
+                                                  const int* __restrict__ cmap, double* __restrict__ F,
+                                                  int* __restrict__ flags) {
+  constexpr int W = NT / 64;  // waves
   __shared__ double S[NF * (NF + 1)];
   __shared__ double rowl[NF], coll[NF];
   const NDNodeH d = nodes[lvl[blockIdx.x]];
   const int nf = d.ns + d.nb, ld = nf + 1;
   double* A = F + d.foff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nf; i += 4)
+  for (int i = wave; i < nf; i += W)
     for (int j = lane; j < nf; j += 64) S[i * ld + j] = A[(long long)i * nf + j];
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ n
     const int nfc = c.ns + c.nb;
     const int* map = cmap + d.cmap_off[s];
     const double* U = F + c.foff + (long long)c.ns * nfc + c.ns;
-    for (int i = wave; i < c.nb; i += 4) {
+    for (int i = wave; i < c.nb; i += W) {
       const int r = map[i] * ld;
       for (int j = lane; j < c.nb; j += 64) S[r + map[j]] += U[(long long)i * nfc + j];
     }
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ n
   bool bad = false;
   constexpr int NJ = (NF + 63) / 64;  // row chunks of 64 columns
   for (int l = 0; l < d.ns; ++l) {
-    for (int j = threadIdx.x; j < nf; j += 256) {
+    for (int j = threadIdx.x; j < nf; j += NT) {
       rowl[j] = S[l * ld + j];
       coll[j] = S[j * ld + l];
     }
@@ -106,32 +107,38 @@ __global__ __launch_bounds__(256) void k_front_lds(const NDNodeH* __restrict__ n
     double piv = rowl[l];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
     const double pinv = 1.0 / piv;
+    // loads are unconditional (columns past nf read column 0 and are not
+    // stored), so the loads of a row pair are all in flight before the updates
     double rv[NJ];  // this lane's columns of the pivot row
 #pragma unroll
-    for (int c = 0; c < NJ; ++c) rv[c] = lane + 64 * c < nf ? rowl[lane + 64 * c] : 0.0;
-    for (int i = wave; i < nf; i += 4) {
-      double* srow = S + i * ld;
-      if (i == l) {  // pivot row (wave-uniform): scaled by 1/p, 1/p on the diagonal
+    for (int c = 0; c < NJ; ++c) rv[c] = rowl[lane + 64 * c < nf ? lane + 64 * c : 0];
+    // rows i and i + W per iteration; the pivot row is scaled by 1/p (1/p on the
+    // diagonal), the others become s - (c_i / p) r_j (-c_i / p in the pivot column)
+    for (int i = wave; i < nf; i += 2 * W) {
+      const int i2 = i + W;
+      const bool has2 = i2 < nf;
+      double* r1 = S + i * ld;
+      double* r2 = S + (has2 ? i2 : i) * ld;
+      double s1[NJ], s2[NJ];
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) {
-          const int j = lane + 64 * c;
-          if (j < nf) srow[j] = j == l ? pinv : rv[c] * pinv;
-        }
-      } else {  // other rows: s - (c_i / p) r_j, and -c_i / p in the pivot column
-        const double ci = coll[i] * pinv;
-        double sv[NJ];
+      for (int c = 0; c < NJ; ++c) {
+        const int j = lane + 64 * c < nf ? lane + 64 * c : 0;
+        s1[c] = r1[j];
+        s2[c] = r2[j];
+      }
+      const double c1 = coll[i] * pinv, c2 = coll[has2 ? i2 : i] * pinv;
 #pragma unroll
-        for (int c = 0; c < NJ; ++c) sv[c] = lane + 64 * c < nf ? srow[lane + 64 * c] : 0.0;
-#pragma unroll
-        for (int c = 0; c < NJ; ++c) {
-          const int j = lane + 64 * c;
-          if (j < nf) srow[j] = j == l ? -ci : sv[c] - ci * rv[c];
+      for (int c = 0; c < NJ; ++c) {
+        const int j = lane + 64 * c;
+        if (j < nf) {
+          r1[j] = i == l ? (j == l ? pinv : rv[c] * pinv) : (j == l ? -c1 : s1[c] - c1 * rv[c]);
+          if (has2) r2[j] = i2 == l ? (j == l ? pinv : rv[c] * pinv) : (j == l ? -c2 : s2[c] - c2 * rv[c]);
         }
       }
     }
     __syncthreads();
   }
-  for (int i = wave; i < nf; i += 4)
+  for (int i = wave; i < nf; i += W)
     for (int j = lane; j < nf; j += 64) A[(long long)i * nf + j] = S[i * ld + j];
   if (bad) atomicOr(flags, 32);
 }
@@ -376,12 +383,12 @@ hipError_t launch_coarse_factor(Ctx* c) {
         if (d.child[s] >= 0) nbmax = std::max(nbmax, co.nd_nodes[d.child[s]].nb);
     }
     if (nfmax <= 72) {
-      hipLaunchKernelGGL(k_front_lds<72>, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_nd_cmap,
+      hipLaunchKernelGGL((k_front_lds<72, 256>), dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_nd_cmap,
                          c->d_coarse, c->d_flags);
       continue;
     }
     if (nfmax <= ND_LDS_NF) {
-      hipLaunchKernelGGL(k_front_lds<ND_LDS_NF>, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl,
+      hipLaunchKernelGGL((k_front_lds<ND_LDS_NF, 512>), dim3(nn), dim3(512), 0, c->stream, c->d_nd_nodes, lvl,
                          c->d_nd_cmap, c->d_coarse, c->d_flags);
       continue;
     }
