@@ -67,6 +67,15 @@ def library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2604_09113_amd.build.build()")
+    # torch brings its own copy of the HIP runtime; when both are in one process,
+    # torch's has to start first (started after the library's, it finds no GPU),
+    # so bring it up before the library is loaded
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     dp = C.POINTER(C.c_double)

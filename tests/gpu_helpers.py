@@ -40,3 +40,63 @@ def oracle_fine_operator(P, cell):
         x, _ = P.local_solve(cell, e, z)
         F[:, j] = cell.D * x
     return F
+
+
+def cut_to_rank(rom):
+    """The oracle's ROM truncated to its numerical rank (the reduced size the
+    library is run with at full size)."""
+    nr = max(c["n_used"] for c in rom["clusters"])
+    out = dict(rom, n_r=nr)
+    out["clusters"] = [dict(c, U=c["U"][:, :nr], coeff=c["coeff"][:, :nr]) for c in rom["clusters"]]
+    return out
+
+
+def oracle_cells(prob, roms, cells):
+    """Oracle Cell objects of selected cells only (the oracle's own cell build,
+    without building the whole lattice)."""
+    from oracle.bddc import Problem
+    from oracle.dofs import Dofs
+    from oracle.geometry import material_tensor
+    P = Problem.__new__(Problem)
+    P.prob, P.p, P.q, P.m = prob, prob["p"], prob["q"], prob["m"]
+    P.nx, P.ny, P.rho, P.moments = prob["nx"], prob["ny"], prob["rho"], prob["moments"]
+    P.dofs = Dofs(P.nx, P.ny, P.p, P.moments)
+    P.Cmat = material_tensor(prob["E"], prob["nu"])
+    P.roms, P.assembly, P.nrhs = roms, "rom", prob["traction"].shape[0]
+    return P, {c: P._build_cell(c) for c in cells}
+
+
+def sampled_cell_errors(prob, roms, s, cells):
+    """Largest relative errors of K, S (active slots), theta and Itil of the
+    sampled cells against the oracle."""
+    from oracle.geometry import geometry_coefficients
+    from oracle.rom import stabilised_reduced
+    P, oc = oracle_cells(prob, roms, cells)
+    wk = ws = wt = wi = 0.0
+    for c in cells:
+        cell = oc[c]
+        C, _ = geometry_coefficients(cell.X, prob["q"], P.Cmat)
+        th = s.export(1, c, 1)[0]
+        wt = max(wt, np.abs(th - C).max() / np.abs(C).max())
+        _, v = stabilised_reduced(roms[int(prob["family"][c])], float(prob["t"][c]), prob["rho"])
+        it = s.export(2, c, 1)[0]
+        wi = max(wi, np.abs(it[:len(v)] - v).max() / max(1.0, np.abs(v).max()))
+        wk = max(wk, rel(s.export(0, c, 1)[0], cell.K))
+        a = cell.slot_active
+        ws = max(ws, rel(s.export(3, c, 1)[0][np.ix_(a, a)], cell.S))
+    return wk, ws, wt, wi
+
+
+def compliance_fTu(prob, u, rhs):
+    """f_r^T u with the oracle's traction load on the right-edge cells."""
+    from oracle.bddc import traction_load
+    from oracle.dofs import edge_nodes_local
+    from oracle.geometry import cell_control_points
+    p, nx, ny, m = prob["p"], prob["nx"], prob["ny"], prob["m"]
+    J = 0.0
+    for iy in range(ny):
+        X = cell_control_points(prob["ctrl"], m, nx - 1, iy)
+        fe = traction_load(X, p, prob["traction"][rhs, iy])
+        for n, (a, b) in enumerate(edge_nodes_local(p, "right")):
+            J += fe[n] @ u[p * iy + b, p * (nx - 1) + a]
+    return J

@@ -1,0 +1,172 @@
+"""The other workloads at their full sizes, through the C ABI, with the ROMs
+cut to their numerical rank.  The oracle cannot solve these lattices, so it is
+compared on sampled cells and the solutions are checked through properties
+that hold at any size.
+
+  - 64 x 64, p = 6 (FP64 method at scale, rtol 1e-10): converged true
+    residual, sampled cells against the oracle, the mixed-precision solve
+    within 1e-8 of the FP64 one.
+  - 64 x 64, p = 6, order-3 maps (differentiation): the adjoint gradient of
+    the compliance against central finite differences along 50 random
+    directions in (control net, thickness) at h = 1e-6 and at h = 1e-2, and
+    along the gradient itself at h = 1e-6.  J carries a rounding noise of
+    about 1e-12 |J| here: the combination J(x+2h) - 2 J(x+h) + 2 J(x-h)
+    - J(x-2h), which has no derivative term below h^3, measured at most
+    3.6e-12 |J| for every h from 1e-6 to 1e-2, so a difference quotient
+    carries up to ~eta |J| / h of it.  Each check asserts
+    |fd - adjoint| <= 1e-5 |adjoint| + eta |J| / h with eta = 4e-12; at
+    h = 1e-2 the noise term is 3e-6 and the truncation error measured
+    below 2.3e-6 |adjoint|.
+  - 256 x 256, p = 8, order-3 warped maps, 8 random load cases (mixed
+    precision with adjoint): every load case converged, mixed against FP64
+    displacements (1e-8) and gradients, J_r = f_r^T u_r with the oracle's
+    traction, sampled cells against the oracle."""
+import numpy as np
+import pytest
+
+from conftest import oracle_roms
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(prob, roms, stream=None):
+    from gpu_helpers import rom_arrays
+    from paper_2604_09113_amd import lbddc
+    s = lbddc.Solver(0, stream)
+    for rom in roms.values():
+        s.load_rom(**rom_arrays(rom))
+    s.set_problem(prob["nx"], prob["ny"], prob["p"], prob["q"], prob["m"], prob["ctrl"], prob["family"], prob["t"],
+                  prob["E"], prob["nu"], prob["rho"], prob["moments"], prob["traction"])
+    return s
+
+
+def _theta_tol(prob):
+    """theta is built from control-point differences across a cell of width
+    1 / max(nx, ny) while the coordinates are O(1): the Jacobian alone carries
+    ~eps max(nx, ny) relative rounding, and theta takes a few products of it."""
+    return max(1e-13, 8 * np.finfo(np.float64).eps * max(prob["nx"], prob["ny"]))
+
+
+def _sample(prob):
+    nx, ny = prob["nx"], prob["ny"]
+    rng = np.random.default_rng(11)
+    fixed = [0, nx, nx - 1, (ny // 2) * nx + nx // 2, nx * ny - 1]
+    return fixed + [int(c) for c in rng.integers(0, nx * ny, 3)]
+
+
+def test_cfg2_64x64_p6_fp64_at_scale():
+    from gpu_helpers import cut_to_rank, sampled_cell_errors
+    from paper_2604_09113_amd import lbddc
+    prob = make_problem(2)
+    roms = {f: cut_to_rank(r) for f, r in oracle_roms(prob).items()}
+    s = _solver(prob, roms)
+    s.assemble(lbddc.FP64)
+    s.setup(lbddc.FP64)
+    info = s.solve(rtol=prob["rtol"], max_iter=3000)
+    u64 = s.displacement(0)
+    print(f"\n[cfg2] fp64: {info[0]['iters']} its, rel_res {info[0]['rel_res']:.2e} true {info[0]['true_rel_res']:.2e}")
+    assert info[0]["rel_res"] <= prob["rtol"] and info[0]["true_rel_res"] <= 10 * prob["rtol"]
+    wk, ws, wt, wi = sampled_cell_errors(prob, roms, s, _sample(prob))
+    print(f"[cfg2] sampled cells: K {wk:.2e} S {ws:.2e} theta {wt:.2e} Itil {wi:.2e}")
+    assert wk <= 1e-10 and ws <= 1e-10 and wt <= _theta_tol(prob) and wi <= 1e-13
+    s.setup(lbddc.MIXED)
+    infom = s.solve(rtol=prob["rtol"], max_iter=3000)
+    d = np.abs(s.displacement(0) - u64).max() / np.abs(u64).max()
+    print(f"[cfg2] mixed: {infom[0]['iters']} its; |u_mixed - u_fp64| / |u| = {d:.2e}")
+    assert d <= 1e-8
+    s.close()
+
+
+def test_cfg4_64x64_p6_gradient_vs_central_fd():
+    import torch
+    from gpu_helpers import cut_to_rank
+    from paper_2604_09113_amd import lbddc
+    prob = make_problem(4)
+    roms = {f: cut_to_rank(r) for f, r in oracle_roms(prob).items()}
+    s = _solver(prob, roms, torch.cuda.current_stream().cuda_stream)
+
+    def compliance(ctrl_h, t_h):
+        ctrl = torch.tensor(ctrl_h, dtype=torch.float64, device="cuda").contiguous()
+        t = torch.tensor(t_h, dtype=torch.float64, device="cuda").contiguous()
+        s.set_geometry_device(ctrl.data_ptr(), t.data_ptr())
+        s.assemble(lbddc.FP64)
+        s.setup(lbddc.FP64)
+        info = s.solve(rtol=prob["rtol"], max_iter=3000)
+        assert info[0]["rel_res"] <= prob["rtol"]
+        out = s.compliance_gradient()
+        torch.cuda.synchronize()
+        return out
+
+    J, gX, gt = compliance(prob["ctrl"], prob["t"])
+    # thickness directions vanish on cells within 1e-3 of a ROM cluster edge:
+    # the MDEIM fit is piecewise in t and its derivative jumps there
+    edges = []
+    for f, r in prob["rom"].items():
+        edges += list(np.linspace(r["lo"], r["hi"], r["n_k"] + 1))
+    smooth = np.min(np.abs(prob["t"][:, None] - np.array(edges)[None, :]), axis=1) > 1e-3
+    eta = 4e-12
+    rng = np.random.default_rng(2026)
+
+    def check(dX, dt, h):
+        fd = (compliance(prob["ctrl"] + h * dX, prob["t"] + h * dt)[0][0] -
+              compliance(prob["ctrl"] - h * dX, prob["t"] - h * dt)[0][0]) / (2 * h)
+        ad = (gX[0] * dX).sum() + (gt[0] * dt).sum()
+        return fd, ad, abs(fd - ad) <= 1e-5 * abs(ad) + eta * abs(J[0]) / h
+
+    # along the gradient (thickness part masked as above)
+    dX, dt = gX[0].copy(), gt[0] * smooth
+    nrm = np.sqrt((dX ** 2).sum() + (dt ** 2).sum())
+    fd, ad, ok = check(dX / nrm, dt / nrm, 1e-6)
+    print(f"\n[cfg4] along the gradient, h = 1e-6: fd {fd:.10e} adjoint {ad:.10e} rel {abs(fd - ad) / abs(ad):.2e}")
+    assert ok
+    worst = {1e-6: 0.0, 1e-2: 0.0}
+    for k in range(50):
+        dX = rng.normal(size=prob["ctrl"].shape)
+        dt = rng.normal(size=prob["t"].shape) * smooth
+        nrm = np.sqrt((dX ** 2).sum() + (dt ** 2).sum())
+        for h in worst:
+            fd, ad, ok = check(dX / nrm, dt / nrm, h)
+            worst[h] = max(worst[h], abs(fd - ad) / abs(ad))
+            assert ok, (k, h, fd, ad)
+            if k < 3:
+                print(f"[cfg4] direction {k}, h = {h:.0e}: fd {fd:.10e} adjoint {ad:.10e}")
+    print(f"[cfg4] J {J[0]:.10e}; 50 random directions, worst |fd - adjoint| / |adjoint|: "
+          f"h = 1e-6 {worst[1e-6]:.2e}, h = 1e-2 {worst[1e-2]:.2e}")
+    s.close()
+
+
+def test_cfg5_256x256_p8_eight_loads_mixed_and_adjoint():
+    from gpu_helpers import cut_to_rank, sampled_cell_errors, compliance_fTu
+    from paper_2604_09113_amd import lbddc
+    prob = make_problem(5)
+    nrhs = prob["traction"].shape[0]
+    roms = {f: cut_to_rank(r) for f, r in oracle_roms(prob).items()}
+    s = _solver(prob, roms)
+    s.assemble(lbddc.FP64)
+    s.setup(lbddc.FP64)
+    rtol = 1e-10
+    info = s.solve(rtol=rtol, max_iter=5000)
+    u64 = [s.displacement(r) for r in range(nrhs)]
+    J64, gX64, gt64 = s.compliance_gradient()
+    print(f"\n[cfg5] fp64 iterations {[i['iters'] for i in info]}")
+    for r in range(nrhs):
+        assert info[r]["rel_res"] <= rtol and info[r]["true_rel_res"] <= 10 * rtol
+        Jo = compliance_fTu(prob, u64[r], r)
+        assert abs(J64[r] - Jo) <= 1e-11 * abs(Jo), (r, J64[r], Jo)
+    s.setup(lbddc.MIXED)
+    infom = s.solve(rtol=rtol, max_iter=5000)
+    Jm, gXm, gtm = s.compliance_gradient()
+    worst_u = 0.0
+    for r in range(nrhs):
+        assert infom[r]["rel_res"] <= rtol
+        worst_u = max(worst_u, np.abs(s.displacement(r) - u64[r]).max() / np.abs(u64[r]).max())
+    eg = max(np.abs(gXm - gX64).max() / np.abs(gX64).max(), np.abs(gtm - gt64).max() / np.abs(gt64).max())
+    eJ = np.abs(Jm - J64).max() / np.abs(J64).max()
+    print(f"[cfg5] mixed iterations {[i['iters'] for i in infom]}; |u_mixed - u_fp64| / |u| <= {worst_u:.2e}, "
+          f"J {eJ:.2e}, gradients {eg:.2e}")
+    assert worst_u <= 1e-8 and eJ <= 1e-9 and eg <= 1e-6
+    wk, ws, wt, wi = sampled_cell_errors(prob, roms, s, _sample(prob))
+    print(f"[cfg5] sampled cells: K {wk:.2e} S {ws:.2e} theta {wt:.2e} Itil {wi:.2e}")
+    assert wk <= 1e-10 and ws <= 1e-10 and wt <= _theta_tol(prob) and wi <= 1e-13
+    s.close()

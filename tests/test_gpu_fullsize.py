@@ -25,35 +25,13 @@ pytestmark = pytest.mark.gpu
 SAMPLE = [0, 128, 127, 777, 8191, 16383, 5000, 12345]
 
 
-def _cut_to_rank(rom):
-    nr = max(c["n_used"] for c in rom["clusters"])
-    out = dict(rom, n_r=nr)
-    out["clusters"] = [dict(c, U=c["U"][:, :nr], coeff=c["coeff"][:, :nr]) for c in rom["clusters"]]
-    return out
-
-
-def _oracle_cells(prob, roms, cells):
-    """Oracle Cell objects of selected cells only (the oracle's own cell build,
-    without building the whole lattice)."""
-    from oracle.bddc import Problem
-    from oracle.dofs import Dofs
-    from oracle.geometry import material_tensor
-    P = Problem.__new__(Problem)
-    P.prob, P.p, P.q, P.m = prob, prob["p"], prob["q"], prob["m"]
-    P.nx, P.ny, P.rho, P.moments = prob["nx"], prob["ny"], prob["rho"], prob["moments"]
-    P.dofs = Dofs(P.nx, P.ny, P.p, P.moments)
-    P.Cmat = material_tensor(prob["E"], prob["nu"])
-    P.roms, P.assembly, P.nrhs = roms, "rom", prob["traction"].shape[0]
-    return P, {c: P._build_cell(c) for c in cells}
-
-
 @pytest.fixture(scope="module")
 def full():
-    from gpu_helpers import rom_arrays
+    from gpu_helpers import rom_arrays, cut_to_rank
     from paper_2604_09113_amd import lbddc
     prob = make_problem(3)
     print("\n[fullsize] training the oracle ROMs", flush=True)
-    roms = {f: _cut_to_rank(r) for f, r in oracle_roms(prob).items()}
+    roms = {f: cut_to_rank(r) for f, r in oracle_roms(prob).items()}
     s = lbddc.Solver(0)
     for rom in roms.values():
         s.load_rom(**rom_arrays(rom))
@@ -72,7 +50,8 @@ def test_fullsize_sampled_cells(full):
     from oracle.geometry import geometry_coefficients
     from oracle.rom import stabilised_reduced
     prob, roms, s, _ = full
-    P, cells = _oracle_cells(prob, roms, SAMPLE)
+    from gpu_helpers import oracle_cells
+    P, cells = oracle_cells(prob, roms, SAMPLE)
     wk = ws = wl = 0.0
     for c in SAMPLE:
         cell = cells[c]
@@ -97,7 +76,8 @@ def test_fullsize_weights(full):
     nx = prob["nx"]
     c0 = 64 * nx + 64
     nb = [c0 + dy * nx + dx for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-    P, cells = _oracle_cells(prob, roms, nb)
+    from gpu_helpers import oracle_cells
+    P, cells = oracle_cells(prob, roms, nb)
     tot = {}
     for c in nb:
         cell = cells[c]
