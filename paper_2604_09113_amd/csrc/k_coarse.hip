@@ -41,15 +41,51 @@ __global__ __launch_bounds__(256) void k_extend_add(const NDNodeH* __restrict__ 
   const int ch = d.child[slot];
   if (ch < 0) return;
   const NDNodeH c = nodes[ch];
-  const int nfc = c.ns + c.nb, nf = d.ns + d.nb;
+  const int nfc = c.ns + c.nb, nf = d.ns + d.nb, nb = c.nb;
   const int* map = cmap + d.cmap_off[slot];
   const double* U = F + c.foff;
   double* P = F + d.foff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = r0 + wave; i < min(c.nb, r0 + 16); i += 4) {
-    double* prow = P + (long long)map[i] * nf;
+  const int rend = min(nb, r0 + 16);
+  constexpr int KC = 16;  // column chunks of 64 held per lane
+  if (nb > 64 * KC) {
+    for (int i = r0 + wave; i < rend; i += 4) {
+      double* prow = P + (long long)map[i] * nf;
+      const double* urow = U + (long long)(c.ns + i) * nfc + c.ns;
+      for (int j = lane; j < nb; j += 64) prow[map[j]] += urow[j];
+    }
+    return;
+  }
+  // the map entries of the lane's columns and of the wave's rows first; then,
+  // per row, every load of the row before any add (columns past nb read the
+  // position of column 0 and are not stored)
+  int mj[KC], mi[4];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int j = lane + 64 * k;
+    mj[k] = map[j < nb ? j : 0];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = r0 + wave + 4 * q;
+    mi[q] = map[i < rend ? i : 0];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = r0 + wave + 4 * q;
+    if (i >= rend) break;
+    double* prow = P + (long long)mi[q] * nf;
     const double* urow = U + (long long)(c.ns + i) * nfc + c.ns;
-    for (int j = lane; j < c.nb; j += 64) prow[map[j]] += urow[j];
+    double u[KC], pv[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int j = lane + 64 * k;
+      u[k] = urow[j < nb ? j : 0];
+      pv[k] = prow[mj[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (lane + 64 * k < nb) prow[mj[k]] = pv[k] + u[k];
   }
 }
 
@@ -154,13 +190,21 @@ __global__ __launch_bounds__(256) void k_lv_diag(const NDNodeH* __restrict__ nod
   const int kn = min(GJB, d.ns - k0), nf = d.ns + d.nb;
   double* A = F + d.foff + (long long)k0 * nf + k0;
   const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  // every load in flight before the identity padding is applied
   double B[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int i = tr + 16 * a, j = tc + 16 * b;
-      B[a][b] = (i < kn && j < kn) ? A[(long long)i * nf + j] : (i == j ? 1.0 : 0.0);
+      B[a][b] = A[(long long)(i < kn ? i : 0) * nf + (j < kn ? j : 0)];
+    }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      if (!(i < kn && j < kn)) B[a][b] = i == j ? 1.0 : 0.0;
     }
   int buf = 0;
   bool bad = false;
@@ -259,16 +303,37 @@ __global__ __launch_bounds__(256) void k_lv_panel(const NDNodeH* __restrict__ no
   double* A = F + d.foff;
   const int t = threadIdx.x;
   double* cp = Cp + d.cp_off;
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    const int r = idx >> 6, q = idx & 63, i = j0 + r;
-    if (i < nf && q < kn && (i < k0 || i >= k0 + kn)) cp[(long long)i * GJB + q] = A[(long long)i * nf + k0 + q];
-  }
   const bool any = j0 != k0 || kn < GJB;  // the tile holds columns outside K
+  // every load first, from clamped addresses (values outside the ranges are
+  // not used), so that the 48 loads of a thread are in flight together:
+  // the pivot-column block of the tile's rows (for Cp), F[K][K], the tile's
+  // pivot rows
+  double vc[16], vp[16], va[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, i = j0 + r;
+    vc[m] = A[(long long)(i < nf ? i : 0) * nf + k0 + (q < kn ? q : 0)];
+  }
+  if (any) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = t + 256 * m, a = idx >> 6, b = idx & 63, j = j0 + b;
+      const long long row = (long long)(k0 + (a < kn ? a : 0)) * nf;
+      vp[m] = A[row + k0 + (b < kn ? b : 0)];
+      va[m] = A[row + (j < nf ? j : 0)];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, i = j0 + r;
+    if (i < nf && q < kn && (i < k0 || i >= k0 + kn)) cp[(long long)i * GJB + q] = vc[m];
+  }
   if (!any) return;
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    const int a = idx >> 6, b = idx & 63, j = j0 + b;
-    Pt[b][a] = (a < kn && b < kn) ? A[(long long)(k0 + a) * nf + k0 + b] : 0.0;
-    As[a][b] = (a < kn && j < nf) ? A[(long long)(k0 + a) * nf + j] : 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int idx = t + 256 * m, a = idx >> 6, b = idx & 63, j = j0 + b;
+    Pt[b][a] = (a < kn && b < kn) ? vp[m] : 0.0;
+    As[a][b] = (a < kn && j < nf) ? va[m] : 0.0;
   }
   __syncthreads();
   double acc[4][4];
@@ -295,25 +360,39 @@ __global__ __launch_bounds__(256) void k_lv_update(const NDNodeH* __restrict__ n
   if (i0 == k0 && kn == GJB) return;  // pivot rows only
   double* A = F + d.foff;
   const double* cp = Cp + d.cp_off;
-  const int t = threadIdx.x;
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    const int r = idx >> 6, q = idx & 63, i = i0 + r, j = j0 + q;
-    Ct[q][r] = (i < nf && q < kn && (i < k0 || i >= k0 + kn)) ? cp[(long long)i * GJB + q] : 0.0;
-    Rs[r][q] = (r < kn && j < nf) ? A[(long long)(k0 + r) * nf + j] : 0.0;
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  // every load first, from clamped addresses: Cp and the pivot rows for the
+  // product, and the thread's 16 old entries, which stay in flight during it
+  double vct[16], vrs[16], old[4][4];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, i = i0 + r, j = j0 + q;
+    vct[m] = cp[(long long)(i < nf ? i : 0) * GJB + (q < kn ? q : 0)];
+    vrs[m] = A[(long long)(k0 + (r < kn ? r : 0)) * nf + (j < nf ? j : 0)];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+      old[a][b] = A[(long long)(i < nf ? i : 0) * nf + (j < nf ? j : 0)];
+    }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, i = i0 + r, j = j0 + q;
+    Ct[q][r] = (i < nf && q < kn && (i < k0 || i >= k0 + kn)) ? vct[m] : 0.0;
+    Rs[r][q] = (r < kn && j < nf) ? vrs[m] : 0.0;
   }
   __syncthreads();
   double acc[4][4];
   tile_product(Ct, Rs, kn, acc);
-  const int tr = t >> 4, tc = t & 15;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
       if (i >= nf || j >= nf || (i >= k0 && i < k0 + kn)) continue;
-      double* e = A + (long long)i * nf + j;
-      if (j >= k0 && j < k0 + kn) *e = -acc[a][b];
-      else *e -= acc[a][b];
+      A[(long long)i * nf + j] = (j >= k0 && j < k0 + kn) ? -acc[a][b] : old[a][b] - acc[a][b];
     }
 }
 
@@ -334,16 +413,51 @@ __global__ __launch_bounds__(256) void k_lv_update_rows(const NDNodeH* __restric
   double* A = F + d.foff;
   const double* cp = Cp + d.cp_off;
   const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
-  for (int idx = t; idx < GJB * GJB; idx += 256) {
-    const int r = idx >> 6, q = idx & 63, i = i0 + r;
-    Ct[q][r] = (i < nf && q < kn && (i < k0 || i >= k0 + kn)) ? cp[(long long)i * GJB + q] : 0.0;
+  // loads from clamped addresses, all of a tile's in flight together; the
+  // next tile's pivot rows and old entries are requested before the current
+  // tile's product
+  double vrs[16], old[4][4];
+  auto load_tile = [&](int j0) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, j = j0 + q;
+      vrs[m] = A[(long long)(k0 + (r < kn ? r : 0)) * nf + (j < nf ? j : 0)];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
+        old[a][b] = A[(long long)(i < nf ? i : 0) * nf + (j < nf ? j : 0)];
+      }
+  };
+  {
+    double vct[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, i = i0 + r;
+      vct[m] = cp[(long long)(i < nf ? i : 0) * GJB + (q < kn ? q : 0)];
+    }
+    load_tile(0);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, i = i0 + r;
+      Ct[q][r] = (i < nf && q < kn && (i < k0 || i >= k0 + kn)) ? vct[m] : 0.0;
+    }
   }
   for (int j0 = 0; j0 < nf; j0 += GJB) {
-    for (int idx = t; idx < GJB * GJB; idx += 256) {
-      const int r = idx >> 6, q = idx & 63, j = j0 + q;
-      Rs[r][q] = (r < kn && j < nf) ? A[(long long)(k0 + r) * nf + j] : 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = t + 256 * m, r = idx >> 6, q = idx & 63, j = j0 + q;
+      Rs[r][q] = (r < kn && j < nf) ? vrs[m] : 0.0;
     }
+    double cur[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cur[a][b] = old[a][b];
     __syncthreads();
+    if (j0 + GJB < nf) load_tile(j0 + GJB);
     double acc[4][4];
     tile_product(Ct, Rs, kn, acc);
 #pragma unroll
@@ -352,9 +466,7 @@ __global__ __launch_bounds__(256) void k_lv_update_rows(const NDNodeH* __restric
       for (int b = 0; b < 4; ++b) {
         const int i = i0 + tr + 16 * a, j = j0 + tc + 16 * b;
         if (i >= nf || j >= nf || (i >= k0 && i < k0 + kn)) continue;
-        double* e = A + (long long)i * nf + j;
-        if (j >= k0 && j < k0 + kn) *e = -acc[a][b];
-        else *e -= acc[a][b];
+        A[(long long)i * nf + j] = (j >= k0 && j < k0 + kn) ? -acc[a][b] : cur[a][b] - acc[a][b];
       }
     __syncthreads();
   }

@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kBlk) void k_gather_dot(const double* __restrict__ 
   __shared__ double sh[kBlk];
   int g = blockIdx.x * kBlk + threadIdx.x;
   double s = 0.0;
+  const double wv = red ? w[g < N ? g : 0] : 0.0;  // requested with the owner list
   if (g < N) {
     // the owners in increasing cell order, all four values requested at once
     // (a missing owner reads entry 0 and adds nothing)
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(kBlk) void k_gather_dot(const double* __restrict__ 
     out[g] = s;
   }
   if (red) {
-    double d = (g < N) ? s * w[g] : 0.0;
+    double d = (g < N) ? s * wv : 0.0;
     d = block_sum(d, sh);
     if (threadIdx.x == 0) red[blockIdx.x] = d;
   }
@@ -230,8 +231,20 @@ constexpr int kVB = kBlk * kVec;  // entries per workgroup
 // fixed-order sum of red[0, n) by one workgroup; every workgroup that calls it
 // on the same data gets the same value
 __device__ inline double wg_sum(const double* __restrict__ red, int n, double* sh) {
+  // each thread adds red[t], red[t + kBlk], ... in that order; the loads of
+  // eight terms are issued together (clamped index, unused values discarded)
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += kBlk) s += red[i];
+  for (int base = 0; base < n; base += 8 * kBlk) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = base + threadIdx.x + k * kBlk;
+      v[k] = red[i < n ? i : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (base + threadIdx.x + k * kBlk < n) s += v[k];
+  }
   s = block_sum(s, sh);
   __syncthreads();
   return s;
@@ -246,6 +259,18 @@ __global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, dou
                                                      const double* __restrict__ red_pq, int nred, int rz_slot,
                                                      double* __restrict__ red_rr) {
   __shared__ double sh[kBlk];
+  // the vector entries are requested first (clamped index) and arrive while
+  // the workgroup sums the p.q partials
+  const int g0 = blockIdx.x * kVB + threadIdx.x;
+  double xv[kVec], pv[kVec], rv[kVec], qv[kVec];
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const int g = g0 + j * kBlk, gc = g < N ? g : 0;
+    xv[j] = x[gc];
+    pv[j] = p[gc];
+    rv[j] = r[gc];
+    qv[j] = q[gc];
+  }
   const double pq = wg_sum(red_pq, nred, sh);
   const double alpha = scal[rz_slot] / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -253,16 +278,15 @@ __global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, dou
     scal[2] = alpha;
     if (!(pq > 0.0)) scal[7] = 1.0;
   }
-  const int g0 = blockIdx.x * kVB + threadIdx.x;
   double d = 0.0;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
     const int g = g0 + j * kBlk;
     if (g < N) {
-      x[g] += alpha * p[g];
-      const double rv = r[g] - alpha * q[g];
-      r[g] = rv;
-      d += rv * rv;
+      x[g] = xv[j] + alpha * pv[j];
+      const double rn = rv[j] - alpha * qv[j];
+      r[g] = rn;
+      d += rn * rn;
     }
   }
   d = block_sum(d, sh);
@@ -278,6 +302,15 @@ __global__ __launch_bounds__(kBlk) void k_update_p4(double* __restrict__ p, cons
                                                     const double* __restrict__ red_rz, int nred, int old_slot,
                                                     int new_slot, int init) {
   __shared__ double sh[kBlk];
+  // z and p requested first (clamped index), while the r.z partials are summed
+  const int g0 = blockIdx.x * kVB + threadIdx.x;
+  double zv[kVec], pv[kVec];
+#pragma unroll
+  for (int j = 0; j < kVec; ++j) {
+    const int g = g0 + j * kBlk, gc = g < N ? g : 0;
+    zv[j] = z[gc];
+    pv[j] = p[gc];
+  }
   const double rz = wg_sum(red_rz, nred, sh);
   const double beta = init ? 0.0 : rz / scal[old_slot];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -285,11 +318,10 @@ __global__ __launch_bounds__(kBlk) void k_update_p4(double* __restrict__ p, cons
     scal[5] = beta;
     if (!(rz > 0.0)) scal[7] = 1.0;
   }
-  const int g0 = blockIdx.x * kVB + threadIdx.x;
 #pragma unroll
   for (int j = 0; j < kVec; ++j) {
     const int g = g0 + j * kBlk;
-    if (g < N) p[g] = init ? z[g] : z[g] + beta * p[g];
+    if (g < N) p[g] = init ? zv[j] : zv[j] + beta * pv[j];
   }
 }
 
