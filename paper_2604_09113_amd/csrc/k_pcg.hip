@@ -339,44 +339,93 @@ __global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b
 }
 
 // ---- interior recovery: u_I = -L^-T (Y u_U) (tractions act on skeleton dofs only)
+// u_I = -L_II^-T (Y u_U) for one cell per 64-lane wave (Y = L_II^-1 K_IU).
+// The cell's packed L_II is staged in LDS with all of its loads in flight
+// together; s = -Y u_U is formed with lane k taking rows k and k + 64; the
+// back substitution L_II^T u_I = s then runs right-looking: at step k the
+// owner of entry k holds its final value, which is divided by L_kk, read by
+// every lane with readlane, and subtracted, times L_kj, from the entries
+// j < k.  No barrier and no global load inside the substitution.
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
 template <int P>
 __global__ __launch_bounds__(64) void k_recover(const double* __restrict__ L, const double* __restrict__ Y,
                                                 const int* __restrict__ RU, const double* __restrict__ x, int nx,
                                                 int Gx, double* __restrict__ u, double* __restrict__ ucell) {
   constexpr int NI = 2 * (P - 1) * (P - 1), NU = 8 * P, NDOF = 2 * (P + 1) * (P + 1);
-  __shared__ double uu[NU];
-  __shared__ double s[NI];
+  constexpr int NLP = NI * (NI + 1) / 2;
+  static_assert(NU <= 64 && NI <= 128, "two interior entries per lane");
+  __shared__ double Ls[NLP];
+  __shared__ double uu[64];
   const int cell = blockIdx.x, l = threadIdx.x;
-  for (int j = l; j < NU; j += 64) {
-    int g = RU[(size_t)cell * NU + j];
-    uu[j] = g >= 0 ? x[g] : 0.0;
+  const int g = l < NU ? RU[(size_t)cell * NU + l] : -1;
+  // L_II into LDS, sixteen loads per lane in flight at a time
+  const double* Lc = L + (size_t)cell * NLP;
+  for (int base = 0; base < NLP; base += 64 * 16) {
+    double t[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = base + l + 64 * k;
+      t[k] = Lc[i < NLP ? i : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int i = base + l + 64 * k;
+      if (i < NLP) Ls[i] = t[k];
+    }
   }
+  const double xv = x[g >= 0 ? g : 0];
+  uu[l] = g >= 0 ? xv : 0.0;
   __syncthreads();
-  const double* Yc = Y + (size_t)cell * NI * NU;
-  for (int k = l; k < NI; k += 64) {
-    double a = 0.0;
-    for (int j = 0; j < NU; ++j) a += Yc[(size_t)k * NU + j] * uu[j];
-    s[k] = -a;
+  // s = -Y u_U: rows k0 = l and k1 = l + 64 (rows past NI read row 0)
+  const int k0 = l, k1 = l + 64;
+  const double* y0 = Y + ((size_t)cell * NI + (k0 < NI ? k0 : 0)) * NU;
+  const double* y1 = Y + ((size_t)cell * NI + (k1 < NI ? k1 : 0)) * NU;
+  double a0 = 0.0, a1 = 0.0;
+  for (int j0 = 0; j0 < NU; j0 += 16) {
+    double v0[16], v1[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int jj = j0 + j < NU ? j0 + j : 0;
+      v0[j] = y0[jj];
+      v1[j] = y1[jj];
+    }
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (j0 + j < NU) {
+        a0 += v0[j] * uu[j0 + j];
+        a1 += v1[j] * uu[j0 + j];
+      }
   }
-  __syncthreads();
-  const double* Lc = L + (size_t)cell * (NI * (NI + 1) / 2);
+  double s0 = -a0, s1 = -a1;
+  // L_kj = column j of the packed L_II at offset k - j
+  const int c0 = k0 * NI - k0 * (k0 - 1) / 2, c1 = k1 * NI - k1 * (k1 - 1) / 2;
   for (int k = NI - 1; k >= 0; --k) {
-    const double* col = Lc + (size_t)k * NI - (size_t)k * (k - 1) / 2;  // rows k..NI-1
-    double a = 0.0;
-    for (int i = k + 1 + l; i < NI; i += 64) a += col[i - k] * s[i];
-    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-    if (l == 0) s[k] = (s[k] - a) / col[0];
-    __syncthreads();
+    const int ck = k * NI - k * (k - 1) / 2;
+    const double sk = (k < 64 ? lane_value(s0, k) : lane_value(s1, k - 64)) / Ls[ck];
+    if (k < 64) {
+      if (l == k) s0 = sk;
+    } else {
+      if (l == k - 64) s1 = sk;
+    }
+    if (k0 < k) s0 -= Ls[c0 + k - k0] * sk;
+    if (k1 < k) s1 -= Ls[c1 + k - k1] * sk;
   }
   const int ix = cell % nx, iy = cell / nx;
-  for (int k = l; k < NI; k += 64) {
-    int n = k >> 1, comp = k & 1;
-    int a = n % (P - 1) + 1, b = n / (P - 1) + 1;
-    u[((size_t)(P * iy + b) * Gx + P * ix + a) * 2 + comp] = s[k];
-    if (ucell) ucell[(size_t)cell * NDOF + k] = s[k];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = h ? k1 : k0;
+    if (k >= NI) continue;
+    const double v = h ? s1 : s0;
+    const int n = k >> 1, comp = k & 1;
+    const int a = n % (P - 1) + 1, b = n / (P - 1) + 1;
+    u[((size_t)(P * iy + b) * Gx + P * ix + a) * 2 + comp] = v;
+    if (ucell) ucell[(size_t)cell * NDOF + k] = v;
   }
-  if (ucell)
-    for (int j = l; j < NU; j += 64) ucell[(size_t)cell * NDOF + NI + j] = uu[j];
+  if (ucell && l < NU) ucell[(size_t)cell * NDOF + NI + l] = uu[l];
 }
 
 __global__ void k_scatter_skel(const double* __restrict__ x, const int* __restrict__ node, int NU,
