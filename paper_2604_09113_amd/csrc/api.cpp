@@ -352,6 +352,10 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
     c->err = "pinned host allocation failed";
     ok = false;
   }
+  if (ok && hipHostGetDevicePointer((void**)&c->d_hred, c->h_red, 0) != hipSuccess) {
+    c->err = "pinned host buffer has no device address";
+    ok = false;
+  }
   if (!ok) { free_problem(c); return LBDDC_E_NOMEM; }
   // family -> slot table after the 8 flag words
   std::vector<int> flags(128, 0);
@@ -520,7 +524,7 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
 
 lbddc_status lbddc_set_timing(lbddc_ctx* x, int32_t mask) {
   if (!x) return LBDDC_E_ARG;
-  if (mask & ~LBDDC_TIME_ALL) return fail(&x->c, LBDDC_E_ARG, "set_timing: unknown phase bits");
+  if (mask & ~(LBDDC_TIME_ALL | LBDDC_TIME_SAMPLE)) return fail(&x->c, LBDDC_E_ARG, "set_timing: unknown phase bits");
   x->c.timing = mask;
   return LBDDC_OK;
 }

@@ -243,6 +243,7 @@ struct Ctx {
   double *d_zc = nullptr, *d_tc = nullptr, *d_xc = nullptr;  // coarse vectors [NC]
   double* d_red = nullptr;     // reduction partials [kRedSlots][kMaxBlocks]
   double* d_scal = nullptr;    // scalars
+  double* d_hred = nullptr;    // h_red as a device address (kernels write the r.r partials there)
   double* h_scal = nullptr;    // pinned
   double* d_vred = nullptr;    // interface-vector partials: p.q, r.z, r.r [3][NU / 256 + 16]
   double* h_red = nullptr;     // pinned copy of the r.r partials

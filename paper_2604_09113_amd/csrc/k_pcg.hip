@@ -253,11 +253,13 @@ __device__ inline double wg_sum(const double* __restrict__ red, int n, double* s
 // alpha = rz / (p.q) from the p.q partials (each workgroup sums them in the same
 // order); x += alpha p; r -= alpha q; partial r.r per workgroup.  Workgroup 0
 // records p.q and alpha and flags p.q <= 0 in scal[7].
+// host: the pinned host buffer, as a device address: [7] breakdown flag,
+// [32 + block] r.r partials (read by the host once the kernel has finished)
 __global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, double* __restrict__ r,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      double* __restrict__ scal, int N,
                                                      const double* __restrict__ red_pq, int nred, int rz_slot,
-                                                     double* __restrict__ red_rr) {
+                                                     double* __restrict__ host) {
   __shared__ double sh[kBlk];
   // the vector entries are requested first (clamped index) and arrive while
   // the workgroup sums the p.q partials
@@ -277,6 +279,7 @@ __global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, dou
     scal[1] = pq;
     scal[2] = alpha;
     if (!(pq > 0.0)) scal[7] = 1.0;
+    host[7] = scal[7];
   }
   double d = 0.0;
 #pragma unroll
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, dou
     }
   }
   d = block_sum(d, sh);
-  if (threadIdx.x == 0) red_rr[blockIdx.x] = d;
+  if (threadIdx.x == 0) host[32 + blockIdx.x] = d;
 }
 
 // rz_new from the r.z partials; p = z (init) or z + beta p with
@@ -489,6 +492,11 @@ static void prolong(Ctx* c, bool fp32) {
 #undef PLC
 }
 
+// With LBDDC_TIME_SAMPLE, one operator launch and one preconditioner
+// application in kSample record events (kRing is a multiple of kSample).
+constexpr int kSample = 4;
+static_assert(Ctx::kRing % kSample == 0, "a ring slot is timed on every use or never");
+
 // Device times of the timed PCG phases, accumulated from the event ring.
 struct PhaseAcc {
   double op = 0, pre = 0, coarse = 0, cf = 0, cb = 0;
@@ -521,10 +529,10 @@ static void harvest_apply(Ctx* c, int s, PhaseAcc& a) {
 
 // z = S_BDDC^-1 r (Alg. 1), with the partial dot r.z into red; the timed
 // phases record their events into ring slot `slot`
-static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red, int slot) {
+static hipError_t apply_M(Ctx* c, bool fp32, const double* r, double* z, double* red, int slot, bool timed) {
   const int nbU = (c->NU + kBlk - 1) / kBlk, nbC = (c->NC + kBlk - 1) / kBlk;
   hipEvent_t* e = c->pev[slot];
-  const bool tp = c->timing & LBDDC_TIME_PRE, tc = c->timing & LBDDC_TIME_COARSE;
+  const bool tp = timed && (c->timing & LBDDC_TIME_PRE), tc = timed && (c->timing & LBDDC_TIME_COARSE);
   if (tp) hipEventRecord(e[2], c->stream);
   pre_local(c, fp32, r);
   if (tp) hipEventRecord(e[3], c->stream);
@@ -549,7 +557,7 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   double* red = c->d_red;
   // partials: p.q and r.z per gather workgroup (nb); r.r per update workgroup
   // (nv) right after the scalar slots, so that one copy brings both to the host
-  double *red_pq = c->d_vred, *red_rz = c->d_vred + nb, *red_rr = c->d_scal + 32;
+  double *red_pq = c->d_vred, *red_rz = c->d_vred + nb;
   double* scal = c->d_scal;
   // scalar slots: 1 p.q, 2 alpha, 5 beta, 6 f.f, 7 breakdown flag, 10/11 r.z (alternating)
   hipLaunchKernelGGL(k_fill_p, dim3(256), dim3(256), 0, c->stream, x, (long long)N, 0.0);
@@ -562,20 +570,29 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   // which time its events completed long ago, and the rest after the loop
   PhaseAcc acc;
   int napp = 0, nop = 0;
+  // with LBDDC_TIME_SAMPLE only operator launches and applications whose count
+  // is a multiple of kSample record events, and the totals are scaled to all
+  const int every = (c->timing & LBDDC_TIME_SAMPLE) ? kSample : 1;
+  auto timed = [&](int k) { return k % every == 0; };
   auto apply = [&](void) -> hipError_t {
     const int sl = napp % Ctx::kRing;
-    if (napp >= Ctx::kRing) harvest_apply(c, sl, acc);
+    if (napp >= Ctx::kRing && timed(napp - Ctx::kRing)) harvest_apply(c, sl, acc);
+    const bool tm = timed(napp);
     ++napp;
-    return apply_M(c, fp32, r, z, red_rz, sl);
+    return apply_M(c, fp32, r, z, red_rz, sl, tm);
   };
   auto finish = [&](hipError_t e) {
-    for (int k = std::max(0, napp - Ctx::kRing); k < napp; ++k) harvest_apply(c, k % Ctx::kRing, acc);
-    for (int k = std::max(0, nop - Ctx::kRing); k < nop; ++k) harvest_op(c, k % Ctx::kRing, acc);
-    if (t_op) *t_op += acc.op;
-    if (t_pre) *t_pre += acc.pre;
-    if (t_coarse) *t_coarse += acc.coarse;
-    if (t_cfwd) *t_cfwd += acc.cf;
-    if (t_cbwd) *t_cbwd += acc.cb;
+    for (int k = std::max(0, napp - Ctx::kRing); k < napp; ++k)
+      if (timed(k)) harvest_apply(c, k % Ctx::kRing, acc);
+    for (int k = std::max(0, nop - Ctx::kRing); k < nop; ++k)
+      if (timed(k)) harvest_op(c, k % Ctx::kRing, acc);
+    const int napp_t = (napp + every - 1) / every, nop_t = (nop + every - 1) / every;
+    const double sa = napp_t ? (double)napp / napp_t : 0.0, so = nop_t ? (double)nop / nop_t : 0.0;
+    if (t_op) *t_op += acc.op * so;
+    if (t_pre) *t_pre += acc.pre * sa;
+    if (t_coarse) *t_coarse += acc.coarse * sa;
+    if (t_cfwd) *t_cfwd += acc.cf * sa;
+    if (t_cbwd) *t_cbwd += acc.cb * sa;
     if (n_apply) *n_apply += napp;
     return e;
   };
@@ -597,17 +614,16 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   const bool top = c->timing & LBDDC_TIME_OP;
   while (it < max_iter) {
     const int so = nop % Ctx::kRing;
-    if (nop >= Ctx::kRing) harvest_op(c, so, acc);
+    if (nop >= Ctx::kRing && timed(nop - Ctx::kRing)) harvest_op(c, so, acc);
+    const bool tm = top && timed(nop);
     ++nop;
-    if (top) hipEventRecord(c->pev[so][0], c->stream);
+    if (tm) hipEventRecord(c->pev[so][0], c->stream);
     op_local(c, p);
-    if (top) hipEventRecord(c->pev[so][1], c->stream);
+    if (tm) hipEventRecord(c->pev[so][1], c->stream);
     hipLaunchKernelGGL(k_gather_dot, dim3(nb), dim3(kBlk), 0, c->stream, c->d_partU, c->d_uown4, q, N,
                        p, red_pq);
     hipLaunchKernelGGL(k_update_xr4, dim3(nv), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red_pq, nb, slot,
-                       red_rr);
-    e = hipMemcpyAsync(c->h_red, scal, (32 + nv) * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e != hipSuccess) return e;
+                       c->d_hred);
     hipEventRecord(c->ev[6], c->stream);
     // speculatively enqueue the preconditioner and the direction update of the next iteration
     e = apply();

@@ -22,7 +22,7 @@ X_K, X_THETA, X_ITIL, X_S, X_D, X_PSI, X_SC, X_LOAD, X_FINE = range(9)
 Q_NCELL, Q_NDOF_FREE, Q_N_SKELETON, Q_N_INTERIOR, Q_N_COARSE, Q_N_I_ROM, Q_NU_CELL, Q_NC_CELL, Q_NRHS, \
     Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES, \
     Q_COARSE_SWEEP_LAUNCHES = range(15)
-TIME_OP, TIME_PRE, TIME_COARSE, TIME_ALL = 1, 2, 4, 7
+TIME_OP, TIME_PRE, TIME_COARSE, TIME_ALL, TIME_SAMPLE = 1, 2, 4, 7, 8
 PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor", "solve", "op_kernel",
           "pre_kernel", "coarse_solve", "recovery", "gradient", "adjoint_kernel", "coarse_fwd_sweep",
           "coarse_bwd_sweep"]
@@ -211,7 +211,8 @@ class Solver:
         return out
 
     def set_timing(self, mask):
-        """PCG phases timed by solve (TIME_OP | TIME_PRE | TIME_COARSE; TIME_ALL after creation)."""
+        """PCG phases timed by solve (TIME_OP | TIME_PRE | TIME_COARSE, optionally | TIME_SAMPLE for one
+        iteration in four; TIME_ALL after creation)."""
         self._check(self.lib.lbddc_set_timing(self.ctx, int(mask)))
 
     def phase_times(self):
