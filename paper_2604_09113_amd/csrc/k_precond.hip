@@ -28,32 +28,58 @@
 
 namespace lbddc {
 
-// In-place Gauss-Jordan inverse of the SPD n x n block A (row stride LDA) by
-// the 256 threads of the workgroup: rows go to the waves, columns to the lanes
-// (n <= 64); colp is a length-n scratch.  Sets *bad on a non-positive pivot.
-template <typename T, int LDA>
-__device__ void gj_inverse(T* A, int n, T* colp, int* bad) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int l = 0; l < n; ++l) {
-    if (threadIdx.x < n) colp[threadIdx.x] = A[threadIdx.x * LDA + l];
-    __syncthreads();
-    T piv = colp[l];
-    if (!(piv > (T)0)) { if (threadIdx.x == 0) *bad = 1; piv = (T)1; }
-    const T pinv = (T)1 / piv;
-    const T rl = lane < n ? A[l * LDA + lane] : (T)0;  // pivot row, read before any write below
-    __syncthreads();
-    for (int i = wave; i < n; i += 4) {
-      if (lane >= n) continue;
-      T* a = A + i * LDA + lane;
-      if (i == l) {
-        *a = lane == l ? pinv : rl * pinv;
-      } else {
-        const T ci = colp[i] * pinv;
-        *a = lane == l ? -ci : *a - ci * rl;
+// Value of v held by lane `src` (wave-uniform), through scalar reads.
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// In-place Gauss-Jordan inverse of the SPD N x N block A (row stride LDA,
+// N <= 64; no pivoting) by wave 0 alone, with lane j holding column j in
+// registers.  Pivot step l:
+//   A[l][j] <- A[l][j] / p (1 / p on the diagonal),
+//   A[i][j] <- A[i][j] - (A[i][l] / p) A[l][j], A[i][l] <- -A[i][l] / p  (i != l).
+// The register array is rotated by one row per step, so that row l sits at
+// index 0 at step l and every index is a compile-time constant (after N steps
+// the rows are back in order); the pivot column entries A[i][l] come from lane
+// l by readlane.  A step needs neither a barrier nor LDS traffic.  Sets *bad
+// on a non-positive pivot.  The other waves wait at the closing barrier.
+template <typename T, int LDA, int N>
+__device__ __forceinline__ void gj_inverse_wave(T* A, int* bad) {
+  static_assert(N <= 64, "one column per lane");
+  if (threadIdx.x < 64) {
+    // lanes j >= N carry a copy of column 0 through the sweep: their values
+    // are never read by other lanes nor stored
+    const int j = threadIdx.x, jc = j < N ? j : 0;
+    T col[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) col[i] = A[i * LDA + jc];
+    for (int l = 0; l < N; ++l) {
+      const T rl = col[0];  // A[l][j]
+      T piv = lane_bcast(rl, l);
+      if (!(piv > (T)0)) {
+        if (j == 0) *bad = 1;
+        piv = (T)1;
       }
+      const T pinv = (T)1 / piv;
+      const bool jl = j == l;
+#pragma unroll
+      for (int i = 1; i < N; ++i) {
+        const T ci = lane_bcast(col[i], l) * pinv;
+        col[i - 1] = jl ? -ci : col[i] - ci * rl;
+      }
+      col[N - 1] = jl ? pinv : rl * pinv;
     }
-    __syncthreads();
+    if (j < N) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) A[i * LDA + j] = col[i];
+    }
   }
+  __syncthreads();
 }
 
 typedef float flt4m __attribute__((ext_vector_type(4)));
@@ -90,11 +116,15 @@ __device__ __forceinline__ void mfma_mm(FA a, FB b, FO out) {
   for (int t = wave; t < TM * TN; t += 4) {
     const int r0 = (t / TN) * 16, c0 = (t % TN) * 16;
     v4 acc = v4{0, 0, 0, 0};
+    // bounds that hold for every tile are known at compile time, so operand
+    // reads from memory need no branch (and no wait per read)
+    const bool row_ok = M % 16 == 0 || r0 + l16 < M, col_ok = N % 16 == 0 || c0 + l16 < N;
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 4) {
       const int k = k0 + kl;
-      const T av = (r0 + l16 < M && k < K) ? a(r0 + l16, k) : (T)0;
-      const T bv = (k < K && c0 + l16 < N) ? b(k, c0 + l16) : (T)0;
+      const bool k_ok = K % 4 == 0 || k < K;
+      const T av = (row_ok && k_ok) ? a(r0 + l16, k) : (T)0;
+      const T bv = (k_ok && col_ok) ? b(k, c0 + l16) : (T)0;
       acc = Mf<T>::op(av, bv, acc);
     }
 #pragma unroll
@@ -131,7 +161,6 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
     double SPs[NU][NC + 1];  // S Psi
   };
   __shared__ Work wk;
-  __shared__ T colp[NE];
   __shared__ double Dv[NU];
   __shared__ double Ps[NU][NC + 1];  // coarse basis (unscaled)
   __shared__ int bad;
@@ -144,29 +173,52 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   auto& Scol = wk.s.Scol;
   const double* S = Sg + (size_t)cell * NSP;
   if (tid == 0) bad = 0;
-  for (int idx = tid; idx < NE * NE; idx += 256) {
-    int i = idx / NE, j = idx % NE, I = 8 + i, J = 8 + j;
-    int hi = I > J ? I : J, lo = I > J ? J : I;
-    A[i][j] = (T)S[hi * (hi + 1) / 2 + lo];
+  // every global load of the cell first, from clamped positions (values past
+  // the ranges are not used): the edge block of the packed S, its corner
+  // columns, the weights' diagonals, the constraint rows
+  constexpr int NLA = (NE * NE + 255) / 256, NLS = (NE * 8 + 255) / 256;
+  constexpr int NCV = 4 * NCE * (P + 1) * 2;
+  static_assert(NU <= 256 && NCV <= 256, "one weight and one constraint value per thread");
+  // the index map first: the weight's denominator is gathered through it
+  const int gw = tid < NU ? RU[(size_t)cell * NU + tid] : -1;
+  double va[NLA], vs[NLS];
+#pragma unroll
+  for (int m = 0; m < NLA; ++m) {
+    const int idx = tid + 256 * m < NE * NE ? tid + 256 * m : 0;
+    const int I = 8 + idx / NE, J = 8 + idx % NE;
+    const int hi = I > J ? I : J, lo = I > J ? J : I;
+    va[m] = S[hi * (hi + 1) / 2 + lo];
   }
-  for (int idx = tid; idx < NE * 8; idx += 256) {
-    int i = idx / 8, j = idx % 8, I = 8 + i;
-    Scol[i][j] = (T)S[I * (I + 1) / 2 + j];
+#pragma unroll
+  for (int m = 0; m < NLS; ++m) {
+    const int idx = tid + 256 * m < NE * 8 ? tid + 256 * m : 0;
+    const int I = 8 + idx / 8;
+    vs[m] = S[I * (I + 1) / 2 + idx % 8];
   }
-  for (int j = tid; j < NU; j += 256) {
-    int g = RU[(size_t)cell * NU + j];
-    Dv[j] = g >= 0 ? diagK[(size_t)cell * NU + j] / Ktot[g] : 0.0;
+  const double dk = diagK[(size_t)cell * NU + (tid < NU ? tid : 0)];
+  const double* cc = cons + (size_t)cell * 4 * NCE * (P + 1) * 2;
+  const double cv = cc[tid < NCV ? tid : 0];
+  const double kt = Ktot[gw >= 0 ? gw : 0];
+#pragma unroll
+  for (int m = 0; m < NLA; ++m) {
+    const int idx = tid + 256 * m;
+    if (idx < NE * NE) A[idx / NE][idx % NE] = (T)va[m];
   }
+#pragma unroll
+  for (int m = 0; m < NLS; ++m) {
+    const int idx = tid + 256 * m;
+    if (idx < NE * 8) Scol[idx / 8][idx % 8] = (T)vs[m];
+  }
+  if (tid < NU) Dv[tid] = gw >= 0 ? dk / kt : 0.0;
   // constraint rows: Chat (edge dofs) and the corner columns
   for (int idx = tid; idx < NCC * NE; idx += 256) Ch[idx / NE][idx % NE] = (T)0;
   for (int idx = tid; idx < NCC * 8; idx += 256) Cc[idx / 8][idx % 8] = (T)0;
   __syncthreads();
-  const double* cc = cons + (size_t)cell * 4 * NCE * (P + 1) * 2;
-  for (int idx = tid; idx < 4 * NCE * (P + 1) * 2; idx += 256) {
+  for (int idx = tid; idx < NCV; idx += 256) {
     const int comp = idx & 1, n = (idx >> 1) % (P + 1), et = (idx >> 1) / (P + 1);
     const int e = et / NCE;
     if (left && e == 0) continue;  // the clamped side carries no constraints
-    const T v = (T)cc[idx];
+    const T v = (T)cv;
     if (n == 0 || n == P) {
       int corner = (e == 0) ? (n == 0 ? 0 : 2) : (e == 1) ? (n == 0 ? 1 : 3) : (e == 2) ? (n == 0 ? 0 : 1) : (n == 0 ? 2 : 3);
       if (left && (corner == 0 || corner == 2)) continue;
@@ -177,7 +229,7 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   }
   __syncthreads();
   // Shat^-1 in place
-  gj_inverse<T, NE + 1>(&A[0][0], NE, colp, &bad);
+  gj_inverse_wave<T, NE + 1, NE>(&A[0][0], &bad);
   // X = Shat^-1 Chat^T
   mfma_mm<T, NE, NCC, NE>([&](int i, int k) { return A[i][k]; }, [&](int k, int a) { return Ch[a][k]; },
                           [&](int i, int a, T v) { X[i][a] = v; });
@@ -186,7 +238,7 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   mfma_mm<T, NCC, NCC, NE>([&](int a, int i) { return Ch[a][i]; }, [&](int i, int b) { return X[i][b]; },
                            [&](int a, int b, T v) { Tm[a][b] = (left && a == b && a < NCE) ? (T)1 : v; });
   __syncthreads();
-  gj_inverse<T, NCC + 1>(&Tm[0][0], NCC, colp, &bad);
+  gj_inverse_wave<T, NCC + 1, NCC>(&Tm[0][0], &bad);
   // W2 = X That^-1
   mfma_mm<T, NE, NCC, NCC>([&](int i, int b) { return X[i][b]; }, [&](int b, int a) { return Tm[b][a]; },
                            [&](int i, int a, T v) { W2[i][a] = v; });
