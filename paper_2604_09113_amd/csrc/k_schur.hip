@@ -41,7 +41,19 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
   for (int i = tid; i < NU; i += 256) msk[i] = left ? dirmask[i] : 0;
   __syncthreads();
   const double* Kc = K + (size_t)cell * NPAIR * 4;
+  // every load of the thread's entries first, from clamped positions (entries
+  // outside the lower triangle read entry 0 and are replaced below), so the
+  // 66 loads are in flight together
   double A[NA][NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+      const int I = tr + 16 * a, J = tc + 16 * b;
+      const bool in = I < NDOF && J <= I;
+      const int Ic = in ? I : 0, Jc = in ? J : 0, n1 = Ic >> 1, n2 = Jc >> 1;
+      A[a][b] = Kc[((size_t)(n1 * (n1 + 1) / 2 + n2)) * 4 + 2 * (Ic & 1) + (Jc & 1)];
+    }
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
@@ -49,8 +61,7 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
       const int I = tr + 16 * a, J = tc + 16 * b;
       double v = 0.0;
       if (I < NDOF && J <= I) {
-        const int n1 = I >> 1, n2 = J >> 1;
-        v = Kc[((size_t)(n1 * (n1 + 1) / 2 + n2)) * 4 + 2 * (I & 1) + (J & 1)];
+        v = A[a][b];
         const bool mI = I >= NI && msk[I - NI], mJ = J >= NI && msk[J - NI];
         if (I == J && I >= NI) diagK[(size_t)cell * NU + I - NI] = mI ? 0.0 : v;
         if (mI || mJ) v = (I == J) ? 1.0 : 0.0;
