@@ -138,15 +138,16 @@ __global__ __launch_bounds__(64) void k_prolong(const T* __restrict__ Psi, const
   }
 }
 
-// block-level fixed-tree sum of v (blockDim = kBlk); result valid in thread 0
+// block-level fixed-order sum of v (blockDim = kBlk = four waves): a
+// butterfly of xor-shuffles within each wave, then the four wave sums in
+// order; the result is valid in every thread
+static_assert(kBlk == 256, "four waves per block");
 __device__ inline double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int o = kBlk / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
-    __syncthreads();
-  }
-  return sh[0];
+  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
 // out[g] = sum of owners' partials; optional partial dot out . w per block
