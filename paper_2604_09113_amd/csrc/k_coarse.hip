@@ -116,19 +116,58 @@ __global__ __launch_bounds__(NT) void k_front_lds(const NDNodeH* __restrict__ no
   const int nf = d.ns + d.nb, ld = nf + 1;
   double* A = F + d.foff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int i = wave; i < nf; i += W)
-    for (int j = lane; j < nf; j += 64) S[i * ld + j] = A[(long long)i * nf + j];
+  constexpr int NR = (NF + W - 1) / W, NJ0 = (NF + 63) / 64;  // rows per wave, column chunks
+  // the thread's entries of the front, every load in flight together: the
+  // row address advances in a per-lane pointer (rows past nf re-read the last
+  // row, columns past nf read column 0; neither is stored)
+  {
+    double v[NR][NJ0];
+    const double* pr = A + (wave < nf ? (long long)wave * nf : 0);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+#pragma unroll
+      for (int c = 0; c < NJ0; ++c) v[k][c] = pr[lane + 64 * c < nf ? lane + 64 * c : 0];
+      pr += wave + W * (k + 1) < nf ? (long long)W * nf : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int i = wave + W * k;
+      if (i >= nf) break;
+#pragma unroll
+      for (int c = 0; c < NJ0; ++c)
+        if (lane + 64 * c < nf) S[i * ld + lane + 64 * c] = v[k][c];
+    }
+  }
   __syncthreads();
   for (int s = 0; s < 2; ++s) {
     const int ch = d.child[s];
     if (ch < 0) continue;
     const NDNodeH c = nodes[ch];
-    const int nfc = c.ns + c.nb;
+    const int nfc = c.ns + c.nb, nb = c.nb;
     const int* map = cmap + d.cmap_off[s];
     const double* U = F + c.foff + (long long)c.ns * nfc + c.ns;
-    for (int i = wave; i < c.nb; i += W) {
-      const int r = map[i] * ld;
-      for (int j = lane; j < c.nb; j += 64) S[r + map[j]] += U[(long long)i * nfc + j];
+    // the child's update rows are at most nf long: the map entries and the
+    // values are all requested before the adds
+    int mj[NJ0], mi[NR];
+    double u[NR][NJ0];
+#pragma unroll
+    for (int cc = 0; cc < NJ0; ++cc) mj[cc] = map[lane + 64 * cc < nb ? lane + 64 * cc : 0];
+    const double* ur = U + (wave < nb ? (long long)wave * nfc : 0);
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const int i = wave + W * k;
+      mi[k] = map[i < nb ? i : 0];
+#pragma unroll
+      for (int cc = 0; cc < NJ0; ++cc) u[k][cc] = ur[lane + 64 * cc < nb ? lane + 64 * cc : 0];
+      ur += i + W < nb ? (long long)W * nfc : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      if (wave + W * k >= nb) break;
+      const int r = mi[k] * ld;
+#pragma unroll
+      for (int cc = 0; cc < NJ0; ++cc)
+        if (lane + 64 * cc < nb) S[r + mj[cc]] += u[k][cc];
     }
     __syncthreads();
   }
