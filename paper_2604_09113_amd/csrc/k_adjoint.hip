@@ -56,19 +56,35 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
   const GP ut = (GP)utg[td.x];
   const GP ut2 = (GP)ut2g[td.x];
   __syncthreads();
-  // products w_P u[n1, i1] u[n2, i2] of the pair rows this lane feeds (4 pairs x 4 components)
-  auto pair_products = [&](int pt, double (&uu)[4][4]) {
+  // products w_P u[n1, i1] u[n2, i2] of the pair rows this lane feeds (4 pairs
+  // x 4 components).  The node pairs are in triangular order, P = n1 (n1 + 1)
+  // / 2 + n2 with n2 <= n1, so (n1, n2) is computed rather than loaded; the
+  // displacement entries of a pair tile are requested a tile ahead (pair_load,
+  // unconditional: pairs out of range read node 0 and get weight 0), and the
+  // products are formed when the tile starts (pair_products)
+  double ra[4][4], rw[4];
+  auto pair_load = [&](int pt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int P = pt * 16 + 4 * grp + v;
-      if (pt < NPT && P < npair && valid) {
-        const int2 nn = pairs[P];
-        const double w = nn.x == nn.y ? 1.0 : 2.0;
-        const double a0 = uc[2 * nn.x], a1 = uc[2 * nn.x + 1], c0 = uc[2 * nn.y], c1 = uc[2 * nn.y + 1];
-        uu[v][0] = w * a0 * c0; uu[v][1] = w * a0 * c1; uu[v][2] = w * a1 * c0; uu[v][3] = w * a1 * c1;
-      } else {
-        uu[v][0] = uu[v][1] = uu[v][2] = uu[v][3] = 0.0;
-      }
+      const bool ok = pt < NPT && P < npair && valid;
+      const int Pc = ok ? P : 0;
+      int n1 = (int)((sqrtf(8.0f * (float)Pc + 1.0f) - 1.0f) * 0.5f);
+      if ((n1 + 1) * (n1 + 2) / 2 <= Pc) ++n1;
+      if (n1 * (n1 + 1) / 2 > Pc) --n1;
+      const int n2 = Pc - n1 * (n1 + 1) / 2;
+      rw[v] = ok ? (n1 == n2 ? 1.0 : 2.0) : 0.0;
+      ra[v][0] = uc[2 * n1];
+      ra[v][1] = uc[2 * n1 + 1];
+      ra[v][2] = uc[2 * n2];
+      ra[v][3] = uc[2 * n2 + 1];
+    }
+  };
+  auto pair_products = [&](double (&uu)[4][4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double w = rw[v], a0 = ra[v][0], a1 = ra[v][1], c0 = ra[v][2], c1 = ra[v][3];
+      uu[v][0] = w * a0 * c0; uu[v][1] = w * a0 * c1; uu[v][2] = w * a1 * c0; uu[v][3] = w * a1 * c1;
     }
   };
   dbl4 hacc2[RB];  // second accumulator chain of H (odd kk), added in a fixed order at the end
@@ -91,7 +107,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) a2[rb][kk] = ap2[(rb * 4 + kk) * 64];
   };
-  double uu[4][4], un[4][4];
+  double uu[4][4];
   // one step: Ihat of the 16 pairs x 16 cells on MFMA, H += Uhat2^T Z, G += u u Ihat
   auto step = [&](int s, const double (&a)[KC], const double (&a2)[RB][4]) {
     dbl4 d = dbl4{0, 0, 0, 0};
@@ -126,19 +142,18 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
   double aA[KC], a2A[RB][4], aB[KC], a2B[RB][4];
   load(wave, 0, aA, a2A);
   load(wave, 1, aB, a2B);
-  pair_products(wave, uu);
+  pair_load(wave);
+  pair_products(uu);
+  pair_load(wave + 4);  // next pair tile: its loads overlap this tile's work
   for (int pt = wave; pt < NPT; pt += 4) {
-    pair_products(pt + 4, un);  // next pair tile: loads overlap this tile's work
     for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
       step(s, aA, a2A);
       load(pt, s + 2, aA, a2A);
       step(s + 1, aB, a2B);
       load(pt, s + 3, aB, a2B);
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) uu[v][e] = un[v][e];
+    pair_products(uu);
+    pair_load(pt + 8);
   }
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) hacc[rb] += hacc2[rb];
