@@ -345,8 +345,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_gcell, (size_t)ncell * (c->m + 1) * (c->m + 1) * 2) &&
             dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) &&
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
-            dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8) &&
-            dalloc_t(c, &c->d_pairs, (size_t)2 * c->npair);
+            dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8);
   if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(32 + c->NU / 1024 + 16) * sizeof(double)) != hipSuccess) {
     c->h_red = nullptr;
     c->err = "pinned host allocation failed";
@@ -369,13 +368,6 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
   if (e == hipSuccess) e = hipMemcpy(c->d_t, d->t, ncell * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_trac, d->traction, (size_t)c->nrhs * c->ny * 2 * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem upload"); }
-  {
-    std::vector<int> pr(2 * c->npair);
-    for (int n1 = 0, P = 0; n1 < c->nN; ++n1)
-      for (int n2 = 0; n2 <= n1; ++n2, ++P) { pr[2 * P] = n1; pr[2 * P + 1] = n2; }
-    if (e == hipSuccess) e = hipMemcpy(c->d_pairs, pr.data(), pr.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem upload"); }
-  }
   c->fam_host.assign(d->family, d->family + ncell);
   c->t_host.assign(d->t, d->t + ncell);
   // validate the maps on the device (det J) right away

@@ -259,7 +259,6 @@ struct Ctx {
   double* d_J = nullptr;       // [nrhs]
   int* d_adj_tiles = nullptr;  // 16-cell tiles of the adjoint contraction
   void* d_adj_ptrs = nullptr;  // per-group tile pointers (A and transposed layouts)
-  int* d_pairs = nullptr;      // [npair] (n1, n2) of each node pair
   std::vector<int> group_counts;
   double* d_ucell = nullptr;   // [ncell][ndof] local displacement (permuted)
 

@@ -27,8 +27,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
                                                  const double* const* __restrict__ ut2g,
                                                  const double* __restrict__ theta, const double* __restrict__ itil,
                                                  const double* __restrict__ ucell, const int* __restrict__ sorted,
-                                                 const int4* __restrict__ tiles, const int2* __restrict__ pairs,
-                                                 double* __restrict__ Hout, double* __restrict__ Gout, int ns,
+                                                 const int4* __restrict__ tiles, double* __restrict__ Hout, double* __restrict__ Gout, int ns,
                                                  int npair, int NPT, int itil_stride, int ndof) {
   extern __shared__ double lds[];
   const int4 td = tiles[blockIdx.x];
@@ -353,12 +352,12 @@ __global__ void k_compliance(const double* __restrict__ part, int n, double* __r
 
 template <int KC>
 static void launch_adj(Ctx* c, const double* const* pu, const double* const* pu2, const int4* tiles, int ntiles,
-                       const int2* pairs, const double* ucell, const double* theta16) {
+                       const double* ucell, const double* theta16) {
   constexpr int RB = (4 * KC + 15) / 16;
   if (c->ns % 2 != 0) return;  // the kernel takes the steps of s in pairs (ns = 4 (q + 1)^2)
   const size_t lds = (size_t)4 * 16 * c->ns * 4 * sizeof(double);
   hipLaunchKernelGGL((k_adjoint<KC, RB>), dim3(ntiles), dim3(256), lds, c->stream, pu, pu2, theta16, c->d_itil,
-                     ucell, c->d_sorted, tiles, pairs, c->d_H, c->d_G, c->ns, c->npair, c->NPT, 4 * c->KC,
+                     ucell, c->d_sorted, tiles, c->d_H, c->d_G, c->ns, c->npair, c->NPT, 4 * c->KC,
                      c->ndof);
 }
 
@@ -399,21 +398,20 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     if (fam_n[s] == 0) continue;
     const int4* tl = reinterpret_cast<const int4*>(c->d_adj_tiles) + fam_first[s];
-    const int2* pr = reinterpret_cast<const int2*>(c->d_pairs);
     const double* uc = c->d_ucell + (size_t)rhs * c->ncell * c->ndof;
     const double* th = c->d_theta_t + (size_t)fam_first[s] * c->ns * 64;
     switch (c->roms[c->fam_ids[s]].KC) {
-      case 1: launch_adj<1>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 2: launch_adj<2>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 3: launch_adj<3>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 4: launch_adj<4>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 5: launch_adj<5>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 6: launch_adj<6>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 7: launch_adj<7>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 8: launch_adj<8>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 9: launch_adj<9>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 10: launch_adj<10>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
-      case 11: launch_adj<11>(c, pu, pu + G, tl, fam_n[s], pr, uc, th); break;
+      case 1: launch_adj<1>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 2: launch_adj<2>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 3: launch_adj<3>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 4: launch_adj<4>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 5: launch_adj<5>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 6: launch_adj<6>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 7: launch_adj<7>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 8: launch_adj<8>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 9: launch_adj<9>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 10: launch_adj<10>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
+      case 11: launch_adj<11>(c, pu, pu + G, tl, fam_n[s], uc, th); break;
       default: return hipErrorInvalidValue;
     }
     e = hipGetLastError();

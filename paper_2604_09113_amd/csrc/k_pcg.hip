@@ -199,32 +199,6 @@ __global__ __launch_bounds__(kBlk) void k_reduce(const double* __restrict__ red,
   }
 }
 
-// x += alpha p; r -= alpha q; partial r.r
-__global__ __launch_bounds__(kBlk) void k_update_xr(double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ p, const double* __restrict__ q,
-                                                    const double* __restrict__ scal, int N, double* __restrict__ red) {
-  __shared__ double sh[kBlk];
-  const double alpha = scal[2];
-  int g = blockIdx.x * kBlk + threadIdx.x;
-  double d = 0.0;
-  if (g < N) {
-    x[g] += alpha * p[g];
-    double rv = r[g] - alpha * q[g];
-    r[g] = rv;
-    d = rv * rv;
-  }
-  d = block_sum(d, sh);
-  if (threadIdx.x == 0) red[blockIdx.x] = d;
-}
-
-// p = z + beta p  (beta from scal[5]; first call with beta forced to 0 via `init`)
-__global__ void k_update_p(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ scal,
-                           int N, int init) {
-  int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  p[g] = init ? z[g] : z[g] + scal[5] * p[g];
-}
-
 // ---- interface-vector kernels of the iteration: kVec entries per thread ----
 constexpr int kVec = 4;
 constexpr int kVB = kBlk * kVec;  // entries per workgroup
