@@ -346,7 +346,8 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
             dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) &&
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
             dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8);
-  if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(32 + c->NU / 1024 + 16) * sizeof(double)) != hipSuccess) {
+  if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(32 + c->NU / 1024 + 16) * sizeof(double),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     c->h_red = nullptr;
     c->err = "pinned host allocation failed";
     ok = false;

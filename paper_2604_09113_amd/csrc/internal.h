@@ -246,7 +246,7 @@ struct Ctx {
   double* d_hred = nullptr;    // h_red as a device address (kernels write the r.r partials there)
   double* h_scal = nullptr;    // pinned
   double* d_vred = nullptr;    // interface-vector partials: p.q, r.z, r.r [3][NU / 256 + 16]
-  double* h_red = nullptr;     // pinned copy of the r.r partials
+  double* h_red = nullptr;     // pinned, coherent: the r.r partials and breakdown flag of the last update
   double* d_u = nullptr;       // [nrhs][Gy][Gx][2]
   std::vector<lbddc_solve_info> info;
 

@@ -11,6 +11,8 @@
 // fine operator and the coarse basis are stored and applied in FP32.
 // Every sum runs in a fixed order (owner lists sorted by cell, block
 // reductions with a fixed tree), so results are bitwise reproducible.
+#include <chrono>
+
 #include "internal.h"
 
 namespace lbddc {
@@ -229,7 +231,7 @@ __device__ inline double wg_sum(const double* __restrict__ red, int n, double* s
 // order); x += alpha p; r -= alpha q; partial r.r per workgroup.  Workgroup 0
 // records p.q and alpha and flags p.q <= 0 in scal[7].
 // host: the pinned host buffer, as a device address: [7] breakdown flag,
-// [32 + block] r.r partials (read by the host once the kernel has finished)
+// [32 + block] r.r partials (the host reads each slot once it has been written)
 __global__ __launch_bounds__(kBlk) void k_update_xr4(double* __restrict__ x, double* __restrict__ r,
                                                      const double* __restrict__ p, const double* __restrict__ q,
                                                      double* __restrict__ scal, int N,
@@ -477,6 +479,43 @@ struct PhaseAcc {
   double op = 0, pre = 0, coarse = 0, cf = 0, cb = 0;
 };
 
+// The host learns that an iteration's update has finished from the pinned
+// buffer it writes (coherent host memory, so the stores reach the host
+// directly), not from an event: an event marker between two kernels leaves
+// the device idle for several microseconds.  Before the update is enqueued
+// the host fills its slots (breakdown flag 7, r.r partials 32 ..) with a
+// signalling-NaN pattern; arithmetic produces only quiet NaNs, so a slot that
+// no longer holds the pattern has been written.
+constexpr unsigned long long kUnset = 0x7ff4c0ffee5e7f11ull;
+static inline int hred_slot(int k) { return k == 0 ? 7 : 31 + k; }  // k = 0 .. nv
+
+static void hred_unset(Ctx* c, int nv) {
+  for (int k = 0; k <= nv; ++k)
+    __atomic_store_n(reinterpret_cast<unsigned long long*>(c->h_red + hred_slot(k)), kUnset, __ATOMIC_RELAXED);
+}
+
+// Spin until every slot is written.  The spin is bounded: past 50 ms the
+// stream is synchronised instead (which also reports a device error); a slot
+// still unset once everything enqueued has finished is an error.
+static hipError_t hred_wait(Ctx* c, int nv) {
+  auto written = [&](int k) {
+    return __atomic_load_n(reinterpret_cast<const unsigned long long*>(c->h_red + hred_slot(k)), __ATOMIC_ACQUIRE) !=
+           kUnset;
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  int k = 0;
+  for (unsigned spins = 0;; ++spins) {
+    while (k <= nv && written(k)) ++k;
+    if (k > nv) return hipSuccess;
+    if ((spins & 1023u) == 1023u && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+      const hipError_t e = hipStreamSynchronize(c->stream);
+      if (e != hipSuccess) return e;
+      while (k <= nv && written(k)) ++k;
+      return k > nv ? hipSuccess : hipErrorLaunchFailure;
+    }
+  }
+}
+
 static double elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0;
   return hipEventElapsedTime(&ms, a, b) == hipSuccess ? ms : 0.0;
@@ -588,6 +627,7 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
   if (c->h_scal[7] != 0.0) return finish(hipErrorUnknown);  // breakdown, reported by the caller
   const bool top = c->timing & LBDDC_TIME_OP;
   while (it < max_iter) {
+    hred_unset(c, nv);
     const int so = nop % Ctx::kRing;
     if (nop >= Ctx::kRing && timed(nop - Ctx::kRing)) harvest_op(c, so, acc);
     const bool tm = top && timed(nop);
@@ -599,14 +639,13 @@ hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_inf
                        p, red_pq);
     hipLaunchKernelGGL(k_update_xr4, dim3(nv), dim3(kBlk), 0, c->stream, x, r, p, q, scal, N, red_pq, nb, slot,
                        c->d_hred);
-    hipEventRecord(c->ev[6], c->stream);
     // speculatively enqueue the preconditioner and the direction update of the next iteration
     e = apply();
     if (e != hipSuccess) return e;
     const int next = slot == 10 ? 11 : 10;
     hipLaunchKernelGGL(k_update_p4, dim3(nv), dim3(kBlk), 0, c->stream, p, z, scal, N, red_rz, nb, slot, next, 0);
     slot = next;
-    e = hipEventSynchronize(c->ev[6]);
+    e = hred_wait(c, nv);
     if (e != hipSuccess) return e;
     ++it;
     if (c->h_red[7] != 0.0) {
