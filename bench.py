@@ -286,7 +286,7 @@ def main():
                 "pcg_fine_restrict_fp32": ph["pre_kernel"] * napp}
 
     # PCG phase events timed inside the timed region: only the dominant kernel's,
-    # on one iteration in four (each event leaves the device idle for a few
+    # on one iteration in eight (each event leaves the device idle for a few
     # microseconds; the library scales the sampled totals to all iterations)
     S = lbddc.TIME_SAMPLE
     mask_of = {"k_nd_fwd": lbddc.TIME_COARSE | S, "k_nd_bwd": lbddc.TIME_COARSE | S,

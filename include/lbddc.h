@@ -232,9 +232,9 @@ lbddc_status lbddc_phase_times(lbddc_ctx* ctx, double* ms, int32_t n);
  * microseconds between kernels; phases that are not timed report 0.  The
  * assembly, setup, recovery and gradient phases are always timed (a few
  * events per call).  With LBDDC_TIME_SAMPLE added, only one operator launch
- * and one preconditioner application in four record events, and the reported
+ * and one preconditioner application in eight record events, and the reported
  * totals are scaled to all of them (the idle time the events cause drops
- * fourfold).  Returns LBDDC_E_ARG for unknown bits. */
+ * eightfold).  Returns LBDDC_E_ARG for unknown bits. */
 enum { LBDDC_TIME_OP = 1, LBDDC_TIME_PRE = 2, LBDDC_TIME_COARSE = 4, LBDDC_TIME_ALL = 7, LBDDC_TIME_SAMPLE = 8 };
 lbddc_status lbddc_set_timing(lbddc_ctx* ctx, int32_t mask);
 

@@ -471,7 +471,7 @@ static void prolong(Ctx* c, bool fp32) {
 
 // With LBDDC_TIME_SAMPLE, one operator launch and one preconditioner
 // application in kSample record events (kRing is a multiple of kSample).
-constexpr int kSample = 4;
+constexpr int kSample = 8;
 static_assert(Ctx::kRing % kSample == 0, "a ring slot is timed on every use or never");
 
 // Device times of the timed PCG phases, accumulated from the event ring.

@@ -51,20 +51,27 @@ bool build_topology(Ctx* c) {
     skel_node_local(p, s, a, b);
     if (a == 0) c->dirmask[2 * s] = c->dirmask[2 * s + 1] = 1;
   }
-  // global skeleton numbering, row-major over the node lattice
+  // global skeleton numbering (every lattice node on a grid line except the
+  // clamped column x = 0), band by band: grid line y = iy p with its nodes in
+  // increasing x, then the interior nodes of the vertical edges between lines
+  // iy and iy + 1, edge by edge in increasing x and each edge in increasing y.
+  // The nodes of every cell edge are then consecutive, as are the slots the
+  // two cells sharing the edge give them, so the sums over a dof's cells and
+  // the per-cell gathers of interface vectors read contiguous runs.
   const int Gx = c->Gx, Gy = c->Gy;
   std::vector<int> sk((size_t)Gx * Gy, -1);
   int nsk = 0;
   std::vector<int> sk_node;
-  for (int gy = 0; gy < Gy; ++gy)
-    for (int gx = 0; gx < Gx; ++gx) {
-      bool dir = gx == 0;
-      bool inter = (gx % p != 0) && (gy % p != 0);
-      if (!dir && !inter) {
-        sk[(size_t)gy * Gx + gx] = nsk++;
-        sk_node.push_back(gy * Gx + gx);
-      }
-    }
+  auto add = [&](int gx, int gy) {
+    sk[(size_t)gy * Gx + gx] = nsk++;
+    sk_node.push_back(gy * Gx + gx);
+  };
+  for (int iy = 0; iy <= ny; ++iy) {
+    for (int gx = 1; gx < Gx; ++gx) add(gx, p * iy);
+    if (iy < ny)
+      for (int vx = 1; vx <= nx; ++vx)
+        for (int k = 1; k < p; ++k) add(p * vx, p * iy + k);
+  }
   c->NU = 2 * nsk;
   c->RU.assign((size_t)c->ncell * nU, -1);
   for (int cell = 0; cell < c->ncell; ++cell) {

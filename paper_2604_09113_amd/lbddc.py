@@ -212,7 +212,7 @@ class Solver:
 
     def set_timing(self, mask):
         """PCG phases timed by solve (TIME_OP | TIME_PRE | TIME_COARSE, optionally | TIME_SAMPLE for one
-        iteration in four; TIME_ALL after creation)."""
+        iteration in eight; TIME_ALL after creation)."""
         self._check(self.lib.lbddc_set_timing(self.ctx, int(mask)))
 
     def phase_times(self):

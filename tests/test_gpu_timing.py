@@ -1,6 +1,6 @@
 """Phase timing of the PCG loop (lbddc_set_timing): the events it records
 change neither the iterates nor the solution, phases that are not timed
-report zero, sampled timing (one iteration in four, scaled to all) reports
+report zero, sampled timing (one iteration in eight, scaled to all) reports
 the same per-application times to within the spread of the launches, and
 unknown bits are rejected."""
 import numpy as np
