@@ -14,6 +14,7 @@
 // g_s = F_ss^-1 b_eff - M^T g_b: one batched matrix-vector kernel per level
 // and direction.
 #include "internal.h"
+#include "wave_gj.h"
 
 namespace lbddc {
 
@@ -218,94 +219,104 @@ __global__ __launch_bounds__(NT) void k_front_lds(const NDNodeH* __restrict__ no
   if (bad) atomicOr(flags, 32);
 }
 
-// In-register inversion of the kn x kn block at A (row stride nf), identity
-// padded to 64 x 64: thread (tr, tc) = (t / 16, t % 16) holds entries
-// (tr + 16a, tc + 16b); one barrier per pivot (double-buffered pivot row and column).
+// Inversion of the kn x kn diagonal block at A (row stride nf), identity
+// padded to 64 x 64, by a Gauss-Jordan sweep regrouped into four 16-pivot
+// blocks.  The block is held in LDS.  For pivot block K (rows and columns
+// [16 kb, 16 kb + 16)):
+//   D <- D^-1                     (D = M[K][K]; one wave, in registers)
+//   R  = D M[K][j]                (the new pivot rows, j outside K)
+//   M[i][j] <- M[i][j] - M[i][K] R,  M[i][K] <- -M[i][K] D,  M[K][j] <- R
+//                                 (i, j outside K)
+// which is the same elimination as sixteen single-pivot steps.  The 16 x 16
+// tile products run on FP64 MFMA, one tile per wave.  Pivot blocks that lie
+// wholly in the padding are skipped (they would leave it unchanged).
+constexpr int DLD = GJB + 1;  // LDS row stride of the block
+
+// 16 x 16 tile product on MFMA 16x16x4 (FP64): lane l supplies a(m, k) and
+// b(k, n) with m = n = l % 16, k = l / 16 + 4 s, and receives C[l / 16 + 4 v][l % 16]
+// in value v of the result.
+typedef double dbl4c __attribute__((ext_vector_type(4)));
+template <typename FA, typename FB>
+__device__ __forceinline__ dbl4c tile16(FA a, FB b) {
+  const int lane = threadIdx.x & 63, mn = lane & 15, kk = lane >> 4;
+  dbl4c acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a(mn, kk + 4 * s), b(kk + 4 * s, mn), acc, 0, 0, 0);
+  return acc;
+}
+
 __global__ __launch_bounds__(256) void k_lv_diag(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
                                                  double* __restrict__ F, int k0, int* __restrict__ flags) {
-  __shared__ double rowb[2][GJB], colb[2][GJB];
+  __shared__ double M[GJB * DLD];
+  __shared__ double R[16 * DLD];
+  __shared__ int bad;
   const NDNodeH d = nodes[lvl[blockIdx.x]];
   if (k0 >= d.ns) return;
   const int kn = min(GJB, d.ns - k0), nf = d.ns + d.nb;
   double* A = F + d.foff + (long long)k0 * nf + k0;
-  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   // every load in flight before the identity padding is applied
-  double B[4][4];
+  double v[16];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int q = 0; q < 16; ++q) {
+    const int i = (t >> 6) + 4 * q, j = t & 63;
+    v[q] = A[(long long)(i < kn ? i : 0) * nf + (j < kn ? j : 0)];
+  }
+  if (t == 0) bad = 0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = tr + 16 * a, j = tc + 16 * b;
-      B[a][b] = A[(long long)(i < kn ? i : 0) * nf + (j < kn ? j : 0)];
-    }
+  for (int q = 0; q < 16; ++q) {
+    const int i = (t >> 6) + 4 * q, j = t & 63;
+    M[i * DLD + j] = (i < kn && j < kn) ? v[q] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int row = lane >> 4, col = lane & 15;  // result value u sits at (row + 4u, col)
+  for (int kb = 0; 16 * kb < kn; ++kb) {
+    const int K0 = 16 * kb;
+    gj_inverse_wave<double, DLD, 16>(M + K0 * DLD + K0, &bad);  // ends with a barrier
+    // R = D^-1 M[K][jb] for the three column blocks jb != kb (waves 0-2)
+    if (wave < 3) {
+      const int jb = wave + (wave >= kb);
+      const dbl4c r = tile16([&](int m, int k) { return M[(K0 + m) * DLD + K0 + k]; },
+                             [&](int k, int n) { return M[(K0 + k) * DLD + 16 * jb + n]; });
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = tr + 16 * a, j = tc + 16 * b;
-      if (!(i < kn && j < kn)) B[a][b] = i == j ? 1.0 : 0.0;
-    }
-  int buf = 0;
-  bool bad = false;
-  // padding pivots (l >= kn) would leave the identity padding unchanged: skipped
-  for (int l = 0; l < kn; ++l) {
-    const int la = l >> 4, lb = l & 15;
-    if (tr == lb) {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (a == la) {
-#pragma unroll
-          for (int bb = 0; bb < 4; ++bb) rowb[buf][tc + 16 * bb] = B[a][bb];
-        }
-    }
-    if (tc == lb) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (b == la) {
-#pragma unroll
-          for (int a = 0; a < 4; ++a) colb[buf][tr + 16 * a] = B[a][b];
-        }
+      for (int u = 0; u < 4; ++u) R[(row + 4 * u) * DLD + 16 * jb + col] = r[u];
     }
     __syncthreads();
-    double piv = rowb[buf][l];
-    if (!(piv > 0.0)) { bad = true; piv = 1.0; }
-    const double pinv = 1.0 / piv;
-    double cs[4], rr[4];
+    // tiles (ib, jb), ib != kb: updates for jb != kb, the new pivot column for
+    // jb == kb; all reads of the old pivot column precede the writes
+    double nv[3][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) cs[a] = colb[buf][tr + 16 * a] * pinv;
+    for (int s = 0; s < 3; ++s) {
+      const int tt = wave + 4 * s, ib = tt / 4 + (tt / 4 >= kb), jb = tt % 4;
+      const dbl4c p = tile16([&](int m, int k) { return M[(16 * ib + m) * DLD + K0 + k]; },
+                             [&](int k, int n) {
+                               return jb == kb ? M[(K0 + k) * DLD + K0 + n] : R[k * DLD + 16 * jb + n];
+                             });
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rr[b] = rowb[buf][tc + 16 * b];
-    // 1. every element: v - (c_i / p) r_j, with the pivot row left unchanged
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const double ca = tr + 16 * a == l ? 0.0 : cs[a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) B[a][b] -= ca * rr[b];
+      for (int u = 0; u < 4; ++u)
+        nv[s][u] = jb == kb ? -p[u] : M[(16 * ib + row + 4 * u) * DLD + 16 * jb + col] - p[u];
     }
-    // 2. pivot row r_j / p (1 / p on the diagonal) and pivot column -c_i / p,
-    //    held by the threads with tr == l % 16 and tc == l % 16; l / 16 is uniform
-#define GJ_FIX(A_)                                                            \
-  case A_:                                                                    \
-    if (tr == lb) {                                                           \
-      _Pragma("unroll") for (int b = 0; b < 4; ++b) B[A_][b] = rr[b] * pinv;  \
-    }                                                                         \
-    if (tc == lb) {                                                           \
-      _Pragma("unroll") for (int a = 0; a < 4; ++a) B[a][A_] = -cs[a];        \
-    }                                                                         \
-    if (tr == lb && tc == lb) B[A_][A_] = pinv;                               \
-    break;
-    switch (la) { GJ_FIX(0) GJ_FIX(1) GJ_FIX(2) GJ_FIX(3) }
-#undef GJ_FIX
-    buf ^= 1;
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+      const int tt = wave + 4 * s, ib = tt / 4 + (tt / 4 >= kb), jb = tt % 4;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) M[(16 * ib + row + 4 * u) * DLD + 16 * jb + col] = nv[s][u];
+    }
+    // the new pivot rows
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q, r = e >> 6, j = e & 63;
+      if ((j >> 4) != kb) M[(K0 + r) * DLD + j] = R[r * DLD + j];
+    }
+    __syncthreads();
   }
-  if (bad) atomicOr(flags, 32);
+  if (t == 0 && bad) atomicOr(flags, 32);
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = tr + 16 * a, j = tc + 16 * b;
-      if (i < kn && j < kn) A[(long long)i * nf + j] = B[a][b];
-    }
+  for (int q = 0; q < 16; ++q) {
+    const int i = (t >> 6) + 4 * q, j = t & 63;
+    if (i < kn && j < kn) A[(long long)i * nf + j] = M[i * DLD + j];
+  }
 }
 
 // 64 x 64 x kn product on a 16 x 16 thread grid, 4 x 4 outputs per thread:
