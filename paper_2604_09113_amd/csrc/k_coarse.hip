@@ -34,7 +34,10 @@ __global__ void k_coarse_entries(const double* __restrict__ sc, const int* __res
   vals[dest[e]] = s;
 }
 
-// extend-add of the update matrix of child slot `slot` of every node of a level
+// extend-add of the update matrix of child slot `slot` of every node of a level;
+// KC column chunks of 64 per lane cover the level's largest child boundary
+// (KC = 0: boundaries past 1024 columns, a plain strided loop)
+template <int KC>
 __global__ __launch_bounds__(256) void k_extend_add(const NDNodeH* __restrict__ nodes, const int* __restrict__ lvl,
                                                     const int* __restrict__ cmap, double* __restrict__ F, int slot) {
   const NDNodeH d = nodes[lvl[blockIdx.x]];
@@ -48,45 +51,55 @@ __global__ __launch_bounds__(256) void k_extend_add(const NDNodeH* __restrict__ 
   double* P = F + d.foff;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rend = min(nb, r0 + 16);
-  constexpr int KC = 16;  // column chunks of 64 held per lane
-  if (nb > 64 * KC) {
+  if constexpr (KC == 0) {
     for (int i = r0 + wave; i < rend; i += 4) {
       double* prow = P + (long long)map[i] * nf;
       const double* urow = U + (long long)(c.ns + i) * nfc + c.ns;
       for (int j = lane; j < nb; j += 64) prow[map[j]] += urow[j];
     }
     return;
-  }
-  // the map entries of the lane's columns and of the wave's rows first; then,
-  // per row, every load of the row before any add (columns past nb read the
-  // position of column 0 and are not stored)
-  int mj[KC], mi[4];
-#pragma unroll
-  for (int k = 0; k < KC; ++k) {
-    const int j = lane + 64 * k;
-    mj[k] = map[j < nb ? j : 0];
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = r0 + wave + 4 * q;
-    mi[q] = map[i < rend ? i : 0];
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int i = r0 + wave + 4 * q;
-    if (i >= rend) break;
-    double* prow = P + (long long)mi[q] * nf;
-    const double* urow = U + (long long)(c.ns + i) * nfc + c.ns;
-    double u[KC], pv[KC];
+  } else {
+    // the map entries of the lane's columns and of the wave's rows first; then
+    // every load of RB rows before any add (columns past nb and rows past the
+    // block read the position of column or row 0 and are not stored)
+    constexpr int RB = KC <= 4 ? 4 : 1;  // rows in flight together
+    int mj[KC], mi[4];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
       const int j = lane + 64 * k;
-      u[k] = urow[j < nb ? j : 0];
-      pv[k] = prow[mj[k]];
+      mj[k] = map[j < nb ? j : 0];
     }
 #pragma unroll
-    for (int k = 0; k < KC; ++k)
-      if (lane + 64 * k < nb) prow[mj[k]] = pv[k] + u[k];
+    for (int q = 0; q < 4; ++q) {
+      const int i = r0 + wave + 4 * q;
+      mi[q] = map[i < rend ? i : 0];
+    }
+#pragma unroll
+    for (int q0 = 0; q0 < 4; q0 += RB) {
+      double u[RB][KC], pv[RB][KC];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int i = r0 + wave + 4 * (q0 + q), ic = i < rend ? i : r0;
+        const double* prow = P + (long long)mi[q0 + q] * nf;
+        const double* urow = U + (long long)(c.ns + ic) * nfc + c.ns;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          const int j = lane + 64 * k;
+          u[q][k] = urow[j < nb ? j : 0];
+          pv[q][k] = prow[mj[k]];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int i = r0 + wave + 4 * (q0 + q);
+        if (i < rend) {
+          double* prow = P + (long long)mi[q0 + q] * nf;
+#pragma unroll
+          for (int k = 0; k < KC; ++k)
+            if (lane + 64 * k < nb) prow[mj[k]] = pv[q][k] + u[q][k];
+        }
+      }
+    }
   }
 }
 
@@ -555,9 +568,16 @@ hipError_t launch_coarse_factor(Ctx* c) {
       continue;
     }
     if (nbmax > 0)
-      for (int s = 0; s < 2; ++s)
-        hipLaunchKernelGGL(k_extend_add, dim3(nn, (nbmax + 15) / 16), dim3(256), 0, c->stream, c->d_nd_nodes, lvl,
-                           c->d_nd_cmap, c->d_coarse, s);
+      for (int s = 0; s < 2; ++s) {
+        const dim3 g(nn, (nbmax + 15) / 16);
+#define EXA(kc) hipLaunchKernelGGL(k_extend_add<kc>, g, dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_nd_cmap, c->d_coarse, s)
+        if (nbmax <= 128) EXA(2);
+        else if (nbmax <= 256) EXA(4);
+        else if (nbmax <= 512) EXA(8);
+        else if (nbmax <= 1024) EXA(16);
+        else EXA(0);
+#undef EXA
+      }
     const int nt = (nfmax + GJB - 1) / GJB;
     for (int k0 = 0; k0 < nsmax; k0 += GJB) {
       hipLaunchKernelGGL(k_lv_diag, dim3(nn), dim3(256), 0, c->stream, c->d_nd_nodes, lvl, c->d_coarse, k0,
