@@ -667,9 +667,14 @@ lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int3
       break;
     }
     case LBDDC_X_PSI: {
+      // stored [cell][nC][nU]; exported [cell][nU][nC]
       auto h = fetch(c->d_Psi, (size_t)nU * nC, p32 ? 4 : 8);
-      for (size_t i = 0; i < (size_t)count * nU * nC; ++i)
-        out[i] = p32 ? (double)((float*)h.data())[i] : ((double*)h.data())[i];
+      for (size_t k = 0; k < (size_t)count; ++k)
+        for (int i = 0; i < nU; ++i)
+          for (int j = 0; j < nC; ++j) {
+            const size_t src = (k * nC + j) * nU + i;
+            out[(k * nU + i) * nC + j] = p32 ? (double)((float*)h.data())[src] : ((double*)h.data())[src];
+          }
       break;
     }
     case LBDDC_X_SC: {

@@ -226,7 +226,7 @@ struct Ctx {
   double* d_diagK = nullptr;   // [ncell][nU]
   double* d_Ktot = nullptr;    // [NU]
   void* d_P = nullptr;         // [ncell][nE(nE+1)/2] D-scaled fine operator (T)
-  void* d_Psi = nullptr;       // [ncell][nU][nC] D-scaled coarse basis (T)
+  void* d_Psi = nullptr;       // [ncell][nC][nU] D-scaled coarse basis (T), column by column
   double* d_D = nullptr;       // [ncell][nU]
   double* d_ScLoc = nullptr;   // [ncell][nC(nC+1)/2]
   double* d_coarse = nullptr;  // nested-dissection fronts

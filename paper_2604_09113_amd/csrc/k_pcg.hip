@@ -58,64 +58,69 @@ __global__ __launch_bounds__(64) void k_op_local(const double* __restrict__ S, c
   if (l < NU) part[(size_t)cell * NU + l] = sym_row<double, NU>(Ss, xs, l);
 }
 
+// Sum over the 64 lanes of each of the 32 values v[0..31] a lane holds: a
+// butterfly that halves the set of values a lane carries at every step (the
+// lane with bit o set keeps the upper half and sends the lower, its partner
+// the reverse), so 31 + 1 exchanges replace 32 separate reductions.  Value j
+// ends in lanes 2j and 2j + 1 (the lane's bits 5..1 pick the halves).  The
+// values live in a vector type, so that the per-lane choice of half stays a
+// register select (an array here would be indexed through memory).
+template <typename T>
+using vec32 = T __attribute__((ext_vector_type(32)));
+template <typename T>
+__device__ __forceinline__ T wave_sum32(vec32<T> v) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 32, m = 32; o >= 2; o >>= 1, m >>= 1) {
+    const bool up = l & o;
+#pragma unroll
+    for (int k = 0; k < m / 2; ++k) {
+      const T lo = v[k], hi = v[m / 2 + k];
+      v[k] = (up ? hi : lo) + __shfl_xor(up ? lo : hi, o);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 1);
+}
+
 // fine correction and coarse restriction of one cell (T = double or float):
 // partU = [0; P r_E] (P packed over the nE = nU - 8 non-corner slots),
-// partC = Psi^T r  (Psi [nU][nC] row-major); nC columns x NCH row chunks over
-// the lanes, chunk partials summed in fixed order.
+// partC = Psi^T r  (Psi stored column by column, [nC][nU]): lane i multiplies
+// row i of Psi by r_i and the column sums are formed by wave_sum32.
 template <typename T, int NU, int NC>
 __global__ __launch_bounds__(64) void k_pre_local(const T* __restrict__ P, const T* __restrict__ Psi,
                                                   const int* __restrict__ RU, const double* __restrict__ r,
                                                   double* __restrict__ partU, double* __restrict__ partC) {
   static_assert(NU <= 64 && NC <= 32, "lane mapping");
   constexpr int NE = NU - 8, NSP = NE * (NE + 1) / 2, NLP = (NSP + 63) / 64;
-  constexpr int NQ = NU * NC, NLQ = (NQ + 63) / 64;
-  constexpr int NCH = 64 / NC, RCH = (NU + NCH - 1) / NCH;
   __shared__ T Ps[NLP * 64];
-  __shared__ T Qs[NLQ * 64];
   __shared__ T rs[64];
-  __shared__ T cr[NCH][NC];
-  const int cell = blockIdx.x, l = threadIdx.x;
+  const int cell = blockIdx.x, l = threadIdx.x, lc = l < NU ? l : 0;
   const T* Pc = P + (size_t)cell * NSP;
-  const T* Qc = Psi + (size_t)cell * NQ;
-  T vp[NLP], vq[NLQ];
+  const T* Qc = Psi + (size_t)cell * NU * NC;
+  T vp[NLP], vq[NC];
 #pragma unroll
   for (int k = 0; k < NLP; ++k) {
     const int i = l + 64 * k;
     vp[k] = (i < NSP) ? Pc[i] : (T)0;
   }
 #pragma unroll
-  for (int k = 0; k < NLQ; ++k) {
-    const int i = l + 64 * k;
-    vq[k] = (i < NQ) ? Qc[i] : (T)0;
-  }
+  for (int j = 0; j < NC; ++j) vq[j] = Qc[j * NU + lc];
   const int g = l < NU ? RU[(size_t)cell * NU + l] : -1;
-  rs[l] = g >= 0 ? (T)r[g] : (T)0;
+  const T rl = g >= 0 ? (T)r[g] : (T)0;
+  rs[l] = rl;
 #pragma unroll
   for (int k = 0; k < NLP; ++k) Ps[l + 64 * k] = vp[k];
-#pragma unroll
-  for (int k = 0; k < NLQ; ++k) Qs[l + 64 * k] = vq[k];
   __syncthreads();
   if (l < NU) partU[(size_t)cell * NU + l] = l >= 8 ? (double)sym_row<T, NE>(Ps, rs + 8, l - 8) : 0.0;
-  const int ch = l / NC, jc = l - ch * NC;
-  if (ch < NCH) {
-    T s = 0;
-    const int i0 = ch * RCH;
+  vec32<T> v;
 #pragma unroll
-    for (int q = 0; q < RCH; ++q)
-      if (i0 + q < NU) s += Qs[(i0 + q) * NC + jc] * rs[i0 + q];
-    cr[ch][jc] = s;
-  }
-  __syncthreads();
-  if (l < NC) {
-    T s = cr[0][l];
-#pragma unroll
-    for (int q = 1; q < NCH; ++q) s += cr[q][l];
-    partC[(size_t)cell * NC + l] = (double)s;
-  }
+  for (int j = 0; j < 32; ++j) v[j] = j < NC ? vq[j] * rl : (T)0;
+  const T cj = wave_sum32<T>(v);
+  if ((l & 1) == 0 && (l >> 1) < NC) partC[(size_t)cell * NC + (l >> 1)] = (double)cj;
 }
 
 // partU += Psi g_loc (coarse prolongation, D already folded into Psi); lane i
-// reads row i of the cell's Psi block straight from memory
+// forms row i, reading entry i of every column of the cell's Psi block
 template <typename T, int NU, int NC>
 __global__ __launch_bounds__(64) void k_prolong(const T* __restrict__ Psi, const int* __restrict__ RC,
                                                 const double* __restrict__ g, double* __restrict__ partU) {
@@ -123,9 +128,9 @@ __global__ __launch_bounds__(64) void k_prolong(const T* __restrict__ Psi, const
   const int cell = blockIdx.x, l = threadIdx.x;
   T row[NC];
   if (l < NU) {
-    const T* Qr = Psi + ((size_t)cell * NU + l) * NC;
+    const T* Qc = Psi + (size_t)cell * NU * NC + l;
 #pragma unroll
-    for (int j = 0; j < NC; ++j) row[j] = Qr[j];
+    for (int j = 0; j < NC; ++j) row[j] = Qc[j * NU];
   }
   if (l < NC) {
     const int gc = RC[(size_t)cell * NC + l];

@@ -219,9 +219,11 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
                                 Ps[8 + i][j] = cmask ? 0.0 : -(double)v;
                               });
   __syncthreads();
+  // stored column by column, [NC][NU]: the PCG kernels read entry i of every
+  // column in lane i
   T* Pso = Psiout + (size_t)cell * NU * NC;
   for (int idx = tid; idx < NU * NC; idx += 256) {
-    const int i = idx / NC, j = idx % NC;
+    const int j = idx / NU, i = idx % NU;
     Pso[idx] = (T)(Dv[i] * Ps[i][j]);
   }
   for (int j = tid; j < NU; j += 256) Dout[(size_t)cell * NU + j] = Dv[j];
