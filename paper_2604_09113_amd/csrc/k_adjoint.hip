@@ -192,10 +192,15 @@ struct ChainArgs {
   double* gt;     // [ncell] dJ/dt
 };
 
-__global__ void k_chain(ChainArgs g) {
+// one thread per cell, templated on the map order so that the control points
+// and their gradient stay in registers (the loop over the edge nodes runs to a
+// fixed bound with the terms past the end masked)
+template <int M>
+__global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
+  constexpr int NP1 = (M + 1) * (M + 1);
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= g.ncell) return;
-  const int ix = cell % g.nx, iy = cell / g.nx, m = g.m, np1 = (m + 1) * (m + 1);
+  const int ix = cell % g.nx, iy = cell / g.nx;
   // dJ/dt = -H . dItil/dt
   const int fam = g.family[cell];
   const int slot = g.fam_slot[fam];
@@ -230,49 +235,71 @@ __global__ void k_chain(ChainArgs g) {
     g.gt[cell] = -dE;
   }
   // dE/dX through Chat(J) at the interpolation points
-  double X[25][2];
-  for (int b = 0; b <= m; ++b)
-    for (int a = 0; a <= m; ++a) {
-      const double* P = g.ctrl + ((size_t)(m * iy + b) * g.netx + m * ix + a) * 2;
-      X[b * (m + 1) + a][0] = P[0];
-      X[b * (m + 1) + a][1] = P[1];
+  double X[NP1][2];
+#pragma unroll
+  for (int b = 0; b <= M; ++b)
+#pragma unroll
+    for (int a = 0; a <= M; ++a) {
+      const double* P = g.ctrl + ((size_t)(M * iy + b) * g.netx + M * ix + a) * 2;
+      X[b * (M + 1) + a][0] = P[0];
+      X[b * (M + 1) + a][1] = P[1];
     }
-  double gX[25][2];
-  for (int a = 0; a < np1; ++a) gX[a][0] = gX[a][1] = 0.0;
+  double gX[NP1][2];
+#pragma unroll
+  for (int a = 0; a < NP1; ++a) gX[a][0] = gX[a][1] = 0.0;
   const double lam = g.lam, mu = g.mu;
   for (int k3 = 0; k3 < g.nL; ++k3) {
-    const double* dN = g.tab + g.T.off_geo_dN + (size_t)k3 * np1 * 2;
+    const double* dNp = g.tab + g.T.off_geo_dN + (size_t)k3 * NP1 * 2;
+    double dN[NP1 * 2];
+#pragma unroll
+    for (int a = 0; a < 2 * NP1; ++a) dN[a] = dNp[a];
+    double Gs[16];  // G[cell][s][i1 i2] of the point, s = (j1 2 + j2) nL + k3
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Gs[4 * jj + e] = g.G[((size_t)cell * g.ns + jj * g.nL + k3) * 4 + e];
     double J[2][2] = {{0, 0}, {0, 0}};
-    for (int a = 0; a < np1; ++a)
+#pragma unroll
+    for (int a = 0; a < NP1; ++a)
+#pragma unroll
       for (int i = 0; i < 2; ++i) { J[i][0] += X[a][i] * dN[2 * a]; J[i][1] += X[a][i] * dN[2 * a + 1]; }
     const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     const double A[2][2] = {{J[1][1] / det, -J[0][1] / det}, {-J[1][0] / det, J[0][0] / det}};
     // forward-mode derivative of Chat along each unit perturbation E_pq of J
     double dEdJ[2][2];
+#pragma unroll
     for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
       for (int qq = 0; qq < 2; ++qq) {
         double dA[2][2];
+#pragma unroll
         for (int j = 0; j < 2; ++j)
+#pragma unroll
           for (int mm = 0; mm < 2; ++mm) dA[j][mm] = -A[j][pp] * A[qq][mm];
         const double ddet = det * A[qq][pp];
         double acc = 0.0;
+#pragma unroll
         for (int j1 = 0; j1 < 2; ++j1)
+#pragma unroll
           for (int j2 = 0; j2 < 2; ++j2) {
             const double aa = A[j1][0] * A[j2][0] + A[j1][1] * A[j2][1];
             const double daa = dA[j1][0] * A[j2][0] + A[j1][0] * dA[j2][0] + dA[j1][1] * A[j2][1] + A[j1][1] * dA[j2][1];
-            const int s = (j1 * 2 + j2) * g.nL + k3;
+#pragma unroll
             for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
               for (int i2 = 0; i2 < 2; ++i2) {
                 const double v = lam * A[j1][i1] * A[j2][i2] + mu * ((i1 == i2 ? aa : 0.0) + A[j1][i2] * A[j2][i1]);
                 const double dv = lam * (dA[j1][i1] * A[j2][i2] + A[j1][i1] * dA[j2][i2]) +
                                   mu * ((i1 == i2 ? daa : 0.0) + dA[j1][i2] * A[j2][i1] + A[j1][i2] * dA[j2][i1]);
                 const double dC = ddet * v + det * dv;
-                acc += g.G[((size_t)cell * g.ns + s) * 4 + 2 * i1 + i2] * dC;
+                acc += Gs[4 * (j1 * 2 + j2) + 2 * i1 + i2] * dC;
               }
           }
         dEdJ[pp][qq] = acc;
       }
-    for (int a = 0; a < np1; ++a)
+#pragma unroll
+    for (int a = 0; a < NP1; ++a)
+#pragma unroll
       for (int c = 0; c < 2; ++c) gX[a][c] -= dEdJ[c][0] * dN[2 * a] + dEdJ[c][1] * dN[2 * a + 1];
   }
   // traction load on the right edge: 2 u . df/dX for the right column of control points
@@ -285,29 +312,35 @@ __global__ void k_chain(ChainArgs g) {
     const double* u = g.ucell + (size_t)cell * g.ndof;
     // u . t at the right-edge nodes (permuted dofs: skeleton slots after the interior ones)
     double ut[17];
-    for (int n = 0; n <= p; ++n) {
-      const int node = (n == 0) ? 1 : (n == p ? 3 : 4 + (p - 1) + (n - 1));
+#pragma unroll
+    for (int n = 0; n < 17; ++n) {
+      const int nn = n <= p ? n : 0;
+      const int node = (nn == 0) ? 1 : (nn == p ? 3 : 4 + (p - 1) + (nn - 1));
       ut[n] = u[g.nI + 2 * node] * t0 + u[g.nI + 2 * node + 1] * t1;
     }
     for (int qd = 0; qd < nq; ++qd) {
       double d0 = 0, d1 = 0;
-      for (int k = 0; k <= m; ++k) {
-        const double* P = &X[k * (m + 1) + m][0];
-        d0 += dB[k * nq + qd] * P[0];
-        d1 += dB[k * nq + qd] * P[1];
+#pragma unroll
+      for (int k = 0; k <= M; ++k) {
+        d0 += dB[k * nq + qd] * X[k * (M + 1) + M][0];
+        d1 += dB[k * nq + qd] * X[k * (M + 1) + M][1];
       }
       const double ds = sqrt(d0 * d0 + d1 * d1);
       double ub = 0.0;
-      for (int n = 0; n <= p; ++n) ub += ut[n] * bl[n * nq + qd];
+#pragma unroll
+      for (int n = 0; n < 17; ++n)
+        if (n <= p) ub += ut[n] * bl[n * nq + qd];
       const double f = 2.0 * w[qd] * ub / ds;
-      for (int k = 0; k <= m; ++k) {
-        gX[k * (m + 1) + m][0] += f * d0 * dB[k * nq + qd];
-        gX[k * (m + 1) + m][1] += f * d1 * dB[k * nq + qd];
+#pragma unroll
+      for (int k = 0; k <= M; ++k) {
+        gX[k * (M + 1) + M][0] += f * d0 * dB[k * nq + qd];
+        gX[k * (M + 1) + M][1] += f * d1 * dB[k * nq + qd];
       }
     }
   }
-  double* out = g.gcell + (size_t)cell * np1 * 2;
-  for (int a = 0; a < np1; ++a) { out[2 * a] = gX[a][0]; out[2 * a + 1] = gX[a][1]; }
+  double* out = g.gcell + (size_t)cell * NP1 * 2;
+#pragma unroll
+  for (int a = 0; a < NP1; ++a) { out[2 * a] = gX[a][0]; out[2 * a + 1] = gX[a][1]; }
 }
 
 // net gradient: sum over the cells sharing each control point (fixed order)
@@ -432,7 +465,12 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   a.H = c->d_H; a.G = c->d_G; a.ucell = c->d_ucell + (size_t)rhs * c->ncell * c->ndof;
   a.trac = c->d_trac + (size_t)rhs * c->ny * 2;
   a.gcell = c->d_gcell; a.gt = c->d_gt + (size_t)rhs * c->ncell;
-  hipLaunchKernelGGL(k_chain, dim3((c->ncell + 127) / 128), dim3(128), 0, c->stream, a);
+  switch (c->m) {
+#define CHN(mm) case mm: hipLaunchKernelGGL(k_chain<mm>, dim3((c->ncell + 63) / 64), dim3(64), 0, c->stream, a); break;
+    CHN(1) CHN(2) CHN(3) CHN(4)
+#undef CHN
+    default: return hipErrorInvalidValue;
+  }
   const int nnet = c->netx * c->nety;
   hipLaunchKernelGGL(k_net_gather, dim3((nnet + 255) / 256), dim3(256), 0, c->stream, c->d_gcell, c->d_net_ptr,
                      c->d_net_own, c->d_gX + (size_t)rhs * nnet * 2, nnet);

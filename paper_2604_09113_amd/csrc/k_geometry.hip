@@ -1,6 +1,7 @@
 // Per-cell geometry kernels.
 //
-// k_geometry (A1 + A2), one thread per cell:
+// k_geometry (A1 + A2), one thread per (cell, interpolation point), templated
+// on the map order:
 //  * Jacobian of the Bernstein cell map at the (q+1)^2 interpolation points and
 //    the pulled-back tensor Chat_{i1 j1 i2 j2} = det J A_{j1 m} C_{i1 m i2 n} A_{j2 n},
 //    A = J^-1 (Sec. 2.2.1, pull-back of the elasticity tensor; Sec. 4.1, its
@@ -29,57 +30,75 @@ struct GeoArgs {
   double* theta; float* theta32; double* itil; float* itil32; int* group; int* flags;
 };
 
-__global__ void k_geometry(GeoArgs g) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+template <int M>
+__global__ __launch_bounds__(256) void k_geometry(GeoArgs g) {
+  constexpr int NP1 = (M + 1) * (M + 1);
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cell = tid / g.nL, k3 = tid - cell * g.nL;
   if (cell >= g.ncell) return;
-  const int ix = cell % g.nx, iy = cell / g.nx, m = g.m, np1 = (m + 1) * (m + 1);
-  double X[25][2];
-  for (int b = 0; b <= m; ++b)
-    for (int a = 0; a <= m; ++a) {
-      const double* P = g.ctrl + ((size_t)(m * iy + b) * g.netx + m * ix + a) * 2;
-      X[b * (m + 1) + a][0] = P[0];
-      X[b * (m + 1) + a][1] = P[1];
+  const int ix = cell % g.nx, iy = cell / g.nx;
+  // the cell's control points, every load issued together
+  double X[NP1][2];
+#pragma unroll
+  for (int b = 0; b <= M; ++b)
+#pragma unroll
+    for (int a = 0; a <= M; ++a) {
+      const double* P = g.ctrl + ((size_t)(M * iy + b) * g.netx + M * ix + a) * 2;
+      X[b * (M + 1) + a][0] = P[0];
+      X[b * (M + 1) + a][1] = P[1];
     }
+  auto jac = [&](const double* dN, double (&J)[2][2]) {
+    double d[NP1][2];
+#pragma unroll
+    for (int a = 0; a < NP1; ++a) {
+      d[a][0] = dN[2 * a];
+      d[a][1] = dN[2 * a + 1];
+    }
+    J[0][0] = J[0][1] = J[1][0] = J[1][1] = 0.0;
+#pragma unroll
+    for (int a = 0; a < NP1; ++a)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        J[i][0] += X[a][i] * d[a][0];
+        J[i][1] += X[a][i] * d[a][1];
+      }
+  };
   bool bad = false;
-  // det J on the check sample
-  for (int k = 0; k < g.T.nchk; ++k) {
-    const double* dN = g.tab + g.T.off_chk_dN + (size_t)k * np1 * 2;
-    double J00 = 0, J01 = 0, J10 = 0, J11 = 0;
-    for (int a = 0; a < np1; ++a) {
-      J00 += X[a][0] * dN[2 * a]; J01 += X[a][0] * dN[2 * a + 1];
-      J10 += X[a][1] * dN[2 * a]; J11 += X[a][1] * dN[2 * a + 1];
-    }
-    if (!(J00 * J11 - J01 * J10 > 0.0)) bad = true;
+  // det J on the check sample, its points shared among the cell's threads
+  for (int k = k3; k < g.T.nchk; k += g.nL) {
+    double J[2][2];
+    jac(g.tab + g.T.off_chk_dN + (size_t)k * NP1 * 2, J);
+    if (!(J[0][0] * J[1][1] - J[0][1] * J[1][0] > 0.0)) bad = true;
   }
   const double lam = g.lam, mu = g.mu;
-  for (int k3 = 0; k3 < g.nL; ++k3) {
-    const double* dN = g.tab + g.T.off_geo_dN + (size_t)k3 * np1 * 2;
-    double J[2][2] = {{0, 0}, {0, 0}};
-    for (int a = 0; a < np1; ++a)
-      for (int i = 0; i < 2; ++i) {
-        J[i][0] += X[a][i] * dN[2 * a];
-        J[i][1] += X[a][i] * dN[2 * a + 1];
-      }
-    double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  {
+    double J[2][2];
+    jac(g.tab + g.T.off_geo_dN + (size_t)k3 * NP1 * 2, J);
+    const double det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
     if (!(det > 0.0)) bad = true;
-    double A[2][2] = {{J[1][1] / det, -J[0][1] / det}, {-J[1][0] / det, J[0][0] / det}};
+    const double A[2][2] = {{J[1][1] / det, -J[0][1] / det}, {-J[1][0] / det, J[0][0] / det}};
+#pragma unroll
     for (int j1 = 0; j1 < 2; ++j1)
+#pragma unroll
       for (int j2 = 0; j2 < 2; ++j2) {
-        double aa = A[j1][0] * A[j2][0] + A[j1][1] * A[j2][1];
-        int s = (j1 * 2 + j2) * g.nL + k3;
+        const double aa = A[j1][0] * A[j2][0] + A[j1][1] * A[j2][1];
+        const int s = (j1 * 2 + j2) * g.nL + k3;
+#pragma unroll
         for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
           for (int i2 = 0; i2 < 2; ++i2) {
             // isotropic C_{i1 m i2 n} = lam d_{i1 m} d_{i2 n} + mu (d_{i1 i2} d_{mn} + d_{i1 n} d_{m i2})
             double v = lam * A[j1][i1] * A[j2][i2] + mu * ((i1 == i2 ? aa : 0.0) + A[j1][i2] * A[j2][i1]);
             v *= det;
-            size_t o = ((size_t)cell * g.ns + s) * 4 + 2 * i1 + i2;
+            const size_t o = ((size_t)cell * g.ns + s) * 4 + 2 * i1 + i2;
             g.theta[o] = v;
             g.theta32[o] = (float)v;
           }
       }
   }
   if (bad) atomicOr(g.flags, 1);
-  // MDEIM online evaluation
+  if (k3 != 0) return;
+  // MDEIM online evaluation, by the cell's first thread
   const int fam = g.family[cell];
   const int slot = (fam >= 0 && fam < 64) ? g.fam_slot[fam] : -1;
   double* it = g.itil + (size_t)cell * g.itil_stride;
@@ -96,17 +115,25 @@ __global__ void k_geometry(GeoArgs g) {
   const double a = lo + k * w, b = lo + (k + 1) * w;
   const double tau = (t - a) / (b - a);
   const double* nodes = g.tab + g.T.off_rnodes[slot];
-  double ell[17];
-  for (int j = 0; j <= R; ++j) {
+  // Lagrange basis at tau (degree R <= 16): fixed-size loops with the terms
+  // past R masked, so the values stay in registers
+  double nd[17], ell[17];
+#pragma unroll
+  for (int j = 0; j < 17; ++j) nd[j] = nodes[j <= R ? j : 0];
+#pragma unroll
+  for (int j = 0; j < 17; ++j) {
     double v = 1.0;
-    for (int l = 0; l <= R; ++l)
-      if (l != j) v *= (tau - nodes[l]) / (nodes[j] - nodes[l]);
+#pragma unroll
+    for (int l = 0; l < 17; ++l)
+      if (l != j && l <= R) v *= (tau - nd[l]) / (nd[j] - nd[l]);
     ell[j] = v;
   }
   const double* cf = g.coeff[slot] + (size_t)k * (R + 1) * nr;
   for (int r = 0; r < nr; ++r) {
     double s = 0.0;
-    for (int j = 0; j <= R; ++j) s += ell[j] * cf[j * nr + r];
+#pragma unroll
+    for (int j = 0; j < 17; ++j)
+      if (j <= R) s += ell[j] * cf[j * nr + r];
     s *= (1.0 - g.rho);
     it[r] = s;
     it32[r] = (float)s;
@@ -231,7 +258,13 @@ hipError_t launch_geometry(Ctx* c) {
   g.rho = c->rho; g.T = c->tab;
   g.theta = c->d_theta; g.theta32 = c->d_theta32; g.itil = c->d_itil; g.itil32 = c->d_itil32;
   g.group = c->d_cluster; g.flags = c->d_flags;
-  hipLaunchKernelGGL(k_geometry, dim3((c->ncell + 127) / 128), dim3(128), 0, c->stream, g);
+  const int nth = c->ncell * c->nL;  // one thread per (cell, interpolation point)
+  switch (c->m) {
+#define GEO(mm) case mm: hipLaunchKernelGGL(k_geometry<mm>, dim3((nth + 255) / 256), dim3(256), 0, c->stream, g); break;
+    GEO(1) GEO(2) GEO(3) GEO(4)
+#undef GEO
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
