@@ -221,8 +221,8 @@ struct Ctx {
 
   // setup
   double* d_S = nullptr;       // [ncell][nU(nU+1)/2]
-  double* d_L = nullptr;       // [ncell][nI(nI+1)/2] column-major packed
-  double* d_Y = nullptr;       // [ncell][nI][nU]
+  double* d_L = nullptr;       // [ncell][nI(nI+1)/2] L_II packed row by row
+  double* d_Y = nullptr;       // [ncell][nU][nI] Y = L_II^-1 K_IU, column by column
   double* d_diagK = nullptr;   // [ncell][nU]
   double* d_Ktot = nullptr;    // [NU]
   void* d_P = nullptr;         // [ncell][nE(nE+1)/2] D-scaled fine operator (T)

@@ -324,13 +324,16 @@ __global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b
 }
 
 // ---- interior recovery: u_I = -L^-T (Y u_U) (tractions act on skeleton dofs only)
-// u_I = -L_II^-T (Y u_U) for one cell per 64-lane wave (Y = L_II^-1 K_IU).
-// The cell's packed L_II is staged in LDS with all of its loads in flight
-// together; s = -Y u_U is formed with lane k taking rows k and k + 64; the
-// back substitution L_II^T u_I = s then runs right-looking: at step k the
-// owner of entry k holds its final value, which is divided by L_kk, read by
-// every lane with readlane, and subtracted, times L_kj, from the entries
-// j < k.  No barrier and no global load inside the substitution.
+// u_I = -L_II^-T (Y u_U) for one cell per 64-lane wave (Y = L_II^-1 K_IU,
+// stored column by column, [nU][nI]; L_II packed row by row, row k holding
+// L[k][0..k]).  Lane l takes interior rows k0 = l and k1 = l + 64: s = -Y u_U
+// with the entries of u_U broadcast by readlane and the columns of Y read
+// coalesced across the lanes; then the back substitution L_II^T u_I = s runs
+// right-looking: at step k the owner of entry k holds its final value, which
+// is divided by L_kk, read by every lane with readlane, and subtracted, times
+// L_kj, from the entries j < k.  Step k reads row k of L_II, a contiguous
+// run that the lanes load coalesced, sixteen steps ahead of its use.  No LDS
+// and no barrier.
 __device__ __forceinline__ double lane_value(double v, int src) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
@@ -342,62 +345,69 @@ __global__ __launch_bounds__(64) void k_recover(const double* __restrict__ L, co
                                                 int Gx, double* __restrict__ u, double* __restrict__ ucell) {
   constexpr int NI = 2 * (P - 1) * (P - 1), NU = 8 * P, NDOF = 2 * (P + 1) * (P + 1);
   constexpr int NLP = NI * (NI + 1) / 2;
+  constexpr int KB = 16;  // substitution steps per batch of L entries
   static_assert(NU <= 64 && NI <= 128, "two interior entries per lane");
-  __shared__ double Ls[NLP];
-  __shared__ double uu[64];
   const int cell = blockIdx.x, l = threadIdx.x;
   const int g = l < NU ? RU[(size_t)cell * NU + l] : -1;
-  // L_II into LDS, sixteen loads per lane in flight at a time
-  const double* Lc = L + (size_t)cell * NLP;
-  for (int base = 0; base < NLP; base += 64 * 16) {
-    double t[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = base + l + 64 * k;
-      t[k] = Lc[i < NLP ? i : 0];
-    }
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int i = base + l + 64 * k;
-      if (i < NLP) Ls[i] = t[k];
-    }
-  }
   const double xv = x[g >= 0 ? g : 0];
-  uu[l] = g >= 0 ? xv : 0.0;
-  __syncthreads();
-  // s = -Y u_U: rows k0 = l and k1 = l + 64 (rows past NI read row 0)
+  const double ul = g >= 0 ? xv : 0.0;  // u_U entry l
   const int k0 = l, k1 = l + 64;
-  const double* y0 = Y + ((size_t)cell * NI + (k0 < NI ? k0 : 0)) * NU;
-  const double* y1 = Y + ((size_t)cell * NI + (k1 < NI ? k1 : 0)) * NU;
+  const bool h0 = k0 < NI, h1 = k1 < NI;
+  const int k0c = h0 ? k0 : 0, k1c = h1 ? k1 : 0;
+  // s = -Y u_U (columns past nU and rows past nI read entry 0 and are not used)
+  const double* Yc = Y + (size_t)cell * NU * NI;
   double a0 = 0.0, a1 = 0.0;
+#pragma unroll
   for (int j0 = 0; j0 < NU; j0 += 16) {
     double v0[16], v1[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int jj = j0 + j < NU ? j0 + j : 0;
-      v0[j] = y0[jj];
-      v1[j] = y1[jj];
+      v0[j] = Yc[(size_t)jj * NI + k0c];
+      v1[j] = Yc[(size_t)jj * NI + k1c];
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j)
       if (j0 + j < NU) {
-        a0 += v0[j] * uu[j0 + j];
-        a1 += v1[j] * uu[j0 + j];
+        const double uj = lane_value(ul, j0 + j);
+        a0 += v0[j] * uj;
+        a1 += v1[j] * uj;
       }
   }
   double s0 = -a0, s1 = -a1;
-  // L_kj = column j of the packed L_II at offset k - j
-  const int c0 = k0 * NI - k0 * (k0 - 1) / 2, c1 = k1 * NI - k1 * (k1 - 1) / 2;
-  for (int k = NI - 1; k >= 0; --k) {
-    const int ck = k * NI - k * (k - 1) / 2;
-    const double sk = (k < 64 ? lane_value(s0, k) : lane_value(s1, k - 64)) / Ls[ck];
-    if (k < 64) {
-      if (l == k) s0 = sk;
-    } else {
-      if (l == k - 64) s1 = sk;
+  // L_kj = L[k (k + 1) / 2 + j]; a lane whose row is not below step k reads
+  // the diagonal L_kk instead, so the owner of entry k holds L_kk
+  const double* Lc = L + (size_t)cell * NLP;
+  auto fetch = [&](int kb, double (&e0)[KB], double (&e1)[KB]) {
+#pragma unroll
+    for (int m = 0; m < KB; ++m) {
+      const int k = kb - m > 0 ? kb - m : 0, rk = k * (k + 1) / 2;
+      e0[m] = Lc[rk + (k0 < k ? k0 : k)];
+      e1[m] = Lc[rk + (k1 < k ? k1 : k)];
     }
-    if (k0 < k) s0 -= Ls[c0 + k - k0] * sk;
-    if (k1 < k) s1 -= Ls[c1 + k - k1] * sk;
+  };
+  double e0[KB], e1[KB], n0[KB], n1[KB];
+  fetch(NI - 1, e0, e1);
+  for (int kb = NI - 1; kb >= 0; kb -= KB) {
+    fetch(kb - KB, n0, n1);  // past step 0 every entry is clamped to the diagonal
+#pragma unroll
+    for (int m = 0; m < KB; ++m) {
+      const int k = kb - m;
+      if (k < 0) break;
+      const double sk = k < 64 ? lane_value(s0, k) / lane_value(e0[m], k) : lane_value(s1, k - 64) / lane_value(e1[m], k - 64);
+      if (k < 64) {
+        if (l == k) s0 = sk;
+      } else {
+        if (l == k - 64) s1 = sk;
+      }
+      if (k0 < k) s0 -= e0[m] * sk;
+      if (k1 < k) s1 -= e1[m] * sk;
+    }
+#pragma unroll
+    for (int m = 0; m < KB; ++m) {
+      e0[m] = n0[m];
+      e1[m] = n1[m];
+    }
   }
   const int ix = cell % nx, iy = cell / nx;
 #pragma unroll
@@ -410,7 +420,7 @@ __global__ __launch_bounds__(64) void k_recover(const double* __restrict__ L, co
     u[((size_t)(P * iy + b) * Gx + P * ix + a) * 2 + comp] = v;
     if (ucell) ucell[(size_t)cell * NDOF + k] = v;
   }
-  if (ucell && l < NU) ucell[(size_t)cell * NDOF + NI + l] = uu[l];
+  if (ucell && l < NU) ucell[(size_t)cell * NDOF + NI + l] = ul;
 }
 
 __global__ void k_scatter_skel(const double* __restrict__ x, const int* __restrict__ node, int NU,

@@ -13,8 +13,9 @@
 // register indices of the still-active blocks are compile-time constants.
 //
 // Outputs per cell: S packed lower row-major [nU(nU+1)/2], L_II packed
-// column-major [nI(nI+1)/2] (column k holds rows k..nI-1), Y = L_II^-1 K_IU
-// stored row-major [nI][nU], and the skeleton diagonal of K (for the weights).
+// row by row [nI(nI+1)/2] (row k holds columns 0..k), Y = L_II^-1 K_IU stored
+// column by column [nU][nI] (the layouts the recovery reads coalesced), and
+// the skeleton diagonal of K (for the weights).
 // Skeleton slots on the clamped side of first-column cells are replaced by
 // identity rows/columns (their Dirichlet values are zero).
 #include "internal.h"
@@ -99,8 +100,8 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
       __syncthreads();
       const double rinv = pv[buf][1];
       if (tid >= k && tid < NDOF) {
-        if (tid < NI) Lc[k * NI - k * (k - 1) / 2 + (tid - k)] = tid == k ? sqrt(pv[buf][0]) : colbuf[buf][tid] * rinv;
-        else Yc[(size_t)k * NU + (tid - NI)] = colbuf[buf][tid] * rinv;
+        if (tid < NI) Lc[tid * (tid + 1) / 2 + k] = tid == k ? sqrt(pv[buf][0]) : colbuf[buf][tid] * rinv;
+        else Yc[(size_t)(tid - NI) * NI + k] = colbuf[buf][tid] * rinv;
       }
       double lr[NA], lcv[NA];
 #pragma unroll
