@@ -165,10 +165,12 @@ __device__ inline void edge_points(const double* ctrl, int netx, int m, int ix, 
   }
 }
 
+// one thread per (cell, edge, edge node): the rows of one node of one edge
 __global__ void k_constraints(ConsArgs g) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.ncell * 4) return;
-  const int cell = id >> 2, e = id & 3, ix = cell % g.nx, iy = cell / g.nx, m = g.m, p = g.p;
+  const int p = g.p, id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.ncell * 4 * (p + 1)) return;
+  const int n = id % (p + 1), ce = id / (p + 1), cell = ce >> 2, e = ce & 3;
+  const int ix = cell % g.nx, iy = cell / g.nx, m = g.m;
   double P[5][2];
   edge_points(g.ctrl, g.netx, m, ix, iy, e, P);
   const int nq = g.T.nq_edge;
@@ -180,27 +182,25 @@ __global__ void k_constraints(ConsArgs g) {
   double xb0 = 0, xb1 = 0;
   for (int k = 0; k <= m; ++k) { xb0 += Bm[k] * P[k][0]; xb1 += Bm[k] * P[k][1]; }
   double* out = g.cons + ((size_t)cell * 4 + e) * g.nce * (p + 1) * 2;
-  for (int n = 0; n <= p; ++n) {
-    double avg = 0, m0 = 0, m1 = 0;
-    for (int qd = 0; qd < nq; ++qd) {
-      double x0 = 0, x1 = 0, d0 = 0, d1 = 0;
-      for (int k = 0; k <= m; ++k) {
-        x0 += B[k * nq + qd] * P[k][0]; x1 += B[k * nq + qd] * P[k][1];
-        d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1];
-      }
-      double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
-      avg += ws;
-      m0 += ws * (x1 - xb1);
-      m1 += ws * (xb0 - x0);
+  double avg = 0, m0 = 0, m1 = 0;
+  for (int qd = 0; qd < nq; ++qd) {
+    double x0 = 0, x1 = 0, d0 = 0, d1 = 0;
+    for (int k = 0; k <= m; ++k) {
+      x0 += B[k * nq + qd] * P[k][0]; x1 += B[k * nq + qd] * P[k][1];
+      d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1];
     }
-    out[(0 * (p + 1) + n) * 2 + 0] = avg;
-    out[(0 * (p + 1) + n) * 2 + 1] = 0.0;
-    out[(1 * (p + 1) + n) * 2 + 0] = 0.0;
-    out[(1 * (p + 1) + n) * 2 + 1] = avg;
-    if (g.nce > 2) {
-      out[(2 * (p + 1) + n) * 2 + 0] = m0;
-      out[(2 * (p + 1) + n) * 2 + 1] = m1;
-    }
+    double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
+    avg += ws;
+    m0 += ws * (x1 - xb1);
+    m1 += ws * (xb0 - x0);
+  }
+  out[(0 * (p + 1) + n) * 2 + 0] = avg;
+  out[(0 * (p + 1) + n) * 2 + 1] = 0.0;
+  out[(1 * (p + 1) + n) * 2 + 0] = 0.0;
+  out[(1 * (p + 1) + n) * 2 + 1] = avg;
+  if (g.nce > 2) {
+    out[(2 * (p + 1) + n) * 2 + 0] = m0;
+    out[(2 * (p + 1) + n) * 2 + 1] = m1;
   }
 }
 
@@ -211,32 +211,37 @@ struct LoadArgs {
   double* load;  // [nrhs][ncell][nU]
 };
 
-__global__ void k_loads(LoadArgs g) {
-  const int id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.ncell * g.nrhs) return;
-  const int cell = id % g.ncell, rhs = id / g.ncell, ix = cell % g.nx, iy = cell / g.nx, p = g.p;
+// one 64-lane workgroup per (cell, load case), lane l writing slot l (nU <= 64,
+// coalesced): zero, or on the loaded edge the load of its node and component.
+// Right-edge node n sits in slot node 1 (n = 0), 3 (n = p) or 4 + (p - 1) + (n - 1).
+__global__ __launch_bounds__(64) void k_loads(LoadArgs g) {
+  const int cell = blockIdx.x, rhs = blockIdx.y, l = threadIdx.x, p = g.p;
+  const int ix = cell % g.nx, iy = cell / g.nx;
+  if (l >= g.nU) return;
   double* out = g.load + ((size_t)rhs * g.ncell + cell) * g.nU;
-  for (int s = 0; s < g.nU; ++s) out[s] = 0.0;
-  if (ix != g.nx - 1) return;
+  const int node = l >> 1, comp = l & 1;
+  int n = -1;
+  if (node == 1) n = 0;
+  else if (node == 3) n = p;
+  else if (node >= 4 + (p - 1) && node < 4 + 2 * (p - 1)) n = node - (4 + (p - 1)) + 1;
+  if (ix != g.nx - 1 || n < 0) {
+    out[l] = 0.0;
+    return;
+  }
   double P[5][2];
   edge_points(g.ctrl, g.netx, g.m, ix, iy, 1, P);
   const int nq = g.T.nq_load;
   const double* w = g.tab + g.T.off_load_w;
   const double* bl = g.tab + g.T.off_load_b;
   const double* dB = g.tab + g.T.off_load_dB;
-  const double t0 = g.trac[((size_t)rhs * g.ny + iy) * 2], t1 = g.trac[((size_t)rhs * g.ny + iy) * 2 + 1];
-  for (int n = 0; n <= p; ++n) {
-    double f = 0;
-    for (int qd = 0; qd < nq; ++qd) {
-      double d0 = 0, d1 = 0;
-      for (int k = 0; k <= g.m; ++k) { d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1]; }
-      f += w[qd] * bl[n * nq + qd] * sqrt(d0 * d0 + d1 * d1);
-    }
-    // right edge node n: corner BR (n = 0), corner TR (n = p), else edge node
-    int node = (n == 0) ? 1 : (n == p ? 3 : 4 + (p - 1) + (n - 1));
-    out[2 * node] = f * t0;
-    out[2 * node + 1] = f * t1;
+  const double tc = g.trac[((size_t)rhs * g.ny + iy) * 2 + comp];
+  double f = 0;
+  for (int qd = 0; qd < nq; ++qd) {
+    double d0 = 0, d1 = 0;
+    for (int k = 0; k <= g.m; ++k) { d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1]; }
+    f += w[qd] * bl[n * nq + qd] * sqrt(d0 * d0 + d1 * d1);
   }
+  out[l] = f * tc;
 }
 
 hipError_t launch_geometry(Ctx* c) {
@@ -270,9 +275,11 @@ hipError_t launch_geometry(Ctx* c) {
 
 hipError_t launch_constraints_loads(Ctx* c) {
   ConsArgs a = {c->d_ctrl, c->d_tab, c->tab, c->ncell, c->nx, c->netx, c->m, c->p, c->nce, c->d_cons};
-  hipLaunchKernelGGL(k_constraints, dim3((c->ncell * 4 + 127) / 128), dim3(128), 0, c->stream, a);
+  const int nth = c->ncell * 4 * (c->p + 1);
+  hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, c->stream, a);
   LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs, c->d_load};
-  hipLaunchKernelGGL(k_loads, dim3((c->ncell * c->nrhs + 127) / 128), dim3(128), 0, c->stream, l);
+  if (c->nU > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_loads, dim3(c->ncell, c->nrhs), dim3(64), 0, c->stream, l);
   return hipGetLastError();
 }
 
