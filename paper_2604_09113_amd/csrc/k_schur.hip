@@ -22,6 +22,18 @@
 
 namespace lbddc {
 
+// 1 / sqrt(p) for p > 0: the hardware estimate refined by two Newton steps,
+// y <- y (3/2 - p y^2 / 2), three dependent operations each: a shorter chain
+// than the correctly rounded square root and division it replaces on the
+// pivot step's critical path (every thread waits for this value).
+__device__ __forceinline__ double rsqrt_refined(double p) {
+  double y = __builtin_amdgcn_rsq(p);
+  const double h = 0.5 * p;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) y = fma(y, fma(-h * y, y, 0.5), y);
+  return y;
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, const int* __restrict__ dirmask, int nx,
                                                double* __restrict__ S, double* __restrict__ L,
@@ -94,7 +106,7 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
           double p0 = A[ph][ph];
           if (!(p0 > 0.0)) { bad = true; p0 = 1.0; }
           pv[buf][0] = p0;
-          pv[buf][1] = 1.0 / sqrt(p0);
+          pv[buf][1] = rsqrt_refined(p0);
         }
       }
       __syncthreads();
