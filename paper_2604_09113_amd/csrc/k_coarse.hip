@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NT) void k_front_lds(const NDNodeH* __restrict__ no
     __syncthreads();
     double piv = rowl[l];
     if (!(piv > 0.0)) { bad = true; piv = 1.0; }
-    const double pinv = 1.0 / piv;
+    const double pinv = recip_refined(piv);
     // loads are unconditional (columns past nf read column 0 and are not
     // stored), so the loads of a row pair are all in flight before the updates
     double rv[NJ];  // this lane's columns of the pivot row

@@ -1,11 +1,25 @@
-// Single-wave helpers shared by the preconditioner setup and the coarse
-// factorisation: a broadcast of one lane's value and an in-register
-// Gauss-Jordan inverse of a small SPD block by one wave.
+// Helpers shared by the preconditioner setup and the coarse factorisation: a
+// refined reciprocal for pivots, a broadcast of one lane's value, and an
+// in-register Gauss-Jordan inverse of a small SPD block by one wave.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace lbddc {
+
+// 1 / p for a pivot p: the hardware reciprocal estimate refined by Newton
+// steps y <- y + y (1 - p y) (two in FP64, one in FP32), a shorter dependent
+// chain than the correctly rounded division on a pivot step's critical path.
+__device__ __forceinline__ double recip_refined(double p) {
+  double y = __builtin_amdgcn_rcp(p);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) y = fma(y, fma(-p, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ float recip_refined(float p) {
+  const float y = __builtin_amdgcn_rcpf(p);
+  return fmaf(y, fmaf(-p, y, 1.0f), y);
+}
 
 // Value of v held by lane `src` (wave-uniform), through scalar reads.
 __device__ __forceinline__ float lane_bcast(float v, int src) {
@@ -44,7 +58,7 @@ __device__ __forceinline__ void gj_inverse_wave(T* A, int* bad) {
         if (j == 0) *bad = 1;
         piv = (T)1;
       }
-      const T pinv = (T)1 / piv;
+      const T pinv = recip_refined(piv);
       const bool jl = j == l;
 #pragma unroll
       for (int i = 1; i < N; ++i) {
