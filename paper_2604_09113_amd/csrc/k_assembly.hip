@@ -141,38 +141,69 @@ __global__ __launch_bounds__(256) void k_assemble(const T* const* __restrict__ u
   }
 }
 
-// Stable counting sort of the cells by group (one workgroup): deterministic.
-__global__ __launch_bounds__(256) void k_group_sort(const int* __restrict__ group, int ncell, int G,
-                                                    int* __restrict__ sorted, int* __restrict__ counts) {
-  __shared__ int cnt[256][16];
-  const int t = threadIdx.x;
-  const int chunk = (ncell + 255) / 256;
-  const int b0 = t * chunk, b1 = min(ncell, b0 + chunk);
-  for (int g = 0; g < 16; ++g) cnt[t][g] = 0;
+// Stable counting sort of the cells by group (one workgroup of 1024 threads,
+// G <= 16 groups): thread t takes cells [t c, t c + c), counts them per group
+// in registers, and the per-group exclusive prefix over the threads (a wave
+// scan by shuffles, then the wave totals) gives each thread its write
+// positions; within a thread the cells keep their order.  Deterministic.
+constexpr int kSortT = 1024;
+__global__ __launch_bounds__(kSortT) void k_group_sort(const int* __restrict__ group, int ncell, int G,
+                                                       int* __restrict__ sorted, int* __restrict__ counts) {
+  __shared__ int wtot[16][kSortT / 64];  // per group, per wave: the wave's count
+  __shared__ int gbase[17];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int chunk = (ncell + kSortT - 1) / kSortT;
+  const int b0 = min(ncell, t * chunk), b1 = min(ncell, b0 + chunk);
+  int cnt[16];
+#pragma unroll
+  for (int g = 0; g < 16; ++g) cnt[g] = 0;
   for (int i = b0; i < b1; ++i) {
     int g = group[i];
     g = g < 0 ? 0 : (g >= G ? G - 1 : g);
-    cnt[t][g]++;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cnt[q] += g == q;
+  }
+  // inclusive wave scan of each group's counts, then the exclusive offset
+  int off[16];
+#pragma unroll
+  for (int g = 0; g < 16; ++g) {
+    int v = cnt[g];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    off[g] = v - cnt[g];
+    if (lane == 63) wtot[g][wave] = v;
+  }
+  __syncthreads();
+  if (t < 16) {  // thread g: prefix over the waves of group g, and the group total
+    int run = 0;
+    for (int w = 0; w < kSortT / 64; ++w) {
+      const int c = wtot[t][w];
+      wtot[t][w] = run;
+      run += c;
+    }
+    gbase[t + 1] = run;
   }
   __syncthreads();
   if (t == 0) {
-    int run = 0;
-    for (int g = 0; g < G; ++g) {
-      int tot = 0;
-      for (int u = 0; u < 256; ++u) {
-        int c = cnt[u][g];
-        cnt[u][g] = run;
-        run += c;
-        tot += c;
-      }
-      counts[g] = tot;
+    gbase[0] = 0;
+    for (int g = 0; g < 16; ++g) {
+      if (g < G) counts[g] = gbase[g + 1];
+      gbase[g + 1] += gbase[g];
     }
   }
   __syncthreads();
+  int pos[16];
+#pragma unroll
+  for (int g = 0; g < 16; ++g) pos[g] = gbase[g] + wtot[g][wave] + off[g];
   for (int i = b0; i < b1; ++i) {
     int g = group[i];
     g = g < 0 ? 0 : (g >= G ? G - 1 : g);
-    sorted[cnt[t][g]++] = i;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (g == q) sorted[pos[q]++] = i;
   }
 }
 
@@ -206,7 +237,7 @@ hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
   }
   if (G > 16) return hipErrorInvalidValue;
   int* d_counts = c->d_flags + 8 + 64;
-  hipLaunchKernelGGL(k_group_sort, dim3(1), dim3(256), 0, c->stream, c->d_cluster, c->ncell, G, c->d_sorted, d_counts);
+  hipLaunchKernelGGL(k_group_sort, dim3(1), dim3(kSortT), 0, c->stream, c->d_cluster, c->ncell, G, c->d_sorted, d_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   int counts[16];
