@@ -20,6 +20,7 @@ from .geometry import map_eval
 from .rom import reduced_coordinates_dt
 from .assembly import rom_Ieff, contract
 from .bddc import edge_map
+from .dofs import edge_nodes_local
 
 
 def chat_dJ(J, Cmat):
@@ -85,20 +86,23 @@ def compliance_gradient(P, unodes):
                 for a in range(m + 1):
                     dN = np.stack([D1[a] * B2[b], B1[a] * D2[b]], axis=1)   # [k3, q]
                     gX[r, m * iy + b, m * ix + a, :] -= np.einsum("kpq,kq->p", dEdJ, dN)
-            if ix == P.nx - 1:
-                trac = prob["traction"][r, iy]
+            if c in P.load_pos:
+                e = P.loaded
+                trac = prob["traction"][r, P.load_pos[c]]
                 xi, w = gauss_legendre(p + 2 * m + 2)
-                _, dx = edge_map(X, "right", xi)
+                _, dx = edge_map(X, e, xi)
                 ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
                 bn = lagrange(gll_nodes(p), xi)               # [p+1, nq]
                 dB = bernstein_deriv(m, xi)                   # [m+1, nq]
-                ur = np.array([[u[d.natural(p, bb, comp)] for comp in range(2)] for bb in range(p + 1)])
-                # 2 u . df/dX_{(beta, m), dd}
-                ut = ur @ trac                                # [p+1]
+                ue = np.array([[u[d.natural(a, b, comp)] for comp in range(2)]
+                               for (a, b) in edge_nodes_local(p, e)])
+                # 2 u . df/dX for the control points (beta along the edge) of edge e
+                ut = ue @ trac                                # [p+1]
                 for beta in range(m + 1):
+                    ja, jb = {"left": (0, beta), "right": (m, beta), "bottom": (beta, 0), "top": (beta, m)}[e]
                     for dd in range(2):
                         dds = dx[:, dd] / ds * dB[beta]
-                        gX[r, m * iy + beta, m * ix + m, dd] += 2.0 * ut @ (bn @ (w * dds))
+                        gX[r, m * iy + jb, m * ix + ja, dd] += 2.0 * ut @ (bn @ (w * dds))
     return J, gX, gt
 
 

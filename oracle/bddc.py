@@ -26,7 +26,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .basis import gll_nodes, lagrange, gauss_legendre, bernstein, bernstein_deriv
-from .dofs import Dofs, EDGES, edge_nodes_local
+from .dofs import Dofs, EDGES, edge_nodes_local, side_cells
 from .geometry import cell_control_points, material_tensor, min_det_jacobian
 from .assembly import rom_K, fast_K
 
@@ -67,14 +67,15 @@ def edge_constraint_rows(X, p, e, moments):
     return rows
 
 
-def traction_load(X, p, trac):
-    """Consistent load of a constant traction on the right edge:
-    f[node, comp] = int_0^1 b_node(xi2) t_comp |dx/dxi2| dxi2 with p+2m+2
-    Gauss points (Sec. 2.2.1, external virtual work; traction times the
-    curve Jacobian)."""
+def traction_load(X, p, trac, e="right"):
+    """Consistent load of a constant traction on edge e of the cell:
+    f[node, comp] = int_0^1 b_node(xi) t_comp |dx/dxi| dxi along the edge,
+    nodes in increasing running coordinate, p+2m+2 Gauss points (Sec. 2.2.1,
+    external virtual work on the Neumann part of the boundary; traction times
+    the curve Jacobian)."""
     m = X.shape[0] - 1
     xi, w = gauss_legendre(p + 2 * m + 2)
-    _, dx = edge_map(X, "right", xi)
+    _, dx = edge_map(X, e, xi)
     ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
     b = lagrange(gll_nodes(p), xi)
     f = b @ (w * ds)
@@ -89,7 +90,11 @@ class Problem:
     """One lattice problem, built on the oracle's own DoF maps.
 
     assembly: 'rom' (MDEIM surrogate, the method), 'fast' (exact trimmed
-    tensor) or 'full' (full quadrature reference)."""
+    tensor) or 'full' (full quadrature reference).  The clamped sides
+    (prob["clamped"], default the left side) carry homogeneous Dirichlet
+    conditions on both components, the loaded side (prob["loaded"], default
+    the right side) carries prob["traction"][r, k] on its k-th cell edge, and
+    the other sides are traction free (Sec. 2.2.1)."""
 
     def __init__(self, prob, roms=None, assembly="rom", moments=None):
         self.prob = prob
@@ -97,7 +102,12 @@ class Problem:
         self.nx, self.ny = prob["nx"], prob["ny"]
         self.rho = prob["rho"]
         self.moments = prob["moments"] if moments is None else moments
-        self.dofs = Dofs(self.nx, self.ny, self.p, self.moments)
+        self.clamped = tuple(prob.get("clamped", ("left",)))
+        self.loaded = prob.get("loaded", "right")
+        if self.loaded in self.clamped:
+            raise ValueError("the loaded side is clamped")
+        self.dofs = Dofs(self.nx, self.ny, self.p, self.moments, self.clamped)
+        self.load_pos = {c: k for c, k in side_cells(self.nx, self.ny, self.loaded)}
         self.Cmat = material_tensor(prob["E"], prob["nu"])
         self.roms = roms
         self.assembly = assembly
@@ -135,13 +145,13 @@ class Problem:
         cell.I_nat = in_nat
         cell.free = free
         cell.K = self.cell_K(c)
-        # loads (natural order, nrhs columns): traction on the right side
-        ix, iy = d.cell_xy(c)
+        # loads (natural order, nrhs columns): traction on the loaded side
         f = np.zeros((2 * d.nB, self.nrhs))
-        if ix == self.nx - 1:
+        if c in self.load_pos:
+            k = self.load_pos[c]
             for r in range(self.nrhs):
-                fe = traction_load(cell.X, p, self.prob["traction"][r, iy])
-                for n, (a, b) in enumerate(edge_nodes_local(p, "right")):
+                fe = traction_load(cell.X, p, self.prob["traction"][r, k], self.loaded)
+                for n, (a, b) in enumerate(edge_nodes_local(p, self.loaded)):
                     for comp in range(2):
                         f[d.natural(a, b, comp), r] += fe[n, comp]
         cell.f = f
@@ -302,7 +312,7 @@ class Problem:
             ix, iy = d.cell_xy(c)
             for b in range(p + 1):
                 for a in range(p + 1):
-                    if p * ix + a == 0:
+                    if d.node_dirichlet[p * iy + b, p * ix + a]:
                         continue
                     out[p * iy + b, p * ix + a, 0] = ui[d.natural(a, b, 0)]
                     out[p * iy + b, p * ix + a, 1] = ui[d.natural(a, b, 1)]

@@ -5,7 +5,9 @@ cell (ix, iy) is local node (a, b) = (gx - p ix, gy - p iy), k = a + (p+1) b.
 
 Classification (reading of Sec. 3.1 that reproduces every dof count printed
 in the scaling study and the 17k-cell statistics):
-  * Dirichlet: nodes on the clamped side x = 0 (gx = 0), strong, whole edge;
+  * Dirichlet: nodes on the clamped sides of the lattice (Sec. 2.2.1, the
+    Dirichlet part of the boundary), strong, whole side; the benchmark clamps
+    the side x = 0 (gx = 0), which is the default;
   * interior u_I: the (p-1)^2 nodes strictly inside a cell;
   * skeleton u: every other node (any cell boundary, including the outer
     traction-free and loaded sides).
@@ -19,11 +21,13 @@ Canonical local orders (also the export order of per-cell results):
   coarse slots:   [BL.x, BL.y, BR.x, BR.y, TL.x, TL.y, TR.x, TR.y] then per
                   edge [left, right, bottom, top]: [avg x, avg y, (moment)];
   interior slots: node (b-1)(p-1) + (a-1), dof slot = 2*node + comp.
-Slots of Dirichlet nodes (left side of first-column cells) are inactive.
+Slots of Dirichlet nodes (e.g. the left side of first-column cells) are
+inactive, as are the coarse slots of Dirichlet vertices and edges.
 """
 import numpy as np
 
 EDGES = ("left", "right", "bottom", "top")
+SIDES = EDGES   # sides of the lattice, in the same order as a cell's edges
 
 
 def skeleton_nodes_local(p):
@@ -54,14 +58,20 @@ def edge_nodes_local(p, e):
 class Dofs:
     """All index maps of an nx x ny lattice of degree-p cells."""
 
-    def __init__(self, nx, ny, p, moments=True):
+    def __init__(self, nx, ny, p, moments=True, clamped=("left",)):
         self.nx, self.ny, self.p, self.moments = nx, ny, p, moments
+        self.clamped = tuple(clamped)
+        for sd in self.clamped:
+            if sd not in SIDES:
+                raise ValueError(f"unknown side {sd}")
         self.ncell = nx * ny
         self.nB = (p + 1) ** 2
         Gx, Gy = p * nx + 1, p * ny + 1
         self.Gx, self.Gy = Gx, Gy
         gx, gy = np.meshgrid(np.arange(Gx), np.arange(Gy), indexing="xy")
-        dir_ = gx == 0
+        cl = self.clamped
+        dir_ = (("left" in cl) & (gx == 0)) | (("right" in cl) & (gx == Gx - 1)) \
+            | (("bottom" in cl) & (gy == 0)) | (("top" in cl) & (gy == Gy - 1))
         inter = (gx % p != 0) & (gy % p != 0)
         skel = ~dir_ & ~inter
         self.node_dirichlet = dir_
@@ -74,24 +84,30 @@ class Dofs:
         self.N_I = 2 * (p - 1) ** 2 * self.ncell
         self.sk_local = skeleton_nodes_local(p)
         self.in_local = interior_nodes_local(p)
-        # coarse numbering: vertices (vx>=1), horizontal edges, vertical edges (vx>=1)
+        # coarse numbering: non-Dirichlet vertices, horizontal edges, vertical
+        # edges (a vertex or edge on a clamped side carries no coarse dof)
         self.nce = 3 if moments else 2
+        on_x = lambda vx: (("left" in cl) and vx == 0) or (("right" in cl) and vx == nx)
+        on_y = lambda vy: (("bottom" in cl) and vy == 0) or (("top" in cl) and vy == ny)
         cid = 0
         self.vert_id = -np.ones((ny + 1, nx + 1), dtype=np.int64)
         for vy in range(ny + 1):
-            for vx in range(1, nx + 1):
-                self.vert_id[vy, vx] = cid
-                cid += 2
+            for vx in range(nx + 1):
+                if not (on_x(vx) or on_y(vy)):
+                    self.vert_id[vy, vx] = cid
+                    cid += 2
         self.hedge_id = -np.ones((ny + 1, nx), dtype=np.int64)
         for vy in range(ny + 1):
             for ex in range(nx):
-                self.hedge_id[vy, ex] = cid
-                cid += self.nce
+                if not on_y(vy):
+                    self.hedge_id[vy, ex] = cid
+                    cid += self.nce
         self.vedge_id = -np.ones((ny, nx + 1), dtype=np.int64)
         for ey in range(ny):
-            for vx in range(1, nx + 1):
-                self.vedge_id[ey, vx] = cid
-                cid += self.nce
+            for vx in range(nx + 1):
+                if not on_x(vx):
+                    self.vedge_id[ey, vx] = cid
+                    cid += self.nce
         self.N_C = cid
 
     def cell_xy(self, c):
@@ -142,3 +158,17 @@ class Dofs:
                         free[self.natural(a, b, comp)] = 2 * f + comp
         return (np.array(skel_nat), np.array(skel_glob), np.array(in_nat),
                 np.array(cg, dtype=np.int64), free)
+
+
+def side_cells(nx, ny, side):
+    """Cells along a side of the lattice with their position along it:
+    [(cell, k)], k = iy on the left and right sides, ix on the bottom and top."""
+    if side == "left":
+        return [(iy * nx, iy) for iy in range(ny)]
+    if side == "right":
+        return [(iy * nx + nx - 1, iy) for iy in range(ny)]
+    if side == "bottom":
+        return [(ix, ix) for ix in range(nx)]
+    if side == "top":
+        return [((ny - 1) * nx + ix, ix) for ix in range(nx)]
+    raise ValueError(f"unknown side {side}")

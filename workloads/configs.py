@@ -11,14 +11,18 @@ Each problem is a plain dict of numpy arrays and scalars:
   family       int32 [ncell] level-set family per cell (0 circle, 1 cross)
   t            float64 [ncell] thickness parameter per cell
   E, nu, rho   material (plane strain) and stabilisation factor
-  traction     float64 [nrhs, ny, 2] constant traction on the right-edge
-               segment of each cell of the last column (physical units)
+  traction     float64 [nrhs, n_side, 2] constant traction on the edge of
+               each cell along the loaded side (physical units); n_side = ny
+               for the left and right sides, nx for the bottom and top
+  clamped      tuple of clamped sides ("left", "right", "bottom", "top")
+  loaded       the loaded side
   moments      whether edge-moment coarse dofs are used
   rtol         PCG relative residual tolerance
   rom          {family: dict(lo, hi, n_k, n_s, n_r, r)} ROM settings
 
-The left side x = 0 is clamped; the other outer sides are traction free
-except the right side, which carries the traction.
+By default the left side x = 0 is clamped and the right side carries the
+traction; the other outer sides are traction free.  The `clamped` and
+`loaded` overrides select other sides.
 """
 import numpy as np
 
@@ -112,18 +116,23 @@ def make_problem(config=1, seed=None, **overrides):
     else:
         t = cfg["t_lo"] + (cfg["t_hi"] - cfg["t_lo"]) * u
     nrhs = cfg["nrhs"]
+    clamped = tuple(cfg.get("clamped", ("left",)))
+    loaded = cfg.get("loaded", "right")
+    n_side = ny if loaded in ("left", "right") else nx
     if cfg["load"] == "unit":
-        traction = np.zeros((nrhs, ny, 2))
-        traction[:, :, 0] = 1.0
+        # unit traction along the outward normal of the loaded side
+        traction = np.zeros((nrhs, n_side, 2))
+        normal = {"left": (-1.0, 0.0), "right": (1.0, 0.0), "bottom": (0.0, -1.0), "top": (0.0, 1.0)}[loaded]
+        traction[:, :, :] = normal
     else:
-        traction = rng.normal(0.0, 1.0, size=(nrhs, ny, 2))
+        traction = rng.normal(0.0, 1.0, size=(nrhs, n_side, 2))
     present = sorted(set(int(f) for f in np.unique(family)))
     rom = {f: cfg["rom"][f] for f in cfg["rom"] if f in present or len(present) == 0}
     return dict(config=config, seed=seed, nx=nx, ny=ny, p=cfg["p"], q=cfg["q"],
                 m=m, ctrl=np.ascontiguousarray(net), family=family,
                 t=np.ascontiguousarray(t, dtype=np.float64), E=1.0, nu=0.3,
                 rho=cfg["rho"], moments=cfg["moments"], rtol=cfg["rtol"],
-                traction=np.ascontiguousarray(traction), rom=rom)
+                traction=np.ascontiguousarray(traction), clamped=clamped, loaded=loaded, rom=rom)
 
 
 def rom_lhs_uniforms(family, n_k, n_s):
