@@ -37,11 +37,13 @@
  * Geometry (Sec. 2.1): an nx x ny lattice of unit parametric cells, cell (ix, iy)
  * has index iy*nx + ix.  The map of every cell is a Bernstein (Bezier) patch of
  * order m taken from one shared control net of (m*ny+1) x (m*nx+1) points,
- * row-major with x fastest: ctrl[(jy*(m*nx+1) + jx)*2 + c].  The left side of the
- * lattice (jx = 0 column of cells) is clamped (homogeneous Dirichlet on both
- * components, strongly, on the whole side); the right side carries a traction
- * that is constant on each cell edge (per unit physical length); the other sides
- * are traction free.
+ * row-major with x fastest: ctrl[(jy*(m*nx+1) + jx)*2 + c].
+ *
+ * Boundary conditions (Sec. 2.2.1): a set of clamped sides of the lattice
+ * (homogeneous Dirichlet on both components, strongly, on the whole side) and
+ * one loaded side that carries a traction, constant on each cell edge of that
+ * side (per unit physical length); the other sides are traction free.  The
+ * benchmark lattices clamp the left side (x = 0) and load the right side.
  *
  * Level sets: each cell belongs to a level-set family with one parameter t (the
  * role of the threshold of Sec. 2.1.2).  The geometry of a family enters only
@@ -75,9 +77,27 @@ typedef enum {
 
 typedef enum {
   LBDDC_FP64 = 0,   /* every step in FP64 */
-  LBDDC_MIXED = 1   /* FP64 operator, recurrence and coarse solve; the constrained local
+  LBDDC_MIXED = 1,  /* FP64 operator, recurrence and coarse solve; the constrained local
                        factorizations and the preconditioner data and solves in FP32 */
+  /* lbddc_assemble only: the theta x Khat contraction (Sec. 4.1, Alg. 4 with
+   * the MDEIM reconstruction of Alg. 5) in FP32 on MFMA with FP32
+   * accumulation, from FP32 copies of the geometry coefficients, the MDEIM
+   * vector and the reduced basis.  The result (relative error ~1e-7, set by
+   * FP32 rounding over a depth of n_r + 1 and the 4 (q+1)^2 geometry terms) is
+   * read with lbddc_export_cells(LBDDC_X_K); it feeds no later stage, since the
+   * operator of the 1e-8 solve needs an FP64-accurate stiffness: after it,
+   * lbddc_setup needs an FP64 or MIXED assemble again. */
+  LBDDC_FP32_CONTRACTION = 2
 } lbddc_precision;
+
+/* Sides of the lattice, as bits of a set (clamped_sides) or one value (loaded_side). */
+enum { LBDDC_SIDE_LEFT = 1, LBDDC_SIDE_RIGHT = 2, LBDDC_SIDE_BOTTOM = 4, LBDDC_SIDE_TOP = 8 };
+
+/* Coarse degrees of freedom (Sec. 3.3.1), as bits: the displacement at every
+ * cross point, two averages per edge, one moment per edge.  Supported sets:
+ * CORNERS | EDGE_AVG and CORNERS | EDGE_AVG | EDGE_MOMENT (the local solves of
+ * Alg. 2 take the cross points as primal; others give LBDDC_E_UNSUPPORTED). */
+enum { LBDDC_CON_CORNERS = 1, LBDDC_CON_EDGE_AVG = 2, LBDDC_CON_EDGE_MOMENT = 4 };
 
 /* Create a context on HIP device `device`.  `stream` is a hipStream_t to enqueue
  * on (NULL = a stream created and owned by the context). */
@@ -110,21 +130,27 @@ typedef struct {
 lbddc_status lbddc_load_rom(lbddc_ctx* ctx, const lbddc_rom_desc* rom);
 
 /* The lattice problem (Sec. 2, 3).  Plane-strain isotropic material (E, nu),
- * stabilisation factor rho (Sec. 2.2.3), coarse dofs: corner values and edge
- * averages, plus edge moments when `moments` is nonzero (Sec. 3.3.1).
- * traction[(r*ny + iy)*2 + c]: component c of load case r on the right edge of
- * cell (nx-1, iy).  Limits: 2 <= p <= 8, q in {1, 2, 3}, 1 <= map_order <= 4,
+ * stabilisation factor rho (Sec. 2.2.3), coarse dofs `constraints`
+ * (LBDDC_CON_* set, Sec. 3.3.1), clamped sides `clamped_sides` (LBDDC_SIDE_*
+ * set, at least one) and the loaded side `loaded_side` (one LBDDC_SIDE_*
+ * value, not clamped).  traction[(r*n_side + k)*2 + c]: component c of load
+ * case r on the loaded edge of the k-th cell along the loaded side, k = iy on
+ * the left and right sides (n_side = ny), k = ix on the bottom and top sides
+ * (n_side = nx).  Limits: 2 <= p <= 8, q in {1, 2, 3}, 1 <= map_order <= 4,
  * 1 <= nrhs <= 16, nx, ny >= 1.  Validates det J > 0 at the interpolation
  * points and on a (2m+2)^2 Gauss sample of every cell (LBDDC_E_DEGENERATE_MAP),
  * that every family has a ROM of degrees (p, q) (LBDDC_E_ROM) and that every t
- * lies in its family's box (LBDDC_E_PARAM_RANGE). */
+ * lies in its family's box (LBDDC_E_PARAM_RANGE).  On failure the previous
+ * problem, if any, stays in place with all its stages. */
 typedef struct {
   int32_t nx, ny, p, q, map_order;
   const double* ctrl;
   const int32_t* family;
   const double* t;
   double E, nu, rho;
-  int32_t moments;
+  uint32_t constraints;
+  uint32_t clamped_sides;
+  int32_t loaded_side;
   int32_t nrhs;
   const double* traction;
 } lbddc_problem_desc;
@@ -132,11 +158,17 @@ lbddc_status lbddc_set_problem(lbddc_ctx* ctx, const lbddc_problem_desc* desc);
 
 /* Replace the control net and the thickness parameters of the current problem
  * (device pointers, same sizes as in set_problem, read on the context's stream
- * before the call returns).  Invalidates assemble and later stages. */
+ * before the call returns; either may be NULL to keep the current values).
+ * The new geometry is validated as in set_problem.  On success it invalidates
+ * assemble and later stages; on failure (LBDDC_E_DEGENERATE_MAP,
+ * LBDDC_E_PARAM_RANGE, ...) the previous geometry and every stage computed
+ * from it stay in place. */
 lbddc_status lbddc_set_geometry_device(lbddc_ctx* ctx, const double* d_ctrl, const double* d_t);
 
 /* Per-cell geometry coefficients, MDEIM evaluation and the batched contraction
- * K_i = sum_q theta_q Khat_q (Alg. 4, 5), plus the cell loads. */
+ * K_i = sum_q theta_q Khat_q (Alg. 4, 5), plus the cell loads.  `prec`:
+ * LBDDC_FP64 and LBDDC_MIXED both contract in FP64 (the operator); see
+ * LBDDC_FP32_CONTRACTION for the FP32 variant. */
 lbddc_status lbddc_assemble(lbddc_ctx* ctx, lbddc_precision prec);
 
 /* Local Schur complements, weights, constrained local factorizations, coarse

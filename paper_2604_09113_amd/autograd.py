@@ -12,8 +12,12 @@ dJ = 2 u^T df - u^T dK u.  It is evaluated in the forward pass, while the
 solver still holds this u, and only when an input requires a gradient.
 
 All arithmetic runs in the library's kernels; torch provides the device
-buffers and the stream (the solver must have been created on the current
-torch stream).
+buffers and the stream.  The solver must have been created on the current
+torch stream, a non-default one (torch.cuda.Stream()): the library then
+enqueues on the stream that torch's own reads and writes of the inputs and
+outputs use, so no other ordering is needed.  (On torch's default stream the
+library would run on a stream of its own, ordered with torch's work only by
+the legacy default-stream rules; that case is refused.)
 """
 import torch
 
@@ -25,6 +29,9 @@ class Compliance(torch.autograd.Function):
     def forward(ctx, ctrl, t, solver, prec=lbddc.FP64, rtol=1e-10, max_iter=1000):
         if ctrl.dtype != torch.float64 or t.dtype != torch.float64 or not ctrl.is_cuda or not t.is_cuda:
             raise TypeError("Compliance: ctrl and t must be float64 device tensors")
+        cur = torch.cuda.current_stream(ctrl.device)
+        if solver.stream is None or solver.stream != cur.cuda_stream:
+            raise ValueError("Compliance: the solver must be created on the current (non-default) torch stream")
         nx, ny, p, q, m = solver.shape
         if tuple(ctrl.shape) != (m * ny + 1, m * nx + 1, 2) or tuple(t.shape) != (nx * ny,):
             raise ValueError("Compliance: ctrl or t does not match the solver's problem")

@@ -29,26 +29,30 @@ bool dalloc(Ctx* c, void** p, size_t bytes) {
 
 }  // namespace lbddc
 
-static void free_problem(Ctx* c) {
+// Free the device and pinned memory of a problem (not the ROMs, events,
+// stream or the context-wide pinned buffers).
+static void release_problem(Ctx* c) {
   if (c->h_red) hipHostFree(c->h_red);
   c->h_red = nullptr;
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
   c->dev_bytes = 0;
-  Ctx fresh;
-  // keep device, stream, ROMs, events and pinned buffers
-  fresh.device = c->device;
-  fresh.stream = c->stream;
-  fresh.own_stream = c->own_stream;
-  fresh.roms = std::move(c->roms);
-  for (int i = 0; i < Ctx::kNumEv; ++i) fresh.ev[i] = c->ev[i];
+}
+
+// A context holding only what outlives a problem: device, stream, ROMs,
+// events, timing mask and the context-wide pinned buffers.  The ROM table is
+// shared (shallow copy): only one of the two contexts ever frees it.
+static void copy_persistent(const Ctx* c, Ctx* n) {
+  n->device = c->device;
+  n->stream = c->stream;
+  n->own_stream = c->own_stream;
+  n->roms = c->roms;
+  for (int i = 0; i < Ctx::kNumEv; ++i) n->ev[i] = c->ev[i];
   for (int i = 0; i < Ctx::kRing; ++i)
-    for (int k = 0; k < Ctx::kRingEv; ++k) fresh.pev[i][k] = c->pev[i][k];
-  fresh.timing = c->timing;
-  fresh.h_flags = c->h_flags;
-  fresh.h_scal = c->h_scal;
-  fresh.err = c->err;
-  *c = std::move(fresh);
+    for (int k = 0; k < Ctx::kRingEv; ++k) n->pev[i][k] = c->pev[i][k];
+  n->timing = c->timing;
+  n->h_flags = c->h_flags;
+  n->h_scal = c->h_scal;
 }
 
 static lbddc_status fail(Ctx* c, lbddc_status s, const char* msg) {
@@ -92,7 +96,7 @@ static lbddc_status check_flags(Ctx* c, const char* phase) {
 
 extern "C" {
 
-int lbddc_version(void) { return 1; }
+int lbddc_version(void) { return 2; }
 
 lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out) {
   if (!out) return LBDDC_E_ARG;
@@ -259,45 +263,19 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
   return LBDDC_OK;
 }
 
-lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
-  if (!x) return LBDDC_E_ARG;
-  Ctx* c = &x->c;
-  if (!d || !d->ctrl || !d->family || !d->t || !d->traction) return fail(c, LBDDC_E_ARG, "set_problem: null pointer");
-  if (d->nx < 1 || d->ny < 1 || (long long)d->nx * d->ny > (1LL << 22)) return fail(c, LBDDC_E_ARG, "set_problem: bad grid size");
-  if (d->p < 2 || d->p > 8) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: 2 <= p <= 8 supported");
-  if (d->q < 1 || d->q > 3 || d->map_order < 1 || d->map_order > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: q or map order out of range");
-  if (d->nrhs < 1 || d->nrhs > 16) return fail(c, LBDDC_E_ARG, "set_problem: 1 <= nrhs <= 16");
-  if (!(d->E > 0) || !(d->nu > -1 && d->nu < 0.5) || !(d->rho >= 0 && d->rho < 1))
-    return fail(c, LBDDC_E_ARG, "set_problem: material or rho out of range");
+// Build a problem into a context that holds only the persistent parts
+// (copy_persistent).  On failure the caller releases what was allocated.
+static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std::vector<int>& fam_ids) {
   const int ncell = d->nx * d->ny;
   const int netx = d->map_order * d->nx + 1, nety = d->map_order * d->ny + 1;
-  for (size_t i = 0; i < (size_t)netx * nety * 2; ++i)
-    if (!std::isfinite(d->ctrl[i])) return fail(c, LBDDC_E_ARG, "set_problem: non-finite control point");
-  for (size_t i = 0; i < (size_t)d->nrhs * d->ny * 2; ++i)
-    if (!std::isfinite(d->traction[i])) return fail(c, LBDDC_E_ARG, "set_problem: non-finite traction");
-  std::vector<int> fam_ids;
-  for (int i = 0; i < ncell; ++i) {
-    int f = d->family[i];
-    auto it = c->roms.find(f);
-    if (it == c->roms.end()) return fail(c, LBDDC_E_ROM, "set_problem: a cell's family has no loaded ROM");
-    if (it->second.p != d->p || it->second.q != d->q) return fail(c, LBDDC_E_ROM, "set_problem: ROM degrees differ from the problem's");
-    double t = d->t[i];
-    if (!std::isfinite(t)) return fail(c, LBDDC_E_ARG, "set_problem: non-finite thickness");
-    if (!(t >= it->second.lo && t <= it->second.hi))
-      return fail(c, LBDDC_E_PARAM_RANGE, "set_problem: a thickness parameter lies outside its ROM box");
-    if (std::find(fam_ids.begin(), fam_ids.end(), f) == fam_ids.end()) fam_ids.push_back(f);
-  }
-  if (fam_ids.size() > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 4 families per problem");
-  std::sort(fam_ids.begin(), fam_ids.end());
-  int G = 0;
-  for (int f : fam_ids) G += c->roms[f].n_k;
-  if (G > 16) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 16 (family, cluster) groups");
-  hipSetDevice(c->device);
-  hipStreamSynchronize(c->stream);
-  free_problem(c);
   c->fam_ids = fam_ids;
   c->nx = d->nx; c->ny = d->ny; c->p = d->p; c->q = d->q; c->m = d->map_order; c->nrhs = d->nrhs;
-  c->E = d->E; c->nu = d->nu; c->rho = d->rho; c->moments = d->moments != 0;
+  c->E = d->E; c->nu = d->nu; c->rho = d->rho;
+  c->moments = (d->constraints & LBDDC_CON_EDGE_MOMENT) != 0;
+  c->clamped = d->clamped_sides;
+  c->load_edge = d->loaded_side == LBDDC_SIDE_LEFT ? 0 : d->loaded_side == LBDDC_SIDE_RIGHT ? 1
+               : d->loaded_side == LBDDC_SIDE_BOTTOM ? 2 : 3;
+  c->n_side = c->load_edge < 2 ? d->ny : d->nx;
   c->ncell = ncell; c->nB = (c->p + 1) * (c->p + 1); c->ndof = 2 * c->nB; c->nN = c->nB;
   c->nIn = (c->p - 1) * (c->p - 1); c->nI = 2 * c->nIn; c->nU = 8 * c->p; c->nE = c->nU - 8;
   c->nce = c->moments ? 3 : 2; c->nC = 8 + 4 * c->nce; c->nL = (c->q + 1) * (c->q + 1); c->ns = 4 * c->nL;
@@ -307,14 +285,19 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
   c->KC = 0;
   for (int f : fam_ids) c->KC = std::max(c->KC, c->roms[f].KC);
   c->NI = c->nI * ncell;
-  c->Nfree = 2 * (c->Gx * c->Gy - c->Gy);
-  if (!build_topology(c)) { lbddc_status s = c->err.empty() ? LBDDC_E_NOMEM : LBDDC_E_NOMEM; free_problem(c); return s; }
+  {
+    const int kx = ((c->clamped & LBDDC_SIDE_LEFT) != 0) + ((c->clamped & LBDDC_SIDE_RIGHT) != 0);
+    const int ky = ((c->clamped & LBDDC_SIDE_BOTTOM) != 0) + ((c->clamped & LBDDC_SIDE_TOP) != 0);
+    c->Nfree = 2 * (c->Gx - kx) * (c->Gy - ky);
+  }
+  if (!build_topology(c)) return LBDDC_E_NOMEM;
   std::vector<double> tab;
   build_tables(c, tab);
   const size_t nU = c->nU, nC = c->nC, NU = c->NU, NC = c->NC;
   bool ok = dalloc_t(c, &c->d_tab, tab.size()) && dalloc_t(c, &c->d_ctrl, (size_t)netx * nety * 2) &&
+            dalloc_t(c, &c->d_ctrl_bak, (size_t)netx * nety * 2) && dalloc_t(c, &c->d_t_bak, ncell) &&
             dalloc_t(c, &c->d_family, ncell) && dalloc_t(c, &c->d_t, ncell) &&
-            dalloc_t(c, &c->d_trac, (size_t)c->nrhs * c->ny * 2) && dalloc_t(c, &c->d_flags, 128) &&
+            dalloc_t(c, &c->d_trac, (size_t)c->nrhs * c->n_side * 2) && dalloc_t(c, &c->d_flags, 128) &&
             dalloc_t(c, &c->d_theta, (size_t)ncell * c->ns * 4) && dalloc_t(c, &c->d_theta32, (size_t)ncell * c->ns * 4) &&
             dalloc_t(c, &c->d_itil, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_itil32, (size_t)ncell * 4 * c->KC) &&
             dalloc_t(c, &c->d_cluster, ncell) && dalloc_t(c, &c->d_sorted, ncell) &&
@@ -356,7 +339,7 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
     c->err = "pinned host buffer has no device address";
     ok = false;
   }
-  if (!ok) { free_problem(c); return LBDDC_E_NOMEM; }
+  if (!ok) return LBDDC_E_NOMEM;
   // family -> slot table after the 8 flag words
   std::vector<int> flags(128, 0);
   for (int f = 0; f < 64; ++f) flags[8 + f] = -1;
@@ -367,16 +350,80 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
   if (e == hipSuccess) e = hipMemcpy(c->d_ctrl, d->ctrl, (size_t)netx * nety * 2 * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_family, d->family, ncell * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_t, d->t, ncell * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(c->d_trac, d->traction, (size_t)c->nrhs * c->ny * 2 * 8, hipMemcpyHostToDevice);
-  if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem upload"); }
+  if (e == hipSuccess) e = hipMemcpy(c->d_trac, d->traction, (size_t)c->nrhs * c->n_side * 2 * 8, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hipfail(c, e, "set_problem upload");
   c->fam_host.assign(d->family, d->family + ncell);
   c->t_host.assign(d->t, d->t + ncell);
   // validate the maps on the device (det J) right away
   e = launch_geometry(c);
-  if (e != hipSuccess) { free_problem(c); return hipfail(c, e, "set_problem geometry"); }
-  lbddc_status s = check_flags(c, "set_problem");
-  if (s != LBDDC_OK) { std::string m = c->err; free_problem(c); c->err = m; return s; }
-  c->have_problem = true;
+  if (e != hipSuccess) return hipfail(c, e, "set_problem geometry");
+  return check_flags(c, "set_problem");
+}
+
+lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!d || !d->ctrl || !d->family || !d->t || !d->traction) return fail(c, LBDDC_E_ARG, "set_problem: null pointer");
+  if (d->nx < 1 || d->ny < 1 || (long long)d->nx * d->ny > (1LL << 22)) return fail(c, LBDDC_E_ARG, "set_problem: bad grid size");
+  if (d->p < 2 || d->p > 8) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: 2 <= p <= 8 supported");
+  if (d->q < 1 || d->q > 3 || d->map_order < 1 || d->map_order > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: q or map order out of range");
+  if (d->nrhs < 1 || d->nrhs > 16) return fail(c, LBDDC_E_ARG, "set_problem: 1 <= nrhs <= 16");
+  if (!(d->E > 0) || !(d->nu > -1 && d->nu < 0.5) || !(d->rho >= 0 && d->rho < 1))
+    return fail(c, LBDDC_E_ARG, "set_problem: material or rho out of range");
+  if (d->constraints & ~7u) return fail(c, LBDDC_E_ARG, "set_problem: unknown constraint bits");
+  if (d->constraints != (LBDDC_CON_CORNERS | LBDDC_CON_EDGE_AVG) &&
+      d->constraints != (LBDDC_CON_CORNERS | LBDDC_CON_EDGE_AVG | LBDDC_CON_EDGE_MOMENT))
+    return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: constraint sets CORNERS|EDGE_AVG and CORNERS|EDGE_AVG|EDGE_MOMENT are supported");
+  if (d->clamped_sides == 0 || (d->clamped_sides & ~15u))
+    return fail(c, LBDDC_E_ARG, "set_problem: clamped_sides must be a nonempty set of LBDDC_SIDE_* bits");
+  if (d->loaded_side != LBDDC_SIDE_LEFT && d->loaded_side != LBDDC_SIDE_RIGHT && d->loaded_side != LBDDC_SIDE_BOTTOM &&
+      d->loaded_side != LBDDC_SIDE_TOP)
+    return fail(c, LBDDC_E_ARG, "set_problem: loaded_side must be one LBDDC_SIDE_* value");
+  if ((uint32_t)d->loaded_side & d->clamped_sides) return fail(c, LBDDC_E_ARG, "set_problem: the loaded side is clamped");
+  const int ncell = d->nx * d->ny;
+  const int netx = d->map_order * d->nx + 1, nety = d->map_order * d->ny + 1;
+  const int n_side = (d->loaded_side == LBDDC_SIDE_LEFT || d->loaded_side == LBDDC_SIDE_RIGHT) ? d->ny : d->nx;
+  for (size_t i = 0; i < (size_t)netx * nety * 2; ++i)
+    if (!std::isfinite(d->ctrl[i])) return fail(c, LBDDC_E_ARG, "set_problem: non-finite control point");
+  for (size_t i = 0; i < (size_t)d->nrhs * n_side * 2; ++i)
+    if (!std::isfinite(d->traction[i])) return fail(c, LBDDC_E_ARG, "set_problem: non-finite traction");
+  std::vector<int> fam_ids;
+  for (int i = 0; i < ncell; ++i) {
+    int f = d->family[i];
+    auto it = c->roms.find(f);
+    if (it == c->roms.end()) return fail(c, LBDDC_E_ROM, "set_problem: a cell's family has no loaded ROM");
+    if (it->second.p != d->p || it->second.q != d->q) return fail(c, LBDDC_E_ROM, "set_problem: ROM degrees differ from the problem's");
+    double t = d->t[i];
+    if (!std::isfinite(t)) return fail(c, LBDDC_E_ARG, "set_problem: non-finite thickness");
+    if (!(t >= it->second.lo && t <= it->second.hi))
+      return fail(c, LBDDC_E_PARAM_RANGE, "set_problem: a thickness parameter lies outside its ROM box");
+    if (std::find(fam_ids.begin(), fam_ids.end(), f) == fam_ids.end()) fam_ids.push_back(f);
+  }
+  if (fam_ids.size() > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 4 families per problem");
+  std::sort(fam_ids.begin(), fam_ids.end());
+  int G = 0;
+  for (int f : fam_ids) G += c->roms[f].n_k;
+  if (G > 16) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 16 (family, cluster) groups");
+  hipSetDevice(c->device);
+  hipStreamSynchronize(c->stream);
+  // the new problem is built beside the current one, which stays in place
+  // (with all its stages) until the new one is complete and valid
+  Ctx* n = new (std::nothrow) Ctx();
+  if (!n) return fail(c, LBDDC_E_NOMEM, "set_problem: host allocation failed");
+  copy_persistent(c, n);
+  lbddc_status s = build_problem(n, d, fam_ids);
+  if (s != LBDDC_OK) {
+    hipStreamSynchronize(c->stream);
+    c->err = n->err;
+    release_problem(n);
+    delete n;
+    return s;
+  }
+  release_problem(c);
+  n->roms = std::move(c->roms);
+  n->have_problem = true;
+  *c = std::move(*n);
+  delete n;
   return LBDDC_OK;
 }
 
@@ -386,25 +433,45 @@ lbddc_status lbddc_set_geometry_device(lbddc_ctx* x, const double* d_ctrl, const
   if (!c->have_problem) return fail(c, LBDDC_E_STATE, "set_geometry_device: no problem");
   if (!d_ctrl && !d_t) return fail(c, LBDDC_E_ARG, "set_geometry_device: null pointers");
   hipSetDevice(c->device);
-  if (d_ctrl) HIPCHK(hipMemcpyAsync(c->d_ctrl, d_ctrl, (size_t)c->netx * c->nety * 2 * 8, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
-  if (d_t) HIPCHK(hipMemcpyAsync(c->d_t, d_t, (size_t)c->ncell * 8, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  const size_t nctrl = (size_t)c->netx * c->nety * 2 * 8, nt = (size_t)c->ncell * 8;
+  // keep the current geometry aside, validate the new one in its place, and
+  // put the old one back if it is rejected
+  HIPCHK(hipMemcpyAsync(c->d_ctrl_bak, c->d_ctrl, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  HIPCHK(hipMemcpyAsync(c->d_t_bak, c->d_t, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  if (d_ctrl) HIPCHK(hipMemcpyAsync(c->d_ctrl, d_ctrl, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  if (d_t) HIPCHK(hipMemcpyAsync(c->d_t, d_t, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   HIPCHK(launch_geometry(c), "set_geometry_device");
   lbddc_status s = check_flags(c, "set_geometry_device");
+  if (s != LBDDC_OK) {
+    const std::string msg = c->err;
+    // the previous geometry and the coefficients computed from it (the
+    // geometry pass is deterministic, so they are restored bit for bit)
+    HIPCHK(hipMemcpyAsync(c->d_ctrl, c->d_ctrl_bak, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device restore");
+    HIPCHK(hipMemcpyAsync(c->d_t, c->d_t_bak, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device restore");
+    HIPCHK(launch_geometry(c), "set_geometry_device restore");
+    lbddc_status s2 = check_flags(c, "set_geometry_device restore");
+    if (s2 != LBDDC_OK) return s2;
+    c->err = msg;
+    return s;
+  }
   c->assembled = c->setup_done = c->solved = false;
-  return s;
+  c->k32_valid = false;
+  return LBDDC_OK;
 }
 
 lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
   if (!x) return LBDDC_E_ARG;
   Ctx* c = &x->c;
   if (!c->have_problem) return fail(c, LBDDC_E_STATE, "assemble: no problem set");
-  if (prec != LBDDC_FP64 && prec != LBDDC_MIXED && (int)prec != 2) return fail(c, LBDDC_E_ARG, "assemble: bad precision");
+  if (prec != LBDDC_FP64 && prec != LBDDC_MIXED && prec != LBDDC_FP32_CONTRACTION)
+    return fail(c, LBDDC_E_ARG, "assemble: bad precision");
   hipSetDevice(c->device);
-  const bool fp32 = (int)prec == 2;
+  const bool fp32 = prec == LBDDC_FP32_CONTRACTION;
   if (fp32 && !c->d_K32) {
     if (!dalloc_t(c, &c->d_K32, (size_t)c->ncell * c->npair * 4)) return LBDDC_E_NOMEM;
   }
   c->assembled = c->setup_done = c->solved = false;
+  c->k32_valid = false;
   HIPCHK(hipEventRecord(c->ev[6], c->stream), "assemble");
   HIPCHK(launch_geometry(c), "assemble geometry");
   HIPCHK(launch_constraints_loads(c), "assemble constraints");
@@ -417,6 +484,7 @@ lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
   if (hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess) c->phase_ms[1] = ms;
   c->asm_prec = prec;
   c->assembled = !fp32;  // the FP32 contraction alone feeds no later stage
+  c->k32_valid = fp32;
   return LBDDC_OK;
 }
 
@@ -598,7 +666,7 @@ lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int3
   if (!out || first < 0 || count < 0 || first + count > c->ncell) return fail(c, LBDDC_E_ARG, "export: bad range");
   const bool need_asm = which == LBDDC_X_K || which == LBDDC_X_LOAD;
   const bool need_setup = which == LBDDC_X_S || which == LBDDC_X_D || which == LBDDC_X_PSI || which == LBDDC_X_SC || which == LBDDC_X_FINE;
-  if (need_asm && !c->assembled && !(which == LBDDC_X_K && c->d_K32)) return fail(c, LBDDC_E_STATE, "export: assemble first");
+  if (need_asm && !c->assembled && !(which == LBDDC_X_K && c->k32_valid)) return fail(c, LBDDC_E_STATE, "export: assemble first");
   if (need_setup && !c->setup_done) return fail(c, LBDDC_E_STATE, "export: setup first");
   hipSetDevice(c->device);
   HIPCHK(hipStreamSynchronize(c->stream), "export");
@@ -611,7 +679,7 @@ lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int3
   const bool p32 = c->setup_prec == LBDDC_MIXED;
   switch (which) {
     case LBDDC_X_K: {
-      const bool use32 = !c->assembled && c->d_K32;
+      const bool use32 = c->k32_valid;
       const size_t per = (size_t)c->npair * 4;
       auto h = use32 ? fetch(c->d_K32, per, 4) : fetch(c->d_K, per, 8);
       for (int k = 0; k < count; ++k) {

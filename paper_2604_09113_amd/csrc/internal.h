@@ -106,7 +106,10 @@ constexpr int ND_SUB_MIN_ROOTS = 256;
 constexpr int ND_SUB_MAX_NF = 256;
 
 struct CoarseLayout {
-  std::vector<int> sb_off, sb_size;   // coarse numbering by grid lines (offset, size)
+  // first coarse id of each grid vertex [(ny+1)(nx+1)], horizontal edge [(ny+1) nx]
+  // (edge ex of line vy) and vertical edge [ny (nx+1)] (edge between lines ey and
+  // ey+1 at vx), -1 on a clamped side; numbered grid line by grid line
+  std::vector<int> vert_first, hedge_first, vedge_first;
   // unique entries of S_C: entry e sums contributions [cstart[e], cstart[e+1]) into dest[e]
   std::vector<long long> dest;        // position in the front storage
   std::vector<int> cstart;
@@ -152,6 +155,9 @@ struct Ctx {
   int nx = 0, ny = 0, p = 0, q = 0, m = 0, nrhs = 1;
   double E = 1, nu = 0.3, rho = 0;
   bool moments = true;
+  uint32_t clamped = LBDDC_SIDE_LEFT;  // clamped sides (LBDDC_SIDE_* set)
+  int load_edge = 1;                   // loaded side as a cell edge: 0 left, 1 right, 2 bottom, 3 top
+  int n_side = 0;                      // cell edges along the loaded side
   int ncell = 0, nB = 0, ndof = 0, nI = 0, nU = 0, nE = 0, nC = 0, nce = 0, nL = 0, ns = 0;
   int nN = 0, npair = 0, NPT = 0, nIn = 0, Gx = 0, Gy = 0, netx = 0, nety = 0;
   long long n_i = 0;
@@ -163,7 +169,6 @@ struct Ctx {
 
   // host topology
   std::vector<int> perm_nat;   // permuted node -> natural node index
-  std::vector<int> dirmask;    // [nU] 1 if the slot is on the left side (clamped for ix == 0)
   std::vector<int> RU, RC;     // [ncell][nU], [ncell][nC]
   CoarseLayout co;
   Tables tab;
@@ -173,9 +178,10 @@ struct Ctx {
   double* d_ctrl = nullptr;    // [nety][netx][2]
   int* d_family = nullptr;
   double* d_t = nullptr;
-  double* d_trac = nullptr;    // [nrhs][ny][2]
+  double* d_trac = nullptr;    // [nrhs][n_side][2]
+  double* d_ctrl_bak = nullptr;  // the previous control net and t while new ones are validated
+  double* d_t_bak = nullptr;
   int* d_perm = nullptr;       // [nN]
-  int* d_dirmask = nullptr;    // [nU]
   int* d_RU = nullptr;         // [ncell][nU]
   int* d_RC = nullptr;         // [ncell][nC]
   int* d_uown_ptr = nullptr;   // [NU+1]
@@ -214,7 +220,8 @@ struct Ctx {
   int* d_tiles = nullptr;      // [ntiles][4]: group, start, count, -
   int ntiles = 0;
   double* d_K = nullptr;       // [ncell][npair][4]
-  float* d_K32 = nullptr;
+  float* d_K32 = nullptr;       // FP32 contraction ([ncell][npair][4]), valid while k32_valid
+  bool k32_valid = false;
   double* d_load = nullptr;    // [nrhs][ncell][nU]
   double* d_cons = nullptr;    // [ncell][4][nce][p+1][2] edge constraint rows
   std::vector<int> group_family, group_cluster;

@@ -185,6 +185,7 @@ struct ChainArgs {
   double lo[4], hi[4];
   int n_k[4], n_r[4], r[4];
   int ncell, nx, ny, netx, m, nL, ns, itil_stride, p, ndof, nI;
+  int edge;  // loaded side as a cell edge (0 left, 1 right, 2 bottom, 3 top)
   double lam, mu, rho;
   Tables T;
   const double* H; const double* G; const double* ucell; const double* trac;
@@ -302,28 +303,45 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
 #pragma unroll
       for (int c = 0; c < 2; ++c) gX[a][c] -= dEdJ[c][0] * dN[2 * a] + dEdJ[c][1] * dN[2 * a + 1];
   }
-  // traction load on the right edge: 2 u . df/dX for the right column of control points
-  if (ix == g.nx - 1) {
+  // traction load on the loaded edge: 2 u . df/dX for the control points along
+  // that edge
+  const int e = g.edge;
+  const bool on_side = (e == 0 && ix == 0) || (e == 1 && ix == g.nx - 1) || (e == 2 && iy == 0) ||
+                       (e == 3 && iy == g.ny - 1);
+  if (on_side) {
     const int nq = g.T.nq_load, p = g.p;
     const double* w = g.tab + g.T.off_load_w;
     const double* bl = g.tab + g.T.off_load_b;
     const double* dB = g.tab + g.T.off_load_dB;
-    const double t0 = g.trac[iy * 2], t1 = g.trac[iy * 2 + 1];
+    const int k_side = e < 2 ? iy : ix;
+    const double t0 = g.trac[k_side * 2], t1 = g.trac[k_side * 2 + 1];
     const double* u = g.ucell + (size_t)cell * g.ndof;
-    // u . t at the right-edge nodes (permuted dofs: skeleton slots after the interior ones)
+    // the edge's control points, and their gradient, in arrays of their own:
+    // every register index stays static (selects over the edge, no indexing
+    // of X by a runtime value)
+    double Pe[M + 1][2], gE[M + 1][2];
+#pragma unroll
+    for (int k = 0; k <= M; ++k)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        Pe[k][cc] = e == 0 ? X[k * (M + 1)][cc] : e == 1 ? X[k * (M + 1) + M][cc] : e == 2 ? X[k][cc] : X[M * (M + 1) + k][cc];
+        gE[k][cc] = 0.0;
+      }
+    // u . t at the edge nodes (permuted dofs: skeleton slots after the interior ones)
     double ut[17];
 #pragma unroll
     for (int n = 0; n < 17; ++n) {
       const int nn = n <= p ? n : 0;
-      const int node = (nn == 0) ? 1 : (nn == p ? 3 : 4 + (p - 1) + (nn - 1));
+      const int node = (nn == 0) ? ((e == 1) ? 1 : (e == 3) ? 2 : 0)
+                                 : (nn == p ? ((e == 0) ? 2 : (e == 2) ? 1 : 3) : 4 + e * (p - 1) + (nn - 1));
       ut[n] = u[g.nI + 2 * node] * t0 + u[g.nI + 2 * node + 1] * t1;
     }
     for (int qd = 0; qd < nq; ++qd) {
       double d0 = 0, d1 = 0;
 #pragma unroll
       for (int k = 0; k <= M; ++k) {
-        d0 += dB[k * nq + qd] * X[k * (M + 1) + M][0];
-        d1 += dB[k * nq + qd] * X[k * (M + 1) + M][1];
+        d0 += dB[k * nq + qd] * Pe[k][0];
+        d1 += dB[k * nq + qd] * Pe[k][1];
       }
       const double ds = sqrt(d0 * d0 + d1 * d1);
       double ub = 0.0;
@@ -333,10 +351,19 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
       const double f = 2.0 * w[qd] * ub / ds;
 #pragma unroll
       for (int k = 0; k <= M; ++k) {
-        gX[k * (M + 1) + M][0] += f * d0 * dB[k * nq + qd];
-        gX[k * (M + 1) + M][1] += f * d1 * dB[k * nq + qd];
+        gE[k][0] += f * d0 * dB[k * nq + qd];
+        gE[k][1] += f * d1 * dB[k * nq + qd];
       }
     }
+#pragma unroll
+    for (int k = 0; k <= M; ++k)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
+        gX[k * (M + 1)][cc] += e == 0 ? gE[k][cc] : 0.0;
+        gX[k * (M + 1) + M][cc] += e == 1 ? gE[k][cc] : 0.0;
+        gX[k][cc] += e == 2 ? gE[k][cc] : 0.0;
+        gX[M * (M + 1) + k][cc] += e == 3 ? gE[k][cc] : 0.0;
+      }
   }
   double* out = g.gcell + (size_t)cell * NP1 * 2;
 #pragma unroll
@@ -463,7 +490,8 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   a.mu = c->E / (2 * (1 + c->nu));
   a.rho = c->rho; a.T = c->tab;
   a.H = c->d_H; a.G = c->d_G; a.ucell = c->d_ucell + (size_t)rhs * c->ncell * c->ndof;
-  a.trac = c->d_trac + (size_t)rhs * c->ny * 2;
+  a.trac = c->d_trac + (size_t)rhs * c->n_side * 2;
+  a.edge = c->load_edge;
   a.gcell = c->d_gcell; a.gt = c->d_gt + (size_t)rhs * c->ncell;
   switch (c->m) {
 #define CHN(mm) case mm: hipLaunchKernelGGL(k_chain<mm>, dim3((c->ncell + 63) / 64), dim3(64), 0, c->stream, a); break;

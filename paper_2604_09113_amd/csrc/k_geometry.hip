@@ -204,37 +204,49 @@ __global__ void k_constraints(ConsArgs g) {
   }
 }
 
-// Right-edge traction of cells in the last column: f[node][c] = t_c int b_node |x'| dxi.
+// Traction on the cell edges along the loaded side:
+// f[node][c] = t_c int b_node |x'| dxi over the edge.
 struct LoadArgs {
   const double* ctrl; const double* tab; const double* trac; Tables T;
   int ncell, nx, ny, netx, m, p, nU, nrhs;
+  int edge, n_side;  // loaded side as a cell edge (0 left, 1 right, 2 bottom, 3 top)
   double* load;  // [nrhs][ncell][nU]
 };
 
+// Skeleton node slot of node n (0..p, increasing running coordinate) of edge e:
+// the corners BL 0, BR 1, TL 2, TR 3, then the interior nodes of the left,
+// right, bottom and top edges, p - 1 each.
+__device__ __forceinline__ int edge_node_slot(int e, int n, int p) {
+  if (n == 0) return (e == 1) ? 1 : (e == 3) ? 2 : 0;
+  if (n == p) return (e == 0) ? 2 : (e == 2) ? 1 : 3;
+  return 4 + e * (p - 1) + (n - 1);
+}
+
 // one 64-lane workgroup per (cell, load case), lane l writing slot l (nU <= 64,
 // coalesced): zero, or on the loaded edge the load of its node and component.
-// Right-edge node n sits in slot node 1 (n = 0), 3 (n = p) or 4 + (p - 1) + (n - 1).
 __global__ __launch_bounds__(64) void k_loads(LoadArgs g) {
-  const int cell = blockIdx.x, rhs = blockIdx.y, l = threadIdx.x, p = g.p;
+  const int cell = blockIdx.x, rhs = blockIdx.y, l = threadIdx.x, p = g.p, e = g.edge;
   const int ix = cell % g.nx, iy = cell / g.nx;
   if (l >= g.nU) return;
   double* out = g.load + ((size_t)rhs * g.ncell + cell) * g.nU;
   const int node = l >> 1, comp = l & 1;
   int n = -1;
-  if (node == 1) n = 0;
-  else if (node == 3) n = p;
-  else if (node >= 4 + (p - 1) && node < 4 + 2 * (p - 1)) n = node - (4 + (p - 1)) + 1;
-  if (ix != g.nx - 1 || n < 0) {
+  for (int k = 0; k <= p; ++k)
+    if (edge_node_slot(e, k, p) == node) n = k;
+  const bool on_side = (e == 0 && ix == 0) || (e == 1 && ix == g.nx - 1) || (e == 2 && iy == 0) ||
+                       (e == 3 && iy == g.ny - 1);
+  if (!on_side || n < 0) {
     out[l] = 0.0;
     return;
   }
+  const int k_side = e < 2 ? iy : ix;
   double P[5][2];
-  edge_points(g.ctrl, g.netx, g.m, ix, iy, 1, P);
+  edge_points(g.ctrl, g.netx, g.m, ix, iy, e, P);
   const int nq = g.T.nq_load;
   const double* w = g.tab + g.T.off_load_w;
   const double* bl = g.tab + g.T.off_load_b;
   const double* dB = g.tab + g.T.off_load_dB;
-  const double tc = g.trac[((size_t)rhs * g.ny + iy) * 2 + comp];
+  const double tc = g.trac[((size_t)rhs * g.n_side + k_side) * 2 + comp];
   double f = 0;
   for (int qd = 0; qd < nq; ++qd) {
     double d0 = 0, d1 = 0;
@@ -277,7 +289,8 @@ hipError_t launch_constraints_loads(Ctx* c) {
   ConsArgs a = {c->d_ctrl, c->d_tab, c->tab, c->ncell, c->nx, c->netx, c->m, c->p, c->nce, c->d_cons};
   const int nth = c->ncell * 4 * (c->p + 1);
   hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, c->stream, a);
-  LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs, c->d_load};
+  LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs,
+                c->load_edge, c->n_side, c->d_load};
   if (c->nU > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_loads, dim3(c->ncell, c->nrhs), dim3(64), 0, c->stream, l);
   return hipGetLastError();

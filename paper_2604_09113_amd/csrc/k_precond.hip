@@ -85,14 +85,13 @@ __device__ __forceinline__ void mfma_mm(FA a, FB b, FO out) {
 template <typename T, int P, int NCE>
 __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, const double* __restrict__ cons,
                                                  const double* __restrict__ diagK, const double* __restrict__ Ktot,
-                                                 const int* __restrict__ RU, int nx, T* __restrict__ Pout,
+                                                 const int* __restrict__ RU, T* __restrict__ Pout,
                                                  T* __restrict__ Psiout, double* __restrict__ Dout,
                                                  double* __restrict__ ScOut, int* __restrict__ flags) {
   constexpr int NU = 8 * P, NE = NU - 8, NCC = 4 * NCE, NC = 8 + NCC;
   constexpr int NSP = NU * (NU + 1) / 2;
   static_assert(NU <= 64, "one row per lane");
   const int cell = blockIdx.x, tid = threadIdx.x;
-  const bool left = (cell % nx) == 0;
   // the first-stage arrays are dead once Psi is formed; S Psi takes their space
   struct Stage1 {
     T A[NE][NE + 1];     // Shat, then Shat^-1, then P
@@ -111,6 +110,9 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   __shared__ double Dv[NU];
   __shared__ double Ps[NU][NC + 1];  // coarse basis (unscaled)
   __shared__ int bad;
+  // clamped corners [0, 4) and clamped edges [4, 8) of the cell: their slots
+  // have no global skeleton dof (Dirichlet), so they carry no constraint
+  __shared__ int clamp[8];
   auto& A = wk.s.A;
   auto& X = wk.s.X;
   auto& W2 = wk.s.W2;
@@ -157,6 +159,10 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
     if (idx < NE * 8) Scol[idx / 8][idx % 8] = (T)vs[m];
   }
   if (tid < NU) Dv[tid] = gw >= 0 ? dk / kt : 0.0;
+  if (tid < 8 && (tid & 1) == 0) clamp[tid >> 1] = gw < 0;                  // corner node tid/2, x slot
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (tid == 2 * (4 + e * (P - 1))) clamp[4 + e] = gw < 0;                   // first interior node of edge e
   // constraint rows: Chat (edge dofs) and the corner columns
   for (int idx = tid; idx < NCC * NE; idx += 256) Ch[idx / NE][idx % NE] = (T)0;
   for (int idx = tid; idx < NCC * 8; idx += 256) Cc[idx / 8][idx % 8] = (T)0;
@@ -164,11 +170,11 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   for (int idx = tid; idx < NCV; idx += 256) {
     const int comp = idx & 1, n = (idx >> 1) % (P + 1), et = (idx >> 1) / (P + 1);
     const int e = et / NCE;
-    if (left && e == 0) continue;  // the clamped side carries no constraints
+    if (clamp[4 + e]) continue;  // a clamped edge carries no constraints
     const T v = (T)cv;
     if (n == 0 || n == P) {
       int corner = (e == 0) ? (n == 0 ? 0 : 2) : (e == 1) ? (n == 0 ? 1 : 3) : (e == 2) ? (n == 0 ? 0 : 1) : (n == 0 ? 2 : 3);
-      if (left && (corner == 0 || corner == 2)) continue;
+      if (clamp[corner]) continue;
       Cc[et][2 * corner + comp] = v;
     } else {
       Ch[et][2 * (e * (P - 1) + n - 1) + comp] = v;
@@ -181,9 +187,9 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   mfma_mm<T, NE, NCC, NE>([&](int i, int k) { return A[i][k]; }, [&](int k, int a) { return Ch[a][k]; },
                           [&](int i, int a, T v) { X[i][a] = v; });
   __syncthreads();
-  // That = Chat X; the clamped edge's rows carry no constraint and get a unit diagonal
+  // That = Chat X; the rows of clamped edges carry no constraint and get a unit diagonal
   mfma_mm<T, NCC, NCC, NE>([&](int a, int i) { return Ch[a][i]; }, [&](int i, int b) { return X[i][b]; },
-                           [&](int a, int b, T v) { Tm[a][b] = (left && a == b && a < NCE) ? (T)1 : v; });
+                           [&](int a, int b, T v) { Tm[a][b] = (a == b && clamp[4 + a / NCE]) ? (T)1 : v; });
   __syncthreads();
   gj_inverse_wave<T, NCC + 1, NCC>(&Tm[0][0], &bad);
   // W2 = X That^-1
@@ -199,23 +205,23 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   for (int i = tid >> 6; i < NE; i += 4)
     for (int j = tid & 63; j <= i; j += 64)
       Pc[i * (i + 1) / 2 + j] = (T)(Dv[8 + i] * (double)A[i][j] * Dv[8 + j]);
-  // coarse basis Psi [NU][NC]: corner rows are the identity (masked on the
-  // clamped side); edge rows: edge constraint columns W2, corner columns
+  // coarse basis Psi [NU][NC]: corner rows are the identity (masked for
+  // clamped corners); edge rows: edge constraint columns W2, corner columns
   // -P S[E, c] - W2 C[:, c] (one product of depth NE + NCC)
   for (int idx = tid; idx < NU * NC; idx += 256) {
     const int i = idx / NC, j = idx % NC;
-    const bool cmask = left && (j == 0 || j == 1 || j == 4 || j == 5);
+    const bool cmask = j < 8 && clamp[j >> 1];
     if (i < 8) {
       Ps[i][j] = (i == j && !cmask) ? 1.0 : 0.0;
     } else if (j >= 8) {
-      const bool emask = left && j < 8 + NCE;
+      const bool emask = clamp[4 + (j - 8) / NCE];
       Ps[i][j] = emask ? 0.0 : (double)W2[i - 8][j - 8];
     }
   }
   mfma_mm<T, NE, 8, NE + NCC>([&](int i, int k) { return k < NE ? A[i][k] : W2[i][k - NE]; },
                               [&](int k, int j) { return k < NE ? Scol[k][j] : Cc[k - NE][j]; },
                               [&](int i, int j, T v) {
-                                const bool cmask = left && (j == 0 || j == 1 || j == 4 || j == 5);
+                                const bool cmask = clamp[j >> 1];
                                 Ps[8 + i][j] = cmask ? 0.0 : -(double)v;
                               });
   __syncthreads();
@@ -269,7 +275,7 @@ static hipError_t precond_T(Ctx* c) {
 #define PC_CASE(pp, ncv)                                                                                          \
   if (c->p == pp && c->nce == ncv) {                                                                             \
     hipLaunchKernelGGL((k_precond<T, pp, ncv>), grid, block, 0, c->stream, c->d_S, c->d_cons, c->d_diagK,         \
-                       c->d_Ktot, c->d_RU, c->nx, Pout, Psi, c->d_D, c->d_ScLoc, c->d_flags);                    \
+                       c->d_Ktot, c->d_RU, Pout, Psi, c->d_D, c->d_ScLoc, c->d_flags);                    \
     return hipGetLastError();                                                                                    \
   }
   PC_CASE(2, 2) PC_CASE(2, 3) PC_CASE(3, 2) PC_CASE(3, 3) PC_CASE(4, 2) PC_CASE(4, 3) PC_CASE(5, 2) PC_CASE(5, 3)

@@ -16,8 +16,9 @@
 // row by row [nI(nI+1)/2] (row k holds columns 0..k), Y = L_II^-1 K_IU stored
 // column by column [nU][nI] (the layouts the recovery reads coalesced), and
 // the skeleton diagonal of K (for the weights).
-// Skeleton slots on the clamped side of first-column cells are replaced by
-// identity rows/columns (their Dirichlet values are zero).
+// Skeleton slots of Dirichlet nodes (slots without a global skeleton dof: the
+// cell edges on clamped sides) are replaced by identity rows/columns (their
+// Dirichlet values are zero).
 #include "internal.h"
 
 namespace lbddc {
@@ -35,7 +36,7 @@ __device__ __forceinline__ double rsqrt_refined(double p) {
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, const int* __restrict__ dirmask, int nx,
+__global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, const int* __restrict__ RU,
                                                double* __restrict__ S, double* __restrict__ L,
                                                double* __restrict__ Y, double* __restrict__ diagK,
                                                int* __restrict__ flags) {
@@ -46,12 +47,11 @@ __global__ __launch_bounds__(256) void k_schur(const double* __restrict__ K, con
   constexpr int NSP = NU * (NU + 1) / 2;
   const int cell = blockIdx.x;
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
-  const bool left = (cell % nx) == 0;
   __shared__ double colbuf[2][256];
   __shared__ double pv[2][2];
   __shared__ double sst[NSP];
   __shared__ int msk[NU];
-  for (int i = tid; i < NU; i += 256) msk[i] = left ? dirmask[i] : 0;
+  for (int i = tid; i < NU; i += 256) msk[i] = RU[(size_t)cell * NU + i] < 0;
   __syncthreads();
   const double* Kc = K + (size_t)cell * NPAIR * 4;
   // every load of the thread's entries first, from clamped positions (entries
@@ -148,7 +148,7 @@ hipError_t launch_schur(Ctx* c) {
   dim3 grid(c->ncell), block(256);
 #define SC_CASE(pp)                                                                                             \
   case pp:                                                                                                      \
-    hipLaunchKernelGGL(k_schur<pp>, grid, block, 0, c->stream, c->d_K, c->d_dirmask, c->nx, c->d_S, c->d_L, \
+    hipLaunchKernelGGL(k_schur<pp>, grid, block, 0, c->stream, c->d_K, c->d_RU, c->d_S, c->d_L, \
                        c->d_Y, c->d_diagK, c->d_flags);                                                        \
     break;
   switch (c->p) {

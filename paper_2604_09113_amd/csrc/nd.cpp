@@ -83,12 +83,22 @@ bool build_nested_dissection(Ctx* c, const std::vector<int>& ent_g1, const std::
     B.at[(size_t)Y * (2 * nx + 1) + X] = (int)B.objs.size();
     B.objs.push_back({X, Y, first, size, -1});
   };
+  // vertices and edges on clamped sides carry no coarse dof and are no objects
   for (int vy = 0; vy <= ny; ++vy)
-    for (int vx = 1; vx <= nx; ++vx) add(2 * vx, 2 * vy, co.sb_off[vy] + 2 * (vx - 1), 2);
+    for (int vx = 0; vx <= nx; ++vx) {
+      const int f = co.vert_first[(size_t)vy * (nx + 1) + vx];
+      if (f >= 0) add(2 * vx, 2 * vy, f, 2);
+    }
   for (int vy = 0; vy <= ny; ++vy)
-    for (int ex = 0; ex < nx; ++ex) add(2 * ex + 1, 2 * vy, co.sb_off[vy] + 2 * nx + nce * ex, nce);
+    for (int ex = 0; ex < nx; ++ex) {
+      const int f = co.hedge_first[(size_t)vy * nx + ex];
+      if (f >= 0) add(2 * ex + 1, 2 * vy, f, nce);
+    }
   for (int ey = 0; ey < ny; ++ey)
-    for (int vx = 1; vx <= nx; ++vx) add(2 * vx, 2 * ey + 1, co.sb_off[ey] + 2 * nx + nce * nx + nce * (vx - 1), nce);
+    for (int vx = 0; vx <= nx; ++vx) {
+      const int f = co.vedge_first[(size_t)ey * (nx + 1) + vx];
+      if (f >= 0) add(2 * vx, 2 * ey + 1, f, nce);
+    }
   B.build(0, nx, 0, ny, -1, 0);
   const int nn = (int)B.nodes.size();
   // own and boundary dof lists, front positions

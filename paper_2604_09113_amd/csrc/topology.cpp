@@ -1,14 +1,15 @@
 // Host-side index maps of the lattice (integer topology only) and the small
 // polynomial tables the kernels read.
 //
-// Dof classification (Sec. 3.1): nodes on the clamped left side are Dirichlet,
+// Dof classification (Sec. 3.1): nodes on the clamped sides are Dirichlet,
 // the (p-1)^2 nodes strictly inside a cell are interior, every other node is a
 // skeleton node (this reading reproduces the dof counts printed for the
 // weak-scaling study).  Coarse dofs (Sec. 3.3.1): two values per non-Dirichlet
 // grid vertex, two averages and (optionally) one moment per non-Dirichlet edge.
 //
 // Coarse numbering by grid lines: line j holds the vertices and horizontal
-// edges of y = j followed by the vertical edges between y = j and y = j + 1.
+// edges of y = j followed by the vertical edges between y = j and y = j + 1
+// (vertices and edges on clamped sides carry no coarse dof).
 // The elimination order of the coarse problem is a nested dissection of the
 // cell grid (nd.cpp); this numbering only names the coarse dofs.
 #include <algorithm>
@@ -45,31 +46,31 @@ bool build_topology(Ctx* c) {
     skel_node_local(p, s, a, b);
     c->perm_nat[n++] = a + (p + 1) * b;
   }
-  c->dirmask.assign(nU, 0);
-  for (int s = 0; s < 4 * p; ++s) {
-    int a, b;
-    skel_node_local(p, s, a, b);
-    if (a == 0) c->dirmask[2 * s] = c->dirmask[2 * s + 1] = 1;
-  }
+  const bool cl_l = c->clamped & LBDDC_SIDE_LEFT, cl_r = c->clamped & LBDDC_SIDE_RIGHT;
+  const bool cl_b = c->clamped & LBDDC_SIDE_BOTTOM, cl_t = c->clamped & LBDDC_SIDE_TOP;
   // global skeleton numbering (every lattice node on a grid line except the
-  // clamped column x = 0), band by band: grid line y = iy p with its nodes in
+  // nodes of the clamped sides), band by band: grid line y = iy p with its nodes in
   // increasing x, then the interior nodes of the vertical edges between lines
   // iy and iy + 1, edge by edge in increasing x and each edge in increasing y.
   // The nodes of every cell edge are then consecutive, as are the slots the
   // two cells sharing the edge give them, so the sums over a dof's cells and
   // the per-cell gathers of interface vectors read contiguous runs.
   const int Gx = c->Gx, Gy = c->Gy;
+  auto node_dir = [&](int gx, int gy) {
+    return (cl_l && gx == 0) || (cl_r && gx == Gx - 1) || (cl_b && gy == 0) || (cl_t && gy == Gy - 1);
+  };
   std::vector<int> sk((size_t)Gx * Gy, -1);
   int nsk = 0;
   std::vector<int> sk_node;
   auto add = [&](int gx, int gy) {
+    if (node_dir(gx, gy)) return;
     sk[(size_t)gy * Gx + gx] = nsk++;
     sk_node.push_back(gy * Gx + gx);
   };
   for (int iy = 0; iy <= ny; ++iy) {
-    for (int gx = 1; gx < Gx; ++gx) add(gx, p * iy);
+    for (int gx = 0; gx < Gx; ++gx) add(gx, p * iy);
     if (iy < ny)
-      for (int vx = 1; vx <= nx; ++vx)
+      for (int vx = 0; vx <= nx; ++vx)
         for (int k = 1; k < p; ++k) add(p * vx, p * iy + k);
   }
   c->NU = 2 * nsk;
@@ -87,19 +88,25 @@ bool build_topology(Ctx* c) {
   // coarse numbering by grid lines: line j holds the vertices and horizontal
   // edges of y = j, then the vertical edges between y = j and y = j + 1
   CoarseLayout& co = c->co;
-  const int nsb = ny + 1;
-  co.sb_off.assign(nsb, 0);
-  co.sb_size.assign(nsb, 0);
+  const auto on_x = [&](int vx) { return (cl_l && vx == 0) || (cl_r && vx == nx); };
+  const auto on_y = [&](int vy) { return (cl_b && vy == 0) || (cl_t && vy == ny); };
+  co.vert_first.assign((size_t)(ny + 1) * (nx + 1), -1);
+  co.hedge_first.assign((size_t)(ny + 1) * nx, -1);
+  co.vedge_first.assign((size_t)ny * (nx + 1), -1);
   int off = 0;
-  for (int j = 0; j < nsb; ++j) {
-    co.sb_off[j] = off;
-    co.sb_size[j] = 2 * nx + nce * nx + (j < ny ? nce * nx : 0);
-    off += co.sb_size[j];
+  for (int vy = 0; vy <= ny; ++vy) {
+    for (int vx = 0; vx <= nx; ++vx)
+      if (!on_x(vx) && !on_y(vy)) { co.vert_first[(size_t)vy * (nx + 1) + vx] = off; off += 2; }
+    for (int ex = 0; ex < nx; ++ex)
+      if (!on_y(vy)) { co.hedge_first[(size_t)vy * nx + ex] = off; off += nce; }
+    if (vy < ny)
+      for (int vx = 0; vx <= nx; ++vx)
+        if (!on_x(vx)) { co.vedge_first[(size_t)vy * (nx + 1) + vx] = off; off += nce; }
   }
   c->NC = off;
-  auto vert = [&](int vx, int vy) { return vx < 1 ? -1 : co.sb_off[vy] + 2 * (vx - 1); };
-  auto hedge = [&](int ex, int vy) { return co.sb_off[vy] + 2 * nx + nce * ex; };
-  auto vedge = [&](int vx, int ey) { return vx < 1 ? -1 : co.sb_off[ey] + 2 * nx + nce * nx + nce * (vx - 1); };
+  auto vert = [&](int vx, int vy) { return co.vert_first[(size_t)vy * (nx + 1) + vx]; };
+  auto hedge = [&](int ex, int vy) { return co.hedge_first[(size_t)vy * nx + ex]; };
+  auto vedge = [&](int vx, int ey) { return co.vedge_first[(size_t)ey * (nx + 1) + vx]; };
   c->RC.assign((size_t)c->ncell * nC, -1);
   for (int cell = 0; cell < c->ncell; ++cell) {
     int ix = cell % nx, iy = cell / nx;
@@ -370,7 +377,7 @@ bool build_topology(Ctx* c) {
     }
     return true;
   };
-  return up(&c->d_perm, c->perm_nat) && up(&c->d_dirmask, c->dirmask) && up(&c->d_RU, c->RU) &&
+  return up(&c->d_perm, c->perm_nat) && up(&c->d_RU, c->RU) &&
          up(&c->d_RC, c->RC) && up(&c->d_uown_ptr, uptr) && up(&c->d_uown, uown) && up(&c->d_cown_ptr, cptr) &&
          up(&c->d_cown, cown) && up(&c->d_uown4, uown4) && up(&c->d_cown4, cown4) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&

@@ -23,6 +23,9 @@ Q_NCELL, Q_NDOF_FREE, Q_N_SKELETON, Q_N_INTERIOR, Q_N_COARSE, Q_N_I_ROM, Q_NU_CE
     Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES, \
     Q_COARSE_SWEEP_LAUNCHES = range(15)
 TIME_OP, TIME_PRE, TIME_COARSE, TIME_ALL, TIME_SAMPLE = 1, 2, 4, 7, 8
+SIDE_LEFT, SIDE_RIGHT, SIDE_BOTTOM, SIDE_TOP = 1, 2, 4, 8
+SIDES = {"left": SIDE_LEFT, "right": SIDE_RIGHT, "bottom": SIDE_BOTTOM, "top": SIDE_TOP}
+CON_CORNERS, CON_EDGE_AVG, CON_EDGE_MOMENT = 1, 2, 4
 PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor", "solve", "op_kernel",
           "pre_kernel", "coarse_solve", "recovery", "gradient", "adjoint_kernel", "coarse_fwd_sweep",
           "coarse_bwd_sweep"]
@@ -50,7 +53,8 @@ class ProblemDesc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("p", C.c_int32), ("q", C.c_int32),
                 ("map_order", C.c_int32), ("ctrl", C.POINTER(C.c_double)), ("family", C.POINTER(C.c_int32)),
                 ("t", C.POINTER(C.c_double)), ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
-                ("moments", C.c_int32), ("nrhs", C.c_int32), ("traction", C.POINTER(C.c_double))]
+                ("constraints", C.c_uint32), ("clamped_sides", C.c_uint32), ("loaded_side", C.c_int32),
+                ("nrhs", C.c_int32), ("traction", C.POINTER(C.c_double))]
 
 
 class SolveInfo(C.Structure):
@@ -125,6 +129,9 @@ class Solver:
         st = self.lib.lbddc_create(device, C.c_void_p(stream) if stream else None, C.byref(self.ctx))
         if st != OK:
             raise LbddcError(st, "lbddc_create failed (no HIP device?)")
+        # the stream the library enqueues on: the given one, or (None) a stream
+        # the library creates and owns
+        self.stream = stream if stream else None
         self._keep = []
 
     def close(self):
@@ -149,14 +156,23 @@ class Solver:
         d = RomDesc(family, p, q, n_k, n_r, r, lo, hi, _dptr(U), _dptr(coeff), _dptr(I_pi))
         self._check(self.lib.lbddc_load_rom(self.ctx, C.byref(d)))
 
-    def set_problem(self, nx, ny, p, q, m, ctrl, family, t, E, nu, rho, moments, traction):
+    def set_problem(self, nx, ny, p, q, m, ctrl, family, t, E, nu, rho, moments, traction,
+                    clamped=("left",), loaded="right", constraints=None):
+        """`moments` selects the coarse set CORNERS | EDGE_AVG (| EDGE_MOMENT);
+        `constraints` (a CON_* mask) overrides it.  `clamped` is a sequence of
+        side names, `loaded` one side name; traction [nrhs, n_side, 2]."""
         ctrl, t, traction = _f64(ctrl), _f64(t), _f64(traction)
         family = np.ascontiguousarray(family, dtype=np.int32)
+        if constraints is None:
+            constraints = CON_CORNERS | CON_EDGE_AVG | (CON_EDGE_MOMENT if moments else 0)
+        cmask = 0
+        for sd in clamped:
+            cmask |= SIDES[sd]
         d = ProblemDesc(nx, ny, p, q, m, _dptr(ctrl), family.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(t),
-                        E, nu, rho, int(bool(moments)), traction.shape[0], _dptr(traction))
+                        E, nu, rho, int(constraints), cmask, SIDES[loaded], traction.shape[0], _dptr(traction))
+        self._check(self.lib.lbddc_set_problem(self.ctx, C.byref(d)))
         self.nrhs = traction.shape[0]
         self.shape = (nx, ny, p, q, m)
-        self._check(self.lib.lbddc_set_problem(self.ctx, C.byref(d)))
 
     def set_geometry_device(self, ctrl_ptr, t_ptr):
         self._check(self.lib.lbddc_set_geometry_device(self.ctx, C.c_void_p(ctrl_ptr), C.c_void_p(t_ptr)))

@@ -13,13 +13,18 @@ def rom_arrays(rom):
                 lo=rom["lo"], hi=rom["hi"], U=U, coeff=coeff, I_pi=rom["I_pi"])
 
 
+def set_problem(s, prob, moments=None):
+    """set_problem with every field of a workloads problem dict."""
+    s.set_problem(prob["nx"], prob["ny"], prob["p"], prob["q"], prob["m"], prob["ctrl"], prob["family"], prob["t"],
+                  prob["E"], prob["nu"], prob["rho"], prob["moments"] if moments is None else moments,
+                  prob["traction"], clamped=prob.get("clamped", ("left",)), loaded=prob.get("loaded", "right"))
+
+
 def make_solver(prob, roms, moments=None):
     s = lbddc.Solver(0)
     for f, rom in roms.items():
         s.load_rom(**rom_arrays(rom))
-    s.set_problem(prob["nx"], prob["ny"], prob["p"], prob["q"], prob["m"], prob["ctrl"], prob["family"], prob["t"],
-                  prob["E"], prob["nu"], prob["rho"], prob["moments"] if moments is None else moments,
-                  prob["traction"])
+    set_problem(s, prob, moments)
     return s
 
 
@@ -55,12 +60,14 @@ def oracle_cells(prob, roms, cells):
     """Oracle Cell objects of selected cells only (the oracle's own cell build,
     without building the whole lattice)."""
     from oracle.bddc import Problem
-    from oracle.dofs import Dofs
+    from oracle.dofs import Dofs, side_cells
     from oracle.geometry import material_tensor
     P = Problem.__new__(Problem)
     P.prob, P.p, P.q, P.m = prob, prob["p"], prob["q"], prob["m"]
     P.nx, P.ny, P.rho, P.moments = prob["nx"], prob["ny"], prob["rho"], prob["moments"]
-    P.dofs = Dofs(P.nx, P.ny, P.p, P.moments)
+    P.clamped, P.loaded = tuple(prob.get("clamped", ("left",))), prob.get("loaded", "right")
+    P.dofs = Dofs(P.nx, P.ny, P.p, P.moments, P.clamped)
+    P.load_pos = {c: k for c, k in side_cells(P.nx, P.ny, P.loaded)}
     P.Cmat = material_tensor(prob["E"], prob["nu"])
     P.roms, P.assembly, P.nrhs = roms, "rom", prob["traction"].shape[0]
     return P, {c: P._build_cell(c) for c in cells}
@@ -100,3 +107,25 @@ def compliance_fTu(prob, u, rhs):
         for n, (a, b) in enumerate(edge_nodes_local(p, "right")):
             J += fe[n] @ u[p * iy + b, p * (nx - 1) + a]
     return J
+
+
+def fp32_contraction_bound(prob, roms, cell_X, c, depth):
+    """First-order rounding bound of the FP32 contraction of cell c, entry by
+    entry: the library rounds Uhat, Itil and theta to FP32 (3 roundings) and
+    accumulates the depth-`depth` reconstruction and the 4 (q+1)^2-term theta
+    sum in FP32, so |K32 - K| <= gamma * Kabs with gamma = (depth + ns + 3) u,
+    u = 2^-24, and Kabs the same contraction of the absolute values
+    |theta| . (|Uhat| |Itil|).  Returns (gamma, Kabs)."""
+    from oracle.assembly import contract
+    from oracle.geometry import geometry_coefficients, material_tensor
+    from oracle.rom import stabilised_reduced
+    rom = roms[int(prob["family"][c])]
+    k, itil = stabilised_reduced(rom, float(prob["t"][c]), prob["rho"])
+    Uhat = np.concatenate([rom["clusters"][k]["U"], rom["I_pi"][:, None]], axis=1)
+    p, q = rom["p"], rom["q"]
+    nB, nL = (p + 1) ** 2, (q + 1) ** 2
+    Iabs = (np.abs(Uhat) @ np.abs(itil)).reshape(nB, nB, 2, 2, nL)
+    C, _ = geometry_coefficients(cell_X, q, material_tensor(prob["E"], prob["nu"]))
+    Kabs = contract(Iabs, np.abs(C))
+    gamma = (depth + 4 * nL + 3) * 2.0 ** -24
+    return gamma, Kabs

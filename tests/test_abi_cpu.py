@@ -35,7 +35,7 @@ def test_status_codes_and_no_device_path():
     if not os.path.exists(lbddc.LIB_PATH):
         pytest.skip("library not built")
     lib = lbddc.library()
-    assert lib.lbddc_version() == 1
+    assert lib.lbddc_version() == 2
     assert lib.lbddc_last_error(None) == b"null context"
     import torch
     if torch.cuda.is_available():
@@ -48,3 +48,33 @@ def test_status_codes_and_no_device_path():
     assert lib.lbddc_setup(None, 0) == lbddc.E_ARG
     assert lib.lbddc_solve(None, 1e-8, 10, None) == lbddc.E_ARG
     assert lib.lbddc_query(None, 0, None) == lbddc.E_ARG
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the descriptor structs have the sizes and field
+    offsets that a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+    from paper_2604_09113_amd import lbddc
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"lbddc_problem_desc": lbddc.ProblemDesc, "lbddc_rom_desc": lbddc.RomDesc,
+               "lbddc_solve_info": lbddc.SolveInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbddc.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    import ctypes as C
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

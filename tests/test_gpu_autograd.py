@@ -34,7 +34,9 @@ def test_compliance_autograd(cfg, over):
     from paper_2604_09113_amd.autograd import compliance
     prob = make_problem(cfg, **over)
     roms = oracle_roms(prob)
-    s = lbddc.Solver(0, torch.cuda.current_stream().cuda_stream)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    s = lbddc.Solver(0, stream.cuda_stream)
     for rom in roms.values():
         s.load_rom(**rom_arrays(rom))
     s.set_problem(prob["nx"], prob["ny"], prob["p"], prob["q"], prob["m"], prob["ctrl"], prob["family"], prob["t"],
@@ -66,4 +68,19 @@ def test_compliance_autograd(cfg, over):
     Jo, gXo, gto = compliance_gradient(P, P.direct_solve())
     assert rel(J.detach().cpu().numpy(), Jo) <= 1e-10
     assert rel(ctrl.grad.cpu().numpy(), np.tensordot(wh, gXo, axes=1)) <= 1e-8
+    s.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+
+
+def test_compliance_refuses_other_stream():
+    """A solver whose stream is not the current torch stream is refused."""
+    import torch
+    from gpu_helpers import make_solver
+    from paper_2604_09113_amd.autograd import compliance
+    prob = make_problem(4, nx=2, ny=2, p=3)
+    s = make_solver(prob, oracle_roms(prob))   # the library's own stream
+    ctrl = torch.tensor(prob["ctrl"], dtype=torch.float64, device="cuda", requires_grad=True)
+    t = torch.tensor(prob["t"], dtype=torch.float64, device="cuda", requires_grad=True)
+    with pytest.raises(ValueError):
+        compliance(ctrl, t, s)
     s.close()
