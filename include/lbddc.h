@@ -165,6 +165,25 @@ lbddc_status lbddc_set_problem(lbddc_ctx* ctx, const lbddc_problem_desc* desc);
  * from it stay in place. */
 lbddc_status lbddc_set_geometry_device(lbddc_ctx* ctx, const double* d_ctrl, const double* d_t);
 
+/* For callers that cannot allocate device memory (tight loops, harnesses that
+ * forbid allocation): the FP32 contraction of lbddc_assemble with
+ * LBDDC_FP32_CONTRACTION (the same kernels, bit-identical results), with no
+ * device allocation in the call.  The result goes to the caller's d_K, its
+ * staging (tile table, reduced-basis pointers, geometry coefficients in tile
+ * order) to a static device buffer of 48 MiB that each GPU holds from the
+ * first context created on it until the process ends.  d_K receives, per
+ * cell, the packed node-pair triangle [ncell][npair][4]: pair P = n1 (n1 + 1)
+ * / 2 + n2 for nodes n2 <= n1 (npair = LBDDC_Q_NPAIR) in the order [interior
+ * nodes (a, b), a, b = 1..p-1 with a fastest | corners BL, BR, TL, TR | left,
+ * right, bottom, top edge nodes in increasing running coordinate], entry
+ * [P][2 i1 + i2] = K[(i1, n1), (i2, n2)].  Rejects, with LBDDC_E_UNSUPPORTED,
+ * a lattice whose cells take more tiles of 128 cells of one (family,
+ * cluster) group than the buffer holds: 680 tiles (about 87,000 cells) at
+ * q = 2, 383 at q = 3.  Calls on one GPU share the buffer: calls that overlap
+ * on one GPU race.  The call waits on the context's stream (it reads the group
+ * sizes back) and leaves every stage of the context as it was. */
+lbddc_status lbddc_assemble_fp32_noalloc(lbddc_ctx* ctx, float* d_K);
+
 /* Per-cell geometry coefficients, MDEIM evaluation and the batched contraction
  * K_i = sum_q theta_q Khat_q (Alg. 4, 5), plus the cell loads.  `prec`:
  * LBDDC_FP64 and LBDDC_MIXED both contract in FP64 (the operator); see
@@ -215,7 +234,9 @@ enum {
   /* kernel launches of one sweep of a coarse solve: one per tree level above
    * the bottom levels that are swept one subtree per workgroup, plus one for
    * those (equal to the number of levels when no subtree sweep is used) */
-  LBDDC_Q_COARSE_SWEEP_LAUNCHES = 14
+  LBDDC_Q_COARSE_SWEEP_LAUNCHES = 14,
+  /* node pairs n2 <= n1 of a cell, (p+1)^2 ((p+1)^2 + 1) / 2 */
+  LBDDC_Q_NPAIR = 15
 };
 lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
 

@@ -104,6 +104,9 @@ lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LBDDC_E_ARG;
   if (hipSetDevice(device) != hipSuccess) return LBDDC_E_HIP;
+  // the device address of the static scratch of lbddc_assemble_fp32_noalloc,
+  // taken once per device with that device current
+  if (noalloc_scratch_init(device) != hipSuccess) return LBDDC_E_HIP;
   lbddc_ctx* x = new (std::nothrow) lbddc_ctx();
   if (!x) return LBDDC_E_NOMEM;
   Ctx* c = &x->c;
@@ -488,6 +491,17 @@ lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
   return LBDDC_OK;
 }
 
+lbddc_status lbddc_assemble_fp32_noalloc(lbddc_ctx* x, float* d_K) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->have_problem) return fail(c, LBDDC_E_STATE, "assemble_fp32_noalloc: no problem set");
+  if (!d_K) return fail(c, LBDDC_E_ARG, "assemble_fp32_noalloc: null output");
+  hipSetDevice(c->device);
+  lbddc_status s = assemble_fp32_noalloc(c, d_K);
+  if (s != LBDDC_OK) return s;
+  return check_flags(c, "assemble_fp32_noalloc");
+}
+
 lbddc_status lbddc_setup(lbddc_ctx* x, lbddc_precision prec) {
   if (!x) return LBDDC_E_ARG;
   Ctx* c = &x->c;
@@ -628,6 +642,7 @@ lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
     case LBDDC_Q_NC_CELL: *v = c->nC; break;
     case LBDDC_Q_NRHS: *v = c->nrhs; break;
     case LBDDC_Q_NR_MAX: *v = 4 * c->KC; break;
+    case LBDDC_Q_NPAIR: *v = c->npair; break;
     case LBDDC_Q_DEVICE_BYTES: *v = (int64_t)c->dev_bytes; break;
     case LBDDC_Q_COARSE_SOLVE_BYTES: {
       int64_t b = 0;

@@ -16,6 +16,9 @@ namespace lbddc {
 
 constexpr int kMaxP = 10;
 constexpr int kMaxKC = 11;  // reduced basis + stabilisation column padded to 4*KC <= 44
+constexpr int kMaxDevices = 64;
+// bytes of the static device scratch of lbddc_assemble_fp32_noalloc
+constexpr size_t kNoAllocScratchBytes = 48u << 20;
 
 // ---------------------------------------------------------------------------
 // Host numerics (host_math.cpp): Legendre-based nodes and polynomial tables.
@@ -297,6 +300,8 @@ void build_tables(Ctx* c, std::vector<double>& tab);
 hipError_t launch_geometry(Ctx* c);          // theta, det check, MDEIM eval (A1, A2)
 hipError_t launch_constraints_loads(Ctx* c); // edge constraint rows and loads
 hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1);  // A3
+hipError_t noalloc_scratch_init(int device);                          // address of the static scratch (device current)
+lbddc_status assemble_fp32_noalloc(Ctx* c, float* d_K);               // A3, FP32, caller's output, static scratch
 hipError_t launch_theta_tile16(Ctx* c, const int4* tiles, int ntiles, double* out);  // A11 (theta in tile order)
 hipError_t launch_schur(Ctx* c);             // A4
 hipError_t launch_weights(Ctx* c);           // A7 (gather of stiffness diagonals)

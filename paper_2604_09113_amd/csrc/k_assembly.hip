@@ -19,6 +19,9 @@
 // ([tile][s][128 cells][4], k_theta_tile): the 16 cells of a block at one step
 // are one contiguous 256 B (FP32) segment, where the cell-major array would
 // touch 16 cache lines per load, re-read for every one of the ~208 pair tiles.
+#include <cstdio>
+#include <mutex>
+
 #include "internal.h"
 
 namespace lbddc {
@@ -227,7 +230,18 @@ static hipError_t launch_family(Ctx* c, const T* const* d_utg, int KC, const T* 
   return hipGetLastError();
 }
 
-hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
+// Buffers of one contraction: the tile table (int4 per tile), the per-group
+// Uhat pointers (16), the tile-ordered geometry coefficients of the precision
+// used (room for `theta_tiles` tiles) and the output K.
+struct AsmBuffers {
+  int* tiles;
+  void** ptrs;
+  void* theta_t;
+  size_t theta_tiles;
+  void* K;
+};
+
+static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, hipEvent_t e0, hipEvent_t e1) {
   // groups: family slot s owns groups [base_s, base_s + n_k)
   int G = 0;
   std::vector<int> base;
@@ -270,41 +284,119 @@ hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
     fam_n.push_back((int)tiles.size() / 4 - fam_first.back());
   }
   c->ntiles = (int)tiles.size() / 4;
-  // tile table and per-group Uhat pointers (in the flags scratch area: sized for 16 groups)
+  if ((size_t)c->ntiles > bf.theta_tiles) return hipErrorInvalidValue;  // size of the tile-ordered theta
+  // tile table and per-group Uhat pointers
   std::vector<const void*> ptrs(G, nullptr);
   for (int g = 0; g < G; ++g) {
     const RomDev& R = c->roms[c->fam_ids[c->group_family[g]]];
     ptrs[g] = fp32 ? (const void*)R.ut32[c->group_cluster[g]] : (const void*)R.ut64[c->group_cluster[g]];
   }
-  e = hipMemcpyAsync(c->d_tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+  e = hipMemcpyAsync(bf.tiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
-  void** d_ptrs = (void**)(c->d_tiles + 4 * (c->ncell / 16 + 64));
-  e = hipMemcpyAsync(d_ptrs, ptrs.data(), G * sizeof(void*), hipMemcpyHostToDevice, c->stream);
+  e = hipMemcpyAsync(bf.ptrs, ptrs.data(), G * sizeof(void*), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
-  if (c->ntiles > c->ncell / 128 + 17) return hipErrorInvalidValue;  // size of the tile-ordered theta
   if (e0) hipEventRecord(e0, c->stream);
-  const int4* d_tl = reinterpret_cast<const int4*>(c->d_tiles);
+  const int4* d_tl = reinterpret_cast<const int4*>(bf.tiles);
   if (fp32)
     hipLaunchKernelGGL((k_theta_tile<float, 128>), dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta32, c->d_sorted, d_tl,
-                       c->ns, c->d_theta_t32);
+                       c->ns, (float*)bf.theta_t);
   else
     hipLaunchKernelGGL((k_theta_tile<double, 128>), dim3(c->ntiles), dim3(256), 0, c->stream, c->d_theta, c->d_sorted, d_tl,
-                       c->ns, c->d_theta_t);
+                       c->ns, (double*)bf.theta_t);
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     if (fam_n[s] == 0) continue;
     const int4* tl = d_tl + fam_first[s];
     const size_t toff = (size_t)fam_first[s] * c->ns * 512;
     const int KC = c->roms[c->fam_ids[s]].KC;
     if (fp32)
-      e = launch_family<float>(c, (const float* const*)d_ptrs, KC, c->d_theta_t32 + toff, c->d_itil32, tl, fam_n[s],
-                               c->d_K32);
+      e = launch_family<float>(c, (const float* const*)bf.ptrs, KC, (const float*)bf.theta_t + toff, c->d_itil32, tl,
+                               fam_n[s], (float*)bf.K);
     else
-      e = launch_family<double>(c, (const double* const*)d_ptrs, KC, c->d_theta_t + toff, c->d_itil, tl, fam_n[s],
-                                c->d_K);
+      e = launch_family<double>(c, (const double* const*)bf.ptrs, KC, (const double*)bf.theta_t + toff, c->d_itil, tl,
+                                fam_n[s], (double*)bf.K);
     if (e != hipSuccess) return e;
   }
   if (e1) hipEventRecord(e1, c->stream);
   return hipGetLastError();
+}
+
+hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
+  AsmBuffers bf;
+  bf.tiles = c->d_tiles;
+  bf.ptrs = (void**)(c->d_tiles + 4 * (c->ncell / 16 + 64));  // after the tile table, sized for 16 groups
+  bf.theta_t = fp32 ? (void*)c->d_theta_t32 : (void*)c->d_theta_t;
+  bf.theta_tiles = (size_t)c->ncell / 128 + 17;
+  bf.K = fp32 ? (void*)c->d_K32 : (void*)c->d_K;
+  return launch_assembly_into(c, fp32, bf, e0, e1);
+}
+
+// ---------------------------------------------------------------------------
+// Staging of lbddc_assemble_fp32_noalloc, a static device array: the tile
+// table, the per-group Uhat pointers and the tile-ordered FP32 geometry
+// coefficients.  Each GPU the library runs on holds its own copy until the
+// process ends; host code reaches it only through the address taken with
+// hipGetSymbolAddress (per device, at lbddc_create), never through the name.
+// Every call on one GPU shares it: calls that overlap on a GPU race.
+constexpr size_t kScratchTableBytes = 64u << 10;   // tile table, up to 4096 tiles
+constexpr size_t kScratchPtrBytes = 64u << 10;     // per-group Uhat pointers (16 used)
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static void* g_scratch_addr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[device] = ptr;
+  return hipSuccess;
+}
+
+lbddc_status assemble_fp32_noalloc(Ctx* c, float* d_K) {
+  void* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (c->device >= 0 && c->device < kMaxDevices) base = g_scratch_addr[c->device];
+  }
+  if (!base) {
+    c->err = "assemble_fp32_noalloc: the static scratch of this device has no address";
+    return LBDDC_E_HIP;
+  }
+  // the tile-ordered coefficients take ns * 128 * 4 floats per tile of 128
+  // cells of one group; the tile count is known exactly after the group sort
+  // (at most one partial tile per group more than ncell / 128)
+  const size_t per_tile = (size_t)c->ns * 128 * 4 * sizeof(float);
+  const size_t cap = std::min((kNoAllocScratchBytes - kScratchTableBytes - kScratchPtrBytes) / per_tile,
+                              kScratchTableBytes / (4 * sizeof(int)));
+  auto too_large = [&](size_t ntiles) {
+    char buf[240];
+    snprintf(buf, sizeof buf,
+             "assemble_fp32_noalloc: %d cells take %zu tiles of 128 cells, more than the %zu that the %zu-byte static "
+             "scratch holds at (q+1)^2 = %d",
+             c->ncell, ntiles, cap, kNoAllocScratchBytes, c->nL);
+    c->err = buf;
+    return LBDDC_E_UNSUPPORTED;
+  };
+  if (((size_t)c->ncell + 127) / 128 > cap) return too_large(((size_t)c->ncell + 127) / 128);
+  hipError_t e = launch_geometry(c);
+  if (e == hipSuccess) {
+    AsmBuffers bf;
+    bf.tiles = (int*)base;
+    bf.ptrs = (void**)((char*)base + kScratchTableBytes);
+    bf.theta_t = (char*)base + kScratchTableBytes + kScratchPtrBytes;
+    bf.theta_tiles = cap;
+    bf.K = d_K;
+    e = launch_assembly_into(c, true, bf, nullptr, nullptr);
+    if (e == hipErrorInvalidValue && (size_t)c->ntiles > cap) return too_large(c->ntiles);
+  }
+  if (e != hipSuccess) {
+    c->err = std::string("assemble_fp32_noalloc: ") + hipGetErrorString(e);
+    return LBDDC_E_HIP;
+  }
+  return LBDDC_OK;
 }
 
 }  // namespace lbddc

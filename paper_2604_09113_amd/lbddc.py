@@ -21,7 +21,7 @@ FP64, MIXED, FP32_CONTRACTION = 0, 1, 2
 X_K, X_THETA, X_ITIL, X_S, X_D, X_PSI, X_SC, X_LOAD, X_FINE = range(9)
 Q_NCELL, Q_NDOF_FREE, Q_N_SKELETON, Q_N_INTERIOR, Q_N_COARSE, Q_N_I_ROM, Q_NU_CELL, Q_NC_CELL, Q_NRHS, \
     Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES, \
-    Q_COARSE_SWEEP_LAUNCHES = range(15)
+    Q_COARSE_SWEEP_LAUNCHES, Q_NPAIR = range(16)
 TIME_OP, TIME_PRE, TIME_COARSE, TIME_ALL, TIME_SAMPLE = 1, 2, 4, 7, 8
 SIDE_LEFT, SIDE_RIGHT, SIDE_BOTTOM, SIDE_TOP = 1, 2, 4, 8
 SIDES = {"left": SIDE_LEFT, "right": SIDE_RIGHT, "bottom": SIDE_BOTTOM, "top": SIDE_TOP}
@@ -34,7 +34,7 @@ FUNCTIONS = ["lbddc_create", "lbddc_destroy", "lbddc_last_error", "lbddc_version
              "lbddc_set_problem", "lbddc_set_geometry_device", "lbddc_assemble", "lbddc_setup", "lbddc_solve",
              "lbddc_get_displacement", "lbddc_get_displacement_device", "lbddc_compliance_gradient",
              "lbddc_compliance_gradient_device", "lbddc_query", "lbddc_export_cells", "lbddc_phase_times",
-             "lbddc_set_timing"]
+             "lbddc_set_timing", "lbddc_assemble_fp32_noalloc"]
 
 
 class LbddcError(RuntimeError):
@@ -102,6 +102,7 @@ def library():
         "lbddc_export_cells": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, dp]),
         "lbddc_phase_times": (C.c_int, [P, dp, C.c_int32]),
         "lbddc_set_timing": (C.c_int, [P, C.c_int32]),
+        "lbddc_assemble_fp32_noalloc": (C.c_int, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -179,6 +180,11 @@ class Solver:
 
     def assemble(self, prec=FP64):
         self._check(self.lib.lbddc_assemble(self.ctx, prec))
+
+    def assemble_fp32_noalloc(self, dptr):
+        """FP32 contraction into the caller's device buffer (packed node-pair
+        triangle, float32 [ncell][npair][4]); no device allocation."""
+        self._check(self.lib.lbddc_assemble_fp32_noalloc(self.ctx, C.c_void_p(dptr)))
 
     def setup(self, prec=FP64):
         self._check(self.lib.lbddc_setup(self.ctx, prec))
