@@ -252,6 +252,10 @@ lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
  *   SC     [nC][nC] local coarse matrix Psi^T S Psi
  *   LOAD   [nrhs][nU] cell load on the skeleton slots
  *   FINE   [nU][nU] the fine-correction operator D [S C^T; C 0]^-1|_u D
+ *   RU     [nU] the global skeleton dof of each skeleton slot (-1: Dirichlet)
+ *   RC     [nC] the global coarse dof of each coarse slot (-1: inactive); the
+ *          coarse dofs are numbered in the elimination order of the coarse
+ *          factorization (RU and RC are integers stored as doubles)
  * Skeleton slots (nU = 8p): nodes [BL, BR, TL, TR, left edge, right edge, bottom
  * edge, top edge] (edge nodes in increasing running coordinate, excluding
  * corners), slot = 2*node + component.  Coarse slots (nC = 20 with moments, 16
@@ -261,9 +265,16 @@ lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
  * their D, PSI, SC and FINE entries are zero. */
 enum {
   LBDDC_X_K = 0, LBDDC_X_THETA = 1, LBDDC_X_ITIL = 2, LBDDC_X_S = 3, LBDDC_X_D = 4,
-  LBDDC_X_PSI = 5, LBDDC_X_SC = 6, LBDDC_X_LOAD = 7, LBDDC_X_FINE = 8
+  LBDDC_X_PSI = 5, LBDDC_X_SC = 6, LBDDC_X_LOAD = 7, LBDDC_X_FINE = 8, LBDDC_X_RU = 9, LBDDC_X_RC = 10
 };
 lbddc_status lbddc_export_cells(lbddc_ctx* ctx, int32_t which, int32_t first, int32_t count, double* out);
+
+/* The exact coarse solve S_C g = z of the preconditioner (Sec. 3.3.4; the
+ * factorization that lbddc_setup computes), applied to a host vector of
+ * LBDDC_Q_N_COARSE entries in the numbering of LBDDC_X_RC: for testing the
+ * factorization against S_C = sum_i R_C^(i)T (Psi^T S Psi)^(i) R_C^(i)
+ * assembled from the exports.  Requires a completed setup. */
+lbddc_status lbddc_coarse_solve(lbddc_ctx* ctx, const double* z, double* g);
 
 /* Device time in milliseconds of the most recent launches of each phase, timed
  * with HIP events on the context stream:

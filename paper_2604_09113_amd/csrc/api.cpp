@@ -502,6 +502,20 @@ lbddc_status lbddc_assemble_fp32_noalloc(lbddc_ctx* x, float* d_K) {
   return check_flags(c, "assemble_fp32_noalloc");
 }
 
+lbddc_status lbddc_coarse_solve(lbddc_ctx* x, const double* z, double* g) {
+  if (!x) return LBDDC_E_ARG;
+  Ctx* c = &x->c;
+  if (!c->setup_done) return fail(c, LBDDC_E_STATE, "coarse_solve: setup first");
+  if (!z || !g) return fail(c, LBDDC_E_ARG, "coarse_solve: null vector");
+  hipSetDevice(c->device);
+  const size_t n = (size_t)c->NC * 8;
+  HIPCHK(hipMemcpyAsync(c->d_zc, z, n, hipMemcpyHostToDevice, c->stream), "coarse_solve");
+  HIPCHK(launch_coarse_solve(c, c->d_zc, c->d_xc), "coarse_solve");
+  HIPCHK(hipMemcpyAsync(g, c->d_xc, n, hipMemcpyDeviceToHost, c->stream), "coarse_solve");
+  HIPCHK(hipStreamSynchronize(c->stream), "coarse_solve");
+  return LBDDC_OK;
+}
+
 lbddc_status lbddc_setup(lbddc_ctx* x, lbddc_precision prec) {
   if (!x) return LBDDC_E_ARG;
   Ctx* c = &x->c;
@@ -795,6 +809,13 @@ lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int3
             o[(size_t)(8 + j) * nU + 8 + i] = v;
           }
       }
+      break;
+    }
+    case LBDDC_X_RU:
+    case LBDDC_X_RC: {
+      const std::vector<int>& R = which == LBDDC_X_RU ? c->RU : c->RC;
+      const int w = which == LBDDC_X_RU ? nU : nC;
+      for (size_t i = 0; i < (size_t)count * w; ++i) out[i] = (double)R[(size_t)first * w + i];
       break;
     }
     default:

@@ -129,3 +129,34 @@ def fp32_contraction_bound(prob, roms, cell_X, c, depth):
     Kabs = contract(Iabs, np.abs(C))
     gamma = (depth + 4 * nL + 3) * 2.0 ** -24
     return gamma, Kabs
+
+
+def assembled_coarse_matrix(s, ncell):
+    """S_C = sum_i R_C^(i)T (Psi^T S Psi)^(i) R_C^(i) assembled with
+    scipy.sparse from the library's per-cell exports (SC and RC): an
+    assembly independent of the library's nested-dissection fronts."""
+    import scipy.sparse as sp
+    from paper_2604_09113_amd import lbddc
+    SC = s.export(lbddc.X_SC, 0, ncell)
+    RC = s.export(lbddc.X_RC, 0, ncell).astype(np.int64)
+    N = s.query(lbddc.Q_N_COARSE)
+    nC = RC.shape[1]
+    rows = np.repeat(RC[:, :, None], nC, axis=2)
+    cols = np.repeat(RC[:, None, :], nC, axis=1)
+    keep = (rows >= 0) & (cols >= 0)
+    return sp.csr_matrix((SC[keep], (rows[keep], cols[keep])), shape=(N, N))
+
+
+def coarse_solve_errors(s, A, nz=3, seed=5):
+    """Backward error max ||A g - z||_inf / (||A||_inf ||g||_inf + ||z||_inf)
+    of the library's coarse solve for random z, and the g it returned."""
+    rng = np.random.default_rng(seed)
+    anorm = abs(A).sum(axis=1).max()
+    worst, out = 0.0, []
+    for _ in range(nz):
+        z = rng.normal(size=A.shape[0])
+        g = s.coarse_solve(z)
+        r = A @ g - z
+        worst = max(worst, np.abs(r).max() / (anorm * np.abs(g).max() + np.abs(z).max()))
+        out.append((z, g))
+    return worst, out

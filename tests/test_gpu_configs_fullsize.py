@@ -20,7 +20,8 @@ that hold at any size.
   - 256 x 256, p = 8, order-3 warped maps, 8 random load cases (mixed
     precision with adjoint): every load case converged, mixed against FP64
     displacements (1e-8) and gradients, J_r = f_r^T u_r with the oracle's
-    traction, sampled cells against the oracle."""
+    traction, sampled cells against the oracle, and the backward error of
+    the coarse solve against S_C assembled with scipy.sparse."""
 import numpy as np
 import pytest
 
@@ -155,6 +156,13 @@ def test_cfg5_256x256_p8_eight_loads_mixed_and_adjoint():
         Jo = compliance_fTu(prob, u64[r], r)
         assert abs(J64[r] - Jo) <= 1e-11 * abs(Jo), (r, J64[r], Jo)
     s.setup(lbddc.MIXED)
+    # the 256^2 coarse tree: backward error of the GPU coarse solve against
+    # S_C assembled with scipy.sparse from the per-cell exports
+    from gpu_helpers import assembled_coarse_matrix, coarse_solve_errors
+    bw, _ = coarse_solve_errors(s, assembled_coarse_matrix(s, prob["nx"] * prob["ny"]))
+    print(f"[cfg5] coarse solve, N_C = {s.query(lbddc.Q_N_COARSE)}, {s.query(lbddc.Q_COARSE_LEVELS)} levels: "
+          f"backward error {bw:.2e}")
+    assert bw <= 1e-15
     infom = s.solve(rtol=rtol, max_iter=5000)
     Jm, gXm, gtm = s.compliance_gradient()
     worst_u = 0.0

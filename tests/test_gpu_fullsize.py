@@ -129,3 +129,28 @@ def test_fullsize_compliance_is_load_times_displacement(full):
             Jo += fe[n] @ u[p * iy + b, p * (nx - 1) + a]
     print(f"[fullsize] J {J[0]:.12e} f^T u {Jo:.12e}")
     assert abs(J[0] - Jo) <= 1e-12 * abs(Jo)
+
+
+def test_fullsize_coarse_factorization_against_scipy(full):
+    """The production coarse tree (13 levels at 128^2: the 16-chunk
+    extend-add, the blocked fronts of several hundred dofs, every sweep
+    kernel) against S_C assembled with scipy.sparse from the per-cell
+    exports: backward error of the GPU coarse solve for random right-hand
+    sides, and the solution against scipy's sparse LU.  Both are backward
+    stable, so they differ by at most ~kappa(S_C) eps (kappa ~ 6e6 at this
+    size by the paper's statistics of a lattice of the same size)."""
+    import scipy.sparse.linalg as spla
+    from gpu_helpers import assembled_coarse_matrix, coarse_solve_errors
+    from paper_2604_09113_amd import lbddc
+    prob, roms, s, _ = full
+    n = prob["nx"] * prob["ny"]
+    for prec in (lbddc.MIXED, lbddc.FP64):
+        s.setup(prec)
+        A = assembled_coarse_matrix(s, n)
+        bw, pairs = coarse_solve_errors(s, A)
+        lu = spla.splu(A.tocsc())
+        fw = max(np.linalg.norm(g - lu.solve(z)) / np.linalg.norm(g) for z, g in pairs)
+        print(f"\n[fullsize] coarse solve ({'mixed' if prec else 'fp64'} setup, N_C = {A.shape[0]}, "
+              f"{s.query(lbddc.Q_COARSE_LEVELS)} levels): backward error {bw:.2e}, vs scipy LU {fw:.2e}")
+        assert bw <= 1e-15 and fw <= 1e-9
+    s.setup(lbddc.MIXED)
