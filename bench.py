@@ -103,6 +103,66 @@ def measured_traffic(kernel):
     return None
 
 
+def measured_peaks():
+    """Peaks measured on this GPU beside the datasheet ones: a device-to-device
+    copy of 2 GiB (bytes read + written per second) and library FP64 / FP32
+    GEMMs of 8192^3 (torch.matmul), each the best of 5 event-timed runs."""
+    import torch
+    out = {}
+    n = (2 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = 1e30
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    out["copy_GBs"] = 2 * n * 8 / (best * 1e-3) / 1e9
+    del src, dst
+    for dt, key in ((torch.float64, "gemm_fp64_TFs"), (torch.float32, "gemm_fp32_TFs")):
+        m = 8192
+        A = torch.randn(m, m, dtype=dt, device="cuda")
+        B = torch.randn(m, m, dtype=dt, device="cuda")
+        best = 1e30
+        for _ in range(6):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            C = A @ B
+            b.record()
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        out[key] = 2.0 * m ** 3 / (best * 1e-3) / 1e12
+        del A, B, C
+    torch.cuda.synchronize()
+    out["note"] = ("copy: torch device copy of 2 GiB; GEMM: torch.matmul (rocBLAS/hipBLASLt) 8192^3; best of 5 after "
+                   "one warm-up; datasheet: HBM 8000 GB/s, FP64 78.6, FP32 157.3 TFLOP/s")
+    return out
+
+
+def host_cpu():
+    """CPU model and core counts of the host (lscpu)."""
+    info = {}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        kv = {l.split(":", 1)[0].strip(): l.split(":", 1)[1].strip() for l in txt.splitlines() if ":" in l}
+        info["cpu_model"] = kv.get("Model name")
+        cps, sockets = kv.get("Core(s) per socket"), kv.get("Socket(s)")
+        if cps and sockets and cps.isdigit() and sockets.isdigit():
+            info["physical_cores"] = int(cps) * int(sockets)
+        info["logical_cpus"] = int(kv.get("CPU(s)", "0")) if kv.get("CPU(s)", "").isdigit() else os.cpu_count()
+    except Exception:
+        info["logical_cpus"] = os.cpu_count()
+    try:
+        info["cpus_available_to_process"] = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    return info
+
+
 def cpu_baseline(prob_full, roms, solver):
     """The CPU oracle on a bounded sample of the same workload: the 12 x 12
     sub-lattice drawn with the same recipe (the oracle's online phase: ROM
@@ -126,6 +186,24 @@ def cpu_baseline(prob_full, roms, solver):
                          nodes=r["lo"] + k * w + w * gll_nodes(r["r"])) for k in range(nk)]
         oroms[f] = dict(family=f, p=r["p"], q=r["q"], lo=r["lo"], hi=r["hi"], n_k=nk, n_r=r["n_r"], r=r["r"],
                         I_pi=r["I_pi"], clusters=clusters)
+    # single-thread per-cell ROM assembly (the paper's per-cell ROM timing
+    # of Table 2 is the context: 2.3-2.5 ms on one core of its laptop)
+    Cm = material_tensor(prob_full["E"], prob_full["nu"])
+    from oracle.geometry import cell_control_points
+    from contextlib import nullcontext
+    try:
+        from threadpoolctl import threadpool_limits
+        one_thread = threadpool_limits(limits=1)
+    except Exception:
+        one_thread = nullcontext()
+    sample = list(range(0, prob_full["nx"] * prob_full["ny"], 331))[:40]
+    with one_thread:
+        t1 = time.perf_counter()
+        for c in sample:
+            ix, iy = c % prob_full["nx"], c // prob_full["nx"]
+            X = cell_control_points(prob_full["ctrl"], prob_full["m"], ix, iy)
+            rom_K(X, oroms[int(prob_full["family"][c])], float(prob_full["t"][c]), prob_full["rho"], Cm)
+        per_cell_ms = (time.perf_counter() - t1) / len(sample) * 1e3
     sub = make_problem(3, nx=12, ny=12)
     t0 = time.perf_counter()
     P = Problem(sub, oroms)
@@ -136,8 +214,6 @@ def cpu_baseline(prob_full, roms, solver):
     # sampled K_i parity of the full-size GPU run against the oracle
     cells = [0, 1, prob_full["nx"] - 1, 777, 8191, 16383]
     Kg = np.stack([solver.export(lbddc.X_K, c, 1)[0] for c in cells])
-    Cm = material_tensor(prob_full["E"], prob_full["nu"])
-    from oracle.geometry import cell_control_points
     errs = []
     for i, c in enumerate(cells):
         ix, iy = c % prob_full["nx"], c // prob_full["nx"]
@@ -147,6 +223,10 @@ def cpu_baseline(prob_full, roms, solver):
     return dict(value=ncell / dt, unit="cells/s", cores=int(cores), kind="oracle",
                 sample=f"12x12-cell sub-lattice of the same workload (144 cells): oracle ROM assembly, Schur, "
                        f"BDDC setup, PCG rtol 1e-8 ({its[0]} iterations), recovery in {dt:.1f}s",
+                host=host_cpu(),
+                single_thread_rom_assembly_ms_per_cell=per_cell_ms,
+                single_thread_sample=f"oracle ROM stiffness (MDEIM + contraction) of {len(sample)} cells of the "
+                                     f"full lattice, one BLAS thread",
                 sampled_Ki_rel_frobenius_vs_gpu_fp64=max(errs))
 
 
@@ -229,6 +309,10 @@ def main():
         return rtol, inf[0]["iters"], err
 
     cal = {lbddc.FP64: calibrate(lbddc.FP64), lbddc.MIXED: calibrate(lbddc.MIXED)}
+    s.setup(lbddc.FP64)
+    fp64_iters8 = s.solve(rtol=1e-8, max_iter=3000)[0]["iters"]
+    s.setup(lbddc.MIXED)
+    mixed_iters8 = s.solve(rtol=1e-8, max_iter=3000)[0]["iters"]
 
     def step(prec):
         s.assemble(lbddc.FP64)
@@ -370,7 +454,22 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         out["cpu_baseline"] = cpu_baseline(prob, roms, s)
+    # context, untimed: the same lattice with circle cells only (the paper's
+    # lattices keep one topology per lattice), iterations at rtol 1e-8
+    if 0 in roms:
+        circ = make_problem(args.config, topo="circle")
+        s.set_problem(circ["nx"], circ["ny"], circ["p"], circ["q"], circ["m"], circ["ctrl"], circ["family"],
+                      circ["t"], circ["E"], circ["nu"], circ["rho"], circ["moments"], circ["traction"])
+        s.assemble(lbddc.FP64)
+        s.setup(lbddc.FP64)
+        it_c = s.solve(rtol=1e-8, max_iter=3000)[0]["iters"]
+        s.setup(lbddc.MIXED)
+        it_cm = s.solve(rtol=1e-8, max_iter=3000)[0]["iters"]
+        out["iterations_rtol_1e8"] = {"mixed_topology": {"fp64": fp64_iters8, "mixed": mixed_iters8},
+                                      "circle_only": {"fp64": it_c, "mixed": it_cm}}
     s.close()
+    log("[bench] measured peaks")
+    out["measured_peaks"] = measured_peaks()
     print(json.dumps(out))
 
 
