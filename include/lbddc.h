@@ -136,7 +136,8 @@ lbddc_status lbddc_load_rom(lbddc_ctx* ctx, const lbddc_rom_desc* rom);
  * value, not clamped).  traction[(r*n_side + k)*2 + c]: component c of load
  * case r on the loaded edge of the k-th cell along the loaded side, k = iy on
  * the left and right sides (n_side = ny), k = ix on the bottom and top sides
- * (n_side = nx).  Limits: 2 <= p <= 8, q in {1, 2, 3}, 1 <= map_order <= 4,
+ * (n_side = nx).  Limits: 2 <= p <= 8 (p >= 3 with edge moments: an edge of
+ * a p = 2 cell has 2 interior dofs for 3 constraints), q in {1, 2, 3}, 1 <= map_order <= 4,
  * 1 <= nrhs <= 16, nx, ny >= 1.  Validates det J > 0 at the interpolation
  * points and on a (2m+2)^2 Gauss sample of every cell (LBDDC_E_DEGENERATE_MAP),
  * that every family has a ROM of degrees (p, q) (LBDDC_E_ROM) and that every t

@@ -319,6 +319,7 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
             dalloc_t(c, &c->d_coarse, (size_t)c->co.nd_front_total) &&
             dalloc_t(c, &c->d_up, (size_t)c->co.nd_up_total + 1) && dalloc_t(c, &c->d_beff, (size_t)c->co.nd_beff_total + 1) &&
             dalloc_t(c, &c->d_gjC, (size_t)c->co.nd_cp_total + 1) &&
+            dalloc_t(c, &c->d_f_blk, (size_t)c->co.f_blk_total + 2) &&
             dalloc_t(c, &c->d_f, (size_t)c->nrhs * NU) && dalloc_t(c, &c->d_x, (size_t)c->nrhs * NU) &&
             dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
             dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
@@ -377,6 +378,9 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
   if (d->constraints != (LBDDC_CON_CORNERS | LBDDC_CON_EDGE_AVG) &&
       d->constraints != (LBDDC_CON_CORNERS | LBDDC_CON_EDGE_AVG | LBDDC_CON_EDGE_MOMENT))
     return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: constraint sets CORNERS|EDGE_AVG and CORNERS|EDGE_AVG|EDGE_MOMENT are supported");
+  if (d->p < 3 && (d->constraints & LBDDC_CON_EDGE_MOMENT))
+    return fail(c, LBDDC_E_UNSUPPORTED,
+                "set_problem: edge moments need p >= 3 (at p = 2 an edge has 2 interior dofs for 3 edge constraints)");
   if (d->clamped_sides == 0 || (d->clamped_sides & ~15u))
     return fail(c, LBDDC_E_ARG, "set_problem: clamped_sides must be a nonempty set of LBDDC_SIDE_* bits");
   if (d->loaded_side != LBDDC_SIDE_LEFT && d->loaded_side != LBDDC_SIDE_RIGHT && d->loaded_side != LBDDC_SIDE_BOTTOM &&
@@ -674,7 +678,7 @@ lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
     case LBDDC_Q_COARSE_SWEEP_LAUNCHES: {
       // levels above the subtree levels one launch each, the subtrees one
       const int L = (int)c->co.nd_levels.size();
-      *v = c->co.sub_level < L ? c->co.sub_level + 1 : L;
+      *v = c->co.fused ? c->co.fused_level + 1 : c->co.sub_level < L ? c->co.sub_level + 1 : L;
       break;
     }
     default: return LBDDC_E_ARG;

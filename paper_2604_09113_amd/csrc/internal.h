@@ -108,6 +108,43 @@ constexpr int ND_SUB_LEVELS = 3;
 constexpr int ND_SUB_MIN_ROOTS = 256;
 constexpr int ND_SUB_MAX_NF = 256;
 
+// The forward sweep of the bottom ND_FUSED_LEVELS levels of the tree can be
+// one launch in which a workgroup takes a whole subtree: its factor rows,
+// index program and vector entries are all requested at the start and staged
+// in LDS, and the levels follow one another with workgroup barriers only.
+constexpr int ND_FUSED_LEVELS = 4;
+constexpr int ND_FUSED_THREADS = 512;
+constexpr int ND_FUSED_LDS_DOUBLES = 19456;   // 152 KiB of LDS per workgroup
+constexpr int ND_FUSED_LOADS = 20;            // 16-byte block loads per thread (block <= 2 * 20 * 512 doubles)
+constexpr int ND_FUSED_ENT = 4;               // vector entries per thread (<= 4 * 512 per subtree)
+constexpr int ND_FUSED_MIN_ROOTS = 64;
+
+// One subtree of the fused sweeps.  Depth d = 0 is the subtree root.
+struct FusedSub {
+  long long fwd_off;           // its packed M^T block in the fused block buffer (doubles, even)
+  int fwd_n;                   // block size (doubles, even)
+  int own_off, own_n;          // its own coarse dofs: one contiguous range (tree order)
+  int vec_n;                   // doubles of the per-node vector area in LDS
+  int node0;                   // first of its nodes in the fused node table
+  int stage_node[ND_FUSED_LEVELS + 1];  // node ranges by depth (relative to node0)
+  int went[ND_FUSED_LEVELS + 1];        // vector entries by depth (absolute)
+  int stage_pairs[ND_FUSED_LEVELS];     // (node, boundary column) pairs by depth
+};
+// A node of a fused subtree; offsets in doubles: mt in the subtree's block,
+// w and up in its LDS vector area, own in its own range; gup = the root's
+// global up offset (-1 below the root); pair0 = the node's first (node,
+// column) pair among those of its depth.  At most ND_FUSED_STAGE_NODES nodes
+// per depth.
+constexpr int ND_FUSED_STAGE_NODES = 8;
+struct FusedNode {
+  int ns, nb, nf, mt, w, up, own, gup, pair0, pad;
+};
+// Copy program of the fused blocks, per node: the M^T part of its top ns rows.
+struct FusedPack {
+  long long foff, fdst;
+  int ns, nb;
+};
+
 struct CoarseLayout {
   // first coarse id of each grid vertex [(ny+1)(nx+1)], horizontal edge [(ny+1) nx]
   // (edge ex of line vy) and vertical edge [ny (nx+1)] (edge between lines ey and
@@ -142,6 +179,14 @@ struct CoarseLayout {
   int sub_fw_rows = 0, sub_child_kparts = 0, sub_nfmax = 0;
   std::vector<NDItem> sub_fw_items, sub_bw_items;
   std::vector<int> sub_fw_off, sub_bw_off;
+  // fused bottom-level sweeps (used when `fused`, levels [fused_level, L))
+  bool fused = false;
+  int fused_level = 0;
+  std::vector<FusedSub> f_subs;
+  std::vector<FusedNode> f_nodes;
+  std::vector<short4> f_went;   // {W index, child-0 up index, child-1 up index, own index} (-1: none)
+  std::vector<FusedPack> f_pack;
+  long long f_blk_total = 0;
 };
 
 
@@ -203,6 +248,11 @@ struct Ctx {
   int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr, *d_nd_pull = nullptr;
   NDItem *d_fw_items = nullptr, *d_bw_items = nullptr;
   NDItem *d_sub_fw_items = nullptr, *d_sub_bw_items = nullptr;
+  FusedSub* d_f_subs = nullptr;
+  FusedNode* d_f_nodes = nullptr;
+  short4* d_f_went = nullptr;
+  FusedPack* d_f_pack = nullptr;
+  double* d_f_blk = nullptr;    // packed factor rows of the fused subtrees
   int *d_sub_fw_off = nullptr, *d_sub_bw_off = nullptr;
   int* d_lvl_nodes = nullptr;
   int* d_flags = nullptr;      // device error flags [8]
@@ -293,6 +343,7 @@ template <class T> bool dalloc_t(Ctx* c, T** p, size_t n) { return dalloc(c, (vo
 // topology (topology.cpp)
 bool build_topology(Ctx* c);
 bool build_nested_dissection(Ctx* c, const std::vector<int>& ent_g1, const std::vector<int>& ent_g2);
+void build_fused_sweeps(Ctx* c);
 void build_tables(Ctx* c, std::vector<double>& tab);
 
 // ---------------------------------------------------------------------------
@@ -307,7 +358,8 @@ hipError_t launch_schur(Ctx* c);             // A4
 hipError_t launch_weights(Ctx* c);           // A7 (gather of stiffness diagonals)
 hipError_t launch_precond(Ctx* c, bool fp32); // A5, A6, A7
 hipError_t launch_coarse_assemble(Ctx* c);   // A8 assembly of S_C blocks
-hipError_t launch_coarse_factor(Ctx* c);     // A8 nested-dissection FP64 factorization
+hipError_t prepare_fused_sweeps(Ctx* c);     // LDS limit of the fused bottom-level sweeps
+hipError_t launch_coarse_factor(Ctx* c);     // A8 nested-dissection FP64 factorization (and the fused blocks)
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid = nullptr);  // A8 solve
 hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32,
                      double* t_op, double* t_pre, double* t_coarse, double* t_cfwd, double* t_cbwd,

@@ -544,6 +544,18 @@ hipError_t launch_coarse_assemble(Ctx* c) {
   return hipGetLastError();
 }
 
+// Copy the M^T rows of the fronts of the fused subtrees into their packed
+// forward blocks (once per factorization).  One workgroup per node.
+__global__ __launch_bounds__(256) void k_fused_pack(const FusedPack* __restrict__ pk, const double* __restrict__ F,
+                                                    double* __restrict__ blk) {
+  const FusedPack q = pk[blockIdx.x];
+  const int nf = q.ns + q.nb, n = q.ns * q.nb;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int k = i / q.nb, r = i - k * q.nb;
+    blk[q.fdst + i] = F[q.foff + (long long)k * nf + q.ns + r];
+  }
+}
+
 hipError_t launch_coarse_factor(Ctx* c) {
   const CoarseLayout& co = c->co;
   for (int l = (int)co.nd_levels.size() - 1; l >= 0; --l) {
@@ -592,6 +604,13 @@ hipError_t launch_coarse_factor(Ctx* c) {
                            k0, c->d_gjC);
     }
   }
+  if (co.fused) {
+    const hipError_t e = prepare_fused_sweeps(c);
+    if (e != hipSuccess) return e;
+  }
+  if (co.fused && !co.f_pack.empty())
+    hipLaunchKernelGGL(k_fused_pack, dim3((unsigned)co.f_pack.size()), dim3(256), 0, c->stream, c->d_f_pack,
+                       c->d_coarse, c->d_f_blk);
   return hipGetLastError();
 }
 
@@ -973,6 +992,147 @@ __global__ __launch_bounds__(256) void k_nd_bwd_sub(const NDItem* __restrict__ i
   }
 }
 
+// Fused forward sweep of the bottom ND_FUSED_LEVELS levels: one workgroup per
+// subtree.  Everything the subtree reads (its packed M^T rows, its vector
+// entry program, its node table, its own right-hand side) is requested at the
+// start with every load in flight and staged in LDS; the levels then follow
+// one another through LDS with workgroup barriers only, so a subtree costs
+// about one round trip to memory instead of a few per level.  The subtree
+// root's up vector and the b_eff of every own row go to global memory.
+// The node of depth range [n0, n1) (at most ND_FUSED_STAGE_NODES nodes) whose
+// (node, column) pairs (first pair in pair0) contain pair idx: the reads of
+// the table are unconditional (clamped), so they are issued together.
+__device__ __forceinline__ int fused_node_of(const FusedNode* nd, int n0, int n1, int idx) {
+  int i = n0;
+#pragma unroll
+  for (int u = 1; u < ND_FUSED_STAGE_NODES; ++u) {
+    const int cidx = n0 + u < n1 ? n0 + u : n0;
+    const int first = nd[cidx].pair0;
+    if (n0 + u < n1 && first <= idx) i = n0 + u;
+  }
+  return i;
+}
+
+__global__ __launch_bounds__(ND_FUSED_THREADS) void k_nd_fwd_fused(const FusedSub* __restrict__ subs,
+                                                                   const FusedNode* __restrict__ nodes,
+                                                                   const short4* __restrict__ went,
+                                                                   const double* __restrict__ blk,
+                                                                   const double* __restrict__ b,
+                                                                   double* __restrict__ up, double* __restrict__ beff) {
+  extern __shared__ double2 sh2[];  // 16-byte aligned for the block stores
+  double* sh = reinterpret_cast<double*>(sh2);
+  __shared__ FusedNode nd[16];
+  const int t = threadIdx.x;
+  const FusedSub S = subs[blockIdx.x];
+  const int nnode = S.stage_node[ND_FUSED_LEVELS];
+  // every independent load first: the block (16-byte loads from clamped
+  // positions), the entry program, the node table, the own right-hand side
+  const double2* src = reinterpret_cast<const double2*>(blk + S.fwd_off);
+  const int nb2 = S.fwd_n >> 1;
+  double2 a[ND_FUSED_LOADS];
+#pragma unroll
+  for (int u = 0; u < ND_FUSED_LOADS; ++u) {
+    const int i = t + ND_FUSED_THREADS * u;
+    a[u] = src[i < nb2 ? i : 0];
+  }
+  const int e0 = S.went[0], e1 = S.went[ND_FUSED_LEVELS];
+  short4 e[ND_FUSED_ENT];
+#pragma unroll
+  for (int u = 0; u < ND_FUSED_ENT; ++u) {
+    const int i = e0 + t + ND_FUSED_THREADS * u;
+    e[u] = went[i < e1 ? i : e0];
+  }
+  const FusedNode fn = nodes[S.node0 + (t < nnode ? t : 0)];
+  const double bv = b[S.own_off + (t < S.own_n ? t : 0)];
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first store
+  // unconditional stores (a lane past the end stores what it read from the
+  // clamped position, the same value as the owner of that position), so that
+  // no load is moved behind a branch and all of them stay in flight together
+  double2* sb = sh2;
+#pragma unroll
+  for (int u = 0; u < ND_FUSED_LOADS; ++u) {
+    const int i = t + ND_FUSED_THREADS * u;
+    sb[i < nb2 ? i : 0] = a[u];
+  }
+  double* vec = sh + S.fwd_n;
+  double* bvs = vec + S.vec_n;
+  nd[t < nnode ? t : 0] = fn;
+  bvs[t < S.own_n ? t : 0] = bv;
+  __syncthreads();
+  for (int d = ND_FUSED_LEVELS - 1; d >= 0; --d) {
+    // w of every front position of the level's nodes: own right-hand side plus
+    // the children's up vectors (b_eff of the own rows is kept for the
+    // backward sweep)
+    // (the LDS reads of the thread's entries are unconditional, from clamped
+    // positions, so they are issued together; unused values are dropped)
+    double bw[ND_FUSED_ENT], c0[ND_FUSED_ENT], c1[ND_FUSED_ENT];
+#pragma unroll
+    for (int u = 0; u < ND_FUSED_ENT; ++u) {
+      const short4 q = e[u];
+      bw[u] = bvs[q.w >= 0 ? q.w : 0];
+      c0[u] = vec[q.y >= 0 ? q.y : 0];
+      c1[u] = vec[q.z >= 0 ? q.z : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < ND_FUSED_ENT; ++u) {
+      const int i = e0 + t + ND_FUSED_THREADS * u;
+      if (i >= S.went[d] && i < S.went[d + 1]) {
+        const short4 q = e[u];
+        double v = q.w >= 0 ? bw[u] : 0.0;
+        if (q.y >= 0) v += c0[u];
+        if (q.z >= 0) v += c1[u];
+        vec[q.x] = v;
+        if (q.w >= 0) beff[S.own_off + q.w] = v;
+      }
+    }
+    __syncthreads();
+    // up[r] = w_b[r] - sum_k M^T[k][r] w_k, one (node, column) per thread
+    if (t < S.stage_pairs[d]) {
+      const int i = fused_node_of(nd, S.stage_node[d], S.stage_node[d + 1], t);
+      {
+        const FusedNode q = nd[i];
+        const int r = t - q.pair0;
+        const double* mt = sh + q.mt + r;
+        const double* w = vec + q.w;
+        // eight terms per step, their LDS reads issued together (positions past
+        // ns read row k again and are not added)
+        double acc = 0.0;
+        for (int k = 0; k < q.ns; k += 8) {
+          double m[8], ww[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int kk = k + u < q.ns ? k + u : k;
+            m[u] = mt[kk * q.nb];
+            ww[u] = w[kk];
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (k + u < q.ns) acc += m[u] * ww[u];
+        }
+        const double v = w[q.ns + r] - acc;
+        if (q.gup >= 0) up[q.gup + r] = v;
+        else vec[q.up + r] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+static size_t fused_lds_bytes(const CoarseLayout& co);
+
+// LDS beyond the default dynamic limit for the fused sweep kernels
+hipError_t prepare_fused_sweeps(Ctx* c) {
+  if (!c->co.fused) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_nd_fwd_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)fused_lds_bytes(c->co));
+}
+
+static size_t fused_lds_bytes(const CoarseLayout& co) {
+  size_t m = 0;
+  for (const FusedSub& S : co.f_subs) m = std::max(m, (size_t)S.fwd_n + S.vec_n + S.own_n);
+  return m * sizeof(double);
+}
+
 template <int Q>
 static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDItem* items, const int* bnd,
                        const double* F, const double* beff, double* x) {
@@ -1023,7 +1183,13 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
   const int L = (int)co.nd_levels.size();
   const int2* pull = (const int2*)c->d_nd_pull;
   // forward: the subtrees of the bottom levels, then the upper levels one launch each
-  if (co.sub_level < L) {
+  int top = co.sub_level;
+  if (co.fused) {
+    top = co.fused_level;
+    hipLaunchKernelGGL(k_nd_fwd_fused, dim3((unsigned)co.f_subs.size()), dim3(ND_FUSED_THREADS),
+                       fused_lds_bytes(co), c->stream, c->d_f_subs, c->d_f_nodes, c->d_f_went, c->d_f_blk,
+                       rhs, c->d_up, c->d_beff);
+  } else if (co.sub_level < L) {
     const int rows = co.sub_fw_rows;
     if (rows <= 16)
       launch_fwd_sub<16>(c, rhs);
@@ -1034,7 +1200,7 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
     else
       launch_fwd_sub<64>(c, rhs);
   }
-  for (int l = co.sub_level - 1; l >= 0; --l) {
+  for (int l = top - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
     if (ni == 0) continue;
     const NDItem* it = c->d_fw_items + i0;
@@ -1053,8 +1219,12 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
   }
   if (mid) hipEventRecord(mid, c->stream);
   // backward: the upper levels one launch each (LDS sized per level; the upper
-  // levels' items were split when the lists were built), then the subtrees
-  for (int l = 0; l < co.sub_level; ++l) {
+  // levels' items were split when the lists were built), then the subtrees.
+  // (A fused backward kernel over the same subtrees needs 137 KB of LDS at
+  // 128^2: one workgroup per CU, two rounds of workgroups, slower than the
+  // three-level subtree kernel.)
+  const int btop = co.sub_level < L ? co.sub_level : L;
+  for (int l = 0; l < btop; ++l) {
     const int i0 = co.bw_off[l], ni = co.bw_off[l + 1] - i0;
     if (ni == 0) continue;
     const NDItem* it = c->d_bw_items + i0;

@@ -12,6 +12,7 @@
 // ancestors].  Each entry of S_C is summed into the front of the deeper of the
 // two owning nodes (the one that eliminates first).
 #include <algorithm>
+#include <map>
 
 #include "internal.h"
 
@@ -232,6 +233,137 @@ bool build_nested_dissection(Ctx* c, const std::vector<int>& ent_g1, const std::
     for (int g : bnd[n]) posn[g] = -1;
   }
   return true;
+}
+
+}  // namespace lbddc
+
+namespace lbddc {
+
+// Program of the fused bottom-level forward sweep (FusedSub): every subtree
+// rooted at level L - ND_FUSED_LEVELS gets its packed M^T rows, the vector
+// entries of each node (where every front position of w comes from) and the
+// offsets of its nodes in LDS.  Sets co.fused only when every subtree fits
+// (single row part per node, LDS, entry and pair budgets); otherwise the
+// per-level kernels and the three-level subtree kernel are used.
+void build_fused_sweeps(Ctx* c) {
+  CoarseLayout& co = c->co;
+  co.fused = false;
+  co.f_subs.clear(); co.f_nodes.clear(); co.f_went.clear(); co.f_pack.clear();
+  co.f_blk_total = 0;
+  const int L = (int)co.nd_levels.size();
+  const int ls = L - ND_FUSED_LEVELS;
+  if (ls < 0 || (int)co.nd_levels[ls].size() < ND_FUSED_MIN_ROOTS) return;
+  for (int l = ls; l < L; ++l)
+    for (int n : co.nd_levels[l])
+      if (co.nd_nodes[n].ns > ND_KPART) return;
+  long long total = 0;
+  std::vector<FusedSub> subs;
+  std::vector<FusedNode> fnodes;
+  std::vector<short4> went;
+  std::vector<FusedPack> pack;
+  for (int root : co.nd_levels[ls]) {
+    // the subtree's nodes by depth below the root
+    std::vector<std::vector<int>> by(ND_FUSED_LEVELS);
+    std::vector<int> stack{root};
+    while (!stack.empty()) {
+      const int n = stack.back();
+      stack.pop_back();
+      const int d = co.nd_nodes[n].level - ls;
+      if (d < 0 || d >= ND_FUSED_LEVELS) return;
+      by[d].push_back(n);
+      for (int s = 1; s >= 0; --s)
+        if (co.nd_nodes[n].child[s] >= 0) stack.push_back(co.nd_nodes[n].child[s]);
+    }
+    for (auto& v : by) std::sort(v.begin(), v.end());
+    FusedSub S{};
+    // own dofs: one contiguous range (tree order)
+    int lo = 1 << 30, tot = 0;
+    for (auto& v : by)
+      for (int n : v) { lo = std::min(lo, co.nd_nodes[n].own_off); tot += co.nd_nodes[n].ns; }
+    for (auto& v : by)
+      for (int n : v)
+        if (co.nd_nodes[n].own_off + co.nd_nodes[n].ns > lo + tot) return;
+    S.own_off = lo;
+    S.own_n = tot;
+    S.node0 = (int)fnodes.size();
+    std::map<int, int> slot;  // node id -> index in fnodes
+    int mt = 0, vec = 0;
+    for (int d = 0; d < ND_FUSED_LEVELS; ++d) {
+      S.stage_node[d] = (int)fnodes.size() - S.node0;
+      if ((int)by[d].size() > ND_FUSED_STAGE_NODES) return;
+      S.stage_pairs[d] = 0;
+      for (int n : by[d]) {
+        const NDNodeH& D = co.nd_nodes[n];
+        FusedNode f{};
+        f.pair0 = S.stage_pairs[d];
+        S.stage_pairs[d] += D.nb;
+        f.ns = D.ns; f.nb = D.nb; f.nf = D.ns + D.nb;
+        f.mt = mt; mt += D.ns * D.nb;
+        f.w = vec; vec += f.nf;
+        f.up = vec; vec += D.nb;
+        f.own = D.own_off - lo;
+        f.gup = d == 0 ? D.up_off : -1;
+        slot[n] = (int)fnodes.size();
+        fnodes.push_back(f);
+        pack.push_back(FusedPack{D.foff, 0, D.ns, D.nb});
+      }
+      if (S.stage_pairs[d] > ND_FUSED_THREADS) return;
+    }
+    S.stage_node[ND_FUSED_LEVELS] = (int)fnodes.size() - S.node0;
+    if ((int)fnodes.size() - S.node0 > 16) return;
+    S.fwd_n = (mt + 1) & ~1;
+    S.vec_n = (vec + 1) & ~1;
+    S.fwd_off = total;
+    total += S.fwd_n;
+    // budgets: LDS, 16-byte loads per thread, one own value per thread
+    if ((long long)S.fwd_n + S.vec_n + S.own_n > ND_FUSED_LDS_DOUBLES) return;
+    if (S.fwd_n / 2 > ND_FUSED_LOADS * ND_FUSED_THREADS) return;
+    if (S.own_n > ND_FUSED_THREADS || S.vec_n >= 32767) return;
+    // vector entries by depth: own right-hand side and the children's up
+    // vectors (the child map gives the front position of each child boundary
+    // entry)
+    for (int d = 0; d < ND_FUSED_LEVELS; ++d) {
+      S.went[d] = (int)went.size();
+      for (int n : by[d]) {
+        const NDNodeH& D = co.nd_nodes[n];
+        const FusedNode& f = fnodes[slot[n]];
+        const size_t first = went.size();
+        for (int j = 0; j < D.ns + D.nb; ++j) {
+          short4 e;
+          e.x = (short)(f.w + j);
+          e.y = e.z = -1;
+          e.w = (short)(j < D.ns ? f.own + j : -1);
+          went.push_back(e);
+        }
+        for (int s = 0; s < 2; ++s) {
+          const int ch = D.child[s];
+          if (ch < 0) continue;
+          const NDNodeH& C = co.nd_nodes[ch];
+          const FusedNode& fc = fnodes[slot.at(ch)];
+          for (int i = 0; i < C.nb; ++i) {
+            const int pos = co.nd_cmap[D.cmap_off[s] + i];
+            short4& e = went[first + pos];
+            (s == 0 ? e.y : e.z) = (short)(fc.up + i);
+          }
+        }
+      }
+    }
+    S.went[ND_FUSED_LEVELS] = (int)went.size();
+    if (S.went[ND_FUSED_LEVELS] - S.went[0] > ND_FUSED_ENT * ND_FUSED_THREADS) return;
+    subs.push_back(S);
+  }
+  {
+    size_t k = 0;
+    for (const FusedSub& S : subs)
+      for (int i = 0; i < S.stage_node[ND_FUSED_LEVELS]; ++i, ++k) pack[k].fdst = S.fwd_off + fnodes[S.node0 + i].mt;
+  }
+  co.f_subs = std::move(subs);
+  co.f_nodes = std::move(fnodes);
+  co.f_went = std::move(went);
+  co.f_pack = std::move(pack);
+  co.f_blk_total = total;
+  co.fused_level = ls;
+  co.fused = true;
 }
 
 }  // namespace lbddc

@@ -326,6 +326,9 @@ bool build_topology(Ctx* c) {
     }
   }
 
+  // the fused bottom-level sweeps, when every subtree fits
+  build_fused_sweeps(c);
+
   // fixed-width owner tables (taken after the coarse renumbering)
   auto owners4 = [&](const std::vector<int>& ptr, const std::vector<int>& own, int N, std::vector<int4>& out) {
     out.assign(N, make_int4(-1, -1, -1, -1));
@@ -385,7 +388,9 @@ bool build_topology(Ctx* c) {
          up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_nd_pull, co.nd_pull) && up(&c->d_fw_items, co.fw_items) &&
          up(&c->d_sub_fw_items, co.sub_fw_items) && up(&c->d_sub_bw_items, co.sub_bw_items) &&
          up(&c->d_sub_fw_off, co.sub_fw_off) && up(&c->d_sub_bw_off, co.sub_bw_off) &&
-         up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes);
+         up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes) &&
+         up(&c->d_f_subs, co.f_subs) && up(&c->d_f_nodes, co.f_nodes) && up(&c->d_f_went, co.f_went) &&
+         up(&c->d_f_pack, co.f_pack);
 }
 
 void build_tables(Ctx* c, std::vector<double>& tab) {

@@ -85,7 +85,7 @@ def test_noalloc_rejects_lattices_beyond_the_scratch():
     import torch
     from gpu_helpers import make_solver
     from paper_2604_09113_amd import lbddc
-    prob = make_problem(2, nx=300, ny=300, p=2, m=1, jitter=0.0)
+    prob = make_problem(2, nx=300, ny=300, p=2, m=1, jitter=0.0, moments=False)
     s = make_solver(prob, oracle_roms(prob))
     buf = torch.zeros(16, dtype=torch.float32, device="cuda")
     with pytest.raises(lbddc.LbddcError) as ei:
