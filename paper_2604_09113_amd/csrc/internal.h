@@ -167,6 +167,7 @@ struct CoarseLayout {
   long long nd_cp_total = 0;  // panel scratch of the largest blocked level
   // per-level work lists of the solve sweeps: (node, first row) items
   std::vector<NDItem> fw_items, bw_items;
+  std::vector<int2> fw_src, sub_fw_src;     // per forward item, 128 gather sources (see push_fw)
   std::vector<int> lvl_nodes;
   std::vector<int> fw_off, bw_off, lvl_off;
   std::vector<int> lvl_nfmax, lvl_nsmax;  // largest front and own-block size per level
@@ -245,7 +246,8 @@ struct Ctx {
   int* d_net_own = nullptr;    // cell*(m+1)^2 + local control point
   int* d_cstart = nullptr; int* d_contrib = nullptr; long long* d_dest = nullptr;
   NDNodeH* d_nd_nodes = nullptr;
-  int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr, *d_nd_pull = nullptr;
+  int *d_nd_bnd = nullptr, *d_nd_cmap = nullptr;
+  int2 *d_fw_src = nullptr, *d_sub_fw_src = nullptr;
   NDItem *d_fw_items = nullptr, *d_bw_items = nullptr;
   NDItem *d_sub_fw_items = nullptr, *d_sub_bw_items = nullptr;
   FusedSub* d_f_subs = nullptr;

@@ -618,12 +618,13 @@ hipError_t launch_coarse_factor(Ctx* c) {
 // (row-major, row stride nf); the lower rows are not needed once the parent
 // has taken U.
 
-// Sum over a child's parts of entry i of its up vector, in part order, for
-// the two children at once.  i = -1: the child does not touch this front
-// position.  pull_load requests the first CK parts of both children
-// unconditionally (a position that is not needed reads up[0]), so that the
-// loads of several positions can all be in flight before pull_sum adds them;
-// pull_sum adds any further parts in a loop.
+// Sum over a child's parts of its up-vector entry at one front position, in
+// part order, for the two children at once.  src = the index in `up` of part 0
+// of each child's entry (-1: the child does not touch this position; part u
+// is u * child_nb further).  pull_load requests the first CK parts of both
+// children unconditionally (a position that is not needed reads up[0]), so
+// that the loads of several positions can all be in flight before pull_sum
+// adds them; pull_sum adds any further parts in a loop.
 template <int CK>
 struct Pulled {
   double t0[CK], t1[CK];
@@ -635,9 +636,9 @@ __device__ __forceinline__ Pulled<CK> pull_load(const NDItem& d, const double* _
   p.n0 = src.x >= 0 ? d.child_kparts[0] : 0;
   p.n1 = src.y >= 0 ? d.child_kparts[1] : 0;
 #pragma unroll
-  for (int u = 0; u < CK; ++u) p.t0[u] = up[u < p.n0 ? d.child_up_off[0] + u * d.child_nb[0] + src.x : 0];
+  for (int u = 0; u < CK; ++u) p.t0[u] = up[u < p.n0 ? src.x + u * d.child_nb[0] : 0];
 #pragma unroll
-  for (int u = 0; u < CK; ++u) p.t1[u] = up[u < p.n1 ? d.child_up_off[1] + u * d.child_nb[1] + src.y : 0];
+  for (int u = 0; u < CK; ++u) p.t1[u] = up[u < p.n1 ? src.y + u * d.child_nb[1] : 0];
   return p;
 }
 template <int CK>
@@ -649,8 +650,8 @@ __device__ __forceinline__ void pull_sum(const NDItem& d, const double* __restri
   for (int u = 0; u < CK; ++u) c0 += u < p.n0 ? p.t0[u] : 0.0;
 #pragma unroll
   for (int u = 0; u < CK; ++u) c1 += u < p.n1 ? p.t1[u] : 0.0;
-  for (int kp = CK; kp < p.n0; ++kp) c0 += up[d.child_up_off[0] + kp * d.child_nb[0] + src.x];
-  for (int kp = CK; kp < p.n1; ++kp) c1 += up[d.child_up_off[1] + kp * d.child_nb[1] + src.y];
+  for (int kp = CK; kp < p.n0; ++kp) c0 += up[src.x + kp * d.child_nb[0]];
+  for (int kp = CK; kp < p.n1; ++kp) c1 += up[src.y + kp * d.child_nb[1]];
 }
 
 // Forward item (node, boundary columns [r0, r0 + 64), own-row part kp = rows
@@ -665,7 +666,7 @@ __device__ __forceinline__ void pull_sum(const NDItem& d, const double* __restri
 // requested before the right-hand side is gathered; the four wave partials
 // are added in a fixed order.  The items of column block 0 store b_eff of
 // their rows for the backward sweep.
-__global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int2* __restrict__ pull,
+__global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int2* __restrict__ fsrc,
                                                 const double* __restrict__ F, const double* __restrict__ b,
                                                 double* __restrict__ up, double* __restrict__ beff) {
   __shared__ double w[128];  // [0, 64): w on rows kb.., [64, 128): w_b on columns r0..
@@ -680,9 +681,9 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
   const bool own = t < 64;
   const bool ok = t < 128 && (own ? kb + t < ke : (d.kpart == 0 && d.first + (t - 64) < d.nb));
   const int j = ok ? (own ? kb + t : d.ns + d.first + (t - 64)) : 0;
-  // the pull map and b ahead of M^T (the counter is in order); leaves and
-  // positions that are not needed read entry 0 of the maps (never empty)
-  const int2 srcl = pull[d.pull_off >= 0 && ok ? d.pull_off + j : 0];
+  // the item's gather sources (at a position known before the item itself)
+  // and b ahead of M^T (the counter is in order)
+  const int2 srcl = fsrc[(long long)blockIdx.x * 128 + (t < 128 ? t : 0)];
   const double bj = b[ok && own ? d.own_off + j : 0];
   __builtin_amdgcn_sched_barrier(0);
   // unconditional loads of M^T: rows past ke read row 0 and meet zeros of w,
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
   }
   if (t < 128) {
     double v = own ? bj : 0.0;
-    if (d.pull_off >= 0) {
+    {
       double c0, c1;
       const int2 src = ok ? srcl : make_int2(-1, -1);
       pull_sum<8>(d, up, src, pull_load<8>(d, up, src), c0, c1);
@@ -827,7 +828,7 @@ __device__ __forceinline__ double read_lane(double v, int src) {
 // column r0 + l, reads the R rows of M^T in its column, and takes w_k from
 // lane k - kb.
 template <int R, int CK>
-__device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict__ pull,
+__device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict__ fsrc,
                                          const double* __restrict__ F, const double* __restrict__ b,
                                          double* __restrict__ up, double* __restrict__ beff) {
   const int lane = threadIdx.x & 63, nf = d.ns + d.nb, r = d.first + lane;
@@ -836,8 +837,8 @@ __device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict
   const bool ok1 = kb + lane < ke, ok2 = d.kpart == 0 && col_ok;
   const int j1 = ok1 ? kb + lane : 0, j2 = ok2 ? d.ns + r : 0;
   const bool has_ch = d.pull_off >= 0;
-  const int2 s1 = pull[has_ch && ok1 ? d.pull_off + j1 : 0];
-  const int2 s2 = pull[has_ch && ok2 ? d.pull_off + j2 : 0];
+  const int2 s1 = fsrc[lane];
+  const int2 s2 = fsrc[64 + lane];
   const double b1 = b[ok1 ? d.own_off + j1 : 0];
   __builtin_amdgcn_sched_barrier(0);  // indices ahead of M^T (the counter is in order)
   // rows past ke read row 0 and meet w = 0; columns past nb are not stored
@@ -945,11 +946,11 @@ __device__ __forceinline__ void bwd_task(const NDItem& d, const int* __restrict_
 // per workgroup.
 template <int R, int CK>
 __global__ __launch_bounds__(256) void k_nd_fwd_w(const NDItem* __restrict__ items, int nitems,
-                                                  const int2* __restrict__ pull, const double* __restrict__ F,
+                                                  const int2* __restrict__ fsrc, const double* __restrict__ F,
                                                   const double* __restrict__ b, double* __restrict__ up,
                                                   double* __restrict__ beff) {
   const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (it < nitems) fwd_task<R, CK>(items[it], pull, F, b, up, beff);
+  if (it < nitems) fwd_task<R, CK>(items[it], fsrc + (long long)it * 128, F, b, up, beff);
 }
 template <int NCH>
 __global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ items, int nitems,
@@ -969,13 +970,14 @@ __global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ ite
 template <int R, int CK>
 __global__ __launch_bounds__(256) void k_nd_fwd_sub(const NDItem* __restrict__ items,
                                                     const int* __restrict__ stage_off, int nst,
-                                                    const int2* __restrict__ pull, const double* __restrict__ F,
+                                                    const int2* __restrict__ fsrc, const double* __restrict__ F,
                                                     const double* __restrict__ b, double* __restrict__ up,
                                                     double* __restrict__ beff) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int* so = stage_off + (long long)blockIdx.x * (nst + 1);
   for (int st = 0; st < nst; ++st) {
-    for (int it = so[st] + wv; it < so[st + 1]; it += 4) fwd_task<R, CK>(items[it], pull, F, b, up, beff);
+    for (int it = so[st] + wv; it < so[st + 1]; it += 4)
+      fwd_task<R, CK>(items[it], fsrc + (long long)it * 128, F, b, up, beff);
     __syncthreads();
   }
 }
@@ -1150,15 +1152,15 @@ static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDI
 constexpr int ND_WAVE_ITEMS = 512;
 
 template <int R>
-static void launch_fwd_w(int ck, int ni, hipStream_t st, const NDItem* items, const int2* pull, const double* F,
+static void launch_fwd_w(int ck, int ni, hipStream_t st, const NDItem* items, const int2* fsrc, const double* F,
                          const double* b, double* up, double* beff) {
   const dim3 grid((ni + 3) / 4);
   if (ck <= 1)
-    hipLaunchKernelGGL((k_nd_fwd_w<R, 1>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 1>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff);
   else if (ck <= 2)
-    hipLaunchKernelGGL((k_nd_fwd_w<R, 2>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 2>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff);
   else
-    hipLaunchKernelGGL((k_nd_fwd_w<R, 8>), grid, dim3(256), 0, st, items, ni, pull, F, b, up, beff);
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 8>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff);
 }
 
 template <int R>
@@ -1166,7 +1168,7 @@ static void launch_fwd_sub(const Ctx* c, const double* rhs) {
   const CoarseLayout& co = c->co;
   const int ck = co.sub_child_kparts;
   const dim3 grid(co.sub_count);
-  const int2* pull = (const int2*)c->d_nd_pull;
+  const int2* pull = c->d_sub_fw_src;
   if (ck <= 1)
     hipLaunchKernelGGL((k_nd_fwd_sub<R, 1>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
                        co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
@@ -1181,7 +1183,6 @@ static void launch_fwd_sub(const Ctx* c, const double* rhs) {
 hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
-  const int2* pull = (const int2*)c->d_nd_pull;
   // forward: the subtrees of the bottom levels, then the upper levels one launch each
   int top = co.sub_level;
   if (co.fused) {
@@ -1204,6 +1205,7 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
     if (ni == 0) continue;
     const NDItem* it = c->d_fw_items + i0;
+    const int2* pull = c->d_fw_src + (long long)i0 * 128;
     const int rows = co.lvl_fw_rows[l], ck = co.lvl_child_kparts[l];
     if (ni >= ND_WAVE_ITEMS && rows <= 48) {
       if (rows <= 16)

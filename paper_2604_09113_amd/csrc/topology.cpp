@@ -239,13 +239,32 @@ bool build_topology(Ctx* c) {
     it.pull_off = pull_off[n];
     return it;
   };
-  auto push_fw = [&](int n, std::vector<NDItem>& out) {
+  // A forward item reads the children's up vectors at 128 front positions:
+  // its own rows kb + t (t < 64) and, for part 0, its boundary columns
+  // first + t - 64 (t >= 64).  src holds, per item and position, the index in
+  // `up` of part 0 of each child's entry there (-1: no entry), so that the
+  // item's gathers wait for one load instead of two.
+  auto push_fw = [&](int n, std::vector<NDItem>& out, std::vector<int2>& src) {
     NDItem it = make_item(n);
+    const NDNodeH& d = co.nd_nodes[n];
     for (int kp = 0; kp < kparts[n]; ++kp)
-      for (int r = 0; r < std::max(1, co.nd_nodes[n].nb); r += 64) {
+      for (int r = 0; r < std::max(1, d.nb); r += 64) {
         it.first = r;
         it.kpart = kp;
         out.push_back(it);
+        const int kb = kp * ND_KPART, ke = std::min(d.ns, kb + ND_KPART);
+        for (int t = 0; t < 128; ++t) {
+          int j = -1;
+          if (t < 64 && kb + t < ke) j = kb + t;
+          if (t >= 64 && kp == 0 && r + t - 64 < d.nb) j = d.ns + r + t - 64;
+          int2 e = make_int2(-1, -1);
+          if (j >= 0 && pull_off[n] >= 0) {
+            const int s0 = co.nd_pull[2 * ((size_t)pull_off[n] + j)], s1 = co.nd_pull[2 * ((size_t)pull_off[n] + j) + 1];
+            if (s0 >= 0) e.x = it.child_up_off[0] + s0;
+            if (s1 >= 0) e.y = it.child_up_off[1] + s1;
+          }
+          src.push_back(e);
+        }
       }
   };
   auto push_bw = [&](int n, int rows, std::vector<NDItem>& out) {
@@ -256,7 +275,7 @@ bool build_topology(Ctx* c) {
       out.push_back(it);
     }
   };
-  co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear();
+  co.fw_items.clear(); co.bw_items.clear(); co.lvl_nodes.clear(); co.fw_src.clear(); co.sub_fw_src.clear();
   co.fw_off.assign(1, 0); co.bw_off.assign(1, 0); co.lvl_off.assign(1, 0);
   co.lvl_nfmax.assign(L, 0);
   co.lvl_nsmax.assign(L, 0);
@@ -273,7 +292,7 @@ bool build_topology(Ctx* c) {
       co.lvl_fw_rows[l] = std::max(co.lvl_fw_rows[l], std::min(d.ns, ND_KPART));
       for (int s = 0; s < 2; ++s)
         if (d.child[s] >= 0) co.lvl_child_kparts[l] = std::max(co.lvl_child_kparts[l], kparts[d.child[s]]);
-      push_fw(n, co.fw_items);
+      push_fw(n, co.fw_items, co.fw_src);
       push_bw(n, co.lvl_bw_rows[l], co.bw_items);
       co.lvl_nodes.push_back(n);
     }
@@ -314,7 +333,7 @@ bool build_topology(Ctx* c) {
         for (auto& v : by) std::sort(v.begin(), v.end());
         for (int st = 0; st < co.sub_nst; ++st) {
           co.sub_fw_off.push_back((int)co.sub_fw_items.size());
-          for (int n : by[co.sub_nst - 1 - st]) push_fw(n, co.sub_fw_items);
+          for (int n : by[co.sub_nst - 1 - st]) push_fw(n, co.sub_fw_items, co.sub_fw_src);
         }
         co.sub_fw_off.push_back((int)co.sub_fw_items.size());
         for (int st = 0; st < co.sub_nst; ++st) {
@@ -385,7 +404,7 @@ bool build_topology(Ctx* c) {
          up(&c->d_cown, cown) && up(&c->d_uown4, uown4) && up(&c->d_cown4, cown4) && up(&c->d_skel_node, sk_node) && up(&c->d_net_ptr, nptr) &&
          up(&c->d_net_own, nown) && up(&c->d_cstart, co.cstart) && up(&c->d_contrib, co.contrib) &&
          up(&c->d_dest, co.dest) && up(&c->d_nd_nodes, co.nd_nodes) &&
-         up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_nd_pull, co.nd_pull) && up(&c->d_fw_items, co.fw_items) &&
+         up(&c->d_nd_bnd, co.nd_bnd) && up(&c->d_nd_cmap, co.nd_cmap) && up(&c->d_fw_src, co.fw_src) && up(&c->d_sub_fw_src, co.sub_fw_src) && up(&c->d_fw_items, co.fw_items) &&
          up(&c->d_sub_fw_items, co.sub_fw_items) && up(&c->d_sub_bw_items, co.sub_bw_items) &&
          up(&c->d_sub_fw_off, co.sub_fw_off) && up(&c->d_sub_bw_off, co.sub_bw_off) &&
          up(&c->d_bw_items, co.bw_items) && up(&c->d_lvl_nodes, co.lvl_nodes) &&
