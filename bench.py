@@ -73,8 +73,11 @@ def kernel_bytes(prob, roms, nC):
     out = {}
     # operator product: packed S, index map, gathered vector, partial result
     out["op"] = ncell * (8 * nU * (nU + 1) // 2 + 4 * nU + 8 * nU + 8 * nU)
-    # Schur: read the lower node-pair triangle of K, write S, L_II, Y and diag
-    out["schur"] = ncell * (8 * 4 * npair + 8 * nU * (nU + 1) // 2 + 8 * nI * (nI + 1) // 2 + 8 * nI * nU + 8 * nU)
+    # Schur: read the lower node-pair triangle of K and the skeleton index map,
+    # write S, the diagonal and the elimination multipliers W (the entries that
+    # are not padding: panel k of nk <= 16 pivots has nk (ndof - 16 k - nk))
+    nW = sum(min(16, nI - 16 * k) * (2 * nN - 16 * k - min(16, nI - 16 * k)) for k in range((nI + 15) // 16))
+    out["schur"] = ncell * (8 * 4 * npair + 4 * nU + 8 * nU * (nU + 1) // 2 + 8 * nW + 8 * nU)
     # fine + coarse restriction (T = fp32 or fp64 preconditioner data)
     out["pre"] = lambda tb: ncell * (tb * nE * (nE + 1) // 2 + tb * nU * nC + 4 * nU + 8 * nU + 8 * nU + 8 * nC)
     return out

@@ -311,8 +311,7 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
             dalloc_t(c, &c->d_load, (size_t)c->nrhs * ncell * nU) &&
             dalloc_t(c, &c->d_cons, (size_t)ncell * 4 * c->nce * (c->p + 1) * 2) &&
             dalloc_t(c, &c->d_S, (size_t)ncell * nU * (nU + 1) / 2) &&
-            dalloc_t(c, &c->d_L, (size_t)ncell * c->nI * (c->nI + 1) / 2) &&
-            dalloc_t(c, &c->d_Y, (size_t)ncell * c->nI * nU) && dalloc_t(c, &c->d_diagK, (size_t)ncell * nU) &&
+            dalloc_t(c, &c->d_W, (size_t)ncell * schur_w_count(c->p)) && dalloc_t(c, &c->d_diagK, (size_t)ncell * nU) &&
             dalloc_t(c, &c->d_Ktot, NU) && dalloc(c, &c->d_P, (size_t)ncell * c->nE * (c->nE + 1) / 2 * 8) &&
             dalloc(c, &c->d_Psi, (size_t)ncell * nU * nC * 8) && dalloc_t(c, &c->d_D, (size_t)ncell * nU) &&
             dalloc_t(c, &c->d_ScLoc, (size_t)ncell * nC * (nC + 1) / 2) &&

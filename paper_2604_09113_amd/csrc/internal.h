@@ -17,6 +17,15 @@ namespace lbddc {
 constexpr int kMaxP = 10;
 constexpr int kMaxKC = 11;  // reduced basis + stabilisation column padded to 4*KC <= 44
 constexpr int kMaxDevices = 64;
+
+// Doubles per cell of the interior elimination multipliers W of the local
+// Schur complement: interior and skeleton dofs each padded to 16-row tiles
+// (NIP and NUT of them), 256 doubles for every tile below each interior
+// panel.
+__host__ __device__ constexpr int schur_w_count(int p) {
+  return 256 * (((2 * (p - 1) * (p - 1) + 15) / 16) * (((2 * (p - 1) * (p - 1) + 15) / 16) + (8 * p + 15) / 16 - 1) -
+                ((2 * (p - 1) * (p - 1) + 15) / 16) * (((2 * (p - 1) * (p - 1) + 15) / 16) - 1) / 2);
+}
 // bytes of the static device scratch of lbddc_assemble_fp32_noalloc
 constexpr size_t kNoAllocScratchBytes = 48u << 20;
 
@@ -283,8 +292,7 @@ struct Ctx {
 
   // setup
   double* d_S = nullptr;       // [ncell][nU(nU+1)/2]
-  double* d_L = nullptr;       // [ncell][nI(nI+1)/2] L_II packed row by row
-  double* d_Y = nullptr;       // [ncell][nU][nI] Y = L_II^-1 K_IU, column by column
+  double* d_W = nullptr;       // [ncell][schur_w_count(p)] interior elimination multipliers
   double* d_diagK = nullptr;   // [ncell][nU]
   double* d_Ktot = nullptr;    // [NU]
   void* d_P = nullptr;         // [ncell][nE(nE+1)/2] D-scaled fine operator (T)

@@ -323,104 +323,67 @@ __global__ void k_dot(const double* __restrict__ a, const double* __restrict__ b
   if (threadIdx.x == 0) red[blockIdx.x] = d;
 }
 
-// ---- interior recovery: u_I = -L^-T (Y u_U) (tractions act on skeleton dofs only)
-// u_I = -L_II^-T (Y u_U) for one cell per 64-lane wave (Y = L_II^-1 K_IU,
-// stored column by column, [nU][nI]; L_II packed row by row, row k holding
-// L[k][0..k]).  Lane l takes interior rows k0 = l and k1 = l + 64: s = -Y u_U
-// with the entries of u_U broadcast by readlane and the columns of Y read
-// coalesced across the lanes; then the back substitution L_II^T u_I = s runs
-// right-looking: at step k the owner of entry k holds its final value, which
-// is divided by L_kk, read by every lane with readlane, and subtracted, times
-// L_kj, from the entries j < k.  Step k reads row k of L_II, a contiguous
-// run that the lanes load coalesced, sixteen steps ahead of its use.  No LDS
-// and no barrier.
-__device__ __forceinline__ double lane_value(double v, int src) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-  return __hiloint2double(hi, lo);
-}
+// ---- interior recovery (tractions act on skeleton dofs only)
+// The interior dofs of one cell per 64-lane wave from the multipliers W of
+// the blocked elimination in the local Schur kernel: interior panels from the
+// last to the first, u_p = -sum_{i > p} W_(p,i)^T u_i over the tiles below
+// panel p (interior and skeleton dofs padded to 16-row tiles, the padding
+// zero).  The padded cell vector lives in LDS.  Lane 16 g + c multiplies the
+// W entries (row c, columns g + 4v) of each tile, read contiguously across
+// the lanes, by u of row c; the 16 lanes of row g then sum their partials,
+// and the panel's 16 values go to LDS for the panels above.
 template <int P>
-__global__ __launch_bounds__(64) void k_recover(const double* __restrict__ L, const double* __restrict__ Y,
-                                                const int* __restrict__ RU, const double* __restrict__ x, int nx,
-                                                int Gx, double* __restrict__ u, double* __restrict__ ucell) {
+__global__ __launch_bounds__(64) void k_recover(const double* __restrict__ W, const int* __restrict__ RU,
+                                                const double* __restrict__ x, int nx, int Gx,
+                                                double* __restrict__ u, double* __restrict__ ucell) {
   constexpr int NI = 2 * (P - 1) * (P - 1), NU = 8 * P, NDOF = 2 * (P + 1) * (P + 1);
-  constexpr int NLP = NI * (NI + 1) / 2;
-  constexpr int KB = 16;  // substitution steps per batch of L entries
-  static_assert(NU <= 64 && NI <= 128, "two interior entries per lane");
-  const int cell = blockIdx.x, l = threadIdx.x;
-  const int g = l < NU ? RU[(size_t)cell * NU + l] : -1;
-  const double xv = x[g >= 0 ? g : 0];
-  const double ul = g >= 0 ? xv : 0.0;  // u_U entry l
-  const int k0 = l, k1 = l + 64;
-  const bool h0 = k0 < NI, h1 = k1 < NI;
-  const int k0c = h0 ? k0 : 0, k1c = h1 ? k1 : 0;
-  // s = -Y u_U (columns past nU and rows past nI read entry 0 and are not used)
-  const double* Yc = Y + (size_t)cell * NU * NI;
-  double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-  for (int j0 = 0; j0 < NU; j0 += 16) {
-    double v0[16], v1[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int jj = j0 + j < NU ? j0 + j : 0;
-      v0[j] = Yc[(size_t)jj * NI + k0c];
-      v1[j] = Yc[(size_t)jj * NI + k1c];
+  constexpr int NIP = (NI + 15) / 16, NT = NIP + (NU + 15) / 16;
+  const int cell = blockIdx.x, l = threadIdx.x, g = l >> 4, c = l & 15;
+  __shared__ double ub[16 * NT];
+  for (int i = l; i < 16 * NT; i += 64) {
+    const int s = i - 16 * NIP;
+    double v = 0.0;
+    if (s >= 0 && s < NU) {
+      const int gi = RU[(size_t)cell * NU + s];
+      v = gi >= 0 ? x[gi] : 0.0;
     }
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-      if (j0 + j < NU) {
-        const double uj = lane_value(ul, j0 + j);
-        a0 += v0[j] * uj;
-        a1 += v1[j] * uj;
-      }
+    ub[i] = v;
   }
-  double s0 = -a0, s1 = -a1;
-  // L_kj = L[k (k + 1) / 2 + j]; a lane whose row is not below step k reads
-  // the diagonal L_kk instead, so the owner of entry k holds L_kk
-  const double* Lc = L + (size_t)cell * NLP;
-  auto fetch = [&](int kb, double (&e0)[KB], double (&e1)[KB]) {
+  __syncthreads();
+  const double* Wc = W + (size_t)cell * schur_w_count(P);
+  for (int p = NIP - 1; p >= 0; --p) {
+    const double* Wp = Wc + 256 * (p * (NT - 1) - p * (p - 1) / 2);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // tiles p + 1 .. NT - 1, all loads in flight (past the last tile: tile
+    // p + 1 again, times zero)
 #pragma unroll
-    for (int m = 0; m < KB; ++m) {
-      const int k = kb - m > 0 ? kb - m : 0, rk = k * (k + 1) / 2;
-      e0[m] = Lc[rk + (k0 < k ? k0 : k)];
-      e1[m] = Lc[rk + (k1 < k ? k1 : k)];
-    }
-  };
-  double e0[KB], e1[KB], n0[KB], n1[KB];
-  fetch(NI - 1, e0, e1);
-  for (int kb = NI - 1; kb >= 0; kb -= KB) {
-    fetch(kb - KB, n0, n1);  // past step 0 every entry is clamped to the diagonal
+    for (int t = 0; t < NT - 1; ++t) {
+      const bool in = p + 1 + t < NT;
+      const int tc = in ? t : 0;
+      const double ut = in ? ub[16 * (p + 1 + t) + c] : 0.0;
 #pragma unroll
-    for (int m = 0; m < KB; ++m) {
-      const int k = kb - m;
-      if (k < 0) break;
-      const double sk = k < 64 ? lane_value(s0, k) / lane_value(e0[m], k) : lane_value(s1, k - 64) / lane_value(e1[m], k - 64);
-      if (k < 64) {
-        if (l == k) s0 = sk;
-      } else {
-        if (l == k - 64) s1 = sk;
-      }
-      if (k0 < k) s0 -= e0[m] * sk;
-      if (k1 < k) s1 -= e1[m] * sk;
+      for (int v = 0; v < 4; ++v) acc[v] = fma(Wp[256 * tc + 64 * v + l], ut, acc[v]);
     }
 #pragma unroll
-    for (int m = 0; m < KB; ++m) {
-      e0[m] = n0[m];
-      e1[m] = n1[m];
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) acc[v] += __shfl_xor(acc[v], o, 16);
+    if (c == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ub[16 * p + g + 4 * v] = -acc[v];
     }
+    __syncthreads();
   }
   const int ix = cell % nx, iy = cell / nx;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int k = h ? k1 : k0;
-    if (k >= NI) continue;
-    const double v = h ? s1 : s0;
+  for (int k = l; k < NI; k += 64) {
+    const double v = ub[k];
     const int n = k >> 1, comp = k & 1;
     const int a = n % (P - 1) + 1, b = n / (P - 1) + 1;
     u[((size_t)(P * iy + b) * Gx + P * ix + a) * 2 + comp] = v;
     if (ucell) ucell[(size_t)cell * NDOF + k] = v;
   }
-  if (ucell && l < NU) ucell[(size_t)cell * NDOF + NI + l] = ul;
+  if (ucell)
+    for (int s = l; s < NU; s += 64) ucell[(size_t)cell * NDOF + NI + s] = ub[16 * NIP + s];
 }
 
 __global__ void k_scatter_skel(const double* __restrict__ x, const int* __restrict__ node, int NU,
@@ -714,7 +677,7 @@ hipError_t launch_recover(Ctx* c, int rhs) {
   hipLaunchKernelGGL(k_fill_p, dim3(512), dim3(256), 0, c->stream, u, (long long)nu, 0.0);
   const double* x = c->d_x + (size_t)rhs * c->NU;
   double* uc = c->d_ucell ? c->d_ucell + (size_t)rhs * c->ncell * c->ndof : nullptr;
-#define RCC(pp) case pp: hipLaunchKernelGGL(k_recover<pp>, dim3(c->ncell), dim3(64), 0, c->stream, c->d_L, c->d_Y, c->d_RU, x, c->nx, c->Gx, u, uc); break;
+#define RCC(pp) case pp: hipLaunchKernelGGL(k_recover<pp>, dim3(c->ncell), dim3(64), 0, c->stream, c->d_W, c->d_RU, x, c->nx, c->Gx, u, uc); break;
   DISPATCH_P(RCC)
 #undef RCC
   hipLaunchKernelGGL(k_scatter_skel, dim3((c->NU + 255) / 256), dim3(256), 0, c->stream, x, c->d_skel_node, c->NU, u);
