@@ -198,13 +198,23 @@ lbddc_status lbddc_setup(lbddc_ctx* ctx, lbddc_precision prec);
 /* PCG with the BDDC preconditioner (Alg. 1) for every load case, from x0 = 0,
  * stopping when ||f - S x||_2 <= rtol ||f||_2 (recurrence residual), then
  * interior recovery.  info[r] (host, nrhs entries, may be NULL) receives the
- * iteration count, the recurrence residual and a recomputed true residual. */
+ * iteration count, the recurrence residual and a recomputed true residual.
+ * Several load cases are solved as blocks of up to 8: each PCG iteration
+ * applies the operator, the preconditioner's cell data and the coarse
+ * factorization once for all cases of the block that have not converged;
+ * every case keeps its own recurrence (its own step lengths) and stops at its
+ * own first iteration that meets rtol, so its iterates, iteration count and
+ * solution equal those of lbddc_solve_sequential. */
 typedef struct {
   int32_t iters;
   double rel_res;
   double true_rel_res;
 } lbddc_solve_info;
 lbddc_status lbddc_solve(lbddc_ctx* ctx, double rtol, int32_t max_iter, lbddc_solve_info* info);
+
+/* lbddc_solve with the load cases solved one after another (one PCG per
+ * case): the reference for the block solve, same arguments and results. */
+lbddc_status lbddc_solve_sequential(lbddc_ctx* ctx, double rtol, int32_t max_iter, lbddc_solve_info* info);
 
 /* Displacement of load case `rhs` on the GLL node lattice, host buffer
  * u[(gy*(p*nx+1) + gx)*2 + c], gy in [0, p*ny], gx in [0, p*nx]. */

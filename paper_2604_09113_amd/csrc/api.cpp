@@ -297,6 +297,8 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
   std::vector<double> tab;
   build_tables(c, tab);
   const size_t nU = c->nU, nC = c->nC, NU = c->NU, NC = c->NC;
+  c->nblk = std::min(c->nrhs, kBlockRhs);
+  const size_t nbk = c->nblk;
   bool ok = dalloc_t(c, &c->d_tab, tab.size()) && dalloc_t(c, &c->d_ctrl, (size_t)netx * nety * 2) &&
             dalloc_t(c, &c->d_ctrl_bak, (size_t)netx * nety * 2) && dalloc_t(c, &c->d_t_bak, ncell) &&
             dalloc_t(c, &c->d_family, ncell) && dalloc_t(c, &c->d_t, ncell) &&
@@ -316,15 +318,17 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
             dalloc(c, &c->d_Psi, (size_t)ncell * nU * nC * 8) && dalloc_t(c, &c->d_D, (size_t)ncell * nU) &&
             dalloc_t(c, &c->d_ScLoc, (size_t)ncell * nC * (nC + 1) / 2) &&
             dalloc_t(c, &c->d_coarse, (size_t)c->co.nd_front_total) &&
-            dalloc_t(c, &c->d_up, (size_t)c->co.nd_up_total + 1) && dalloc_t(c, &c->d_beff, (size_t)c->co.nd_beff_total + 1) &&
+            dalloc_t(c, &c->d_up, ((size_t)c->co.nd_up_total + 1) * nbk) &&
+            dalloc_t(c, &c->d_beff, ((size_t)c->co.nd_beff_total + 1) * nbk) &&
             dalloc_t(c, &c->d_gjC, (size_t)c->co.nd_cp_total + 1) &&
             dalloc_t(c, &c->d_f_blk, (size_t)c->co.f_blk_total + 2) &&
             dalloc_t(c, &c->d_f, (size_t)c->nrhs * NU) && dalloc_t(c, &c->d_x, (size_t)c->nrhs * NU) &&
-            dalloc_t(c, &c->d_r, NU) && dalloc_t(c, &c->d_z, NU) && dalloc_t(c, &c->d_p, NU) && dalloc_t(c, &c->d_q, NU) &&
-            dalloc_t(c, &c->d_partU, (size_t)ncell * nU) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC) &&
-            dalloc_t(c, &c->d_zc, NC) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC) &&
-            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 272)) && dalloc_t(c, &c->d_scal, (size_t)(32 + NU / 1024 + 16)) &&
-            dalloc_t(c, &c->d_vred, (size_t)3 * (NU / 256 + 16)) &&
+            dalloc_t(c, &c->d_r, NU * nbk) && dalloc_t(c, &c->d_z, NU * nbk) && dalloc_t(c, &c->d_p, NU * nbk) &&
+            dalloc_t(c, &c->d_q, NU * nbk) &&
+            dalloc_t(c, &c->d_partU, (size_t)ncell * nU * nbk) && dalloc_t(c, &c->d_partC, (size_t)ncell * nC * nbk) &&
+            dalloc_t(c, &c->d_zc, NC * nbk) && dalloc_t(c, &c->d_tc, NC) && dalloc_t(c, &c->d_xc, NC * nbk) &&
+            dalloc_t(c, &c->d_red, (size_t)(std::max(NU, NC) / 256 + 272)) && dalloc_t(c, &c->d_scal, c->scal_stride() * nbk) &&
+            dalloc_t(c, &c->d_vred, c->vred_stride() * nbk) &&
             dalloc_t(c, &c->d_u, (size_t)c->nrhs * c->Gx * c->Gy * 2) &&
             dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&
             dalloc_t(c, &c->d_H, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_G, (size_t)ncell * c->ns * 4) &&
@@ -332,7 +336,7 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
             dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) &&
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
             dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8);
-  if (ok && hipHostMalloc((void**)&c->h_red, (size_t)(32 + c->NU / 1024 + 16) * sizeof(double),
+  if (ok && hipHostMalloc((void**)&c->h_red, c->scal_stride() * nbk * sizeof(double),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
     c->h_red = nullptr;
     c->err = "pinned host allocation failed";
@@ -549,7 +553,9 @@ lbddc_status lbddc_setup(lbddc_ctx* x, lbddc_precision prec) {
   return LBDDC_OK;
 }
 
-lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solve_info* info) {
+// Both solve entries: the load cases one PCG at a time (block = false), or in
+// blocks of up to kBlockRhs cases (block = true, the default for several).
+static lbddc_status solve_cases(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solve_info* info, bool block) {
   if (!x) return LBDDC_E_ARG;
   Ctx* c = &x->c;
   if (!c->setup_done) return fail(c, LBDDC_E_STATE, "solve: setup first");
@@ -567,33 +573,42 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
   HIPCHK(hipEventCreate(&e_start), "solve");
   HIPCHK(hipEventRecord(e_start, c->stream), "solve");
   lbddc_status status = LBDDC_OK;
-  for (int r = 0; r < c->nrhs; ++r) {
-    // right-hand side: gather-sum of the cell loads (f_I = 0 for edge tractions)
-    HIPCHK(gather_rhs(c, r), "solve rhs");
-    lbddc_solve_info inf{0, 0, 0};
-    hipError_t e = pcg_solve(c, r, rtol, max_iter, &inf, fp32, &t_op, &t_pre, &t_coarse, &t_cf, &t_cb, &napp);
-    nop += inf.iters;
+  const int step = block && c->nrhs > 1 ? c->nblk : 1;
+  for (int r0 = 0; r0 < c->nrhs; r0 += step) {
+    const int nr = std::min(step, c->nrhs - r0);
+    // right-hand sides: gather-sum of the cell loads (f_I = 0 for edge tractions)
+    for (int r = r0; r < r0 + nr; ++r) HIPCHK(gather_rhs(c, r), "solve rhs");
+    lbddc_solve_info* inf = c->info.data() + r0;
+    hipError_t e;
+    if (nr == 1) {
+      e = pcg_solve(c, r0, rtol, max_iter, inf, fp32, &t_op, &t_pre, &t_coarse, &t_cf, &t_cb, &napp);
+      nop += inf->iters;
+    } else {
+      e = pcg_solve_block(c, r0, nr, rtol, max_iter, inf, fp32, &t_op, &t_pre, &t_coarse, &t_cf, &t_cb, &napp,
+                          &nop);
+    }
     if (e == hipErrorUnknown) {
-      c->info[r] = inf;
-      if (info) info[r] = inf;
+      if (info)
+        for (int r = r0; r < r0 + nr; ++r) info[r] = c->info[r];
       hipStreamSynchronize(c->stream);
       return fail(c, LBDDC_E_BREAKDOWN, "solve: PCG breakdown (p^T S p <= 0 or r^T z <= 0)");
     }
     if (e != hipSuccess) return hipfail(c, e, "solve pcg");
-    HIPCHK(pcg_true_residual(c, r, &inf.true_rel_res), "solve residual");
-    hipEvent_t a, b;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    hipEventRecord(a, c->stream);
-    HIPCHK(launch_recover(c, r), "solve recovery");
-    hipEventRecord(b, c->stream);
-    hipEventSynchronize(b);
-    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) t_rec += ms;
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    c->info[r] = inf;
-    if (info) info[r] = inf;
-    if (inf.rel_res > rtol) status = LBDDC_E_NOT_CONVERGED;
+    for (int r = r0; r < r0 + nr; ++r) {
+      HIPCHK(pcg_true_residual(c, r, &c->info[r].true_rel_res), "solve residual");
+      hipEvent_t a, b;
+      hipEventCreate(&a);
+      hipEventCreate(&b);
+      hipEventRecord(a, c->stream);
+      HIPCHK(launch_recover(c, r), "solve recovery");
+      hipEventRecord(b, c->stream);
+      hipEventSynchronize(b);
+      if (hipEventElapsedTime(&ms, a, b) == hipSuccess) t_rec += ms;
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+      if (info) info[r] = c->info[r];
+      if (c->info[r].rel_res > rtol) status = LBDDC_E_NOT_CONVERGED;
+    }
   }
   HIPCHK(hipEventRecord(c->ev[6], c->stream), "solve");
   HIPCHK(hipEventSynchronize(c->ev[6]), "solve");
@@ -612,6 +627,14 @@ lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solv
   c->solved = true;
   if (status != LBDDC_OK) c->err = "solve: PCG reached max_iter before rtol";
   return status;
+}
+
+lbddc_status lbddc_solve(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solve_info* info) {
+  return solve_cases(x, rtol, max_iter, info, true);
+}
+
+lbddc_status lbddc_solve_sequential(lbddc_ctx* x, double rtol, int32_t max_iter, lbddc_solve_info* info) {
+  return solve_cases(x, rtol, max_iter, info, false);
 }
 
 lbddc_status lbddc_set_timing(lbddc_ctx* x, int32_t mask) {

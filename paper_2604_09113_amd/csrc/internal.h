@@ -17,6 +17,8 @@ namespace lbddc {
 constexpr int kMaxP = 10;
 constexpr int kMaxKC = 11;  // reduced basis + stabilisation column padded to 4*KC <= 44
 constexpr int kMaxDevices = 64;
+// load cases solved together by the block PCG (more are taken in blocks)
+constexpr int kBlockRhs = 8;
 
 // Doubles per cell of the interior elimination multipliers W of the local
 // Schur complement: interior and skeleton dofs each padded to 16-row tiles
@@ -312,11 +314,18 @@ struct Ctx {
   double* d_partC = nullptr;   // [ncell][nC]
   double *d_zc = nullptr, *d_tc = nullptr, *d_xc = nullptr;  // coarse vectors [NC]
   double* d_red = nullptr;     // reduction partials [kRedSlots][kMaxBlocks]
-  double* d_scal = nullptr;    // scalars
+  double* d_scal = nullptr;    // scalars, scal_stride() per load case of a block
   double* d_hred = nullptr;    // h_red as a device address (kernels write the r.r partials there)
   double* h_scal = nullptr;    // pinned
   double* d_vred = nullptr;    // interface-vector partials: p.q, r.z, r.r [3][NU / 256 + 16]
   double* h_red = nullptr;     // pinned, coherent: the r.r partials and breakdown flag of the last update
+  // The iteration vectors r, z, p, q (NU), the cell partials, the coarse
+  // vectors zc, xc (NC), the sweep vectors up and beff, the scalars, the
+  // interface partials and the pinned poll buffer hold nblk load cases, one
+  // after another.
+  int nblk = 1;
+  size_t scal_stride() const { return (size_t)(32 + NU / 1024 + 16); }
+  size_t vred_stride() const { return (size_t)3 * (NU / 256 + 16); }
   double* d_u = nullptr;       // [nrhs][Gy][Gx][2]
   std::vector<lbddc_solve_info> info;
 
@@ -370,10 +379,25 @@ hipError_t launch_precond(Ctx* c, bool fp32); // A5, A6, A7
 hipError_t launch_coarse_assemble(Ctx* c);   // A8 assembly of S_C blocks
 hipError_t prepare_fused_sweeps(Ctx* c);     // LDS limit of the fused bottom-level sweeps
 hipError_t launch_coarse_factor(Ctx* c);     // A8 nested-dissection FP64 factorization (and the fused blocks)
-hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid = nullptr);  // A8 solve
+// The load cases of one coarse sweep launch, all served by every workgroup:
+// load case y has its right-hand side and solution y * v doubles after the first,
+// its up vectors y * up and its effective right-hand sides y * beff doubles
+// further; cases whose bit in mask is clear are skipped.
+struct SweepVecs {
+  long long v, up, beff;
+  unsigned mask;
+  int nr;  // load cases 0 .. nr - 1 (those with their bit in mask are solved)
+};
+// A8 solve of nr load cases at once (right-hand sides rhs + k NC, solutions
+// x + k NC; the cases with a clear bit in mask are left untouched)
+hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid = nullptr, int nr = 1,
+                               unsigned mask = 1u);
 hipError_t pcg_solve(Ctx* c, int rhs, double rtol, int max_iter, lbddc_solve_info* info, bool fp32,
                      double* t_op, double* t_pre, double* t_coarse, double* t_cfwd, double* t_cbwd,
                      int* n_apply);  // A9
+hipError_t pcg_solve_block(Ctx* c, int r0, int nr, double rtol, int max_iter, lbddc_solve_info* info, bool fp32,
+                           double* t_op, double* t_pre, double* t_coarse, double* t_cfwd, double* t_cbwd,
+                           int* n_apply, int* n_op);  // A9, nr <= kBlockRhs load cases at once
 hipError_t pcg_true_residual(Ctx* c, int rhs, double* out);
 hipError_t gather_rhs(Ctx* c, int rhs);
 hipError_t launch_recover(Ctx* c, int rhs);  // A10

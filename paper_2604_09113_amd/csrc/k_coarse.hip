@@ -666,9 +666,12 @@ __device__ __forceinline__ void pull_sum(const NDItem& d, const double* __restri
 // requested before the right-hand side is gathered; the four wave partials
 // are added in a fixed order.  The items of column block 0 store b_eff of
 // their rows for the backward sweep.
+template <bool MC>
 __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items, const int2* __restrict__ fsrc,
                                                 const double* __restrict__ F, const double* __restrict__ b,
-                                                double* __restrict__ up, double* __restrict__ beff) {
+                                                double* __restrict__ up, double* __restrict__ beff, SweepVecs sv) {
+  if (sv.mask == 0u) return;
+  const int k0 = __builtin_ctz(sv.mask);  // the first load case; the M^T rows serve every case
   __shared__ double w[128];  // [0, 64): w on rows kb.., [64, 128): w_b on columns r0..
   __shared__ double pr[4][64];
   const NDItem d = items[blockIdx.x];
@@ -681,10 +684,11 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
   const bool own = t < 64;
   const bool ok = t < 128 && (own ? kb + t < ke : (d.kpart == 0 && d.first + (t - 64) < d.nb));
   const int j = ok ? (own ? kb + t : d.ns + d.first + (t - 64)) : 0;
+  const int jb = ok && own ? d.own_off + j : 0;
   // the item's gather sources (at a position known before the item itself)
   // and b ahead of M^T (the counter is in order)
   const int2 srcl = fsrc[(long long)blockIdx.x * 128 + (t < 128 ? t : 0)];
-  const double bj = b[ok && own ? d.own_off + j : 0];
+  const double bj0 = b[k0 * sv.v + jb];
   __builtin_amdgcn_sched_barrier(0);
   // unconditional loads of M^T: rows past ke read row 0 and meet zeros of w,
   // columns past nb read F[0] and are not stored (factor entries are finite)
@@ -695,28 +699,33 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
     const int k = kb + wv + 4 * u;
     a[u] = col[col_ok && k < ke ? (long long)k * nf : 0];
   }
-  if (t < 128) {
-    double v = own ? bj : 0.0;
-    {
-      double c0, c1;
-      const int2 src = ok ? srcl : make_int2(-1, -1);
-      pull_sum<8>(d, up, src, pull_load<8>(d, up, src), c0, c1);
-      v += c0;
-      v += c1;
+  for (int k = k0; k < (MC ? sv.nr : k0 + 1); ++k) {
+    if (MC && !((sv.mask >> k) & 1u)) continue;
+    double* __restrict__ upk = up + k * sv.up;
+    if (t < 128) {
+      double v = own ? (k == k0 ? bj0 : b[k * sv.v + jb]) : 0.0;
+      {
+        double c0, c1;
+        const int2 src = ok ? srcl : make_int2(-1, -1);
+        pull_sum<8>(d, upk, src, pull_load<8>(d, upk, src), c0, c1);
+        v += c0;
+        v += c1;
+      }
+      v = ok ? v : 0.0;
+      if (ok && own && d.first == 0) beff[k * sv.beff + d.own_off + j] = v;
+      w[t] = v;
     }
-    v = ok ? v : 0.0;
-    if (ok && own && d.first == 0) beff[d.own_off + j] = v;
-    w[t] = v;
-  }
-  __syncthreads();
-  double s = 0.0;
+    __syncthreads();
+    double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) s += a[u] * w[wv + 4 * u];
-  pr[wv][lane] = s;
-  __syncthreads();
-  if (wv == 0 && col_ok) {
-    const double tot = ((pr[0][lane] + pr[1][lane]) + pr[2][lane]) + pr[3][lane];
-    up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w[64 + lane] : 0.0) - tot;
+    for (int u = 0; u < 16; ++u) s += a[u] * w[wv + 4 * u];
+    pr[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && col_ok) {
+      const double tot = ((pr[0][lane] + pr[1][lane]) + pr[2][lane]) + pr[3][lane];
+      upk[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w[64 + lane] : 0.0) - tot;
+    }
+    __syncthreads();  // w and pr are rewritten for the next case
   }
 }
 
@@ -726,21 +735,21 @@ __global__ __launch_bounds__(256) void k_nd_fwd(const NDItem* __restrict__ items
 // a pass requested before its first use (the first pass before the vector is
 // gathered); a butterfly sums each row.  LDS: nf doubles rounded up to a
 // multiple of 1024.
-template <int Q, int NCH>
+template <int Q, int NCH, bool MC>
 __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items, const int* __restrict__ bnd,
                                                 const double* __restrict__ F, const double* __restrict__ beff,
-                                                double* __restrict__ x) {
+                                                double* __restrict__ x, SweepVecs sv) {
   extern __shared__ double sh[];
   const NDItem d = items[blockIdx.x];
-  if (d.ns == 0) return;  // no own rows (the whole workgroup)
+  if (d.ns == 0 || sv.mask == 0u) return;  // no own rows (the whole workgroup)
   const int nf = d.ns + d.nb, t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   // boundary indices of the first 1024 front positions (four per thread)
-  int g[4];
+  int g0[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int j = t + 256 * m;
-    g[m] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
+    g0[m] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
   }
   // keep the index loads ahead of the row loads (the counter is in order)
   __builtin_amdgcn_sched_barrier(0);
@@ -757,48 +766,7 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
     ok[q] = k < d.ns;
     rows[q] = F + d.foff + (long long)(ok[q] ? k : 0) * nf;
   }
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int j = lane + 64 * c;
-      a[q][c] = rows[q][j < nf ? j : 0];
-    }
-  // [b_eff; -x_b] into LDS: one load per position through a selected address,
-  // every value stored (the LDS vector is padded to a multiple of 1024); the
-  // first 1024 positions outside the loop, so their loads wait only for the
-  // boundary indices
-  auto gather = [&](int j0) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int j = j0 + t + 256 * m;
-      const bool is_b = j >= d.ns && j < nf, is_s = j < d.ns;
-      const double l = *(is_b ? x + g[m] : beff + (is_s ? d.own_off + j : 0));
-      sh[j] = is_b ? -l : (is_s ? l : 0.0);
-    }
-  };
-  gather(0);
-  for (int j0 = 1024; j0 < nf; j0 += 1024) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int j = j0 + t + 256 * m;
-      g[m] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
-    }
-    gather(j0);
-  }
-  __syncthreads();
-  double s[Q];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) s[q] = 0.0;
-  for (int c0 = 0;;) {
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const double vj = sh[c0 + lane + 64 * c];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) s[q] += a[q][c] * vj;
-    }
-    c0 += 64 * NCH;
-    if (c0 >= nf) break;
+  auto load_pass = [&](int c0) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -806,12 +774,64 @@ __global__ __launch_bounds__(256) void k_nd_bwd(const NDItem* __restrict__ items
         const int j = c0 + lane + 64 * c;
         a[q][c] = rows[q][j < nf ? j : 0];
       }
-  }
+  };
+  load_pass(0);
+  // the first pass of rows stays in registers for every load case in the mask
+  // (fronts wider than one pass reload it, from the cache, for the next case)
+  const bool multi = nf > 64 * NCH;
+  bool first = true;
+  for (int k = 0; k < (MC ? sv.nr : 1); ++k) {
+    if (MC && !((sv.mask >> k) & 1u)) continue;
+    const double* __restrict__ bk = beff + k * sv.beff;
+    double* __restrict__ xk = x + k * sv.v;
+    if (!first) {
+      __syncthreads();  // the previous case's reads of sh are done
+      if (multi) load_pass(0);
+    }
+    first = false;
+    // [b_eff; -x_b] into LDS: one load per position through a selected
+    // address, every value stored (the LDS vector is padded to a multiple of
+    // 1024); the first 1024 positions with the indices read above
+    auto gather = [&](int j0, const int (&g)[4]) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    double v = s[q];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == 0 && ok[q]) x[d.own_off + d.first + wv + 4 * q] = v;
+      for (int m = 0; m < 4; ++m) {
+        const int j = j0 + t + 256 * m;
+        const bool is_b = j >= d.ns && j < nf, is_s = j < d.ns;
+        const double l = *(is_b ? xk + g[m] : bk + (is_s ? d.own_off + j : 0));
+        sh[j] = is_b ? -l : (is_s ? l : 0.0);
+      }
+    };
+    gather(0, g0);
+    for (int j0 = 1024; j0 < nf; j0 += 1024) {
+      int g[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int j = j0 + t + 256 * m;
+        g[m] = bnd[(j >= d.ns && j < nf) ? d.bnd_off + j - d.ns : 0];
+      }
+      gather(j0, g);
+    }
+    __syncthreads();
+    double s[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s[q] = 0.0;
+    for (int c0 = 0;;) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) {
+        const double vj = sh[c0 + lane + 64 * c];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) s[q] += a[q][c] * vj;
+      }
+      c0 += 64 * NCH;
+      if (c0 >= nf) break;
+      load_pass(c0);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      double v = s[q];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0 && ok[q]) xk[d.own_off + d.first + wv + 4 * q] = v;
+    }
   }
 }
 
@@ -827,10 +847,10 @@ __device__ __forceinline__ double read_lane(double v, int src) {
 // k_nd_fwd.  Lane l pulls front position kb + l (own row) and boundary
 // column r0 + l, reads the R rows of M^T in its column, and takes w_k from
 // lane k - kb.
-template <int R, int CK>
+template <int R, int CK, bool MC>
 __device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict__ fsrc,
                                          const double* __restrict__ F, const double* __restrict__ b,
-                                         double* __restrict__ up, double* __restrict__ beff) {
+                                         double* __restrict__ up, double* __restrict__ beff, const SweepVecs& sv) {
   const int lane = threadIdx.x & 63, nf = d.ns + d.nb, r = d.first + lane;
   const int kb = d.kpart * ND_KPART, ke = min(d.ns, kb + R);
   const bool col_ok = r < d.nb;
@@ -839,32 +859,38 @@ __device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict
   const bool has_ch = d.pull_off >= 0;
   const int2 s1 = fsrc[lane];
   const int2 s2 = fsrc[64 + lane];
-  const double b1 = b[ok1 ? d.own_off + j1 : 0];
+  const int k0 = __builtin_ctz(sv.mask);
+  const double b10 = b[k0 * sv.v + (ok1 ? d.own_off + j1 : 0)];
   __builtin_amdgcn_sched_barrier(0);  // indices ahead of M^T (the counter is in order)
   // rows past ke read row 0 and meet w = 0; columns past nb are not stored
   const double* col = col_ok ? F + d.foff + d.ns + r : F;
   double a[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) a[u] = col[col_ok && kb + u < ke ? (long long)(kb + u) * nf : 0];
-  double w1 = b1, w2 = 0.0;
-  if (has_ch) {
-    double c0, c1, e0, e1;
-    const int2 p1 = ok1 ? s1 : make_int2(-1, -1), p2 = ok2 ? s2 : make_int2(-1, -1);
-    const Pulled<CK> l1 = pull_load<CK>(d, up, p1);
-    const Pulled<CK> l2 = pull_load<CK>(d, up, p2);
-    pull_sum<CK>(d, up, p1, l1, c0, c1);
-    pull_sum<CK>(d, up, p2, l2, e0, e1);
-    w1 += c0;
-    w1 += c1;
-    w2 += e0;
-    w2 += e1;
-  }
-  w1 = ok1 ? w1 : 0.0;
-  if (ok1 && d.first == 0) beff[d.own_off + j1] = w1;
-  double acc = 0.0;
+  // the rows of M^T stay in registers for every load case in the mask
+  for (int k = k0; k < (MC ? sv.nr : k0 + 1); ++k) {
+    if (MC && !((sv.mask >> k) & 1u)) continue;
+    double* __restrict__ upk = up + k * sv.up;
+    double w1 = k == k0 ? b10 : b[k * sv.v + (ok1 ? d.own_off + j1 : 0)], w2 = 0.0;
+    if (has_ch) {
+      double c0, c1, e0, e1;
+      const int2 p1 = ok1 ? s1 : make_int2(-1, -1), p2 = ok2 ? s2 : make_int2(-1, -1);
+      const Pulled<CK> l1 = pull_load<CK>(d, upk, p1);
+      const Pulled<CK> l2 = pull_load<CK>(d, upk, p2);
+      pull_sum<CK>(d, upk, p1, l1, c0, c1);
+      pull_sum<CK>(d, upk, p2, l2, e0, e1);
+      w1 += c0;
+      w1 += c1;
+      w2 += e0;
+      w2 += e1;
+    }
+    w1 = ok1 ? w1 : 0.0;
+    if (ok1 && d.first == 0) beff[k * sv.beff + d.own_off + j1] = w1;
+    double acc = 0.0;
 #pragma unroll
-  for (int u = 0; u < R; ++u) acc += a[u] * read_lane(w1, u);
-  if (col_ok) up[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w2 : 0.0) - acc;
+    for (int u = 0; u < R; ++u) acc += a[u] * read_lane(w1, u);
+    if (col_ok) upk[d.up_off + d.kpart * d.nb + r] = (d.kpart == 0 ? w2 : 0.0) - acc;
+  }
 }
 
 // Backward item of 16 own rows [k0, k0 + 16) taken by one wave: rows of
@@ -873,9 +899,9 @@ __device__ __forceinline__ void fwd_task(const NDItem& d, const int2* __restrict
 // over the lanes leaves row 8 b5 + 4 b4 + 2 b3 + b2 (bits of the lane id) in
 // the lanes with b1 = b0 = 0.
 static_assert(ND_BW_ROWS == 16, "bwd_task takes items of 16 rows");
-template <int NCH>
+template <int NCH, bool MC>
 __device__ __forceinline__ void bwd_task(const NDItem& d, const int* __restrict__ bnd, const double* __restrict__ F,
-                                         const double* __restrict__ beff, double* __restrict__ x) {
+                                         const double* __restrict__ beff, double* __restrict__ x, const SweepVecs& sv) {
   if (d.ns == 0) return;
   const int lane = threadIdx.x & 63, nf = d.ns + d.nb;
   int g[NCH];
@@ -897,12 +923,17 @@ __device__ __forceinline__ void bwd_task(const NDItem& d, const int* __restrict_
       a[q][c] = row[j < nf ? j : 0];
     }
   }
+  // the rows stay in registers for every load case in the mask
+  for (int k = 0; k < (MC ? sv.nr : 1); ++k) {
+  if (MC && !((sv.mask >> k) & 1u)) continue;
+  const double* __restrict__ bk = beff + k * sv.beff;
+  double* __restrict__ xk = x + k * sv.v;
   double v[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     const int j = lane + 64 * c;
     const bool is_b = j >= d.ns && j < nf, is_s = j < d.ns;
-    const double l = *(is_b ? x + g[c] : beff + (is_s ? d.own_off + j : 0));
+    const double l = *(is_b ? xk + g[c] : bk + (is_s ? d.own_off + j : 0));
     v[c] = is_b ? -l : (is_s ? l : 0.0);
   }
   double s[16];
@@ -939,25 +970,27 @@ __device__ __forceinline__ void bwd_task(const NDItem& d, const int* __restrict_
   t1 += __shfl_xor(t1, 2);
   t1 += __shfl_xor(t1, 1);
   const int q = (b5 ? 8 : 0) + (b4 ? 4 : 0) + (b3 ? 2 : 0) + (b2 ? 1 : 0);
-  if ((lane & 3) == 0 && d.first + q < d.ns) x[d.own_off + d.first + q] = t1;
+  if ((lane & 3) == 0 && d.first + q < d.ns) xk[d.own_off + d.first + q] = t1;
+  }
 }
 
 // Items of the lower tree levels (many small fronts): one per wave, four
 // per workgroup.
-template <int R, int CK>
+template <int R, int CK, bool MC>
 __global__ __launch_bounds__(256) void k_nd_fwd_w(const NDItem* __restrict__ items, int nitems,
                                                   const int2* __restrict__ fsrc, const double* __restrict__ F,
                                                   const double* __restrict__ b, double* __restrict__ up,
-                                                  double* __restrict__ beff) {
-  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (it < nitems) fwd_task<R, CK>(items[it], fsrc + (long long)it * 128, F, b, up, beff);
+                                                  double* __restrict__ beff, SweepVecs sv) {
+  if (sv.mask == 0u) return;
+  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (all load cases)
+  if (it < nitems) fwd_task<R, CK, MC>(items[it], fsrc + (long long)it * 128, F, b, up, beff, sv);
 }
-template <int NCH>
+template <int NCH, bool MC>
 __global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ items, int nitems,
                                                   const int* __restrict__ bnd, const double* __restrict__ F,
-                                                  const double* __restrict__ beff, double* __restrict__ x) {
-  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (it < nitems) bwd_task<NCH>(items[it], bnd, F, beff, x);
+                                                  const double* __restrict__ beff, double* __restrict__ x, SweepVecs sv) {
+  const int it = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (all load cases)
+  if (it < nitems) bwd_task<NCH, MC>(items[it], bnd, F, beff, x, sv);
 }
 
 // The bottom levels of the tree in one launch per sweep: workgroup = one
@@ -967,29 +1000,30 @@ __global__ __launch_bounds__(256) void k_nd_bwd_w(const NDItem* __restrict__ ite
 // wrote to global memory (up vectors, solution entries): the barrier between
 // stages orders them at workgroup scope.  stage_off[(sub) (nst + 1) + s] is
 // the first item of stage s of subtree `sub`.
-template <int R, int CK>
+template <int R, int CK, bool MC>
 __global__ __launch_bounds__(256) void k_nd_fwd_sub(const NDItem* __restrict__ items,
                                                     const int* __restrict__ stage_off, int nst,
                                                     const int2* __restrict__ fsrc, const double* __restrict__ F,
                                                     const double* __restrict__ b, double* __restrict__ up,
-                                                    double* __restrict__ beff) {
+                                                    double* __restrict__ beff, SweepVecs sv) {
+  if (sv.mask == 0u) return;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int* so = stage_off + (long long)blockIdx.x * (nst + 1);
+  const int* so = stage_off + (long long)blockIdx.x * (nst + 1);  // (all load cases)
   for (int st = 0; st < nst; ++st) {
     for (int it = so[st] + wv; it < so[st + 1]; it += 4)
-      fwd_task<R, CK>(items[it], fsrc + (long long)it * 128, F, b, up, beff);
+      fwd_task<R, CK, MC>(items[it], fsrc + (long long)it * 128, F, b, up, beff, sv);
     __syncthreads();
   }
 }
-template <int NCH>
+template <int NCH, bool MC>
 __global__ __launch_bounds__(256) void k_nd_bwd_sub(const NDItem* __restrict__ items,
                                                     const int* __restrict__ stage_off, int nst,
                                                     const int* __restrict__ bnd, const double* __restrict__ F,
-                                                    const double* __restrict__ beff, double* __restrict__ x) {
+                                                    const double* __restrict__ beff, double* __restrict__ x, SweepVecs sv) {
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int* so = stage_off + (long long)blockIdx.x * (nst + 1);
+  const int* so = stage_off + (long long)blockIdx.x * (nst + 1);  // (all load cases)
   for (int st = 0; st < nst; ++st) {
-    for (int it = so[st] + wv; it < so[st + 1]; it += 4) bwd_task<NCH>(items[it], bnd, F, beff, x);
+    for (int it = so[st] + wv; it < so[st + 1]; it += 4) bwd_task<NCH, MC>(items[it], bnd, F, beff, x, sv);
     __syncthreads();
   }
 }
@@ -1015,12 +1049,20 @@ __device__ __forceinline__ int fused_node_of(const FusedNode* nd, int n0, int n1
   return i;
 }
 
+__device__ __forceinline__ void fused_levels(const FusedSub& S, const FusedNode* nd, const short4 (&e)[ND_FUSED_ENT],
+                                             int e0, const double* sh, double* vec, const double* bvs,
+                                             double* __restrict__ up, double* __restrict__ beff);
+template <bool MC>
 __global__ __launch_bounds__(ND_FUSED_THREADS) void k_nd_fwd_fused(const FusedSub* __restrict__ subs,
                                                                    const FusedNode* __restrict__ nodes,
                                                                    const short4* __restrict__ went,
                                                                    const double* __restrict__ blk,
                                                                    const double* __restrict__ b,
-                                                                   double* __restrict__ up, double* __restrict__ beff) {
+                                                                   double* __restrict__ up, double* __restrict__ beff, SweepVecs sv) {
+  // one workgroup per subtree for all load cases: the subtree's data is staged
+  // once, the levels run once per case in the mask
+  if (sv.mask == 0u) return;
+  const int k0 = __builtin_ctz(sv.mask);
   extern __shared__ double2 sh2[];  // 16-byte aligned for the block stores
   double* sh = reinterpret_cast<double*>(sh2);
   __shared__ FusedNode nd[16];
@@ -1045,7 +1087,7 @@ __global__ __launch_bounds__(ND_FUSED_THREADS) void k_nd_fwd_fused(const FusedSu
     e[u] = went[i < e1 ? i : e0];
   }
   const FusedNode fn = nodes[S.node0 + (t < nnode ? t : 0)];
-  const double bv = b[S.own_off + (t < S.own_n ? t : 0)];
+  const double bv = b[k0 * sv.v + S.own_off + (t < S.own_n ? t : 0)];
   __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first store
   // unconditional stores (a lane past the end stores what it read from the
   // clamped position, the same value as the owner of that position), so that
@@ -1060,7 +1102,26 @@ __global__ __launch_bounds__(ND_FUSED_THREADS) void k_nd_fwd_fused(const FusedSu
   double* bvs = vec + S.vec_n;
   nd[t < nnode ? t : 0] = fn;
   bvs[t < S.own_n ? t : 0] = bv;
-  __syncthreads();
+  for (int k = k0; k < (MC ? sv.nr : k0 + 1); ++k) {
+    if (MC && !((sv.mask >> k) & 1u)) continue;
+    double* upk = up + k * sv.up;
+    double* beffk = beff + k * sv.beff;
+    if (k != k0) {  // the previous case's last level ended with a barrier
+      const double bk = b[k * sv.v + S.own_off + (t < S.own_n ? t : 0)];
+      bvs[t < S.own_n ? t : 0] = bk;
+    }
+    __syncthreads();
+    fused_levels(S, nd, e, e0, sh, vec, bvs, upk, beffk);
+  }
+}
+
+// The levels of one fused forward sweep for one load case (the subtree's
+// M^T, node table and entry program staged, the case's own right-hand side in
+// bvs): see k_nd_fwd_fused.
+__device__ __forceinline__ void fused_levels(const FusedSub& S, const FusedNode* nd, const short4 (&e)[ND_FUSED_ENT],
+                                             int e0, const double* sh, double* vec, const double* bvs,
+                                             double* __restrict__ up, double* __restrict__ beff) {
+  const int t = threadIdx.x;
   for (int d = ND_FUSED_LEVELS - 1; d >= 0; --d) {
     // w of every front position of the level's nodes: own right-hand side plus
     // the children's up vectors (b_eff of the own rows is kept for the
@@ -1125,8 +1186,11 @@ static size_t fused_lds_bytes(const CoarseLayout& co);
 // LDS beyond the default dynamic limit for the fused sweep kernels
 hipError_t prepare_fused_sweeps(Ctx* c) {
   if (!c->co.fused) return hipSuccess;
-  return hipFuncSetAttribute((const void*)k_nd_fwd_fused, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)fused_lds_bytes(c->co));
+  const int lds = (int)fused_lds_bytes(c->co);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_nd_fwd_fused<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_nd_fwd_fused<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 static size_t fused_lds_bytes(const CoarseLayout& co) {
@@ -1135,71 +1199,78 @@ static size_t fused_lds_bytes(const CoarseLayout& co) {
   return m * sizeof(double);
 }
 
-template <int Q>
-static void launch_bwd(int nch, dim3 grid, size_t lds, hipStream_t st, const NDItem* items, const int* bnd,
-                       const double* F, const double* beff, double* x) {
+template <int Q, bool MC>
+static void launch_bwd(int nch, int ni, size_t lds, hipStream_t st, const NDItem* items, const int* bnd,
+                       const double* F, const double* beff, double* x, SweepVecs sv) {
+  const dim3 grid(ni);
   if (nch <= 2)
-    hipLaunchKernelGGL((k_nd_bwd<Q, 2>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+    hipLaunchKernelGGL((k_nd_bwd<Q, 2, MC>), grid, dim3(256), lds, st, items, bnd, F, beff, x, sv);
   else if (nch <= 4)
-    hipLaunchKernelGGL((k_nd_bwd<Q, 4>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+    hipLaunchKernelGGL((k_nd_bwd<Q, 4, MC>), grid, dim3(256), lds, st, items, bnd, F, beff, x, sv);
   else if (nch <= 8)
-    hipLaunchKernelGGL((k_nd_bwd<Q, 8>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+    hipLaunchKernelGGL((k_nd_bwd<Q, 8, MC>), grid, dim3(256), lds, st, items, bnd, F, beff, x, sv);
   else
-    hipLaunchKernelGGL((k_nd_bwd<Q, 16>), grid, dim3(256), lds, st, items, bnd, F, beff, x);
+    hipLaunchKernelGGL((k_nd_bwd<Q, 16, MC>), grid, dim3(256), lds, st, items, bnd, F, beff, x, sv);
 }
 
 // Levels with at least this many items take the one-item-per-wave kernels.
 constexpr int ND_WAVE_ITEMS = 512;
 
-template <int R>
-static void launch_fwd_w(int ck, int ni, hipStream_t st, const NDItem* items, const int2* fsrc, const double* F,
-                         const double* b, double* up, double* beff) {
+template <int R, bool MC>
+static void launch_fwd_w(int ck, int ni, hipStream_t st, const NDItem* items, const int2* fsrc,
+                         const double* F, const double* b, double* up, double* beff, SweepVecs sv) {
   const dim3 grid((ni + 3) / 4);
   if (ck <= 1)
-    hipLaunchKernelGGL((k_nd_fwd_w<R, 1>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff);
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 1, MC>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff, sv);
   else if (ck <= 2)
-    hipLaunchKernelGGL((k_nd_fwd_w<R, 2>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff);
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 2, MC>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff, sv);
   else
-    hipLaunchKernelGGL((k_nd_fwd_w<R, 8>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff);
+    hipLaunchKernelGGL((k_nd_fwd_w<R, 8, MC>), grid, dim3(256), 0, st, items, ni, fsrc, F, b, up, beff, sv);
 }
 
-template <int R>
-static void launch_fwd_sub(const Ctx* c, const double* rhs) {
+template <int R, bool MC>
+static void launch_fwd_sub(const Ctx* c, const double* rhs, SweepVecs sv) {
   const CoarseLayout& co = c->co;
   const int ck = co.sub_child_kparts;
   const dim3 grid(co.sub_count);
   const int2* pull = c->d_sub_fw_src;
   if (ck <= 1)
-    hipLaunchKernelGGL((k_nd_fwd_sub<R, 1>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
-                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+    hipLaunchKernelGGL((k_nd_fwd_sub<R, 1, MC>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
+                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff, sv);
   else if (ck <= 2)
-    hipLaunchKernelGGL((k_nd_fwd_sub<R, 2>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
-                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+    hipLaunchKernelGGL((k_nd_fwd_sub<R, 2, MC>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
+                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff, sv);
   else
-    hipLaunchKernelGGL((k_nd_fwd_sub<R, 8>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
-                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+    hipLaunchKernelGGL((k_nd_fwd_sub<R, 8, MC>), grid, dim3(256), 0, c->stream, c->d_sub_fw_items, c->d_sub_fw_off,
+                       co.sub_nst, pull, c->d_coarse, rhs, c->d_up, c->d_beff, sv);
 }
 
-hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid) {
+// The sweeps of one coarse solve; MC: the kernels loop over the load cases
+// of sv (every workgroup reads its factor rows once for all of them), else
+// one case (the instances without the loop keep the single-case registers).
+template <bool MC>
+static hipError_t coarse_sweeps(Ctx* c, const double* rhs, double* x, hipEvent_t mid, const SweepVecs& sv) {
   const CoarseLayout& co = c->co;
   const int L = (int)co.nd_levels.size();
   // forward: the subtrees of the bottom levels, then the upper levels one launch each
   int top = co.sub_level;
-  if (co.fused) {
+  // (several load cases: the per-wave subtree kernel, whose M^T rows stay in
+  // registers for every case; the fused kernel runs its levels case by case)
+  if (co.fused && !MC) {
     top = co.fused_level;
-    hipLaunchKernelGGL(k_nd_fwd_fused, dim3((unsigned)co.f_subs.size()), dim3(ND_FUSED_THREADS),
+    hipLaunchKernelGGL(k_nd_fwd_fused<MC>, dim3((unsigned)co.f_subs.size()), dim3(ND_FUSED_THREADS),
                        fused_lds_bytes(co), c->stream, c->d_f_subs, c->d_f_nodes, c->d_f_went, c->d_f_blk,
-                       rhs, c->d_up, c->d_beff);
+                       rhs, c->d_up, c->d_beff, sv);
   } else if (co.sub_level < L) {
     const int rows = co.sub_fw_rows;
     if (rows <= 16)
-      launch_fwd_sub<16>(c, rhs);
+      launch_fwd_sub<16, MC>(c, rhs, sv);
     else if (rows <= 32)
-      launch_fwd_sub<32>(c, rhs);
+      launch_fwd_sub<32, MC>(c, rhs, sv);
     else if (rows <= 48)
-      launch_fwd_sub<48>(c, rhs);
+      launch_fwd_sub<48, MC>(c, rhs, sv);
     else
-      launch_fwd_sub<64>(c, rhs);
+      launch_fwd_sub<64, MC>(c, rhs, sv);
   }
   for (int l = top - 1; l >= 0; --l) {
     const int i0 = co.fw_off[l], ni = co.fw_off[l + 1] - i0;
@@ -1209,14 +1280,14 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
     const int rows = co.lvl_fw_rows[l], ck = co.lvl_child_kparts[l];
     if (ni >= ND_WAVE_ITEMS && rows <= 48) {
       if (rows <= 16)
-        launch_fwd_w<16>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+        launch_fwd_w<16, MC>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff, sv);
       else if (rows <= 32)
-        launch_fwd_w<32>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+        launch_fwd_w<32, MC>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff, sv);
       else
-        launch_fwd_w<48>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff);
+        launch_fwd_w<48, MC>(ck, ni, c->stream, it, pull, c->d_coarse, rhs, c->d_up, c->d_beff, sv);
     } else {
-      hipLaunchKernelGGL(k_nd_fwd, dim3(ni), dim3(256), 0, c->stream, it, pull, c->d_coarse, rhs, c->d_up,
-                         c->d_beff);
+      hipLaunchKernelGGL(k_nd_fwd<MC>, dim3(ni), dim3(256), 0, c->stream, it, pull, c->d_coarse, rhs, c->d_up,
+                         c->d_beff, sv);
     }
   }
   if (mid) hipEventRecord(mid, c->stream);
@@ -1233,38 +1304,46 @@ hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t 
     const int nf = std::max(1, co.lvl_nfmax[l]);
     const int nch = (nf + 63) / 64;
     if (co.lvl_bw_rows[l] == 16 && ni >= ND_WAVE_ITEMS && nch <= 4) {
-      const dim3 grid((ni + 3) / 4);
+      const dim3 grid((ni + 3) / 4);  // every load case in each workgroup
       if (nch <= 2)
-        hipLaunchKernelGGL(k_nd_bwd_w<2>, grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
-                           c->d_beff, x);
+        hipLaunchKernelGGL((k_nd_bwd_w<2, MC>), grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
+                           c->d_beff, x, sv);
       else if (nch <= 3)
-        hipLaunchKernelGGL(k_nd_bwd_w<3>, grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
-                           c->d_beff, x);
+        hipLaunchKernelGGL((k_nd_bwd_w<3, MC>), grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
+                           c->d_beff, x, sv);
       else
-        hipLaunchKernelGGL(k_nd_bwd_w<4>, grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
-                           c->d_beff, x);
+        hipLaunchKernelGGL((k_nd_bwd_w<4, MC>), grid, dim3(256), 0, c->stream, it, ni, c->d_nd_bnd, c->d_coarse,
+                           c->d_beff, x, sv);
       continue;
     }
     const size_t lds = (size_t)((nf + 1023) / 1024 * 1024) * sizeof(double);
     if (co.lvl_bw_rows[l] == 4)
-      launch_bwd<1>(nch, dim3(ni), lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      launch_bwd<1, MC>(nch, ni, lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x, sv);
     else
-      launch_bwd<ND_BW_ROWS / 4>(nch, dim3(ni), lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      launch_bwd<ND_BW_ROWS / 4, MC>(nch, ni, lds, c->stream, it, c->d_nd_bnd, c->d_coarse, c->d_beff, x, sv);
   }
   if (co.sub_level < L) {
     const int nch = (std::max(1, co.sub_nfmax) + 63) / 64;
-    const dim3 grid(co.sub_count);
+    const dim3 grid(co.sub_count);  // every load case in each workgroup
     if (nch <= 2)
-      hipLaunchKernelGGL(k_nd_bwd_sub<2>, grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
-                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      hipLaunchKernelGGL((k_nd_bwd_sub<2, MC>), grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
+                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x, sv);
     else if (nch <= 3)
-      hipLaunchKernelGGL(k_nd_bwd_sub<3>, grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
-                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      hipLaunchKernelGGL((k_nd_bwd_sub<3, MC>), grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
+                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x, sv);
     else
-      hipLaunchKernelGGL(k_nd_bwd_sub<4>, grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
-                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x);
+      hipLaunchKernelGGL((k_nd_bwd_sub<4, MC>), grid, dim3(256), 0, c->stream, c->d_sub_bw_items, c->d_sub_bw_off,
+                         co.sub_nst, c->d_nd_bnd, c->d_coarse, c->d_beff, x, sv);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_coarse_solve(Ctx* c, const double* rhs, double* x, hipEvent_t mid, int nr, unsigned mask) {
+  const CoarseLayout& co = c->co;
+  // the load cases' sweep vectors are laid out one after another with the
+  // strides the context allocated
+  const SweepVecs sv{(long long)c->NC, (long long)co.nd_up_total + 1, (long long)co.nd_beff_total + 1, mask, nr};
+  return nr > 1 ? coarse_sweeps<true>(c, rhs, x, mid, sv) : coarse_sweeps<false>(c, rhs, x, mid, sv);
 }
 
 }  // namespace lbddc

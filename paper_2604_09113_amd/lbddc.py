@@ -32,6 +32,7 @@ PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor
 
 FUNCTIONS = ["lbddc_create", "lbddc_destroy", "lbddc_last_error", "lbddc_version", "lbddc_load_rom",
              "lbddc_set_problem", "lbddc_set_geometry_device", "lbddc_assemble", "lbddc_setup", "lbddc_solve",
+             "lbddc_solve_sequential",
              "lbddc_get_displacement", "lbddc_get_displacement_device", "lbddc_compliance_gradient",
              "lbddc_compliance_gradient_device", "lbddc_query", "lbddc_export_cells", "lbddc_phase_times",
              "lbddc_set_timing", "lbddc_assemble_fp32_noalloc", "lbddc_coarse_solve"]
@@ -94,6 +95,7 @@ def library():
         "lbddc_assemble": (C.c_int, [P, C.c_int]),
         "lbddc_setup": (C.c_int, [P, C.c_int]),
         "lbddc_solve": (C.c_int, [P, C.c_double, C.c_int32, C.POINTER(SolveInfo)]),
+        "lbddc_solve_sequential": (C.c_int, [P, C.c_double, C.c_int32, C.POINTER(SolveInfo)]),
         "lbddc_get_displacement": (C.c_int, [P, C.c_int32, dp]),
         "lbddc_get_displacement_device": (C.c_int, [P, C.c_int32, P]),
         "lbddc_compliance_gradient": (C.c_int, [P, dp, dp, dp]),
@@ -190,9 +192,11 @@ class Solver:
     def setup(self, prec=FP64):
         self._check(self.lib.lbddc_setup(self.ctx, prec))
 
-    def solve(self, rtol=1e-8, max_iter=1000, raise_on_not_converged=True):
+    def solve(self, rtol=1e-8, max_iter=1000, raise_on_not_converged=True, sequential=False):
+        """lbddc_solve (load cases in blocks), or lbddc_solve_sequential."""
         info = (SolveInfo * self.nrhs)()
-        st = self.lib.lbddc_solve(self.ctx, rtol, max_iter, info)
+        fn = self.lib.lbddc_solve_sequential if sequential else self.lib.lbddc_solve
+        st = fn(self.ctx, rtol, max_iter, info)
         if st != OK and (st != E_NOT_CONVERGED or raise_on_not_converged):
             self._check(st)
         return [dict(iters=i.iters, rel_res=i.rel_res, true_rel_res=i.true_rel_res) for i in info]
