@@ -233,6 +233,138 @@ def cpu_baseline(prob_full, roms, solver):
                 sampled_Ki_rel_frobenius_vs_gpu_fp64=max(errs))
 
 
+def bench_cases(args, prob, roms):
+    """The workload with several load cases (random edge tractions), solved as
+    one block per PCG: a step is assembly, setup, the block solve of every case
+    at the tolerance calibrated for 1e-8 against an FP64 reference, and the
+    compliance gradients of every case.  Beside it, solve-only times of the
+    block, of the cases one after another and of the first case alone on the
+    same lattice."""
+    import torch
+    from paper_2604_09113_amd import lbddc
+    ncell = prob["nx"] * prob["ny"]
+    nr = prob["traction"].shape[0]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def make(pr):
+        sv = lbddc.Solver(0, stream)
+        for r in roms.values():
+            sv.load_rom(**r)
+        sv.set_problem(pr["nx"], pr["ny"], pr["p"], pr["q"], pr["m"], pr["ctrl"], pr["family"], pr["t"], pr["E"],
+                       pr["nu"], pr["rho"], pr["moments"], pr["traction"], clamped=pr["clamped"], loaded=pr["loaded"])
+        return sv
+
+    s = make(prob)
+    sizes = {"coarse_dofs": s.query(lbddc.Q_N_COARSE), "skeleton_dofs": s.query(lbddc.Q_N_SKELETON)}
+    s.assemble(lbddc.FP64)
+    s.setup(lbddc.FP64)
+    info = s.solve(rtol=1e-13, max_iter=5000)
+    u_ref = [s.displacement(r) for r in range(nr)]
+    log(f"[bench] reference solve ({nr} cases): {[i['iters'] for i in info]} its")
+
+    def calibrate(prec):
+        s.setup(prec)
+        for rtol in (1e-8, 1e-9, 1e-10, 1e-11, 1e-12):
+            inf = s.solve(rtol=rtol, max_iter=5000)
+            err = max(np.abs(s.displacement(r) - u_ref[r]).max() / np.abs(u_ref[r]).max() for r in range(nr))
+            log(f"[bench] {('fp64', 'mixed')[prec]} rtol {rtol:.0e}: {[i['iters'] for i in inf]} its, "
+                f"max_r |u-u_ref| {err:.2e}")
+            if err <= 1e-8:
+                return rtol, [i["iters"] for i in inf], err
+        return rtol, [i["iters"] for i in inf], err
+
+    cal = {lbddc.FP64: calibrate(lbddc.FP64), lbddc.MIXED: calibrate(lbddc.MIXED)}
+
+    def step(prec):
+        s.assemble(lbddc.FP64)
+        s.setup(prec)
+        inf = s.solve(rtol=cal[prec][0], max_iter=5000)
+        s.compliance_gradient()
+        return inf, s.phase_times()
+
+    fwd_bytes = s.query(lbddc.Q_COARSE_FWD_BYTES)
+    bwd_bytes = s.query(lbddc.Q_COARSE_SOLVE_BYTES) - fwd_bytes
+    results = {}
+    for prec in (lbddc.MIXED, lbddc.FP64):
+        s.set_timing(lbddc.TIME_ALL)
+        for _ in range(args.warmup):
+            step(prec)
+        inf, prof = step(prec)
+        # the backward coarse sweep (the largest single kernel time of a step)
+        # timed live on one application in eight
+        s.set_timing(lbddc.TIME_COARSE | lbddc.TIME_SAMPLE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phases = []
+        for _ in range(args.steps):
+            inf, ph = step(prec)
+            phases.append(ph)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        s.set_timing(lbddc.TIME_ALL)
+        err = max(np.abs(s.displacement(r) - u_ref[r]).max() / np.abs(u_ref[r]).max() for r in range(nr))
+        mean = {k: float(np.mean([p[k] for p in phases])) for k in phases[0]}
+        results[prec] = dict(ms_per_step=dt * 1e3, iters=[i["iters"] for i in inf], rtol=cal[prec][0],
+                             u_err_max_over_cases=float(err), phases_ms=prof, timed_phases_ms=mean)
+        log(f"[bench] {('fp64', 'mixed')[prec]}: {dt * 1e3:.1f} ms/step; profiling step {json.dumps(prof)}")
+    # solve only: block, sequential, first case alone (mixed, rtol 1e-8, no phase events)
+    s.set_timing(0)
+    s.setup(lbddc.MIXED)
+
+    def timed_solve(sv, **kw):
+        best = None
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inf = sv.solve(rtol=1e-8, max_iter=5000, **kw)
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3
+            best = t if best is None else min(best, t)
+        return best, [i["iters"] for i in inf]
+
+    t_blk, it_blk = timed_solve(s)
+    t_seq, it_seq = timed_solve(s, sequential=True)
+    s.close()
+    p1 = dict(prob)
+    p1["traction"] = np.ascontiguousarray(prob["traction"][:1])
+    s1 = make(p1)
+    s1.assemble(lbddc.FP64)
+    s1.setup(lbddc.MIXED)
+    s1.set_timing(0)
+    t_one, it_one = timed_solve(s1)
+    s1.close()
+    log(f"[bench] solve only (mixed, rtol 1e-8): block {t_blk:.1f} ms {it_blk}, sequential {t_seq:.1f} ms, "
+        f"first case alone {t_one:.1f} ms {it_one}")
+    mixed = results[lbddc.MIXED]
+    napp = max(mixed["iters"]) + 1
+    t_app = mixed["timed_phases_ms"]["coarse_bwd_sweep"]
+    roof = dict(bound="hbm", achieved=bwd_bytes / (t_app * 1e-3) / 1e9, peak=PEAK["hbm_GBs"], unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = "k_nd_bwd"
+    roof["ms_per_step"] = t_app * napp
+    roof["note"] = (f"backward coarse sweep of the block: every workgroup reads its [F_ss^-1 | M^T] rows once for "
+                    f"all {nr} cases (algorithmic bytes: the factor rows once per application, the cases' vectors "
+                    f"not counted); per-application time event-timed live on one application in eight")
+    roof["traffic"] = None
+    out = {
+        "metric": METRIC, "value": ncell / (mixed["ms_per_step"] * 1e-3), "unit": "cells/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"lattice {prob['nx']}x{prob['ny']} cells, p={prob['p']} (162 dofs/cell), "
+                               f"order-{prob['m']} warped maps, circle/cross cells with thickness, {nr} load cases "
+                               f"(random edge tractions) solved as one block, adjoint gradients of every case",
+                   "cells": ncell, "p": prob["p"], "load_cases": nr,
+                   "n_r": {int(f): r["n_r"] for f, r in roms.items()},
+                   **sizes},
+        "roofline": roof,
+        "mixed": mixed, "fp64": results[lbddc.FP64],
+        "solve_only_ms": {"block": t_blk, "sequential": t_seq, "first_case_alone": t_one,
+                          "block_over_one_case": t_blk / t_one, "sequential_over_block": t_seq / t_blk,
+                          "iterations": {"block": it_blk, "sequential": it_seq, "first_case_alone": it_one}},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +402,9 @@ def main():
     ncell = prob["nx"] * prob["ny"]
     log(f"[bench] workload {prob['nx']}x{prob['ny']} p={prob['p']} m={prob['m']} cells={ncell}")
     roms = train_roms(prob)
+    if prob["traction"].shape[0] > 1:
+        bench_cases(args, prob, roms)
+        return
     stream = torch.cuda.current_stream().cuda_stream
     s = lbddc.Solver(0, stream)
     for f, r in roms.items():
