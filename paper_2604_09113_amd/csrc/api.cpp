@@ -450,6 +450,7 @@ lbddc_status lbddc_set_geometry_device(lbddc_ctx* x, const double* d_ctrl, const
   HIPCHK(hipMemcpyAsync(c->d_t_bak, c->d_t, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   if (d_ctrl) HIPCHK(hipMemcpyAsync(c->d_ctrl, d_ctrl, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   if (d_t) HIPCHK(hipMemcpyAsync(c->d_t, d_t, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  c->geom_gen++;  // (also when the new geometry is rejected and the old one restored: harmless)
   HIPCHK(launch_geometry(c), "set_geometry_device");
   lbddc_status s = check_flags(c, "set_geometry_device");
   if (s != LBDDC_OK) {

@@ -339,6 +339,18 @@ struct Ctx {
   int* d_adj_tiles = nullptr;  // 16-cell tiles of the adjoint contraction
   void* d_adj_ptrs = nullptr;  // per-group tile pointers (A and transposed layouts)
   std::vector<int> group_counts;
+  // Generation of the geometry (t, family): bumped by set_geometry_device.
+  // The assembly's group sort, tile table and per-group pointers depend on it
+  // only, so an assembly with an unchanged generation into the same buffers
+  // reuses them and skips the host round trip of the sort.
+  unsigned long long geom_gen = 1;
+  struct GroupCache {
+    unsigned long long gen = 0;
+    bool fp32 = false;
+    const void* tiles = nullptr;
+    int ntiles = 0;
+    std::vector<int> fam_first, fam_n;
+  } grp;
   double* d_ucell = nullptr;   // [ncell][ndof] local displacement (permuted)
 
   double phase_ms[14] = {0};

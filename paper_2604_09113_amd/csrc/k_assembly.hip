@@ -239,6 +239,7 @@ struct AsmBuffers {
   void* theta_t;
   size_t theta_tiles;
   void* K;
+  bool cacheable;  // the tile table and pointers stay in place between calls
 };
 
 static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, hipEvent_t e0, hipEvent_t e1) {
@@ -250,9 +251,18 @@ static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, 
     G += c->roms[fid].n_k;
   }
   if (G > 16) return hipErrorInvalidValue;
+  Ctx::GroupCache& gc = c->grp;
+  const bool reuse = bf.cacheable && gc.gen == c->geom_gen && gc.fp32 == fp32 && gc.tiles == bf.tiles;
+  std::vector<int> fam_first, fam_n;
+  hipError_t e = hipSuccess;
+  if (reuse) {
+    fam_first = gc.fam_first;
+    fam_n = gc.fam_n;
+    c->ntiles = gc.ntiles;
+  } else {
   int* d_counts = c->d_flags + 8 + 64;
   hipLaunchKernelGGL(k_group_sort, dim3(1), dim3(kSortT), 0, c->stream, c->d_cluster, c->ncell, G, c->d_sorted, d_counts);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   int counts[16];
   e = hipMemcpyAsync(c->h_flags + 8, d_counts, G * sizeof(int), hipMemcpyDeviceToHost, c->stream);
@@ -263,7 +273,6 @@ static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, 
   c->group_counts.assign(counts, counts + G);
   // tiles of 128 cells per group, per family
   std::vector<int> tiles;
-  std::vector<int> fam_first, fam_n;
   int start = 0;
   c->group_family.assign(G, 0);
   c->group_cluster.assign(G, 0);
@@ -295,6 +304,17 @@ static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, 
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(bf.ptrs, ptrs.data(), G * sizeof(void*), hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return e;
+  if (bf.cacheable) {
+    gc.gen = c->geom_gen;
+    gc.fp32 = fp32;
+    gc.tiles = bf.tiles;
+    gc.ntiles = c->ntiles;
+    gc.fam_first = fam_first;
+    gc.fam_n = fam_n;
+  } else {
+    gc.gen = 0;
+  }
+  }
   if (e0) hipEventRecord(e0, c->stream);
   const int4* d_tl = reinterpret_cast<const int4*>(bf.tiles);
   if (fp32)
@@ -327,6 +347,7 @@ hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1) {
   bf.theta_t = fp32 ? (void*)c->d_theta_t32 : (void*)c->d_theta_t;
   bf.theta_tiles = (size_t)c->ncell / 128 + 17;
   bf.K = fp32 ? (void*)c->d_K32 : (void*)c->d_K;
+  bf.cacheable = true;
   return launch_assembly_into(c, fp32, bf, e0, e1);
 }
 
@@ -389,6 +410,7 @@ lbddc_status assemble_fp32_noalloc(Ctx* c, float* d_K) {
     bf.theta_t = (char*)base + kScratchTableBytes + kScratchPtrBytes;
     bf.theta_tiles = cap;
     bf.K = d_K;
+    bf.cacheable = false;  // the staging array is shared by every call on this GPU
     e = launch_assembly_into(c, true, bf, nullptr, nullptr);
     if (e == hipErrorInvalidValue && (size_t)c->ntiles > cap) return too_large(c->ntiles);
   }

@@ -124,3 +124,37 @@ def test_calls_out_of_order_rejected():
     s.setup()
     assert s.solve(rtol=1e-10, max_iter=200)[0]["rel_res"] <= 1e-10
     s.close()
+
+
+def test_assembly_groups_follow_the_geometry():
+    """The assembly reuses its cell sort by ROM cluster while the geometry is
+    unchanged: two assemblies give identical K_i; after set_geometry_device
+    moves cells across the cluster boundary, K_i equals that of a fresh solver
+    built with the new thickness (bit for bit: the same kernels)."""
+    import torch
+    from gpu_helpers import cut_to_rank, make_solver
+    prob = make_problem(3, nx=6, ny=5, p=4)
+    roms = {f: cut_to_rank(r) for f, r in oracle_roms(prob).items()}
+    ncell = prob["nx"] * prob["ny"]
+    s = make_solver(prob, roms)
+    s.assemble()
+    K0 = s.export(0, 0, ncell)
+    s.assemble()
+    assert np.array_equal(s.export(0, 0, ncell), K0)
+    # every cell to the other half of its family's box (n_k = 2 clusters)
+    lo, hi = 0.1, 0.3
+    t1 = np.where(prob["t"] < 0.5 * (lo + hi), prob["t"] + 0.09, prob["t"] - 0.09)
+    ctrl_d = torch.tensor(prob["ctrl"], dtype=torch.float64, device="cuda")
+    t_d = torch.tensor(t1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    s.set_geometry_device(ctrl_d.data_ptr(), t_d.data_ptr())
+    s.assemble()
+    K1 = s.export(0, 0, ncell)
+    s.close()
+    p1 = dict(prob, t=np.ascontiguousarray(t1))
+    s1 = make_solver(p1, roms)
+    s1.assemble()
+    K1_fresh = s1.export(0, 0, ncell)
+    s1.close()
+    assert not np.array_equal(K1, K0)
+    assert np.array_equal(K1, K1_fresh)
