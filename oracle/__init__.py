@@ -10,7 +10,10 @@ Modules (each function cites the passage it follows):
   basis     GLL nodes, Lagrange and Bernstein polynomials     (Sec. 2.2.2, 2.1)
   geometry  map, Jacobian, pulled-back tensor, coefficients   (Sec. 2.2.1, Eq. pull-back; Sec. 4.1)
   trimmed   exact trimmed integrals I(t) and I_Pi             (Sec. 4.1-4.2)
-  rom       offline MDEIM training and online evaluation      (Sec. 4.2, Alg. 3, Alg. 5)
+  implicit  Table 1 level sets, bilinear threshold, implicit-
+            domain quadrature (Saye's height-function method) (Sec. 2.1.2, 2.2.3, Table 1)
+  rom       offline MDEIM training and online evaluation,
+            one or four parameters per cell                   (Sec. 4.2, Alg. 3, Alg. 5)
   assembly  fast/ROM stiffness, full-quadrature reference     (Sec. 4.1, Alg. 4)
   dofs      DoF classification, restriction maps, coarse dofs (Sec. 3.1, 3.3.1)
   bddc      Schur complements, constraints, coarse basis,

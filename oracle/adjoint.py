@@ -40,11 +40,14 @@ def cell_G(Ieff, u_nat, nB):
     return np.einsum("ia,jb,abxyk->ixjyk", U, U, Ieff)
 
 
-def compliance_gradient(P, unodes):
+def compliance_gradient(P, unodes, thresholds=False):
     """Compliance per load case and its gradient w.r.t. the control net and
     the thickness parameters, for an oracle Problem `P` (assembly 'rom') and
     displacements `unodes` [nrhs, Gy, Gx, 2] solving the system.  Returns
-    (J [nrhs], dJ_dctrl [nrhs, *ctrl.shape], dJ_dt [nrhs, ncell])."""
+    (J [nrhs], dJ_dctrl [nrhs, *ctrl.shape], dJ_dt [nrhs, ncell]), and with
+    `thresholds` also dJ_dmu [nrhs, ncell, 4], the gradient with respect to
+    the corner thresholds of the cells of Table 1 level sets (zero rows for
+    the other cells; their dJ_dt entries are zero)."""
     prob, d = P.prob, P.dofs
     p, q, m, rho = P.p, P.q, P.m, P.rho
     nB = d.nB
@@ -53,6 +56,7 @@ def compliance_gradient(P, unodes):
     J = np.zeros(nrhs)
     gX = np.zeros((nrhs,) + prob["ctrl"].shape)
     gt = np.zeros((nrhs, d.ncell))
+    gmu = np.zeros((nrhs, d.ncell, 4))
     pts = interp_nodes(q)
     for r in range(nrhs):
         ufree = np.zeros(d.N)
@@ -62,7 +66,7 @@ def compliance_gradient(P, unodes):
         J[r] = Fg[:, r] @ ufree
     for c, cell in enumerate(P.cells):
         ix, iy = d.cell_xy(c)
-        fam, t = int(prob["family"][c]), float(prob["t"][c])
+        fam, t = int(prob["family"][c]), P.cell_param(c)
         rom = P.roms[fam]
         X = cell.X
         _, Jp = map_eval(X, pts[:, 0], pts[:, 1])
@@ -72,13 +76,17 @@ def compliance_gradient(P, unodes):
         k_cl, Ieff = rom_Ieff(rom, t, rho)
         _, dIr = reduced_coordinates_dt(rom, t)
         Ut = rom["clusters"][k_cl]["U"]
-        dIeff = ((1.0 - rho) * (Ut @ dIr)).reshape(Ieff.shape)
+        dIr = np.atleast_2d(dIr)                          # [d, n_r]
+        dIeffs = [((1.0 - rho) * (Ut @ row)).reshape(Ieff.shape) for row in dIr]
         from .geometry import geometry_coefficients
         C, _ = geometry_coefficients(X, q, P.Cmat)
         for r in range(nrhs):
             u = P.cell_displacement(unodes[r], c)
-            dK_dt = contract(dIeff, C)
-            gt[r, c] = -u @ dK_dt @ u
+            dE = [-u @ contract(dI, C) @ u for dI in dIeffs]
+            if len(dE) == 1:
+                gt[r, c] = dE[0]
+            else:
+                gmu[r, c, :] = dE
             G = cell_G(Ieff, u, nB)                      # [i1 j1 i2 j2 k3]
             # dE/dJ[p, q] at node k3
             dEdJ = np.einsum("iajbk,kiajbpq->kpq", G, dCh)
@@ -103,6 +111,8 @@ def compliance_gradient(P, unodes):
                     for dd in range(2):
                         dds = dx[:, dd] / ds * dB[beta]
                         gX[r, m * iy + jb, m * ix + ja, dd] += 2.0 * ut @ (bn @ (w * dds))
+    if thresholds:
+        return J, gX, gt, gmu
     return J, gX, gt
 
 
@@ -123,12 +133,16 @@ def compliance_direct(prob, roms):
     return np.array(out)
 
 
-def fd_directional(prob, roms, dX, dt, h=1e-6):
-    """Central finite difference of J along (dX, dt)."""
+def fd_directional(prob, roms, dX, dt, h=1e-6, dmu=None):
+    """Central finite difference of J along (dX, dt) (and dmu, the
+    per-cell corner thresholds, when given)."""
     pp = dict(prob)
     pm = dict(prob)
     pp["ctrl"] = prob["ctrl"] + h * dX
     pm["ctrl"] = prob["ctrl"] - h * dX
     pp["t"] = prob["t"] + h * dt
     pm["t"] = prob["t"] - h * dt
+    if dmu is not None:
+        pp["mu"] = prob["mu"] + h * dmu
+        pm["mu"] = prob["mu"] - h * dmu
     return (compliance_direct(pp, roms) - compliance_direct(pm, roms)) / (2 * h)

@@ -29,6 +29,7 @@ from .basis import gll_nodes, lagrange, gauss_legendre, bernstein, bernstein_der
 from .dofs import Dofs, EDGES, edge_nodes_local, side_cells
 from .geometry import cell_control_points, material_tensor, min_det_jacobian
 from .assembly import rom_K, fast_K
+from .trimmed import param_dim
 
 
 def edge_map(X, e, xi):
@@ -120,9 +121,17 @@ class Problem:
         ix, iy = self.dofs.cell_xy(c)
         return cell_control_points(self.prob["ctrl"], self.m, ix, iy)
 
+    def cell_param(self, c):
+        """The geometric parameter of cell c: its thickness t, or for a
+        Table 1 level set its corner thresholds mu[4] (Sec. 2.1.2)."""
+        fam = int(self.prob["family"][c])
+        if param_dim(fam) == 4:
+            return np.asarray(self.prob["mu"][c], dtype=np.float64)
+        return float(self.prob["t"][c])
+
     def cell_K(self, c):
         X = self.control_points(c)
-        fam, t = int(self.prob["family"][c]), float(self.prob["t"][c])
+        fam, t = int(self.prob["family"][c]), self.cell_param(c)
         if self.assembly == "rom":
             return rom_K(X, self.roms[fam], t, self.rho, self.Cmat)
         if self.assembly == "fast":

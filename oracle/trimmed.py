@@ -16,9 +16,17 @@ rounding:
     (D + 2 points, exact for trigonometric polynomials of degree <= D).
 I_Pi is the same integral over the untrimmed square (Sec. 4.1, stabilisation
 term split into square minus trimmed domain).
+
+The level sets of Table 1 with the bilinear threshold (Sec. 2.1.2) trim by
+curves that are neither circles nor lines; their cells are integrated by the
+implicit-domain quadrature of implicit.py with max(12, p + q + 2) Gauss
+points per segment (exact along every segment, since the integrand has
+degree at most 2p + q in each variable, and converged to rounding across
+segments).
 """
 import numpy as np
 from .basis import tensor_basis, interp_basis, gauss_legendre
+from .implicit import TPMS_FAMILIES, tpms_rule
 
 FAMILY_CIRCLE = 0
 FAMILY_CROSS = 1
@@ -107,18 +115,37 @@ def I_cross(p, q, t, method="union"):
             + R(lo, hi, 0.0, lo) + R(lo, hi, hi, 1.0))
 
 
+def tpms_points(p, q, mu, family, extra=0):
+    return tpms_rule(family, mu, max(12, p + q + 2) + extra)
+
+
+def I_tpms(family, p, q, mu):
+    """I(mu) of a Table 1 level set with corner thresholds mu[4]."""
+    return integrate_points(p, q, *tpms_points(p, q, mu, family))
+
+
+def param_dim(family):
+    """Number of geometric parameters of a cell of `family`."""
+    return 4 if int(family) in TPMS_FAMILIES else 1
+
+
 def I_exact(family, p, q, t, I_pi=None):
-    """Exact I(t) for a cell of `family` with parameter t."""
+    """Exact I(t) for a cell of `family` with parameter t (the thickness of
+    the stand-in families, the four corner thresholds of the TPMS ones)."""
     if family == FAMILY_CIRCLE:
         return I_circle(p, q, t, I_pi)
     if family == FAMILY_CROSS:
         return I_cross(p, q, t)
+    if int(family) in TPMS_FAMILIES:
+        return I_tpms(family, p, q, t)
     raise ValueError(f"unknown family {family}")
 
 
 def material_points(family, p, q, t, extra=0):
     """Signed quadrature points covering the material region (weights of
     removed parts are negative).  Used by the full-quadrature reference."""
+    if int(family) in TPMS_FAMILIES:
+        return tpms_points(p, q, t, family, extra=extra)
     if family == FAMILY_CIRCLE:
         n = (2 * p + q + 1 + 1) // 2 + 1 + extra
         x, wx = gauss_legendre(n)

@@ -15,7 +15,12 @@ in for the paper's TPMS cells (Table 1), because both admit exact quadrature:
   |xi_2 - 1/2| < t/2.
 
 The scalar thickness t plays the role of the threshold parameter mu (d = 1).
-"""
-from .configs import CONFIGS, make_problem, rom_lhs_uniforms, family_name
 
-__all__ = ["CONFIGS", "make_problem", "rom_lhs_uniforms", "family_name"]
+The paper's own cells are available too: families 2-5 are the level sets of
+Table 1 (Schwarz Diamond, Schwarz Primitive, Schoen FRD, Schoen IWP) with the
+bilinear threshold through one value per lattice vertex (d = 4, Sec. 2.1.2);
+their quadrature is implicit (the oracle's height-function rule).
+"""
+from .configs import CONFIGS, TPMS_BOX, make_problem, rom_lhs_uniforms, rom_lhs_draws, family_name
+
+__all__ = ["CONFIGS", "TPMS_BOX", "make_problem", "rom_lhs_uniforms", "rom_lhs_draws", "family_name"]

@@ -8,8 +8,14 @@ Each problem is a plain dict of numpy arrays and scalars:
   m            Bernstein order of the map; the shared control net has
                (m*ny+1) x (m*nx+1) points, ctrl[jy, jx] = (x, y)
   ctrl         float64 [(m*ny+1), (m*nx+1), 2]
-  family       int32 [ncell] level-set family per cell (0 circle, 1 cross)
-  t            float64 [ncell] thickness parameter per cell
+  family       int32 [ncell] level-set family per cell (0 circle, 1 cross,
+               2-5 the level sets of Table 1: Schwarz Diamond, Schwarz
+               Primitive, Schoen FRD, Schoen IWP)
+  t            float64 [ncell] thickness parameter per cell (circle, cross)
+  mu           float64 [ncell, 4] corner thresholds of each cell (bottom-left,
+               bottom-right, top-left, top-right) taken from one value per
+               lattice vertex, so neighbouring cells share them (trimmed
+               compatibility); zeros when no cell uses a Table 1 level set
   E, nu, rho   material (plane strain) and stabilisation factor
   traction     float64 [nrhs, n_side, 2] constant traction on the edge of
                each cell along the loaded side (physical units); n_side = ny
@@ -26,7 +32,10 @@ traction; the other outer sides are traction free.  The `clamped` and
 """
 import numpy as np
 
-FAMILY_NAMES = {0: "circle", 1: "cross"}
+FAMILY_NAMES = {0: "circle", 1: "cross", 2: "schwarz_d", 3: "schwarz_p", 4: "schoen_frd", 5: "schoen_iwp"}
+TPMS_TOPOLOGY = {"schwarz_d": 2, "schwarz_p": 3, "schoen_frd": 4, "schoen_iwp": 5}
+# first threshold box of each Table 1 level set (Sec. 5.1.2)
+TPMS_BOX = {2: (0.1, 0.9), 3: (-0.5, 0.8), 4: (-6.5, 0.5), 5: (-2.5, 2.5)}
 
 
 def family_name(f):
@@ -61,6 +70,14 @@ CONFIGS = {
             rtol=1e-8, nrhs=8, load="random",
             rom={0: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6),
                  1: dict(lo=0.1, hi=0.3, n_k=2, n_s=100, n_r=40, r=6)}),
+    # the paper's own cells: a Schwarz Diamond lattice with the bilinear
+    # threshold (d = 4), graded across the lattice like the paper's benchmark
+    # (mu = 0.9 - 0.8 x / L at the vertices) plus U[-0.05, 0.05], clipped to
+    # the box [0.1, 0.9]; 2 clusters per threshold (16), r = 6 (7^4 nodes)
+    6: dict(nx=128, ny=128, p=8, q=2, m=2, jitter=0.03, warp=0.0, topo="schwarz_d",
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=5e-4, moments=True,
+            rtol=1e-8, nrhs=1, load="unit", mu_mode="graded", mu_noise=0.05,
+            rom={2: dict(lo=0.1, hi=0.9, n_k=2, n_s=100, n_r=40, r=6, dim=4)}),
 }
 
 
@@ -105,6 +122,8 @@ def make_problem(config=1, seed=None, **overrides):
         family = np.zeros(ncell, dtype=np.int32)
     elif cfg["topo"] == "cross":
         family = np.ones(ncell, dtype=np.int32)
+    elif cfg["topo"] in TPMS_TOPOLOGY:
+        family = np.full(ncell, TPMS_TOPOLOGY[cfg["topo"]], dtype=np.int32)
     else:
         family = (coin < 0.5).astype(np.int32)
     u = rng.random(ncell)
@@ -115,6 +134,19 @@ def make_problem(config=1, seed=None, **overrides):
         t = 0.5 - r
     else:
         t = cfg["t_lo"] + (cfg["t_hi"] - cfg["t_lo"]) * u
+    mu = np.zeros((ncell, 4))
+    if cfg["topo"] in TPMS_TOPOLOGY:
+        lo, hi = cfg.get("mu_box", TPMS_BOX[TPMS_TOPOLOGY[cfg["topo"]]])
+        vx = np.arange(nx + 1)[None, :] / nx
+        v = np.broadcast_to(hi - (hi - lo) * vx, (ny + 1, nx + 1)).copy()
+        if cfg.get("mu_mode", "graded") == "uniform":
+            v = lo + (hi - lo) * rng.random((ny + 1, nx + 1))
+        else:
+            noise = cfg.get("mu_noise", 0.05) * (hi - lo) / 0.8
+            v += noise * (2.0 * rng.random((ny + 1, nx + 1)) - 1.0)
+        v = np.clip(v, lo, hi)
+        iy, ix = np.divmod(np.arange(ncell), nx)
+        mu = np.stack([v[iy, ix], v[iy, ix + 1], v[iy + 1, ix], v[iy + 1, ix + 1]], axis=1)
     nrhs = cfg["nrhs"]
     clamped = tuple(cfg.get("clamped", ("left",)))
     loaded = cfg.get("loaded", "right")
@@ -130,7 +162,7 @@ def make_problem(config=1, seed=None, **overrides):
     rom = {f: cfg["rom"][f] for f in cfg["rom"] if f in present or len(present) == 0}
     return dict(config=config, seed=seed, nx=nx, ny=ny, p=cfg["p"], q=cfg["q"],
                 m=m, ctrl=np.ascontiguousarray(net), family=family,
-                t=np.ascontiguousarray(t, dtype=np.float64), E=1.0, nu=0.3,
+                t=np.ascontiguousarray(t, dtype=np.float64), mu=np.ascontiguousarray(mu), E=1.0, nu=0.3,
                 rho=cfg["rho"], moments=cfg["moments"], rtol=cfg["rtol"],
                 traction=np.ascontiguousarray(traction), clamped=clamped, loaded=loaded, rom=rom)
 
@@ -140,3 +172,14 @@ def rom_lhs_uniforms(family, n_k, n_s):
     cluster of `family` (d = 1): returns [n_k, n_s]."""
     rng = np.random.default_rng(100 + int(family))
     return rng.random((n_k, n_s))
+
+
+def rom_lhs_draws(family, n_k, n_s, dim):
+    """The draws of the Latin-hypercube sampling of each of the n_k^dim
+    clusters of a family with dim parameters: U[0,1) offsets [n_cl, n_s, dim]
+    and, per coordinate, a random order of the strata [n_cl, dim, n_s]."""
+    rng = np.random.default_rng(100 + int(family))
+    ncl = n_k ** dim
+    u = rng.random((ncl, n_s, dim))
+    perm = np.stack([np.stack([rng.permutation(n_s) for _ in range(dim)]) for _ in range(ncl)])
+    return u, perm
