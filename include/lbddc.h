@@ -14,7 +14,7 @@
  *   solve     PCG on the interface problem with the BDDC preconditioner (Alg. 1)
  *             and interior recovery;
  *   gradient  the compliance f^T u and its gradient with respect to the control
- *             net and the per-cell thickness parameters (discrete adjoint; the
+ *             net and the per-cell geometric parameters (discrete adjoint; the
  *             adjoint state equals u).
  *
  * Conventions
@@ -45,9 +45,13 @@
  * side (per unit physical length); the other sides are traction free.  The
  * benchmark lattices clamp the left side (x = 0) and load the right side.
  *
- * Level sets: each cell belongs to a level-set family with one parameter t (the
- * role of the threshold of Sec. 2.1.2).  The geometry of a family enters only
- * through its trained ROM (Sec. 4.2), which the caller supplies.
+ * Level sets: each cell belongs to a level-set family.  A family has either one
+ * parameter per cell, t (a thickness), or four: the corner values mu_1..mu_4
+ * (bottom-left, bottom-right, top-left, top-right) of the bilinear threshold
+ * function of Sec. 2.1.2, which trims the cell where phi_0 < mu, phi_0 one of
+ * the periodic level sets of Table 1.  The geometry of a family enters only
+ * through its trained ROM (Sec. 4.2), which the caller supplies; its `dim`
+ * says which parameters its cells read.
  */
 #ifndef LBDDC_H
 #define LBDDC_H
@@ -67,7 +71,7 @@ typedef enum {
   LBDDC_E_HIP = -3,            /* a HIP runtime call failed */
   LBDDC_E_STATE = -4,          /* call out of order */
   LBDDC_E_DEGENERATE_MAP = -5, /* det J <= 0 somewhere in a cell (regular maps are required, Sec. 4.1) */
-  LBDDC_E_PARAM_RANGE = -6,    /* a thickness outside the trained box of its family's ROM (Sec. 4.2) */
+  LBDDC_E_PARAM_RANGE = -6,    /* a thickness or threshold outside the trained box of its family's ROM (Sec. 4.2) */
   LBDDC_E_ROM = -7,            /* no ROM for a family, or ROM degrees differ from the problem's */
   LBDDC_E_NOT_CONVERGED = -8,  /* PCG reached max_iter; info holds the last residual */
   LBDDC_E_BREAKDOWN = -9,      /* p^T S p <= 0 or r^T z <= 0 in PCG */
@@ -108,16 +112,23 @@ const char* lbddc_last_error(const lbddc_ctx* ctx);
 int lbddc_version(void);
 
 /* A trained ROM of one level-set family (Sec. 4.2, Alg. 5).  The trimmed-domain
- * tensor I(t) has n_i = (p+1)^4 * 4 * (q+1)^2 entries in the order
+ * tensor I(x) has n_i = (p+1)^4 * 4 * (q+1)^2 entries in the order
  *   (((k1*nB + k2)*2 + j1)*2 + j2)*(q+1)^2 + k3,   nB = (p+1)^2,
  * k1, k2 = a + (p+1) b the GLL nodes of the cell, j1, j2 the parametric
- * derivative directions, k3 = a + (q+1) b the interpolation nodes.
- *   U     [n_k][n_i][n_r]   reduced basis of each cluster (zero columns allowed)
- *   coeff [n_k][r+1][n_r]   I_r at the r+1 GLL points of each cluster interval
- *   I_pi  [n_i]             the same integral over the untrimmed cell
- * Clusters split [lo, hi] into n_k equal intervals; t in cluster
- * min(floor((t-lo)/w), n_k-1).  Limits: 1 <= n_r <= 43, 1 <= r <= 16,
- * 1 <= n_k <= 64.  Loading a family again replaces it. */
+ * derivative directions, k3 = a + (q+1) b the interpolation nodes.  The
+ * parameter x has `dim` coordinates (1: t; 4: mu_1..mu_4), each in [lo, hi].
+ * Every coordinate range splits into n_k equal intervals, so there are
+ * n_cl = n_k^dim clusters (Sec. 4.2.1): x is in cluster
+ * sum_i c_i n_k^i with c_i = min(floor((x_i - lo)/w), n_k - 1).
+ *   U     [n_cl][n_i][n_r]         reduced basis of each cluster (zero columns allowed)
+ *   coeff [n_cl][(r+1)^dim][n_r]   I_r at the tensor grid of r+1 GLL points per
+ *                                  coordinate of the cluster box, node
+ *                                  a_1 + (r+1) a_2 + (r+1)^2 a_3 + ... (Sec. 4.2.3)
+ *   I_pi  [n_i]                    the same integral over the untrimmed cell
+ * The online surrogate is the tensor-product Lagrange interpolant of degree r
+ * per coordinate.  Limits: 1 <= n_r <= 43; dim 1: 1 <= r <= 16, 1 <= n_k <= 16;
+ * dim 4: 1 <= r <= 8, 1 <= n_k <= 2.  `dim` 0 is read as 1.  Loading a family
+ * again replaces it. */
 typedef struct {
   int32_t family;
   int32_t p, q;
@@ -126,6 +137,7 @@ typedef struct {
   const double* U;
   const double* coeff;
   const double* I_pi;
+  int32_t dim;
 } lbddc_rom_desc;
 lbddc_status lbddc_load_rom(lbddc_ctx* ctx, const lbddc_rom_desc* rom);
 
@@ -138,11 +150,16 @@ lbddc_status lbddc_load_rom(lbddc_ctx* ctx, const lbddc_rom_desc* rom);
  * the left and right sides (n_side = ny), k = ix on the bottom and top sides
  * (n_side = nx).  Limits: 2 <= p <= 8 (p >= 3 with edge moments: an edge of
  * a p = 2 cell has 2 interior dofs for 3 constraints), q in {1, 2, 3}, 1 <= map_order <= 4,
- * 1 <= nrhs <= 16, nx, ny >= 1.  Validates det J > 0 at the interpolation
- * points and on a (2m+2)^2 Gauss sample of every cell (LBDDC_E_DEGENERATE_MAP),
- * that every family has a ROM of degrees (p, q) (LBDDC_E_ROM) and that every t
- * lies in its family's box (LBDDC_E_PARAM_RANGE).  On failure the previous
- * problem, if any, stays in place with all its stages. */
+ * 1 <= nrhs <= 16, nx, ny >= 1.  t[ncell] is read for cells of families with
+ * dim 1, mu[ncell][4] for cells of families with dim 4 (mu may be NULL when
+ * there are none; a lattice meets the trimmed compatibility of Sec. 2.1.3 when
+ * neighbouring cells share their common corner values).  At most 16
+ * (family, cluster) pairs per problem.  Validates det J > 0 at the
+ * interpolation points and on a (2m+2)^2 Gauss sample of every cell
+ * (LBDDC_E_DEGENERATE_MAP), that every family has a ROM of degrees (p, q)
+ * (LBDDC_E_ROM) and that every parameter lies in its family's box
+ * (LBDDC_E_PARAM_RANGE).  On failure the previous problem, if any, stays in
+ * place with all its stages. */
 typedef struct {
   int32_t nx, ny, p, q, map_order;
   const double* ctrl;
@@ -154,17 +171,19 @@ typedef struct {
   int32_t loaded_side;
   int32_t nrhs;
   const double* traction;
+  const double* mu;
 } lbddc_problem_desc;
 lbddc_status lbddc_set_problem(lbddc_ctx* ctx, const lbddc_problem_desc* desc);
 
-/* Replace the control net and the thickness parameters of the current problem
- * (device pointers, same sizes as in set_problem, read on the context's stream
- * before the call returns; either may be NULL to keep the current values).
+/* Replace the control net, the thickness parameters and the corner thresholds
+ * of the current problem (device pointers, same sizes as in set_problem, read
+ * on the context's stream before the call returns; any may be NULL to keep the
+ * current values, not all three).
  * The new geometry is validated as in set_problem.  On success it invalidates
  * assemble and later stages; on failure (LBDDC_E_DEGENERATE_MAP,
  * LBDDC_E_PARAM_RANGE, ...) the previous geometry and every stage computed
  * from it stay in place. */
-lbddc_status lbddc_set_geometry_device(lbddc_ctx* ctx, const double* d_ctrl, const double* d_t);
+lbddc_status lbddc_set_geometry_device(lbddc_ctx* ctx, const double* d_ctrl, const double* d_t, const double* d_mu);
 
 /* For callers that cannot allocate device memory (tight loops, harnesses that
  * forbid allocation): the FP32 contraction of lbddc_assemble with
@@ -223,13 +242,17 @@ lbddc_status lbddc_get_displacement(lbddc_ctx* ctx, int32_t rhs, double* u);
 lbddc_status lbddc_get_displacement_device(lbddc_ctx* ctx, int32_t rhs, double* d_u);
 
 /* Compliance J_r = f_r^T u_r of every load case and its gradient with respect
- * to the control net and the thickness parameters:
+ * to the control net and the cell parameters:
  *   dJ = 2 u^T df - u^T dK u  (the adjoint state of the compliance is u).
- * Host outputs: J[nrhs], dJ_dctrl[nrhs][ctrl size], dJ_dt[nrhs][ncell]; any may
- * be NULL.  Requires a completed solve. */
-lbddc_status lbddc_compliance_gradient(lbddc_ctx* ctx, double* J, double* dJ_dctrl, double* dJ_dt);
+ * Host outputs: J[nrhs], dJ_dctrl[nrhs][ctrl size], dJ_dt[nrhs][ncell] (zero
+ * for cells of dim-4 families), dJ_dmu[nrhs][ncell][4] (per cell and corner;
+ * zero for cells of dim-1 families; a threshold shared by the cells around a
+ * lattice vertex has the sum of their entries as its derivative); any may be
+ * NULL.  Requires a completed solve. */
+lbddc_status lbddc_compliance_gradient(lbddc_ctx* ctx, double* J, double* dJ_dctrl, double* dJ_dt, double* dJ_dmu);
 /* Same into device memory (context stream, not synchronised). */
-lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* ctx, double* d_J, double* d_dJ_dctrl, double* d_dJ_dt);
+lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* ctx, double* d_J, double* d_dJ_dctrl, double* d_dJ_dt,
+                                              double* d_dJ_dmu);
 
 /* Sizes.  `what`: */
 enum {
@@ -256,7 +279,7 @@ lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
  * for testing.  Layouts per cell:
  *   K      [2nB][2nB], dof i*nB + k (component i, node k = a + (p+1) b)
  *   THETA  [4][2][2][(q+1)^2]: C[i1][j1][i2][j2][k3] geometry coefficients
- *   ITIL   [LBDDC_Q_NR_MAX]: [(1 - rho) I_r(t), rho, 0 ...] (zero padded)
+ *   ITIL   [LBDDC_Q_NR_MAX]: [(1 - rho) I_r(x), rho, 0 ...] (zero padded)
  *   S      [nU][nU] local Schur complement over the skeleton slots
  *   D      [nU] partition-of-unity weights
  *   PSI    [nU][nC] D-weighted coarse basis D Psi (the form the solver applies)

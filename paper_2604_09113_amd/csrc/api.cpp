@@ -166,8 +166,13 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
   Ctx* c = &x->c;
   if (!d || !d->U || !d->coeff || !d->I_pi) return fail(c, LBDDC_E_ARG, "load_rom: null pointer");
   if (d->p < 2 || d->p > kMaxP || d->q < 1 || d->q > 3) return fail(c, LBDDC_E_UNSUPPORTED, "load_rom: p or q out of range");
-  if (d->n_r < 1 || d->n_r > 43 || d->r < 1 || d->r > 16 || d->n_k < 1 || d->n_k > 64)
+  const int dim = d->dim == 0 ? 1 : d->dim;
+  if (dim != 1 && dim != 4) return fail(c, LBDDC_E_UNSUPPORTED, "load_rom: dim must be 1 or 4");
+  if (d->n_r < 1 || d->n_r > 43 || d->r < 1 || d->r > (dim == 1 ? 16 : 8) || d->n_k < 1 ||
+      d->n_k > (dim == 1 ? 16 : 2))
     return fail(c, LBDDC_E_UNSUPPORTED, "load_rom: n_r, r or n_k out of range");
+  int ncl = 1, nnode = 1;
+  for (int i = 0; i < dim; ++i) { ncl *= d->n_k; nnode *= d->r + 1; }
   if (d->family < 0 || d->family >= 64) return fail(c, LBDDC_E_ARG, "load_rom: family id must be in [0, 64)");
   if (!(d->hi > d->lo) || !std::isfinite(d->lo) || !std::isfinite(d->hi)) return fail(c, LBDDC_E_ARG, "load_rom: bad box");
   hipSetDevice(c->device);
@@ -192,13 +197,14 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
     for (int n2 = 0; n2 <= n1; ++n2, ++P) { pn1[P] = n1; pn2[P] = n2; }
   RomDev R;
   R.family = d->family; R.p = p; R.q = q; R.n_k = d->n_k; R.n_r = d->n_r; R.r = d->r;
+  R.dim = dim; R.ncl = ncl;
   R.lo = d->lo; R.hi = d->hi; R.KC = KC;
   const size_t tile_n = (size_t)NPT * ns * KC * 64;
   const int RB = (4 * KC + 15) / 16;
   const size_t tile2_n = (size_t)NPT * ns * RB * 4 * 64;
   std::vector<double> h64(tile_n), h2(tile2_n);
   std::vector<float> h32(tile_n);
-  for (int k = 0; k < d->n_k; ++k) {
+  for (int k = 0; k < ncl; ++k) {
     const double* U = d->U + (size_t)k * n_i * d->n_r;
     for (int pt = 0; pt < NPT; ++pt)
       for (int s = 0; s < ns; ++s)
@@ -250,7 +256,7 @@ lbddc_status lbddc_load_rom(lbddc_ctx* x, const lbddc_rom_desc* d) {
     R.ut32.push_back(d32);
     R.ucol64.push_back(d2);
   }
-  const size_t nco = (size_t)d->n_k * (d->r + 1) * d->n_r;
+  const size_t nco = (size_t)ncl * nnode * d->n_r;
   if (hipMalloc(&R.coeff, nco * 8) != hipSuccess) return fail(c, LBDDC_E_NOMEM, "load_rom: allocation failed");
   if (hipMemcpy(R.coeff, d->coeff, nco * 8, hipMemcpyHostToDevice) != hipSuccess)
     return fail(c, LBDDC_E_HIP, "load_rom: copy failed");
@@ -302,6 +308,7 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
   bool ok = dalloc_t(c, &c->d_tab, tab.size()) && dalloc_t(c, &c->d_ctrl, (size_t)netx * nety * 2) &&
             dalloc_t(c, &c->d_ctrl_bak, (size_t)netx * nety * 2) && dalloc_t(c, &c->d_t_bak, ncell) &&
             dalloc_t(c, &c->d_family, ncell) && dalloc_t(c, &c->d_t, ncell) &&
+            dalloc_t(c, &c->d_mu, (size_t)ncell * 4) && dalloc_t(c, &c->d_mu_bak, (size_t)ncell * 4) &&
             dalloc_t(c, &c->d_trac, (size_t)c->nrhs * c->n_side * 2) && dalloc_t(c, &c->d_flags, 128) &&
             dalloc_t(c, &c->d_theta, (size_t)ncell * c->ns * 4) && dalloc_t(c, &c->d_theta32, (size_t)ncell * c->ns * 4) &&
             dalloc_t(c, &c->d_itil, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_itil32, (size_t)ncell * 4 * c->KC) &&
@@ -333,7 +340,7 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
             dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&
             dalloc_t(c, &c->d_H, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_G, (size_t)ncell * c->ns * 4) &&
             dalloc_t(c, &c->d_gcell, (size_t)ncell * (c->m + 1) * (c->m + 1) * 2) &&
-            dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) &&
+            dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) && dalloc_t(c, &c->d_gmu, (size_t)c->nrhs * ncell * 4) &&
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
             dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8);
   if (ok && hipHostMalloc((void**)&c->h_red, c->scal_stride() * nbk * sizeof(double),
@@ -357,10 +364,16 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
   if (e == hipSuccess) e = hipMemcpy(c->d_ctrl, d->ctrl, (size_t)netx * nety * 2 * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_family, d->family, ncell * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_t, d->t, ncell * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = d->mu ? hipMemcpy(c->d_mu, d->mu, (size_t)ncell * 4 * 8, hipMemcpyHostToDevice)
+                                 : hipMemset(c->d_mu, 0, (size_t)ncell * 4 * 8);
+  // dJ/dmu stays zero for problems without four-parameter families
+  if (e == hipSuccess) e = hipMemset(c->d_gmu, 0, (size_t)c->nrhs * ncell * 4 * 8);
   if (e == hipSuccess) e = hipMemcpy(c->d_trac, d->traction, (size_t)c->nrhs * c->n_side * 2 * 8, hipMemcpyHostToDevice);
   if (e != hipSuccess) return hipfail(c, e, "set_problem upload");
   c->fam_host.assign(d->family, d->family + ncell);
   c->t_host.assign(d->t, d->t + ncell);
+  c->any_dim4 = false;
+  for (int f : fam_ids) c->any_dim4 |= c->roms[f].dim == 4;
   // validate the maps on the device (det J) right away
   e = launch_geometry(c);
   if (e != hipSuccess) return hipfail(c, e, "set_problem geometry");
@@ -403,16 +416,26 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
     auto it = c->roms.find(f);
     if (it == c->roms.end()) return fail(c, LBDDC_E_ROM, "set_problem: a cell's family has no loaded ROM");
     if (it->second.p != d->p || it->second.q != d->q) return fail(c, LBDDC_E_ROM, "set_problem: ROM degrees differ from the problem's");
-    double t = d->t[i];
-    if (!std::isfinite(t)) return fail(c, LBDDC_E_ARG, "set_problem: non-finite thickness");
-    if (!(t >= it->second.lo && t <= it->second.hi))
-      return fail(c, LBDDC_E_PARAM_RANGE, "set_problem: a thickness parameter lies outside its ROM box");
+    if (it->second.dim == 4) {
+      if (!d->mu) return fail(c, LBDDC_E_ARG, "set_problem: a family has four parameters per cell and mu is NULL");
+      for (int k = 0; k < 4; ++k) {
+        const double v = d->mu[(size_t)i * 4 + k];
+        if (!std::isfinite(v)) return fail(c, LBDDC_E_ARG, "set_problem: non-finite threshold");
+        if (!(v >= it->second.lo && v <= it->second.hi))
+          return fail(c, LBDDC_E_PARAM_RANGE, "set_problem: a corner threshold lies outside its ROM box");
+      }
+    } else {
+      double t = d->t[i];
+      if (!std::isfinite(t)) return fail(c, LBDDC_E_ARG, "set_problem: non-finite thickness");
+      if (!(t >= it->second.lo && t <= it->second.hi))
+        return fail(c, LBDDC_E_PARAM_RANGE, "set_problem: a thickness parameter lies outside its ROM box");
+    }
     if (std::find(fam_ids.begin(), fam_ids.end(), f) == fam_ids.end()) fam_ids.push_back(f);
   }
   if (fam_ids.size() > 4) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 4 families per problem");
   std::sort(fam_ids.begin(), fam_ids.end());
   int G = 0;
-  for (int f : fam_ids) G += c->roms[f].n_k;
+  for (int f : fam_ids) G += c->roms[f].ncl;
   if (G > 16) return fail(c, LBDDC_E_UNSUPPORTED, "set_problem: at most 16 (family, cluster) groups");
   hipSetDevice(c->device);
   hipStreamSynchronize(c->stream);
@@ -437,19 +460,21 @@ lbddc_status lbddc_set_problem(lbddc_ctx* x, const lbddc_problem_desc* d) {
   return LBDDC_OK;
 }
 
-lbddc_status lbddc_set_geometry_device(lbddc_ctx* x, const double* d_ctrl, const double* d_t) {
+lbddc_status lbddc_set_geometry_device(lbddc_ctx* x, const double* d_ctrl, const double* d_t, const double* d_mu) {
   if (!x) return LBDDC_E_ARG;
   Ctx* c = &x->c;
   if (!c->have_problem) return fail(c, LBDDC_E_STATE, "set_geometry_device: no problem");
-  if (!d_ctrl && !d_t) return fail(c, LBDDC_E_ARG, "set_geometry_device: null pointers");
+  if (!d_ctrl && !d_t && !d_mu) return fail(c, LBDDC_E_ARG, "set_geometry_device: null pointers");
   hipSetDevice(c->device);
-  const size_t nctrl = (size_t)c->netx * c->nety * 2 * 8, nt = (size_t)c->ncell * 8;
+  const size_t nctrl = (size_t)c->netx * c->nety * 2 * 8, nt = (size_t)c->ncell * 8, nmu = 4 * nt;
   // keep the current geometry aside, validate the new one in its place, and
   // put the old one back if it is rejected
   HIPCHK(hipMemcpyAsync(c->d_ctrl_bak, c->d_ctrl, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   HIPCHK(hipMemcpyAsync(c->d_t_bak, c->d_t, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  HIPCHK(hipMemcpyAsync(c->d_mu_bak, c->d_mu, nmu, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   if (d_ctrl) HIPCHK(hipMemcpyAsync(c->d_ctrl, d_ctrl, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   if (d_t) HIPCHK(hipMemcpyAsync(c->d_t, d_t, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
+  if (d_mu) HIPCHK(hipMemcpyAsync(c->d_mu, d_mu, nmu, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device");
   c->geom_gen++;  // (also when the new geometry is rejected and the old one restored: harmless)
   HIPCHK(launch_geometry(c), "set_geometry_device");
   lbddc_status s = check_flags(c, "set_geometry_device");
@@ -459,6 +484,7 @@ lbddc_status lbddc_set_geometry_device(lbddc_ctx* x, const double* d_ctrl, const
     // geometry pass is deterministic, so they are restored bit for bit)
     HIPCHK(hipMemcpyAsync(c->d_ctrl, c->d_ctrl_bak, nctrl, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device restore");
     HIPCHK(hipMemcpyAsync(c->d_t, c->d_t_bak, nt, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device restore");
+    HIPCHK(hipMemcpyAsync(c->d_mu, c->d_mu_bak, nmu, hipMemcpyDeviceToDevice, c->stream), "set_geometry_device restore");
     HIPCHK(launch_geometry(c), "set_geometry_device restore");
     lbddc_status s2 = check_flags(c, "set_geometry_device restore");
     if (s2 != LBDDC_OK) return s2;

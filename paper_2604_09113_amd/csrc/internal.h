@@ -63,15 +63,56 @@ struct Tables {
   int total;
 };
 
+// cluster index and local coordinates of a cell's thresholds (the clamped
+// per-coordinate interval, as in k_geometry; a value outside the box has
+// already raised the range flag there)
+__device__ inline int mdeim4_cluster(const double* mu, double lo, double hi, int nk, double tau[4], double hstep[4]) {
+  const double w = (hi - lo) / nk;
+  int k = 0;
+  for (int i = 3; i >= 0; --i) {
+    const double v = mu[i];
+    int ci = (int)floor((v - lo) / w);
+    if (ci > nk - 1) ci = nk - 1;
+    if (ci < 0) ci = 0;
+    const double a = lo + ci * w, b = lo + (ci + 1) * w;
+    tau[i] = (v - a) / (b - a);
+    hstep[i] = b - a;
+    k = k * nk + ci;
+  }
+  return k;
+}
+
+// Lagrange basis value l_a(tau) on the r+1 nodes x, and its derivative
+__device__ inline double lag_value(const double* x, int R, int a, double tau) {
+  double v = 1.0;
+  for (int l = 0; l <= R; ++l)
+    if (l != a) v *= (tau - x[l]) / (x[a] - x[l]);
+  return v;
+}
+
+__device__ inline double lag_deriv(const double* x, int R, int a, double tau) {
+  double s = 0.0;
+  for (int l = 0; l <= R; ++l) {
+    if (l == a) continue;
+    double term = 1.0 / (x[a] - x[l]);
+    for (int q = 0; q <= R; ++q)
+      if (q != a && q != l) term *= (tau - x[q]) / (x[a] - x[q]);
+    s += term;
+  }
+  return s;
+}
+
 // A loaded ROM of one family.
 struct RomDev {
   int family = -1, p = 0, q = 0, n_k = 0, n_r = 0, r = 0;
+  int dim = 1;                      // parameters per cell: 1 (t) or 4 (corner thresholds)
+  int ncl = 0;                      // clusters, n_k^dim
   double lo = 0, hi = 0;
   int KC = 0;                       // k-chunks of the contraction (4*KC >= n_r + 1)
   std::vector<double*> ut64;        // per cluster: tiled [NPT][ns][KC][64] FP64
   std::vector<float*> ut32;         // per cluster: tiled [NPT][ns][KC][64] FP32
   std::vector<double*> ucol64;      // per cluster: [NPT][ns][16][4*KC] plain rows (adjoint)
-  double* coeff = nullptr;          // [n_k][r+1][n_r]
+  double* coeff = nullptr;          // [ncl][(r+1)^dim][n_r]
 };
 
 // Node of the nested-dissection tree of the coarse problem (same layout on the
@@ -239,8 +280,11 @@ struct Ctx {
   int* d_family = nullptr;
   double* d_t = nullptr;
   double* d_trac = nullptr;    // [nrhs][n_side][2]
-  double* d_ctrl_bak = nullptr;  // the previous control net and t while new ones are validated
+  double* d_ctrl_bak = nullptr;  // the previous control net, t and mu while new ones are validated
   double* d_t_bak = nullptr;
+  double* d_mu = nullptr;      // [ncell][4] corner thresholds (cells of dim-4 families)
+  double* d_mu_bak = nullptr;
+  bool any_dim4 = false;       // some family of the problem has four parameters per cell
   int* d_perm = nullptr;       // [nN]
   int* d_RU = nullptr;         // [ncell][nU]
   int* d_RC = nullptr;         // [ncell][nC]
@@ -334,6 +378,7 @@ struct Ctx {
   double* d_G = nullptr;       // [ncell][ns][4]
   double* d_gcell = nullptr;   // [ncell][(m+1)^2][2]
   double* d_gt = nullptr;      // [nrhs][ncell]
+  double* d_gmu = nullptr;     // [nrhs][ncell][4]
   double* d_gX = nullptr;      // [nrhs][nety*netx*2]
   double* d_J = nullptr;       // [nrhs]
   int* d_adj_tiles = nullptr;  // 16-cell tiles of the adjoint contraction

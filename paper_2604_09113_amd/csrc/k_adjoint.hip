@@ -183,7 +183,7 @@ struct ChainArgs {
   const double* ctrl; const int* family; const double* t; const double* tab; const int* fam_slot;
   const double* coeff[4];
   double lo[4], hi[4];
-  int n_k[4], n_r[4], r[4];
+  int n_k[4], n_r[4], r[4], dim[4];
   int ncell, nx, ny, netx, m, nL, ns, itil_stride, p, ndof, nI;
   int edge;  // loaded side as a cell edge (0 left, 1 right, 2 bottom, 3 top)
   double lam, mu, rho;
@@ -202,10 +202,12 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= g.ncell) return;
   const int ix = cell % g.nx, iy = cell / g.nx;
-  // dJ/dt = -H . dItil/dt
+  // dJ/dt = -H . dItil/dt (cells of four-parameter families: k_chain_mu4)
   const int fam = g.family[cell];
   const int slot = g.fam_slot[fam];
-  {
+  if (g.dim[slot] == 4) {
+    g.gt[cell] = 0.0;
+  } else {
     const double t = g.t[cell], lo = g.lo[slot], hi = g.hi[slot];
     const int nk = g.n_k[slot], R = g.r[slot], nr = g.n_r[slot];
     const double w = (hi - lo) / nk;
@@ -370,6 +372,73 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
   for (int a = 0; a < NP1; ++a) { out[2 * a] = gX[a][0]; out[2 * a + 1] = gX[a][1]; }
 }
 
+// dJ/dmu_i = -(1 - rho) sum_j H_j sum_nodes d/dmu_i [l_1 l_2 l_3 l_4](node)
+// coeff[node][j] for the cells of four-parameter families (the derivative of
+// the tensor Lagrange interpolant of Alg. 5, H = dE/dItil from the adjoint
+// contraction): one 64-lane workgroup per cell, lane j < n_r accumulating the
+// four sums of its coefficient column, then a fixed-order butterfly over the
+// lanes.  Other cells get zeros.
+struct ChainMu4Args {
+  const int* family; const double* mu; const int* fam_slot; const double* tab;
+  const double* coeff[4];
+  double lo[4], hi[4];
+  int n_k[4], n_r[4], r[4], dim[4], off_rnodes[4];
+  int itil_stride;
+  double rho;
+  const double* H;
+  double* gmu;  // [ncell][4]
+};
+
+__global__ __launch_bounds__(64) void k_chain_mu4(ChainMu4Args g) {
+  const int cell = blockIdx.x, lane = threadIdx.x;
+  const int fam = g.family[cell];
+  const int slot = g.fam_slot[fam];
+  if (g.dim[slot] != 4) {
+    if (lane < 4) g.gmu[(size_t)cell * 4 + lane] = 0.0;
+    return;
+  }
+  const int R = g.r[slot], R1 = R + 1, nr = g.n_r[slot];
+  double tau[4], hs[4];
+  const int k = mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo[slot], g.hi[slot], g.n_k[slot], tau, hs);
+  __shared__ double ell[4][9], dell[4][9];
+  if (lane < 4 * R1) {
+    const int i = lane / R1, a = lane - i * R1;
+    const double* x = g.tab + g.off_rnodes[slot];
+    ell[i][a] = lag_value(x, R, a, tau[i]);
+    dell[i][a] = lag_deriv(x, R, a, tau[i]) / hs[i];
+  }
+  __syncthreads();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (lane < nr) {
+    const double h = g.H[(size_t)cell * g.itil_stride + lane];
+    const double* cf = g.coeff[slot] + (size_t)k * R1 * R1 * R1 * R1 * nr + lane;
+    for (int a4 = 0; a4 < R1; ++a4)
+      for (int a3 = 0; a3 < R1; ++a3)
+        for (int a2 = 0; a2 < R1; ++a2) {
+          const double l234 = ell[1][a2] * ell[2][a3] * ell[3][a4];
+          const double d2 = dell[1][a2] * ell[2][a3] * ell[3][a4];
+          const double d3 = ell[1][a2] * dell[2][a3] * ell[3][a4];
+          const double d4 = ell[1][a2] * ell[2][a3] * dell[3][a4];
+          for (int a1 = 0; a1 < R1; ++a1) {
+            const double v = h * cf[0];
+            cf += nr;
+            acc[0] += dell[0][a1] * l234 * v;
+            acc[1] += ell[0][a1] * d2 * v;
+            acc[2] += ell[0][a1] * d3 * v;
+            acc[3] += ell[0][a1] * d4 * v;
+          }
+        }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
+  if (lane < 4) {
+    const double v = lane == 0 ? acc[0] : lane == 1 ? acc[1] : lane == 2 ? acc[2] : acc[3];
+    g.gmu[(size_t)cell * 4 + lane] = -(1.0 - g.rho) * v;
+  }
+}
+
 // net gradient: sum over the cells sharing each control point (fixed order)
 __global__ void k_net_gather(const double* __restrict__ gcell, const int* __restrict__ ptr,
                              const int* __restrict__ own, double* __restrict__ gnet, int nnet) {
@@ -430,7 +499,7 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   int start = 0, g0 = 0;
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     fam_first.push_back((int)tiles.size() / 4);
-    for (int k = 0; k < c->roms[c->fam_ids[s]].n_k; ++k, ++g0) {
+    for (int k = 0; k < c->roms[c->fam_ids[s]].ncl; ++k, ++g0) {
       for (int o = 0; o < c->group_counts[g0]; o += 16) {
         tiles.push_back(g0);
         tiles.push_back(start + o);
@@ -483,6 +552,7 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
     const RomDev& R = c->roms[c->fam_ids[s]];
     a.coeff[s] = R.coeff; a.lo[s] = R.lo; a.hi[s] = R.hi; a.n_k[s] = R.n_k; a.n_r[s] = R.n_r; a.r[s] = R.r;
+    a.dim[s] = R.dim;
   }
   a.ncell = c->ncell; a.nx = c->nx; a.ny = c->ny; a.netx = c->netx; a.m = c->m; a.nL = c->nL; a.ns = c->ns;
   a.itil_stride = 4 * c->KC; a.p = c->p; a.ndof = c->ndof; a.nI = c->nI;
@@ -498,6 +568,18 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
     CHN(1) CHN(2) CHN(3) CHN(4)
 #undef CHN
     default: return hipErrorInvalidValue;
+  }
+  if (c->any_dim4) {
+    ChainMu4Args b = {};
+    b.family = c->d_family; b.mu = c->d_mu; b.fam_slot = c->d_flags + 8; b.tab = c->d_tab;
+    for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
+      const RomDev& R = c->roms[c->fam_ids[s]];
+      b.coeff[s] = R.coeff; b.lo[s] = R.lo; b.hi[s] = R.hi; b.n_k[s] = R.n_k; b.n_r[s] = R.n_r; b.r[s] = R.r;
+      b.dim[s] = R.dim; b.off_rnodes[s] = c->tab.off_rnodes[s];
+    }
+    b.itil_stride = 4 * c->KC; b.rho = c->rho; b.H = c->d_H;
+    b.gmu = c->d_gmu + (size_t)rhs * c->ncell * 4;
+    hipLaunchKernelGGL(k_chain_mu4, dim3(c->ncell), dim3(64), 0, c->stream, b);
   }
   const int nnet = c->netx * c->nety;
   hipLaunchKernelGGL(k_net_gather, dim3((nnet + 255) / 256), dim3(256), 0, c->stream, c->d_gcell, c->d_net_ptr,
@@ -543,7 +625,8 @@ static lbddc_status grad_common(lbddc_ctx* x) {
   return LBDDC_OK;
 }
 
-extern "C" lbddc_status lbddc_compliance_gradient(lbddc_ctx* x, double* J, double* dJ_dctrl, double* dJ_dt) {
+extern "C" lbddc_status lbddc_compliance_gradient(lbddc_ctx* x, double* J, double* dJ_dctrl, double* dJ_dt,
+                                                  double* dJ_dmu) {
   lbddc_status s = grad_common(x);
   if (s != LBDDC_OK) return s;
   Ctx* c = &x->c;
@@ -554,6 +637,9 @@ extern "C" lbddc_status lbddc_compliance_gradient(lbddc_ctx* x, double* J, doubl
     e = hipMemcpyAsync(dJ_dctrl, c->d_gX, c->nrhs * nnet * 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess && dJ_dt)
     e = hipMemcpyAsync(dJ_dt, c->d_gt, (size_t)c->nrhs * c->ncell * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && dJ_dmu)
+    e = hipMemcpyAsync(dJ_dmu, c->d_gmu, (size_t)c->nrhs * c->ncell * 4 * sizeof(double), hipMemcpyDeviceToHost,
+                       c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     c->err = std::string("compliance_gradient copy: ") + hipGetErrorString(e);
@@ -563,7 +649,7 @@ extern "C" lbddc_status lbddc_compliance_gradient(lbddc_ctx* x, double* J, doubl
 }
 
 extern "C" lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* x, double* d_J, double* d_dJ_dctrl,
-                                                         double* d_dJ_dt) {
+                                                         double* d_dJ_dt, double* d_dJ_dmu) {
   lbddc_status s = grad_common(x);
   if (s != LBDDC_OK) return s;
   Ctx* c = &x->c;
@@ -574,6 +660,9 @@ extern "C" lbddc_status lbddc_compliance_gradient_device(lbddc_ctx* x, double* d
     e = hipMemcpyAsync(d_dJ_dctrl, c->d_gX, c->nrhs * nnet * 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
   if (e == hipSuccess && d_dJ_dt)
     e = hipMemcpyAsync(d_dJ_dt, c->d_gt, (size_t)c->nrhs * c->ncell * sizeof(double), hipMemcpyDeviceToDevice,
+                       c->stream);
+  if (e == hipSuccess && d_dJ_dmu)
+    e = hipMemcpyAsync(d_dJ_dmu, c->d_gmu, (size_t)c->nrhs * c->ncell * 4 * sizeof(double), hipMemcpyDeviceToDevice,
                        c->stream);
   if (e != hipSuccess) {
     c->err = std::string("compliance_gradient_device copy: ") + hipGetErrorString(e);

@@ -243,12 +243,12 @@ struct AsmBuffers {
 };
 
 static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, hipEvent_t e0, hipEvent_t e1) {
-  // groups: family slot s owns groups [base_s, base_s + n_k)
+  // groups: family slot s owns groups [base_s, base_s + n_cl)
   int G = 0;
   std::vector<int> base;
   for (int fid : c->fam_ids) {
     base.push_back(G);
-    G += c->roms[fid].n_k;
+    G += c->roms[fid].ncl;
   }
   if (G > 16) return hipErrorInvalidValue;
   Ctx::GroupCache& gc = c->grp;
@@ -278,7 +278,7 @@ static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, 
   c->group_cluster.assign(G, 0);
   for (size_t s = 0; s < c->fam_ids.size(); ++s) {
     fam_first.push_back((int)tiles.size() / 4);
-    for (int k = 0; k < c->roms[c->fam_ids[s]].n_k; ++k) {
+    for (int k = 0; k < c->roms[c->fam_ids[s]].ncl; ++k) {
       int g = base[s] + k;
       c->group_family[g] = (int)s;
       c->group_cluster[g] = k;

@@ -10,7 +10,10 @@
 //  * det J > 0 check at the interpolation points and a Gauss sample;
 //  * MDEIM online step (Alg. 5): cluster of t, Lagrange interpolation of the
 //    fitted reduced coordinates, stabilised vector [(1-rho) I_r(t), rho]
-//    (Alg. 4 folds the stabilisation into the last column).
+//    (Alg. 4 folds the stabilisation into the last column).  For families
+//    with four parameters per cell (the corner thresholds of Sec. 2.1.2) this
+//    kernel finds the cluster and checks the box; k_mdeim4 evaluates the
+//    tensor-product interpolant.
 // k_constraints: edge-average and edge-moment rows of the coarse dofs
 //  (Sec. 3.3.1) by Gauss quadrature along the physical edge.
 // k_loads: consistent load of the right-edge traction (Sec. 2.2.1).
@@ -19,11 +22,11 @@
 namespace lbddc {
 
 struct GeoArgs {
-  const double* ctrl; const int* family; const double* t; const double* tab;
+  const double* ctrl; const int* family; const double* t; const double* thr; const double* tab;
   const int* fam_slot;        // family id -> slot (or -1); indexed by family id (< 64)
-  const double* coeff[4];     // per slot [n_k][r+1][n_r]
+  const double* coeff[4];     // per slot [n_cl][(r+1)^dim][n_r]
   double lo[4], hi[4];
-  int n_k[4], n_r[4], r[4], group_base[4];
+  int n_k[4], n_r[4], r[4], dim[4], group_base[4];
   int ncell, nx, netx, m, nL, ns, itil_stride;
   double lam, mu, rho;
   Tables T;
@@ -105,6 +108,23 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs g) {
   float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
   for (int r = 0; r < g.itil_stride; ++r) { it[r] = 0.0; it32[r] = 0.0f; }
   if (slot < 0) { atomicOr(g.flags, 4); g.group[cell] = 0; return; }
+  if (g.dim[slot] == 4) {
+    // cluster sum_i c_i n_k^i of the corner thresholds, first one fastest
+    const double lo = g.lo[slot], hi = g.hi[slot];
+    const int nk = g.n_k[slot];
+    const double w = (hi - lo) / nk;
+    int k = 0;
+    for (int i = 3; i >= 0; --i) {
+      const double v = g.thr[(size_t)cell * 4 + i];
+      if (!(v >= lo && v <= hi)) { atomicOr(g.flags, 2); g.group[cell] = g.group_base[slot]; return; }
+      int ci = (int)floor((v - lo) / w);
+      if (ci > nk - 1) ci = nk - 1;
+      if (ci < 0) ci = 0;
+      k = k * nk + ci;
+    }
+    g.group[cell] = g.group_base[slot] + k;
+    return;
+  }
   const double t = g.t[cell], lo = g.lo[slot], hi = g.hi[slot];
   const int nk = g.n_k[slot], R = g.r[slot], nr = g.n_r[slot];
   if (!(t >= lo && t <= hi)) { atomicOr(g.flags, 2); g.group[cell] = g.group_base[slot]; return; }
@@ -141,6 +161,61 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs g) {
   it[nr] = g.rho;
   it32[nr] = (float)g.rho;
   g.group[cell] = g.group_base[slot] + k;
+}
+
+// MDEIM online step for the cells of four-parameter families (Alg. 5 with a
+// tensor fitting grid, Sec. 4.2.3): one 64-lane workgroup per cell.  The
+// cell's cluster box gives tau_i = (mu_i - a_i) / (b_i - a_i); lanes
+// 4 (r+1) evaluate the Lagrange bases l_i(tau_i) at the r+1 GLL points into
+// LDS; lane j < n_r then sums sum_nodes l_1(a_1) l_2(a_2) l_3(a_3) l_4(a_4)
+// coeff[node][j] over the (r+1)^4 nodes (node a_1 + (r+1)(a_2 + (r+1)(a_3 +
+// (r+1) a_4))), one coalesced row of the cluster's coefficients per node.
+struct Mdeim4Args {
+  const int* family; const double* mu; const int* fam_slot; const double* tab;
+  const double* coeff[4];
+  double lo[4], hi[4];
+  int n_k[4], n_r[4], r[4], dim[4], off_rnodes[4];
+  int ncell, itil_stride;
+  double rho;
+  double* itil; float* itil32;
+};
+
+__global__ __launch_bounds__(64) void k_mdeim4(Mdeim4Args g) {
+  const int cell = blockIdx.x, lane = threadIdx.x;
+  const int fam = g.family[cell];
+  const int slot = (fam >= 0 && fam < 64) ? g.fam_slot[fam] : -1;
+  if (slot < 0 || g.dim[slot] != 4) return;  // uniform over the workgroup
+  const int R = g.r[slot], R1 = R + 1, nr = g.n_r[slot];
+  double tau[4], hs[4];
+  const int k = mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo[slot], g.hi[slot], g.n_k[slot], tau, hs);
+  __shared__ double ell[4][9];
+  if (lane < 4 * R1) {
+    const int i = lane / R1, a = lane - i * R1;
+    ell[i][a] = lag_value(g.tab + g.off_rnodes[slot], R, a, tau[i]);
+  }
+  __syncthreads();
+  if (lane > nr) return;
+  double* it = g.itil + (size_t)cell * g.itil_stride;
+  float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
+  if (lane == nr) {
+    it[nr] = g.rho;
+    it32[nr] = (float)g.rho;
+    return;
+  }
+  const double* cf = g.coeff[slot] + (size_t)k * R1 * R1 * R1 * R1 * nr + lane;
+  double s = 0.0;
+  for (int a4 = 0; a4 < R1; ++a4)
+    for (int a3 = 0; a3 < R1; ++a3)
+      for (int a2 = 0; a2 < R1; ++a2) {
+        const double w3 = ell[3][a4] * ell[2][a3] * ell[1][a2];
+        for (int a1 = 0; a1 < R1; ++a1) {
+          s += (w3 * ell[0][a1]) * cf[0];
+          cf += nr;
+        }
+      }
+  s *= (1.0 - g.rho);
+  it[lane] = s;
+  it32[lane] = (float)s;
 }
 
 // Edge rows: for edge e of a cell, averages int_e u_c ds and moment
@@ -258,15 +333,16 @@ __global__ __launch_bounds__(64) void k_loads(LoadArgs g) {
 
 hipError_t launch_geometry(Ctx* c) {
   GeoArgs g = {};
-  g.ctrl = c->d_ctrl; g.family = c->d_family; g.t = c->d_t; g.tab = c->d_tab;
+  g.ctrl = c->d_ctrl; g.family = c->d_family; g.t = c->d_t; g.thr = c->d_mu; g.tab = c->d_tab;
   static_assert(sizeof(int) == 4, "");
   g.fam_slot = c->d_flags + 8;  // family -> slot table lives after the flags
   int base = 0;
   for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
     const RomDev& R = c->roms[c->fam_ids[s]];
     g.coeff[s] = R.coeff; g.lo[s] = R.lo; g.hi[s] = R.hi; g.n_k[s] = R.n_k; g.n_r[s] = R.n_r; g.r[s] = R.r;
+    g.dim[s] = R.dim;
     g.group_base[s] = base;
-    base += R.n_k;
+    base += R.ncl;
   }
   g.ncell = c->ncell; g.nx = c->nx; g.netx = c->netx; g.m = c->m; g.nL = c->nL; g.ns = c->ns;
   g.itil_stride = 4 * c->KC;
@@ -281,6 +357,19 @@ hipError_t launch_geometry(Ctx* c) {
     GEO(1) GEO(2) GEO(3) GEO(4)
 #undef GEO
     default: return hipErrorInvalidValue;
+  }
+  if (c->any_dim4) {
+    Mdeim4Args a = {};
+    a.family = c->d_family; a.mu = c->d_mu; a.fam_slot = c->d_flags + 8; a.tab = c->d_tab;
+    for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
+      const RomDev& R = c->roms[c->fam_ids[s]];
+      if (R.dim == 4 && R.r > 8) return hipErrorInvalidValue;  // LDS of the bases holds r <= 8
+      a.coeff[s] = R.coeff; a.lo[s] = R.lo; a.hi[s] = R.hi; a.n_k[s] = R.n_k; a.n_r[s] = R.n_r; a.r[s] = R.r;
+      a.dim[s] = R.dim; a.off_rnodes[s] = c->tab.off_rnodes[s];
+    }
+    a.ncell = c->ncell; a.itil_stride = 4 * c->KC; a.rho = c->rho;
+    a.itil = c->d_itil; a.itil32 = c->d_itil32;
+    hipLaunchKernelGGL(k_mdeim4, dim3(c->ncell), dim3(64), 0, c->stream, a);
   }
   return hipGetLastError();
 }

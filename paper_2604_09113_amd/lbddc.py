@@ -47,7 +47,8 @@ class LbddcError(RuntimeError):
 class RomDesc(C.Structure):
     _fields_ = [("family", C.c_int32), ("p", C.c_int32), ("q", C.c_int32), ("n_k", C.c_int32),
                 ("n_r", C.c_int32), ("r", C.c_int32), ("lo", C.c_double), ("hi", C.c_double),
-                ("U", C.POINTER(C.c_double)), ("coeff", C.POINTER(C.c_double)), ("I_pi", C.POINTER(C.c_double))]
+                ("U", C.POINTER(C.c_double)), ("coeff", C.POINTER(C.c_double)), ("I_pi", C.POINTER(C.c_double)),
+                ("dim", C.c_int32)]
 
 
 class ProblemDesc(C.Structure):
@@ -55,7 +56,7 @@ class ProblemDesc(C.Structure):
                 ("map_order", C.c_int32), ("ctrl", C.POINTER(C.c_double)), ("family", C.POINTER(C.c_int32)),
                 ("t", C.POINTER(C.c_double)), ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
                 ("constraints", C.c_uint32), ("clamped_sides", C.c_uint32), ("loaded_side", C.c_int32),
-                ("nrhs", C.c_int32), ("traction", C.POINTER(C.c_double))]
+                ("nrhs", C.c_int32), ("traction", C.POINTER(C.c_double)), ("mu", C.POINTER(C.c_double))]
 
 
 class SolveInfo(C.Structure):
@@ -91,15 +92,15 @@ def library():
         "lbddc_version": (C.c_int, []),
         "lbddc_load_rom": (C.c_int, [P, C.POINTER(RomDesc)]),
         "lbddc_set_problem": (C.c_int, [P, C.POINTER(ProblemDesc)]),
-        "lbddc_set_geometry_device": (C.c_int, [P, P, P]),
+        "lbddc_set_geometry_device": (C.c_int, [P, P, P, P]),
         "lbddc_assemble": (C.c_int, [P, C.c_int]),
         "lbddc_setup": (C.c_int, [P, C.c_int]),
         "lbddc_solve": (C.c_int, [P, C.c_double, C.c_int32, C.POINTER(SolveInfo)]),
         "lbddc_solve_sequential": (C.c_int, [P, C.c_double, C.c_int32, C.POINTER(SolveInfo)]),
         "lbddc_get_displacement": (C.c_int, [P, C.c_int32, dp]),
         "lbddc_get_displacement_device": (C.c_int, [P, C.c_int32, P]),
-        "lbddc_compliance_gradient": (C.c_int, [P, dp, dp, dp]),
-        "lbddc_compliance_gradient_device": (C.c_int, [P, P, P, P]),
+        "lbddc_compliance_gradient": (C.c_int, [P, dp, dp, dp, dp]),
+        "lbddc_compliance_gradient_device": (C.c_int, [P, P, P, P, P]),
         "lbddc_query": (C.c_int, [P, C.c_int32, C.POINTER(C.c_int64)]),
         "lbddc_export_cells": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, dp]),
         "lbddc_phase_times": (C.c_int, [P, dp, C.c_int32]),
@@ -154,18 +155,22 @@ class Solver:
             raise LbddcError(st, self.lib.lbddc_last_error(self.ctx).decode())
         return st
 
-    def load_rom(self, family, p, q, n_k, n_r, r, lo, hi, U, coeff, I_pi):
-        """U [n_k, n_i, n_r], coeff [n_k, r+1, n_r], I_pi [n_i] (float64)."""
+    def load_rom(self, family, p, q, n_k, n_r, r, lo, hi, U, coeff, I_pi, dim=1):
+        """U [n_k^dim, n_i, n_r], coeff [n_k^dim, (r+1)^dim, n_r], I_pi [n_i]
+        (float64); dim 1 (thickness t) or 4 (corner thresholds mu)."""
         U, coeff, I_pi = _f64(U), _f64(coeff), _f64(I_pi)
-        d = RomDesc(family, p, q, n_k, n_r, r, lo, hi, _dptr(U), _dptr(coeff), _dptr(I_pi))
+        d = RomDesc(family, p, q, n_k, n_r, r, lo, hi, _dptr(U), _dptr(coeff), _dptr(I_pi), dim)
         self._check(self.lib.lbddc_load_rom(self.ctx, C.byref(d)))
 
     def set_problem(self, nx, ny, p, q, m, ctrl, family, t, E, nu, rho, moments, traction,
-                    clamped=("left",), loaded="right", constraints=None):
+                    clamped=("left",), loaded="right", constraints=None, mu=None):
         """`moments` selects the coarse set CORNERS | EDGE_AVG (| EDGE_MOMENT);
         `constraints` (a CON_* mask) overrides it.  `clamped` is a sequence of
-        side names, `loaded` one side name; traction [nrhs, n_side, 2]."""
+        side names, `loaded` one side name; traction [nrhs, n_side, 2];
+        mu [ncell, 4] the corner thresholds of cells of four-parameter
+        families (None when there are none)."""
         ctrl, t, traction = _f64(ctrl), _f64(t), _f64(traction)
+        mu = None if mu is None else _f64(mu)
         family = np.ascontiguousarray(family, dtype=np.int32)
         if constraints is None:
             constraints = CON_CORNERS | CON_EDGE_AVG | (CON_EDGE_MOMENT if moments else 0)
@@ -173,13 +178,15 @@ class Solver:
         for sd in clamped:
             cmask |= SIDES[sd]
         d = ProblemDesc(nx, ny, p, q, m, _dptr(ctrl), family.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(t),
-                        E, nu, rho, int(constraints), cmask, SIDES[loaded], traction.shape[0], _dptr(traction))
+                        E, nu, rho, int(constraints), cmask, SIDES[loaded], traction.shape[0], _dptr(traction),
+                        None if mu is None else _dptr(mu))
         self._check(self.lib.lbddc_set_problem(self.ctx, C.byref(d)))
         self.nrhs = traction.shape[0]
         self.shape = (nx, ny, p, q, m)
 
-    def set_geometry_device(self, ctrl_ptr, t_ptr):
-        self._check(self.lib.lbddc_set_geometry_device(self.ctx, C.c_void_p(ctrl_ptr), C.c_void_p(t_ptr)))
+    def set_geometry_device(self, ctrl_ptr, t_ptr, mu_ptr=None):
+        self._check(self.lib.lbddc_set_geometry_device(self.ctx, C.c_void_p(ctrl_ptr), C.c_void_p(t_ptr),
+                                                       C.c_void_p(mu_ptr)))
 
     def assemble(self, prec=FP64):
         self._check(self.lib.lbddc_assemble(self.ctx, prec))
@@ -215,17 +222,20 @@ class Solver:
     def displacement_device(self, rhs, dptr):
         self._check(self.lib.lbddc_get_displacement_device(self.ctx, rhs, C.c_void_p(dptr)))
 
-    def compliance_gradient(self):
+    def compliance_gradient(self, thresholds=False):
+        """(J, dJ/dctrl, dJ/dt), and dJ/dmu [nrhs, ncell, 4] with `thresholds`."""
         nx, ny, p, q, m = self.shape
         J = np.zeros(self.nrhs)
         gX = np.zeros((self.nrhs, m * ny + 1, m * nx + 1, 2))
         gt = np.zeros((self.nrhs, nx * ny))
-        self._check(self.lib.lbddc_compliance_gradient(self.ctx, _dptr(J), _dptr(gX), _dptr(gt)))
-        return J, gX, gt
+        gmu = np.zeros((self.nrhs, nx * ny, 4)) if thresholds else None
+        self._check(self.lib.lbddc_compliance_gradient(self.ctx, _dptr(J), _dptr(gX), _dptr(gt),
+                                                       None if gmu is None else _dptr(gmu)))
+        return (J, gX, gt, gmu) if thresholds else (J, gX, gt)
 
-    def compliance_gradient_device(self, J_ptr, gX_ptr, gt_ptr):
+    def compliance_gradient_device(self, J_ptr, gX_ptr, gt_ptr, gmu_ptr=None):
         self._check(self.lib.lbddc_compliance_gradient_device(self.ctx, C.c_void_p(J_ptr), C.c_void_p(gX_ptr),
-                                                              C.c_void_p(gt_ptr)))
+                                                              C.c_void_p(gt_ptr), C.c_void_p(gmu_ptr)))
 
     def export(self, which, first, count):
         nx, ny, p, q, m = self.shape

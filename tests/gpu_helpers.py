@@ -10,14 +10,15 @@ def rom_arrays(rom):
     U = np.stack([c["U"] for c in rom["clusters"]])
     coeff = np.stack([c["coeff"] for c in rom["clusters"]])
     return dict(family=rom["family"], p=rom["p"], q=rom["q"], n_k=rom["n_k"], n_r=rom["n_r"], r=rom["r"],
-                lo=rom["lo"], hi=rom["hi"], U=U, coeff=coeff, I_pi=rom["I_pi"])
+                lo=rom["lo"], hi=rom["hi"], U=U, coeff=coeff, I_pi=rom["I_pi"], dim=rom.get("dim", 1))
 
 
 def set_problem(s, prob, moments=None):
     """set_problem with every field of a workloads problem dict."""
     s.set_problem(prob["nx"], prob["ny"], prob["p"], prob["q"], prob["m"], prob["ctrl"], prob["family"], prob["t"],
                   prob["E"], prob["nu"], prob["rho"], prob["moments"] if moments is None else moments,
-                  prob["traction"], clamped=prob.get("clamped", ("left",)), loaded=prob.get("loaded", "right"))
+                  prob["traction"], clamped=prob.get("clamped", ("left",)), loaded=prob.get("loaded", "right"),
+                  mu=prob.get("mu"))
 
 
 def make_solver(prob, roms, moments=None):

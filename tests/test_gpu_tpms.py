@@ -1,0 +1,141 @@
+"""GPU parity on lattices of the paper's own cells: Table 1 level sets with
+the bilinear threshold through shared vertex values (d = 4, Sec. 2.1.2), the
+graded recipe of the four-parameter workload at small sizes, against the
+oracle (its implicit-domain quadrature, its four-parameter ROM, its solve and
+adjoint):
+
+  - Schwarz Diamond with 2 clusters per threshold (16 clusters; the oracle
+    trains the ones the lattice visits), Schoen IWP with one cluster;
+  - the stabilised reduced vector [(1 - rho) I_r(mu), rho] of every cell
+    within 1e-13 (tensor Lagrange interpolation over (r+1)^4 nodes), K_i
+    within 1e-10;
+  - displacement against the oracle's direct solve within 1e-8 of its
+    largest entry, PCG from the GPU to rtol 1e-13;
+  - J, dJ/dX and dJ/dmu within 1e-8 of the oracle's adjoint, dJ/dt zero on
+    these cells, and dJ/dmu against central differences of the GPU's own
+    compliance along a random direction of the thresholds;
+  - a threshold outside the ROM box is rejected (LBDDC_E_PARAM_RANGE) by
+    set_problem and by set_geometry_device, which keeps the previous state.
+"""
+import numpy as np
+import pytest
+
+from conftest import oracle_roms
+from workloads import make_problem
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "schwarz_d": dict(nx=4, ny=3, p=3, topo="schwarz_d",
+                      rom={2: dict(lo=0.05, hi=0.95, n_k=2, n_s=6, n_r=6, r=1, dim=4)}),
+    # a narrower threshold range than the paper's [-2.5, 2.5]^4, so that one
+    # cluster with a quadratic fit keeps every K_i positive definite
+    "schoen_iwp": dict(nx=3, ny=2, p=4, topo="schoen_iwp", mu_box=(0.0, 1.0),
+                       rom={5: dict(lo=-0.1, hi=1.1, n_k=1, n_s=8, n_r=8, r=2, dim=4)}),
+}
+
+
+def _prob(name):
+    return make_problem(6, **CASES[name])
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    from oracle.bddc import Problem
+    name = request.param
+    prob = _prob(name)
+    print(f"\n[tpms {name}] oracle ROM and solve", flush=True)
+    roms = oracle_roms(prob)
+    P = Problem(prob, roms)
+    P.setup()
+    u = P.direct_solve()
+    return name, prob, roms, P, u
+
+
+def test_itil_and_stiffness(case):
+    from gpu_helpers import make_solver
+    from oracle.assembly import rom_K
+    from oracle.rom import stabilised_reduced
+    from paper_2604_09113_amd import lbddc
+    name, prob, roms, P, _ = case
+    s = make_solver(prob, roms)
+    s.assemble()
+    nc = prob["nx"] * prob["ny"]
+    it = s.export(lbddc.X_ITIL, 0, nc)
+    K = s.export(lbddc.X_K, 0, nc)
+    s.close()
+    e_it, e_K = 0.0, 0.0
+    for c in range(nc):
+        f = int(prob["family"][c])
+        _, ref = stabilised_reduced(roms[f], prob["mu"][c], prob["rho"])
+        e_it = max(e_it, np.abs(it[c][:len(ref)] - ref).max() / np.abs(ref).max())
+        assert np.all(it[c][len(ref):] == 0.0)
+        Kr = rom_K(P.control_points(c), roms[f], prob["mu"][c], prob["rho"], P.Cmat)
+        e_K = max(e_K, np.abs(K[c] - Kr).max() / np.abs(Kr).max())
+    print(f"[tpms {name}] Itil {e_it:.2e}  K {e_K:.2e}")
+    assert e_it <= 1e-13 and e_K <= 1e-10
+
+
+def test_solution_and_gradients(case):
+    from gpu_helpers import make_solver
+    from oracle.adjoint import compliance_gradient
+    from paper_2604_09113_amd import lbddc
+    name, prob, roms, P, u = case
+    s = make_solver(prob, roms)
+    s.assemble()
+    s.setup(lbddc.FP64)
+    info = s.solve(rtol=1e-13, max_iter=2000)
+    ug = s.displacement(0)
+    eu = np.abs(ug - u[0]).max() / np.abs(u[0]).max()
+    J, gX, gt, gmu = s.compliance_gradient(thresholds=True)
+    Jo, gXo, gto, gmuo = compliance_gradient(P, u, thresholds=True)
+    eJ = abs(J[0] - Jo[0]) / abs(Jo[0])
+    eX = np.abs(gX - gXo).max() / np.abs(gXo).max()
+    emu = np.abs(gmu - gmuo).max() / np.abs(gmuo).max()
+    print(f"[tpms {name}] {info[0]['iters']} iterations; u {eu:.2e} J {eJ:.2e} dJ/dX {eX:.2e} dJ/dmu {emu:.2e}")
+    assert eu <= 1e-8 and eJ <= 1e-8 and eX <= 1e-8 and emu <= 1e-8
+    assert np.all(gt == 0.0)
+    # central differences of the GPU's own compliance along a threshold direction
+    import torch
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=prob["mu"].shape)
+    d /= np.linalg.norm(d)
+    h = 1e-5
+    Js = []
+    for sg in (1.0, -1.0):
+        mu_d = torch.tensor(prob["mu"] + sg * h * d, dtype=torch.float64, device="cuda")
+        s.set_geometry_device(None, None, mu_d.data_ptr())
+        s.assemble()
+        s.setup(lbddc.FP64)
+        s.solve(rtol=1e-14, max_iter=3000)
+        Js.append(s.compliance_gradient()[0][0])
+        torch.cuda.synchronize()
+    s.close()
+    fd = (Js[0] - Js[1]) / (2 * h)
+    ad = (gmu[0] * d).sum()
+    print(f"[tpms {name}] dJ/dmu . d: adjoint {ad:.10e} central difference {fd:.10e}")
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+def test_threshold_outside_box_rejected():
+    import torch
+    from gpu_helpers import make_solver, set_problem
+    from paper_2604_09113_amd import lbddc
+    prob = _prob("schoen_iwp")
+    roms = oracle_roms(prob)
+    s = make_solver(prob, roms)
+    s.assemble()
+    K0 = s.export(lbddc.X_K, 0, 2)
+    bad = dict(prob, mu=prob["mu"].copy())
+    bad["mu"][1, 2] = 1.2
+    with pytest.raises(lbddc.LbddcError) as ei:
+        set_problem(s, bad)
+    assert ei.value.status == lbddc.E_PARAM_RANGE
+    mu_d = torch.tensor(bad["mu"], dtype=torch.float64, device="cuda")
+    with pytest.raises(lbddc.LbddcError) as ei:
+        s.set_geometry_device(None, None, mu_d.data_ptr())
+    assert ei.value.status == lbddc.E_PARAM_RANGE
+    s.assemble()
+    K1 = s.export(lbddc.X_K, 0, 2)
+    s.close()
+    assert np.array_equal(K0, K1)
