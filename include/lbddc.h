@@ -318,8 +318,9 @@ lbddc_status lbddc_coarse_solve(lbddc_ctx* ctx, const double* z, double* g);
  *   (mean per launch), [8] coarse solve (mean per application), [9] recovery,
  *   [10] gradient, [11] adjoint contraction kernel, [12] forward sweep of the
  *   coarse solve (mean per application; one launch per tree level), [13] its
- *   backward sweep (same).
- * `n` entries are written (n <= 14). */
+ *   backward sweep (same), [14] the geometry coefficients and the MDEIM
+ *   evaluation of assemble.
+ * `n` entries are written (n <= 15). */
 lbddc_status lbddc_phase_times(lbddc_ctx* ctx, double* ms, int32_t n);
 
 /* PCG phases timed by lbddc_solve (bit mask; LBDDC_TIME_ALL after create):
@@ -335,6 +336,29 @@ lbddc_status lbddc_phase_times(lbddc_ctx* ctx, double* ms, int32_t n);
  * eightfold).  Returns LBDDC_E_ARG for unknown bits. */
 enum { LBDDC_TIME_OP = 1, LBDDC_TIME_PRE = 2, LBDDC_TIME_COARSE = 4, LBDDC_TIME_ALL = 7, LBDDC_TIME_SAMPLE = 8 };
 lbddc_status lbddc_set_timing(lbddc_ctx* ctx, int32_t mask);
+
+/* Offline stage (Sec. 4.2, Alg. 3): snapshot integrals of cells trimmed by the
+ * level sets of Table 1 (family 2 Schwarz Diamond, 3 Schwarz Primitive, 4
+ * Schoen FRD, 5 Schoen IWP) with the bilinear threshold of Sec. 2.1.2, for
+ * training their ROMs.  For each of `count` threshold vectors mu[count][4]
+ * (host), the trimmed cell {phi_0 < mu} is integrated on the GPU by an
+ * implicit-domain quadrature after Saye's height-function method (the method
+ * the paper's QUGaR/algoim quadrature implements, Sec. 2.2.3), and out (host)
+ * receives either the whole tensor I(mu) of n_i = (p+1)^4 4 (q+1)^2 entries in
+ * the order of lbddc_rom_desc (n_entries = 0: out[count][n_i]) or the entries
+ * listed in entries[n_entries] (out[count][n_entries]; the magic points of the
+ * fitting stage).  Allocates and frees its own device memory; not for hot
+ * loops.  Limits: 2 <= p <= 8, 1 <= q <= 3; a rule of more than 131072 points
+ * or a failed root iteration returns LBDDC_E_NUMERIC. */
+lbddc_status lbddc_implicit_tensors(lbddc_ctx* ctx, int32_t family, int32_t p, int32_t q, int32_t count,
+                                   const double* mu, int32_t n_entries, const int64_t* entries, double* out);
+
+/* For testing the offline quadrature: the same rule computed on the host for
+ * one threshold vector, n Gauss points per segment (1 <= n <= 24); points
+ * (x, y) and weights w into host buffers of cap entries, their number in
+ * *count.  LBDDC_E_NUMERIC when cap is too small or an iteration fails. */
+lbddc_status lbddc_implicit_rule_host(int32_t family, const double* mu, int32_t n, int32_t cap, double* x, double* y,
+                                      double* w, int32_t* count);
 
 #ifdef __cplusplus
 }

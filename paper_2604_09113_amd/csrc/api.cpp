@@ -511,6 +511,7 @@ lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
   c->k32_valid = false;
   HIPCHK(hipEventRecord(c->ev[6], c->stream), "assemble");
   HIPCHK(launch_geometry(c), "assemble geometry");
+  HIPCHK(hipEventRecord(c->ev[2], c->stream), "assemble");
   HIPCHK(launch_constraints_loads(c), "assemble constraints");
   HIPCHK(launch_assembly(c, fp32, c->ev[0], c->ev[1]), "assemble contraction");
   HIPCHK(hipEventRecord(c->ev[7], c->stream), "assemble");
@@ -519,6 +520,7 @@ lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
   float ms = 0;
   if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) c->phase_ms[0] = ms;
   if (hipEventElapsedTime(&ms, c->ev[6], c->ev[7]) == hipSuccess) c->phase_ms[1] = ms;
+  if (hipEventElapsedTime(&ms, c->ev[6], c->ev[2]) == hipSuccess) c->phase_ms[14] = ms;
   c->asm_prec = prec;
   c->assembled = !fp32;  // the FP32 contraction alone feeds no later stage
   c->k32_valid = fp32;
@@ -736,7 +738,7 @@ lbddc_status lbddc_query(const lbddc_ctx* x, int32_t what, int64_t* v) {
 }
 
 lbddc_status lbddc_phase_times(lbddc_ctx* x, double* ms, int32_t n) {
-  if (!x || !ms || n < 0 || n > 14) return LBDDC_E_ARG;
+  if (!x || !ms || n < 0 || n > 15) return LBDDC_E_ARG;
   for (int i = 0; i < n; ++i) ms[i] = x->c.phase_ms[i];
   return LBDDC_OK;
 }

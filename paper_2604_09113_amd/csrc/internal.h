@@ -398,7 +398,7 @@ struct Ctx {
   } grp;
   double* d_ucell = nullptr;   // [ncell][ndof] local displacement (permuted)
 
-  double phase_ms[14] = {0};
+  double phase_ms[15] = {0};
   static constexpr int kNumEv = 9;
   hipEvent_t ev[kNumEv] = {};
   // events of the timed PCG phases, a ring of kRing iterations read back at the

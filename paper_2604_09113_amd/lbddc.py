@@ -28,14 +28,15 @@ SIDES = {"left": SIDE_LEFT, "right": SIDE_RIGHT, "bottom": SIDE_BOTTOM, "top": S
 CON_CORNERS, CON_EDGE_AVG, CON_EDGE_MOMENT = 1, 2, 4
 PHASES = ["assembly_kernel", "assemble", "schur_kernel", "setup", "coarse_factor", "solve", "op_kernel",
           "pre_kernel", "coarse_solve", "recovery", "gradient", "adjoint_kernel", "coarse_fwd_sweep",
-          "coarse_bwd_sweep"]
+          "coarse_bwd_sweep", "geometry"]
 
 FUNCTIONS = ["lbddc_create", "lbddc_destroy", "lbddc_last_error", "lbddc_version", "lbddc_load_rom",
              "lbddc_set_problem", "lbddc_set_geometry_device", "lbddc_assemble", "lbddc_setup", "lbddc_solve",
              "lbddc_solve_sequential",
              "lbddc_get_displacement", "lbddc_get_displacement_device", "lbddc_compliance_gradient",
              "lbddc_compliance_gradient_device", "lbddc_query", "lbddc_export_cells", "lbddc_phase_times",
-             "lbddc_set_timing", "lbddc_assemble_fp32_noalloc", "lbddc_coarse_solve"]
+             "lbddc_set_timing", "lbddc_assemble_fp32_noalloc", "lbddc_coarse_solve", "lbddc_implicit_tensors",
+             "lbddc_implicit_rule_host"]
 
 
 class LbddcError(RuntimeError):
@@ -107,6 +108,10 @@ def library():
         "lbddc_set_timing": (C.c_int, [P, C.c_int32]),
         "lbddc_assemble_fp32_noalloc": (C.c_int, [P, P]),
         "lbddc_coarse_solve": (C.c_int, [P, dp, dp]),
+        "lbddc_implicit_tensors": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32,
+                                             C.POINTER(C.c_int64), dp]),
+        "lbddc_implicit_rule_host": (C.c_int, [C.c_int32, dp, C.c_int32, C.c_int32, dp, dp, dp,
+                                               C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -237,6 +242,22 @@ class Solver:
         self._check(self.lib.lbddc_compliance_gradient_device(self.ctx, C.c_void_p(J_ptr), C.c_void_p(gX_ptr),
                                                               C.c_void_p(gt_ptr), C.c_void_p(gmu_ptr)))
 
+    def implicit_tensors(self, family, p, q, mu, entries=None):
+        """Offline snapshots of a Table 1 family on the GPU: I(mu) for every row
+        of mu [count, 4], whole ([count, n_i]) or at `entries` ([count, ne])."""
+        mu = _f64(np.atleast_2d(mu))
+        count = mu.shape[0]
+        n_i = (p + 1) ** 4 * 4 * (q + 1) ** 2
+        if entries is None:
+            out = np.zeros((count, n_i))
+            ne, ep = 0, None
+        else:
+            ent = np.ascontiguousarray(entries, dtype=np.int64)
+            out = np.zeros((count, len(ent)))
+            ne, ep = len(ent), ent.ctypes.data_as(C.POINTER(C.c_int64))
+        self._check(self.lib.lbddc_implicit_tensors(self.ctx, family, p, q, count, _dptr(mu), ne, ep, _dptr(out)))
+        return out
+
     def export(self, which, first, count):
         nx, ny, p, q, m = self.shape
         nB, nU, nC, nL = (p + 1) ** 2, 8 * p, self.query(Q_NC_CELL), (q + 1) ** 2
@@ -263,3 +284,16 @@ class Solver:
         out = np.zeros(len(PHASES))
         self._check(self.lib.lbddc_phase_times(self.ctx, _dptr(out), len(PHASES)))
         return dict(zip(PHASES, out.tolist()))
+
+
+def implicit_rule_host(family, mu, n, cap=1 << 18):
+    """The offline implicit-domain rule computed on the host (a test entry):
+    points x, y and weights w of the trimmed cell {phi_0 < mu}."""
+    lib = library()
+    x, y, w = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    cnt = C.c_int32()
+    st = lib.lbddc_implicit_rule_host(family, _dptr(_f64(mu)), n, cap, _dptr(x), _dptr(y), _dptr(w), C.byref(cnt))
+    if st != OK:
+        raise LbddcError(st, "implicit_rule_host failed")
+    k = cnt.value
+    return x[:k], y[:k], w[:k]

@@ -11,6 +11,14 @@ Both stand-in families are trimmed by circles or axis-aligned lines, so their
 snapshots are integrated exactly (to rounding): the integrand is a polynomial
 of total degree 4p - 2 + 2q (at most 2p + q per variable), integrated by Gauss
 rules over rectangles and a polar Gauss x trapezoid rule over the disk.
+The level sets of Table 1 with the bilinear threshold (Sec. 2.1.2) have four
+parameters per cell and curved, implicitly given boundaries; their trainer
+(train_implicit) runs the snapshot and fitting quadratures on the GPU through
+lbddc_implicit_tensors (an implicit-domain quadrature after Saye's method),
+with n_k clusters per threshold (n_k^4 in all), Latin-hypercube samples per
+cluster and the (r+1)^4 tensor grid of GLL fitting nodes, first threshold
+fastest.
+
 Readings shared with the rest of the library: clusters split [lo, hi] evenly;
 LHS takes one sample per stratum; columns of the SVD basis are signed so that
 their largest entry is positive; the rank is cut where sigma_j / sigma_1 <=
@@ -175,3 +183,59 @@ def train(family, p, q, lo, hi, n_k, n_s, n_r, r, lhs_u, rank_tol=1e-13, log=Non
         C[k, :, :ranks[k]] = coefs[k]
     return dict(family=family, p=p, q=q, n_k=n_k, n_r=nr, r=r, lo=lo, hi=hi, U=U, coeff=C,
                 I_pi=integ.untrimmed())
+
+
+def _lhs(a, b, u, perm):
+    """One coordinate of a Latin-hypercube sample set: stratum perm[s], offset u[s]."""
+    return a + (np.asarray(perm) + u) * (b - a) / len(u)
+
+
+def train_implicit(solver, family, p, q, lo, hi, n_k, n_s, n_r, r, lhs_u, lhs_perm, rank_tol=1e-13, only=None,
+                   log=None):
+    """ROM of a Table 1 level set with four corner thresholds per cell, its
+    snapshots and fitting values integrated on the GPU (solver: an
+    lbddc.Solver).  lhs_u [n_k^4, n_s, 4] offsets and lhs_perm [n_k^4, 4, n_s]
+    stratum orders of the Latin-hypercube sampling; `only` restricts training
+    to the listed clusters (the others keep zero arrays).  Returns the arrays
+    of lbddc_load_rom with dim = 4."""
+    ncl = n_k ** 4
+    w = (hi - lo) / n_k
+    g = gll_nodes01(r)
+    bases, coefs, ranks = [], [], []
+    for k in range(ncl):
+        c = [(k // n_k ** i) % n_k for i in range(4)]
+        box = [(lo + ci * w, lo + (ci + 1) * w) for ci in c]
+        if only is not None and k not in only:
+            bases.append(None)
+            coefs.append(None)
+            ranks.append(0)
+            continue
+        X = np.stack([_lhs(box[i][0], box[i][1], lhs_u[k][:, i], lhs_perm[k][i]) for i in range(4)], axis=1)
+        snaps = solver.implicit_tensors(family, p, q, X).T
+        U, s, _ = np.linalg.svd(snaps, full_matrices=False)
+        big = np.argmax(np.abs(U), axis=0)
+        U = U * np.sign(U[big, np.arange(U.shape[1])])
+        rank = min(n_r, int(np.sum(s / s[0] > rank_tol)))
+        Ur = U[:, :rank]
+        mp = _deim(Ur)
+        # fitting grid: first threshold fastest
+        f = [box[i][0] + (box[i][1] - box[i][0]) * g for i in range(4)]
+        grid = np.array([[f[0][a], f[1][b], f[2][cc], f[3][d]]
+                         for d in range(r + 1) for cc in range(r + 1) for b in range(r + 1) for a in range(r + 1)])
+        vals = solver.implicit_tensors(family, p, q, grid, entries=mp)
+        coef = np.linalg.solve(Ur[mp], vals.T).T
+        bases.append(Ur)
+        coefs.append(coef)
+        ranks.append(rank)
+        if log:
+            log(f"family {family} cluster {k}: rank {rank}, sigma ratio {s[rank - 1] / s[0]:.1e}")
+    nr = max(ranks)
+    n_i = (p + 1) ** 4 * 4 * (q + 1) ** 2
+    U = np.zeros((ncl, n_i, nr))
+    C = np.zeros((ncl, (r + 1) ** 4, nr))
+    for k in range(ncl):
+        if bases[k] is not None:
+            U[k, :, :ranks[k]] = bases[k]
+            C[k, :, :ranks[k]] = coefs[k]
+    return dict(family=family, p=p, q=q, n_k=n_k, n_r=nr, r=r, lo=lo, hi=hi, U=U, coeff=C,
+                I_pi=_Integrator(p, q).untrimmed(), dim=4)
