@@ -86,21 +86,33 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
       uu[v][0] = w * a0 * c0; uu[v][1] = w * a0 * c1; uu[v][2] = w * a1 * c0; uu[v][3] = w * a1 * c1;
     }
   };
-  dbl4 hacc2[RB];  // second accumulator chain of H (odd kk), added in a fixed order at the end
+  // Deep reduced bases (KC > 6) would need more than 256 registers with the
+  // double-buffered operands, the second H chain and the displacement
+  // prefetch of the shallow ones, and run one wave per SIMD; their lean form
+  // (one H chain, the transposed tile loaded one step ahead, the pair
+  // products formed at the start of each tile) keeps two.
+  constexpr bool LEAN = KC > 6;
+  dbl4 hacc2[LEAN ? 1 : RB];  // second accumulator chain of H (odd kk), added in a fixed order at the end
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) hacc2[rb] = dbl4{0, 0, 0, 0};
-  // MFMA operands of step s of pair tile pt; steps past the end belong to the
-  // wave's next tile (pt + 4), and past the last tile to any valid address
-  auto load = [&](int ptl, int sl, double (&a)[KC], double (&a2)[RB][4]) {
+  for (int rb = 0; rb < (LEAN ? 1 : RB); ++rb) hacc2[rb] = dbl4{0, 0, 0, 0};
+  auto base = [&](int& ptl, int& sl) {
     if (sl >= ns) {
       sl -= ns;
       ptl += 4;
     }
     if (ptl >= NPT) ptl = NPT - 1;
+  };
+  // MFMA operands of step s of pair tile pt; steps past the end belong to the
+  // wave's next tile (pt + 4), and past the last tile to any valid address
+  auto load_a = [&](int ptl, int sl, double (&a)[KC]) {
+    base(ptl, sl);
     const GP ap = ut + ((size_t)ptl * ns + sl) * KC * 64 + lane;
-    const GP ap2 = ut2 + ((size_t)ptl * ns + sl) * RB * 4 * 64 + lane;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) a[kc] = ap[kc * 64];
+  };
+  auto load_h = [&](int ptl, int sl, double (&a2)[RB][4]) {
+    base(ptl, sl);
+    const GP ap2 = ut2 + ((size_t)ptl * ns + sl) * RB * 4 * 64 + lane;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
       const double z = t4[0] * uu[kk][0] + t4[1] * uu[kk][1] + t4[2] * uu[kk][2] + t4[3] * uu[kk][3];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
-        if (kk & 1) hacc2[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc2[rb], 0, 0, 0);
+        if (!LEAN && (kk & 1)) hacc2[LEAN ? 0 : rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc2[LEAN ? 0 : rb], 0, 0, 0);
         else hacc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[rb][kk], z, hacc[rb], 0, 0, 0);
       }
     }
@@ -136,26 +148,51 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
     const double gm = (lo ? x1 : x0) + __shfl_xor(lo ? x0 : x1, 16);
     Gw[(col * ns + s) * 4 + grp] += gm;
   };
-  // two operand sets take the steps in turn, each reloaded (two steps ahead)
-  // right after the step that used it, without copies between them
-  double aA[KC], a2A[RB][4], aB[KC], a2B[RB][4];
-  load(wave, 0, aA, a2A);
-  load(wave, 1, aB, a2B);
-  pair_load(wave);
-  pair_products(uu);
-  pair_load(wave + 4);  // next pair tile: its loads overlap this tile's work
-  for (int pt = wave; pt < NPT; pt += 4) {
-    for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
-      step(s, aA, a2A);
-      load(pt, s + 2, aA, a2A);
-      step(s + 1, aB, a2B);
-      load(pt, s + 3, aB, a2B);
+  if constexpr (LEAN) {
+    double aA[KC], aB[KC], a2[RB][4];
+    load_a(wave, 0, aA);
+    load_a(wave, 1, aB);
+    load_h(wave, 0, a2);
+    for (int pt = wave; pt < NPT; pt += 4) {
+      pair_load(pt);
+      pair_products(uu);
+      for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
+        step(s, aA, a2);
+        load_a(pt, s + 2, aA);
+        load_h(pt, s + 1, a2);
+        step(s + 1, aB, a2);
+        load_a(pt, s + 3, aB);
+        load_h(pt, s + 2, a2);
+      }
     }
+  } else {
+    // two operand sets take the steps in turn, each reloaded (two steps ahead)
+    // right after the step that used it, without copies between them
+    double aA[KC], a2A[RB][4], aB[KC], a2B[RB][4];
+    load_a(wave, 0, aA);
+    load_h(wave, 0, a2A);
+    load_a(wave, 1, aB);
+    load_h(wave, 1, a2B);
+    pair_load(wave);
     pair_products(uu);
-    pair_load(pt + 8);
+    pair_load(wave + 4);  // next pair tile: its loads overlap this tile's work
+    for (int pt = wave; pt < NPT; pt += 4) {
+      for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
+        step(s, aA, a2A);
+        load_a(pt, s + 2, aA);
+        load_h(pt, s + 2, a2A);
+        step(s + 1, aB, a2B);
+        load_a(pt, s + 3, aB);
+        load_h(pt, s + 3, a2B);
+      }
+      pair_products(uu);
+      pair_load(pt + 8);
+    }
   }
+  if constexpr (!LEAN) {
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb) hacc[rb] += hacc2[rb];
+    for (int rb = 0; rb < RB; ++rb) hacc[rb] += hacc2[rb];
+  }
   __syncthreads();
   // G: sum the four waves in a fixed order and write
   for (int i = threadIdx.x; i < GW; i += 256) {
