@@ -285,6 +285,7 @@ struct Ctx {
   double* d_mu = nullptr;      // [ncell][4] corner thresholds (cells of dim-4 families)
   double* d_mu_bak = nullptr;
   bool any_dim4 = false;       // some family of the problem has four parameters per cell
+  std::vector<int> tile_fam_first, tile_fam_n;  // each family's range of the contraction's 128-cell tiles
   int* d_perm = nullptr;       // [nN]
   int* d_RU = nullptr;         // [ncell][nU]
   int* d_RC = nullptr;         // [ncell][nC]
@@ -425,6 +426,9 @@ void build_tables(Ctx* c, std::vector<double>& tab);
 // ---------------------------------------------------------------------------
 // Kernel launchers.  All enqueue on c->stream and return hipGetLastError().
 hipError_t launch_geometry(Ctx* c);          // theta, det check, MDEIM eval (A1, A2)
+// MDEIM evaluation of a four-parameter family over its tiles [first, first + n)
+// of the cluster-sorted cell order (after the group sort of the contraction)
+hipError_t launch_mdeim4(Ctx* c, int slot, const int* d_tiles, int first, int n);
 hipError_t launch_constraints_loads(Ctx* c); // edge constraint rows and loads
 hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1);  // A3
 hipError_t noalloc_scratch_init(int device);                          // address of the static scratch (device current)

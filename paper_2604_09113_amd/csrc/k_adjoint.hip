@@ -409,71 +409,80 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
   for (int a = 0; a < NP1; ++a) { out[2 * a] = gX[a][0]; out[2 * a + 1] = gX[a][1]; }
 }
 
-// dJ/dmu_i = -(1 - rho) sum_j H_j sum_nodes d/dmu_i [l_1 l_2 l_3 l_4](node)
-// coeff[node][j] for the cells of four-parameter families (the derivative of
-// the tensor Lagrange interpolant of Alg. 5, H = dE/dItil from the adjoint
-// contraction): one 64-lane workgroup per cell, lane j < n_r accumulating the
-// four sums of its coefficient column, then a fixed-order butterfly over the
-// lanes.  Other cells get zeros.
+// dJ/dmu_i = -(1 - rho) sum_nodes d/dmu_i [l_1 l_2 l_3 l_4](node) h(node),
+// h(node) = sum_j H_j coeff[node][j], for the cells of four-parameter
+// families (the derivative of the tensor Lagrange interpolant of Alg. 5; H =
+// dE/dItil from the adjoint contraction), on the tiles of the cluster-sorted
+// cell order: a workgroup takes 64 cells of a tile, the cluster's
+// coefficients pass through LDS one (a_1, a_2) plane at a time, wave w takes
+// the nodes j = w mod 4 of each plane for the cell of its lane, and the four
+// waves' sums are added in a fixed order.
 struct ChainMu4Args {
-  const int* family; const double* mu; const int* fam_slot; const double* tab;
-  const double* coeff[4];
-  double lo[4], hi[4];
-  int n_k[4], n_r[4], r[4], dim[4], off_rnodes[4];
+  const double* mu; const double* tab;
+  const double* coeff;
+  double lo, hi;
+  int n_k, n_r, r, off_rnodes;
   int itil_stride;
   double rho;
   const double* H;
   double* gmu;  // [ncell][4]
 };
 
-__global__ __launch_bounds__(64) void k_chain_mu4(ChainMu4Args g) {
-  const int cell = blockIdx.x, lane = threadIdx.x;
-  const int fam = g.family[cell];
-  const int slot = g.fam_slot[fam];
-  if (g.dim[slot] != 4) {
-    if (lane < 4) g.gmu[(size_t)cell * 4 + lane] = 0.0;
-    return;
+__global__ __launch_bounds__(256) void k_chain_mu4(ChainMu4Args g, const int* __restrict__ sorted,
+                                                   const int4* __restrict__ tiles) {
+  const int4 td = tiles[blockIdx.x];
+  const int c0 = 64 * blockIdx.y;
+  const int ncells = td.z - c0;
+  if (ncells <= 0) return;  // uniform over the workgroup
+  const int t = threadIdx.x, cl = t & 63, w = t >> 6;
+  const bool valid = cl < ncells;
+  const int cell = sorted[td.y + c0 + (valid ? cl : 0)];
+  const int R = g.r, R1 = R + 1, nr = g.n_r, plane = R1 * R1;
+  __shared__ double ell[64][4][9], dell[64][4][9];
+  __shared__ double cf[81][44];
+  __shared__ double red[4][64][4];
+  {
+    double tau[4], hs[4];
+    mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo, g.hi, g.n_k, tau, hs);
+    const double* x = g.tab + g.off_rnodes;
+    for (int a = 0; a < R1; ++a) {
+      ell[cl][w][a] = lag_value(x, R, a, tau[w]);
+      dell[cl][w][a] = lag_deriv(x, R, a, tau[w]) / hs[w];
+    }
   }
-  const int R = g.r[slot], R1 = R + 1, nr = g.n_r[slot];
-  double tau[4], hs[4];
-  const int k = mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo[slot], g.hi[slot], g.n_k[slot], tau, hs);
-  __shared__ double ell[4][9], dell[4][9];
-  if (lane < 4 * R1) {
-    const int i = lane / R1, a = lane - i * R1;
-    const double* x = g.tab + g.off_rnodes[slot];
-    ell[i][a] = lag_value(x, R, a, tau[i]);
-    dell[i][a] = lag_deriv(x, R, a, tau[i]) / hs[i];
-  }
-  __syncthreads();
+  double tau0[4], hs0[4];
+  const int k = mdeim4_cluster(g.mu + (size_t)sorted[td.y] * 4, g.lo, g.hi, g.n_k, tau0, hs0);
+  const double* C = g.coeff + (size_t)k * plane * plane * nr;
+  double h[43];
+#pragma unroll
+  for (int j = 0; j < 43; ++j) h[j] = j < nr ? g.H[(size_t)cell * g.itil_stride + j] : 0.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (lane < nr) {
-    const double h = g.H[(size_t)cell * g.itil_stride + lane];
-    const double* cf = g.coeff[slot] + (size_t)k * R1 * R1 * R1 * R1 * nr + lane;
-    for (int a4 = 0; a4 < R1; ++a4)
-      for (int a3 = 0; a3 < R1; ++a3)
-        for (int a2 = 0; a2 < R1; ++a2) {
-          const double l234 = ell[1][a2] * ell[2][a3] * ell[3][a4];
-          const double d2 = dell[1][a2] * ell[2][a3] * ell[3][a4];
-          const double d3 = ell[1][a2] * dell[2][a3] * ell[3][a4];
-          const double d4 = ell[1][a2] * ell[2][a3] * dell[3][a4];
-          for (int a1 = 0; a1 < R1; ++a1) {
-            const double v = h * cf[0];
-            cf += nr;
-            acc[0] += dell[0][a1] * l234 * v;
-            acc[1] += ell[0][a1] * d2 * v;
-            acc[2] += ell[0][a1] * d3 * v;
-            acc[3] += ell[0][a1] * d4 * v;
-          }
-        }
-  }
+  for (int a4 = 0; a4 < R1; ++a4)
+    for (int a3 = 0; a3 < R1; ++a3) {
+      __syncthreads();
+      const double* src = C + (size_t)(a3 + R1 * a4) * plane * nr;
+      for (int i = t; i < plane * nr; i += 256) cf[i / nr][i % nr] = src[i];
+      __syncthreads();
+      const double l3 = ell[cl][2][a3], l4 = ell[cl][3][a4], d3 = dell[cl][2][a3], d4 = dell[cl][3][a4];
+      for (int j = w; j < plane; j += 4) {
+        const int a1 = j % R1, a2 = j / R1;
+        double v = 0.0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+        for (int q = 0; q < 43; ++q)
+          if (q < nr) v += h[q] * cf[j][q];
+        const double l1 = ell[cl][0][a1], l2 = ell[cl][1][a2], d1 = dell[cl][0][a1], d2 = dell[cl][1][a2];
+        acc[0] += d1 * l2 * l3 * l4 * v;
+        acc[1] += l1 * d2 * l3 * l4 * v;
+        acc[2] += l1 * l2 * d3 * l4 * v;
+        acc[3] += l1 * l2 * l3 * d4 * v;
+      }
+    }
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc[i] += __shfl_xor(acc[i], o);
-  if (lane < 4) {
-    const double v = lane == 0 ? acc[0] : lane == 1 ? acc[1] : lane == 2 ? acc[2] : acc[3];
-    g.gmu[(size_t)cell * 4 + lane] = -(1.0 - g.rho) * v;
-  }
+  for (int i = 0; i < 4; ++i) red[w][cl][i] = acc[i];
+  __syncthreads();
+  if (w == 0 && valid)
+    for (int i = 0; i < 4; ++i)
+      g.gmu[(size_t)cell * 4 + i] = -(1.0 - g.rho) * (((red[0][cl][i] + red[1][cl][i]) + red[2][cl][i]) + red[3][cl][i]);
 }
 
 // net gradient: sum over the cells sharing each control point (fixed order)
@@ -607,16 +616,18 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
     default: return hipErrorInvalidValue;
   }
   if (c->any_dim4) {
-    ChainMu4Args b = {};
-    b.family = c->d_family; b.mu = c->d_mu; b.fam_slot = c->d_flags + 8; b.tab = c->d_tab;
-    for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
-      const RomDev& R = c->roms[c->fam_ids[s]];
-      b.coeff[s] = R.coeff; b.lo[s] = R.lo; b.hi[s] = R.hi; b.n_k[s] = R.n_k; b.n_r[s] = R.n_r; b.r[s] = R.r;
-      b.dim[s] = R.dim; b.off_rnodes[s] = c->tab.off_rnodes[s];
+    for (size_t sl = 0; sl < c->fam_ids.size() && sl < c->tile_fam_first.size(); ++sl) {
+      const RomDev& R = c->roms[c->fam_ids[sl]];
+      if (R.dim != 4 || c->tile_fam_n[sl] == 0) continue;
+      if (R.r > 8 || R.n_r > 43) return hipErrorInvalidValue;
+      ChainMu4Args b = {};
+      b.mu = c->d_mu; b.tab = c->d_tab; b.coeff = R.coeff; b.lo = R.lo; b.hi = R.hi;
+      b.n_k = R.n_k; b.n_r = R.n_r; b.r = R.r; b.off_rnodes = c->tab.off_rnodes[sl];
+      b.itil_stride = 4 * c->KC; b.rho = c->rho; b.H = c->d_H;
+      b.gmu = c->d_gmu + (size_t)rhs * c->ncell * 4;
+      hipLaunchKernelGGL(k_chain_mu4, dim3(c->tile_fam_n[sl], 2), dim3(256), 0, c->stream, b, c->d_sorted,
+                         reinterpret_cast<const int4*>(c->d_tiles) + c->tile_fam_first[sl]);
     }
-    b.itil_stride = 4 * c->KC; b.rho = c->rho; b.H = c->d_H;
-    b.gmu = c->d_gmu + (size_t)rhs * c->ncell * 4;
-    hipLaunchKernelGGL(k_chain_mu4, dim3(c->ncell), dim3(64), 0, c->stream, b);
   }
   const int nnet = c->netx * c->nety;
   hipLaunchKernelGGL(k_net_gather, dim3((nnet + 255) / 256), dim3(256), 0, c->stream, c->d_gcell, c->d_net_ptr,

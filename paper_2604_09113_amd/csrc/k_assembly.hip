@@ -315,6 +315,13 @@ static hipError_t launch_assembly_into(Ctx* c, bool fp32, const AsmBuffers& bf, 
     gc.gen = 0;
   }
   }
+  c->tile_fam_first = fam_first;
+  c->tile_fam_n = fam_n;
+  // the reduced coordinates of the four-parameter families, on the same tiles
+  for (size_t s = 0; s < c->fam_ids.size(); ++s) {
+    e = launch_mdeim4(c, (int)s, bf.tiles, fam_first[s], fam_n[s]);
+    if (e != hipSuccess) return e;
+  }
   if (e0) hipEventRecord(e0, c->stream);
   const int4* d_tl = reinterpret_cast<const int4*>(bf.tiles);
   if (fp32)

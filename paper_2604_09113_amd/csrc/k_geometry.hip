@@ -164,58 +164,95 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs g) {
 }
 
 // MDEIM online step for the cells of four-parameter families (Alg. 5 with a
-// tensor fitting grid, Sec. 4.2.3): one 64-lane workgroup per cell.  The
-// cell's cluster box gives tau_i = (mu_i - a_i) / (b_i - a_i); lanes
-// 4 (r+1) evaluate the Lagrange bases l_i(tau_i) at the r+1 GLL points into
-// LDS; lane j < n_r then sums sum_nodes l_1(a_1) l_2(a_2) l_3(a_3) l_4(a_4)
-// coeff[node][j] over the (r+1)^4 nodes (node a_1 + (r+1)(a_2 + (r+1)(a_3 +
-// (r+1) a_4))), one coalesced row of the cluster's coefficients per node.
+// tensor fitting grid, Sec. 4.2.3), on the tiles of the cluster-sorted cell
+// order that the contraction uses (every cell of a tile is in the same
+// cluster): a workgroup takes 64 cells of a tile and evaluates
+//   Itil_j(cell) = (1 - rho) sum_nodes l_1(a_1) l_2(a_2) l_3(a_3) l_4(a_4) coeff[node][j]
+// over the (r+1)^4 nodes (node a_1 + (r+1)(a_2 + (r+1)(a_3 + (r+1) a_4))).
+// The cluster's coefficients pass through LDS one (a_1, a_2) plane at a time
+// and serve all 64 cells; wave w accumulates the quarter w of the n_r
+// columns for the cell of its lane (LDS reads are broadcasts).
 struct Mdeim4Args {
-  const int* family; const double* mu; const int* fam_slot; const double* tab;
-  const double* coeff[4];
-  double lo[4], hi[4];
-  int n_k[4], n_r[4], r[4], dim[4], off_rnodes[4];
-  int ncell, itil_stride;
+  const double* mu; const double* tab;
+  const double* coeff;
+  double lo, hi;
+  int n_k, n_r, r, off_rnodes;
+  int itil_stride;
   double rho;
   double* itil; float* itil32;
 };
 
-__global__ __launch_bounds__(64) void k_mdeim4(Mdeim4Args g) {
-  const int cell = blockIdx.x, lane = threadIdx.x;
-  const int fam = g.family[cell];
-  const int slot = (fam >= 0 && fam < 64) ? g.fam_slot[fam] : -1;
-  if (slot < 0 || g.dim[slot] != 4) return;  // uniform over the workgroup
-  const int R = g.r[slot], R1 = R + 1, nr = g.n_r[slot];
-  double tau[4], hs[4];
-  const int k = mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo[slot], g.hi[slot], g.n_k[slot], tau, hs);
-  __shared__ double ell[4][9];
-  if (lane < 4 * R1) {
-    const int i = lane / R1, a = lane - i * R1;
-    ell[i][a] = lag_value(g.tab + g.off_rnodes[slot], R, a, tau[i]);
+__global__ __launch_bounds__(256) void k_mdeim4(Mdeim4Args g, const int* __restrict__ sorted,
+                                                const int4* __restrict__ tiles) {
+  const int4 td = tiles[blockIdx.x];
+  const int c0 = 64 * blockIdx.y;
+  const int ncells = td.z - c0;
+  if (ncells <= 0) return;  // uniform over the workgroup
+  const int t = threadIdx.x, cl = t & 63, w = t >> 6;
+  const bool valid = cl < ncells;
+  const int cell = sorted[td.y + c0 + (valid ? cl : 0)];
+  const int R = g.r, R1 = R + 1, nr = g.n_r, plane = R1 * R1;
+  __shared__ double ell[64][4][9];
+  __shared__ double cf[81][44];
+  {
+    double tau[4], hs[4];
+    mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo, g.hi, g.n_k, tau, hs);
+    const double* x = g.tab + g.off_rnodes;
+    for (int a = 0; a < R1; ++a) ell[cl][w][a] = lag_value(x, R, a, tau[w]);
   }
-  __syncthreads();
-  if (lane > nr) return;
-  double* it = g.itil + (size_t)cell * g.itil_stride;
-  float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
-  if (lane == nr) {
-    it[nr] = g.rho;
-    it32[nr] = (float)g.rho;
-    return;
-  }
-  const double* cf = g.coeff[slot] + (size_t)k * R1 * R1 * R1 * R1 * nr + lane;
-  double s = 0.0;
+  // the tile's cluster (the same for all its cells)
+  double tau0[4], hs0[4];
+  const int k = mdeim4_cluster(g.mu + (size_t)sorted[td.y] * 4, g.lo, g.hi, g.n_k, tau0, hs0);
+  const double* C = g.coeff + (size_t)k * plane * plane * nr;
+  const int RQ = (nr + 3) >> 2, r0 = w * RQ;
+  double acc[11];
+#pragma unroll
+  for (int q = 0; q < 11; ++q) acc[q] = 0.0;
   for (int a4 = 0; a4 < R1; ++a4)
-    for (int a3 = 0; a3 < R1; ++a3)
+    for (int a3 = 0; a3 < R1; ++a3) {
+      __syncthreads();
+      const double* src = C + (size_t)(a3 + R1 * a4) * plane * nr;
+      for (int i = t; i < plane * nr; i += 256) cf[i / nr][i % nr] = src[i];
+      __syncthreads();
+      const double w34 = ell[cl][2][a3] * ell[cl][3][a4];
       for (int a2 = 0; a2 < R1; ++a2) {
-        const double w3 = ell[3][a4] * ell[2][a3] * ell[1][a2];
+        const double w234 = w34 * ell[cl][1][a2];
         for (int a1 = 0; a1 < R1; ++a1) {
-          s += (w3 * ell[0][a1]) * cf[0];
-          cf += nr;
+          const double wt = w234 * ell[cl][0][a1];
+          const double* row = cf[a1 + R1 * a2] + r0;
+#pragma unroll
+          for (int q = 0; q < 11; ++q)
+            if (q < RQ && r0 + q < nr) acc[q] += wt * row[q];
         }
       }
-  s *= (1.0 - g.rho);
-  it[lane] = s;
-  it32[lane] = (float)s;
+    }
+  if (!valid) return;
+  double* it = g.itil + (size_t)cell * g.itil_stride;
+  float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
+#pragma unroll
+  for (int q = 0; q < 11; ++q)
+    if (q < RQ && r0 + q < nr) {
+      const double v = (1.0 - g.rho) * acc[q];
+      it[r0 + q] = v;
+      it32[r0 + q] = (float)v;
+    }
+  if (w == 0) {
+    it[nr] = g.rho;
+    it32[nr] = (float)g.rho;
+  }
+}
+
+hipError_t launch_mdeim4(Ctx* c, int slot, const int* d_tiles, int first, int n) {
+  const RomDev& R = c->roms[c->fam_ids[slot]];
+  if (R.dim != 4 || n == 0) return hipSuccess;
+  if (R.r > 8 || R.n_r > 43) return hipErrorInvalidValue;  // LDS bases hold r <= 8, four column quarters of <= 11
+  Mdeim4Args a = {};
+  a.mu = c->d_mu; a.tab = c->d_tab; a.coeff = R.coeff; a.lo = R.lo; a.hi = R.hi;
+  a.n_k = R.n_k; a.n_r = R.n_r; a.r = R.r; a.off_rnodes = c->tab.off_rnodes[slot];
+  a.itil_stride = 4 * c->KC; a.rho = c->rho; a.itil = c->d_itil; a.itil32 = c->d_itil32;
+  hipLaunchKernelGGL(k_mdeim4, dim3(n, 2), dim3(256), 0, c->stream, a, c->d_sorted,
+                     reinterpret_cast<const int4*>(d_tiles) + first);
+  return hipGetLastError();
 }
 
 // Edge rows: for edge e of a cell, averages int_e u_c ds and moment
@@ -357,19 +394,6 @@ hipError_t launch_geometry(Ctx* c) {
     GEO(1) GEO(2) GEO(3) GEO(4)
 #undef GEO
     default: return hipErrorInvalidValue;
-  }
-  if (c->any_dim4) {
-    Mdeim4Args a = {};
-    a.family = c->d_family; a.mu = c->d_mu; a.fam_slot = c->d_flags + 8; a.tab = c->d_tab;
-    for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {
-      const RomDev& R = c->roms[c->fam_ids[s]];
-      if (R.dim == 4 && R.r > 8) return hipErrorInvalidValue;  // LDS of the bases holds r <= 8
-      a.coeff[s] = R.coeff; a.lo[s] = R.lo; a.hi[s] = R.hi; a.n_k[s] = R.n_k; a.n_r[s] = R.n_r; a.r[s] = R.r;
-      a.dim[s] = R.dim; a.off_rnodes[s] = c->tab.off_rnodes[s];
-    }
-    a.ncell = c->ncell; a.itil_stride = 4 * c->KC; a.rho = c->rho;
-    a.itil = c->d_itil; a.itil32 = c->d_itil32;
-    hipLaunchKernelGGL(k_mdeim4, dim3(c->ncell), dim3(64), 0, c->stream, a);
   }
   return hipGetLastError();
 }
