@@ -489,6 +489,7 @@ def bench_tpms(args, prob, solver):
                          phases_ms=prof)
         log(f"[bench] {('fp64', 'mixed')[prec]}: {dt * 1e3:.1f} ms/step, phases {json.dumps(prof)}")
     mixed = res[lbddc.MIXED]
+    nn = (scfg["r"] + 1) ** 4
     # the dominant kernel of the step: the adjoint contraction (transposed
     # MFMA product at depth n_r + 1 = 41, padded to 44), algorithmic flops
     # twice those of the assembly contraction

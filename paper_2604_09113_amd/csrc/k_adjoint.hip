@@ -413,10 +413,13 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
 // h(node) = sum_j H_j coeff[node][j], for the cells of four-parameter
 // families (the derivative of the tensor Lagrange interpolant of Alg. 5; H =
 // dE/dItil from the adjoint contraction), on the tiles of the cluster-sorted
-// cell order: a workgroup takes 64 cells of a tile, the cluster's
-// coefficients pass through LDS one (a_1, a_2) plane at a time, wave w takes
-// the nodes j = w mod 4 of each plane for the cell of its lane, and the four
-// waves' sums are added in a fixed order.
+// cell order.  For 64 cells of a tile, h = H coeff^T is a dense product on
+// FP64 MFMA 16x16x4: wave w owns cells 16w..16w+15 (A operand: their H, n_r
+// zero-padded to 48, in registers) and runs over 16-node blocks (B operand:
+// the cluster's coefficients, a 64-node slab staged in LDS for all four
+// waves); each result tile is weighted by the four derivative products of
+// the cells' Lagrange bases and summed, and the 16 lanes of a row group then
+// add their node columns with a butterfly.
 struct ChainMu4Args {
   const double* mu; const double* tab;
   const double* coeff;
@@ -434,14 +437,13 @@ __global__ __launch_bounds__(256) void k_chain_mu4(ChainMu4Args g, const int* __
   const int c0 = 64 * blockIdx.y;
   const int ncells = td.z - c0;
   if (ncells <= 0) return;  // uniform over the workgroup
-  const int t = threadIdx.x, cl = t & 63, w = t >> 6;
-  const bool valid = cl < ncells;
-  const int cell = sorted[td.y + c0 + (valid ? cl : 0)];
-  const int R = g.r, R1 = R + 1, nr = g.n_r, plane = R1 * R1;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int R = g.r, R1 = R + 1, nr = g.n_r, nn = R1 * R1 * R1 * R1;
   __shared__ double ell[64][4][9], dell[64][4][9];
-  __shared__ double cf[81][44];
-  __shared__ double red[4][64][4];
+  __shared__ double cf[64][49];
   {
+    const int cl = t & 63;  // thread t: cell cl, coordinate w
+    const int cell = sorted[td.y + c0 + (cl < ncells ? cl : 0)];
     double tau[4], hs[4];
     mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo, g.hi, g.n_k, tau, hs);
     const double* x = g.tab + g.off_rnodes;
@@ -452,37 +454,71 @@ __global__ __launch_bounds__(256) void k_chain_mu4(ChainMu4Args g, const int* __
   }
   double tau0[4], hs0[4];
   const int k = mdeim4_cluster(g.mu + (size_t)sorted[td.y] * 4, g.lo, g.hi, g.n_k, tau0, hs0);
-  const double* C = g.coeff + (size_t)k * plane * plane * nr;
-  double h[43];
+  const double* C = g.coeff + (size_t)k * nn * nr;
+  const int kq = lane >> 4, col = lane & 15;
+  // A operand: H of cell 16 w + col at columns 4 ks + kq
+  double hA[12];
+  {
+    const int cl = 16 * w + col;
+    const int cell = sorted[td.y + c0 + (cl < ncells ? cl : 0)];
 #pragma unroll
-  for (int j = 0; j < 43; ++j) h[j] = j < nr ? g.H[(size_t)cell * g.itil_stride + j] : 0.0;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int a4 = 0; a4 < R1; ++a4)
-    for (int a3 = 0; a3 < R1; ++a3) {
-      __syncthreads();
-      const double* src = C + (size_t)(a3 + R1 * a4) * plane * nr;
-      for (int i = t; i < plane * nr; i += 256) cf[i / nr][i % nr] = src[i];
-      __syncthreads();
-      const double l3 = ell[cl][2][a3], l4 = ell[cl][3][a4], d3 = dell[cl][2][a3], d4 = dell[cl][3][a4];
-      for (int j = w; j < plane; j += 4) {
-        const int a1 = j % R1, a2 = j / R1;
-        double v = 0.0;
+    for (int ks = 0; ks < 12; ++ks) {
+      const int j = 4 * ks + kq;
+      hA[ks] = j < nr ? g.H[(size_t)cell * g.itil_stride + j] : 0.0;
+    }
+  }
+  double acc[4][4];
 #pragma unroll
-        for (int q = 0; q < 43; ++q)
-          if (q < nr) v += h[q] * cf[j][q];
-        const double l1 = ell[cl][0][a1], l2 = ell[cl][1][a2], d1 = dell[cl][0][a1], d2 = dell[cl][1][a2];
-        acc[0] += d1 * l2 * l3 * l4 * v;
-        acc[1] += l1 * d2 * l3 * l4 * v;
-        acc[2] += l1 * l2 * d3 * l4 * v;
-        acc[3] += l1 * l2 * l3 * d4 * v;
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[v][i] = 0.0;
+  for (int n0 = 0; n0 < nn; n0 += 64) {
+    __syncthreads();
+    for (int i = t; i < 64 * 48; i += 256) {
+      const int jn = i / 48, j = i - jn * 48, n = n0 + jn;
+      cf[jn][j] = (n < nn && j < nr) ? C[(size_t)n * nr + j] : 0.0;
+    }
+    __syncthreads();
+    const int blocks = min(4, (nn - n0 + 15) >> 4);
+    for (int nb = 0; nb < blocks; ++nb) {
+      dbl4 d = dbl4{0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks < 12; ++ks)
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(hA[ks], cf[16 * nb + col][4 * ks + kq], d, 0, 0, 0);
+      // d[v]: cell 16 w + kq + 4 v, node n0 + 16 nb + col
+      const int n = n0 + 16 * nb + col;
+      if (n >= nn) continue;
+      const int a1 = n % R1, q1 = n / R1, a2 = q1 % R1, q2 = q1 / R1, a3 = q2 % R1, a4 = q2 / R1;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cl = 16 * w + kq + 4 * v;
+        const double l1 = ell[cl][0][a1], l2 = ell[cl][1][a2], l3 = ell[cl][2][a3], l4 = ell[cl][3][a4];
+        const double d1 = dell[cl][0][a1], d2 = dell[cl][1][a2], d3 = dell[cl][2][a3], d4 = dell[cl][3][a4];
+        const double l12 = l1 * l2, l34 = l3 * l4;
+        acc[v][0] += d1 * l2 * l34 * d[v];
+        acc[v][1] += l1 * d2 * l34 * d[v];
+        acc[v][2] += l12 * d3 * l4 * d[v];
+        acc[v][3] += l12 * l3 * d4 * d[v];
       }
     }
+  }
+  // add the node columns of each row group: butterfly over the 16 lanes
 #pragma unroll
-  for (int i = 0; i < 4; ++i) red[w][cl][i] = acc[i];
-  __syncthreads();
-  if (w == 0 && valid)
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
     for (int i = 0; i < 4; ++i)
-      g.gmu[(size_t)cell * 4 + i] = -(1.0 - g.rho) * (((red[0][cl][i] + red[1][cl][i]) + red[2][cl][i]) + red[3][cl][i]);
+#pragma unroll
+      for (int o = 8; o >= 1; o >>= 1) acc[v][i] += __shfl_xor(acc[v][i], o);
+  if (col == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int cl = 16 * w + kq + 4 * v;
+      if (cl >= ncells) continue;
+      const int cell = sorted[td.y + c0 + cl];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g.gmu[(size_t)cell * 4 + i] = -(1.0 - g.rho) * acc[v][i];
+    }
+  }
 }
 
 // net gradient: sum over the cells sharing each control point (fixed order)

@@ -166,12 +166,17 @@ __global__ __launch_bounds__(256) void k_geometry(GeoArgs g) {
 // MDEIM online step for the cells of four-parameter families (Alg. 5 with a
 // tensor fitting grid, Sec. 4.2.3), on the tiles of the cluster-sorted cell
 // order that the contraction uses (every cell of a tile is in the same
-// cluster): a workgroup takes 64 cells of a tile and evaluates
-//   Itil_j(cell) = (1 - rho) sum_nodes l_1(a_1) l_2(a_2) l_3(a_3) l_4(a_4) coeff[node][j]
-// over the (r+1)^4 nodes (node a_1 + (r+1)(a_2 + (r+1)(a_3 + (r+1) a_4))).
-// The cluster's coefficients pass through LDS one (a_1, a_2) plane at a time
-// and serve all 64 cells; wave w accumulates the quarter w of the n_r
-// columns for the cell of its lane (LDS reads are broadcasts).
+// cluster).  For 64 cells of a tile it is the dense product
+//   Itil[cell][j] = (1 - rho) sum_nodes W[cell][node] coeff[node][j],
+//   W[cell][node] = l_1(a_1) l_2(a_2) l_3(a_3) l_4(a_4)   (Lagrange bases at the cell's tau),
+// over the (r+1)^4 nodes (node a_1 + (r+1)(a_2 + (r+1)(a_3 + (r+1) a_4))), on
+// FP64 MFMA 16x16x4: wave w owns cells 16w..16w+15 and the three 16-column
+// blocks of j (n_r <= 43, zero-padded to 48), forms its A operand (16 cells x
+// 4 nodes of W) from the per-cell bases in LDS, and reads the B operand (4
+// nodes x 16 columns) from a 64-node slab of the cluster's coefficients
+// staged in LDS for all four waves.
+typedef double dbl4g __attribute__((ext_vector_type(4)));
+
 struct Mdeim4Args {
   const double* mu; const double* tab;
   const double* coeff;
@@ -188,57 +193,64 @@ __global__ __launch_bounds__(256) void k_mdeim4(Mdeim4Args g, const int* __restr
   const int c0 = 64 * blockIdx.y;
   const int ncells = td.z - c0;
   if (ncells <= 0) return;  // uniform over the workgroup
-  const int t = threadIdx.x, cl = t & 63, w = t >> 6;
-  const bool valid = cl < ncells;
-  const int cell = sorted[td.y + c0 + (valid ? cl : 0)];
-  const int R = g.r, R1 = R + 1, nr = g.n_r, plane = R1 * R1;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int R = g.r, R1 = R + 1, nr = g.n_r, nn = R1 * R1 * R1 * R1;
   __shared__ double ell[64][4][9];
-  __shared__ double cf[81][44];
+  __shared__ double cf[64][49];
   {
+    const int cl = t & 63;  // thread t: cell cl, coordinate w
+    const int cell = sorted[td.y + c0 + (cl < ncells ? cl : 0)];
     double tau[4], hs[4];
     mdeim4_cluster(g.mu + (size_t)cell * 4, g.lo, g.hi, g.n_k, tau, hs);
     const double* x = g.tab + g.off_rnodes;
     for (int a = 0; a < R1; ++a) ell[cl][w][a] = lag_value(x, R, a, tau[w]);
   }
-  // the tile's cluster (the same for all its cells)
   double tau0[4], hs0[4];
   const int k = mdeim4_cluster(g.mu + (size_t)sorted[td.y] * 4, g.lo, g.hi, g.n_k, tau0, hs0);
-  const double* C = g.coeff + (size_t)k * plane * plane * nr;
-  const int RQ = (nr + 3) >> 2, r0 = w * RQ;
-  double acc[11];
+  const double* C = g.coeff + (size_t)k * nn * nr;
+  const int row = 16 * w + (lane & 15), kq = lane >> 4, col = lane & 15;
+  dbl4g acc[3];
 #pragma unroll
-  for (int q = 0; q < 11; ++q) acc[q] = 0.0;
-  for (int a4 = 0; a4 < R1; ++a4)
-    for (int a3 = 0; a3 < R1; ++a3) {
-      __syncthreads();
-      const double* src = C + (size_t)(a3 + R1 * a4) * plane * nr;
-      for (int i = t; i < plane * nr; i += 256) cf[i / nr][i % nr] = src[i];
-      __syncthreads();
-      const double w34 = ell[cl][2][a3] * ell[cl][3][a4];
-      for (int a2 = 0; a2 < R1; ++a2) {
-        const double w234 = w34 * ell[cl][1][a2];
-        for (int a1 = 0; a1 < R1; ++a1) {
-          const double wt = w234 * ell[cl][0][a1];
-          const double* row = cf[a1 + R1 * a2] + r0;
+  for (int rb = 0; rb < 3; ++rb) acc[rb] = dbl4g{0, 0, 0, 0};
+  for (int n0 = 0; n0 < nn; n0 += 64) {
+    __syncthreads();
+    for (int i = t; i < 64 * 48; i += 256) {
+      const int jn = i / 48, j = i - jn * 48, n = n0 + jn;
+      cf[jn][j] = (n < nn && j < nr) ? C[(size_t)n * nr + j] : 0.0;
+    }
+    __syncthreads();
+    const int steps = min(16, (nn - n0 + 3) >> 2);
+    for (int st = 0; st < steps; ++st) {
+      const int jn = 4 * st + kq, n = n0 + jn;
+      double a = 0.0;
+      if (n < nn) {
+        const int a1 = n % R1, q1 = n / R1, a2 = q1 % R1, q2 = q1 / R1, a3 = q2 % R1, a4 = q2 / R1;
+        a = ell[row][0][a1] * ell[row][1][a2] * ell[row][2][a3] * ell[row][3][a4];
+      }
 #pragma unroll
-          for (int q = 0; q < 11; ++q)
-            if (q < RQ && r0 + q < nr) acc[q] += wt * row[q];
-        }
+      for (int rb = 0; rb < 3; ++rb) acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, cf[jn][16 * rb + col], acc[rb], 0, 0, 0);
+    }
+  }
+  // lane (g, c) holds cells 16 w + g + 4 v, columns 16 rb + c
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int cl = 16 * w + kq + 4 * v;
+    if (cl >= ncells) continue;
+    const int cell = sorted[td.y + c0 + cl];
+    double* it = g.itil + (size_t)cell * g.itil_stride;
+    float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
+#pragma unroll
+    for (int rb = 0; rb < 3; ++rb) {
+      const int j = 16 * rb + col;
+      if (j < nr) {
+        const double val = (1.0 - g.rho) * acc[rb][v];
+        it[j] = val;
+        it32[j] = (float)val;
+      } else if (j == nr) {
+        it[j] = g.rho;
+        it32[j] = (float)g.rho;
       }
     }
-  if (!valid) return;
-  double* it = g.itil + (size_t)cell * g.itil_stride;
-  float* it32 = g.itil32 + (size_t)cell * g.itil_stride;
-#pragma unroll
-  for (int q = 0; q < 11; ++q)
-    if (q < RQ && r0 + q < nr) {
-      const double v = (1.0 - g.rho) * acc[q];
-      it[r0 + q] = v;
-      it32[r0 + q] = (float)v;
-    }
-  if (w == 0) {
-    it[nr] = g.rho;
-    it32[nr] = (float)g.rho;
   }
 }
 
