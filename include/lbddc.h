@@ -346,12 +346,15 @@ lbddc_status lbddc_set_timing(lbddc_ctx* ctx, int32_t mask);
  * the paper's QUGaR/algoim quadrature implements, Sec. 2.2.3), and out (host)
  * receives either the whole tensor I(mu) of n_i = (p+1)^4 4 (q+1)^2 entries in
  * the order of lbddc_rom_desc (n_entries = 0: out[count][n_i]) or the entries
- * listed in entries[n_entries] (out[count][n_entries]; the magic points of the
- * fitting stage).  Allocates and frees its own device memory; not for hot
- * loops.  Limits: 2 <= p <= 8, 1 <= q <= 3; a rule of more than 131072 points
- * or a failed root iteration returns LBDDC_E_NUMERIC. */
+ * listed in entries (out[count][n_entries]; the magic points of the fitting
+ * stage): one list entries[n_entries] for every vector, or with
+ * entries_per_rule != 0 one list per vector, entries[count][n_entries].
+ * Allocates and frees its own device memory; not for hot loops.  Limits:
+ * 2 <= p <= 8, 1 <= q <= 3, n_entries <= 48; a rule of more than 131072
+ * points or a failed root iteration returns LBDDC_E_NUMERIC. */
 lbddc_status lbddc_implicit_tensors(lbddc_ctx* ctx, int32_t family, int32_t p, int32_t q, int32_t count,
-                                   const double* mu, int32_t n_entries, const int64_t* entries, double* out);
+                                   const double* mu, int32_t n_entries, const int64_t* entries,
+                                   int32_t entries_per_rule, double* out);
 
 /* For testing the offline quadrature: the same rule computed on the host for
  * one threshold vector, n Gauss points per segment (1 <= n <= 24); points

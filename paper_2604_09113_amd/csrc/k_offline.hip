@@ -146,14 +146,15 @@ struct EntrySink {
 
 __global__ __launch_bounds__(64) void k_rule_entries(const double* __restrict__ mu, int fam, int count, rule::Cfg g,
                                                      int p, int q, const double* nodes, const double* qnodes,
-                                                     const int* dec, int ne, double* out, int* err) {
+                                                     const int* dec, int ne, int dec_stride, double* out, int* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
   rule::Cell c;
   c.fam = fam;
   for (int k = 0; k < 4; ++k) c.mu[k] = mu[(size_t)i * 4 + k];
   EntrySink s;
-  s.ne = ne; s.P1 = p + 1; s.Q1 = q + 1; s.dec = dec; s.nodes = nodes; s.qnodes = qnodes; s.err = 0;
+  s.ne = ne; s.P1 = p + 1; s.Q1 = q + 1; s.dec = dec + (size_t)i * dec_stride; s.nodes = nodes; s.qnodes = qnodes;
+  s.err = 0;
   for (int e = 0; e < kMaxEntries; ++e) s.acc[e] = 0.0;
   rule::cell_rule(c, g, s);
   for (int e = 0; e < ne; ++e) out[(size_t)i * ne + e] = s.acc[e];
@@ -175,7 +176,7 @@ static int offline_rule_points(int p, int q) { return std::max(12, p + q + 2); }
 
 extern "C" lbddc_status lbddc_implicit_tensors(lbddc_ctx* x, int32_t family, int32_t p, int32_t q, int32_t count,
                                                const double* mu, int32_t n_entries, const int64_t* entries,
-                                               double* out) {
+                                               int32_t entries_per_rule, double* out) {
   if (!x) return LBDDC_E_ARG;
   Ctx* c = &x->c;
   if (family < 2 || family > 5) return off_fail(c, LBDDC_E_ARG, "implicit_tensors: family must be 2..5 (Table 1)");
@@ -188,18 +189,19 @@ extern "C" lbddc_status lbddc_implicit_tensors(lbddc_ctx* x, int32_t family, int
     if (!std::isfinite(mu[i])) return off_fail(c, LBDDC_E_ARG, "implicit_tensors: non-finite threshold");
   const int nB = (p + 1) * (p + 1), nL = (q + 1) * (q + 1);
   const long long n_i = (long long)nB * nB * 4 * nL;
-  for (int e = 0; e < n_entries; ++e)
+  const size_t n_ent_all = (size_t)n_entries * (entries_per_rule ? count : 1);
+  for (size_t e = 0; e < n_ent_all; ++e)
     if (entries[e] < 0 || entries[e] >= n_i) return off_fail(c, LBDDC_E_ARG, "implicit_tensors: entry index out of range");
   hipSetDevice(c->device);
   const int n = offline_rule_points(p, q);
   std::vector<double> gx, gw;
   gauss_rule(n, gx, gw);
   const std::vector<double> nodes = gll_points(p), qnodes = gll_points(q);
-  // whole tensors: rules into point buffers, 64 at a time; entries: 16384
+  // whole tensors: rules into point buffers, 512 at a time; entries: 65536
   // rules at a time, each thread summing its entries as it makes its points
   const int cap = 1 << 17;
   const bool ent_mode = n_entries > 0;
-  const int batch = ent_mode ? 16384 : 64;
+  const int batch = ent_mode ? 65536 : 512;
   const size_t nout = ent_mode ? (size_t)n_entries : (size_t)n_i;
   double *d_g = nullptr, *d_mu = nullptr, *d_px = nullptr, *d_py = nullptr, *d_pw = nullptr, *d_out = nullptr;
   int *d_np = nullptr, *d_err = nullptr, *d_dec = nullptr;
@@ -208,7 +210,7 @@ extern "C" lbddc_status lbddc_implicit_tensors(lbddc_ctx* x, int32_t family, int
             hipMalloc(&d_px, npt * 8) == hipSuccess && hipMalloc(&d_py, npt * 8) == hipSuccess &&
             hipMalloc(&d_pw, npt * 8) == hipSuccess && hipMalloc(&d_out, (size_t)batch * nout * 8) == hipSuccess &&
             hipMalloc(&d_np, batch * 4) == hipSuccess && hipMalloc(&d_err, batch * 4) == hipSuccess &&
-            (!ent_mode || hipMalloc(&d_dec, (size_t)n_entries * 8 * 4) == hipSuccess);
+            (!ent_mode || hipMalloc(&d_dec, (size_t)n_entries * 8 * 4 * (entries_per_rule ? batch : 1)) == hipSuccess);
   auto release = [&]() {
     for (void* ptr : {(void*)d_g, (void*)d_mu, (void*)d_px, (void*)d_py, (void*)d_pw, (void*)d_out, (void*)d_np,
                       (void*)d_err, (void*)d_dec})
@@ -223,19 +225,24 @@ extern "C" lbddc_status lbddc_implicit_tensors(lbddc_ctx* x, int32_t family, int
   tab.insert(tab.end(), nodes.begin(), nodes.end());
   tab.insert(tab.end(), qnodes.begin(), qnodes.end());
   hipError_t e = hipMemcpy(d_g, tab.data(), tab.size() * 8, hipMemcpyHostToDevice);
-  if (e == hipSuccess && ent_mode) {
-    std::vector<int> dec((size_t)n_entries * 8);
+  // entry e of a rule decoded as {a1, b1, j1, a2, b2, j2, a3, b3}
+  auto decode = [&](const int64_t* ent, size_t n, std::vector<int>& dec) {
+    dec.resize(n * 8);
     const int P1 = p + 1, Q1 = q + 1;
-    for (int k = 0; k < n_entries; ++k) {
-      long long idx = entries[k];
+    for (size_t k = 0; k < n; ++k) {
+      long long idx = ent[k];
       const int k3 = (int)(idx % nL);
       idx /= nL;
       const int j2 = (int)(idx & 1), j1 = (int)((idx >> 1) & 1);
       idx >>= 2;
       const int k2 = (int)(idx % nB), k1 = (int)(idx / nB);
       const int v[8] = {k1 % P1, k1 / P1, j1, k2 % P1, k2 / P1, j2, k3 % Q1, k3 / Q1};
-      for (int j = 0; j < 8; ++j) dec[(size_t)k * 8 + j] = v[j];
+      for (int j = 0; j < 8; ++j) dec[k * 8 + j] = v[j];
     }
+  };
+  std::vector<int> dec;
+  if (e == hipSuccess && ent_mode && !entries_per_rule) {
+    decode(entries, (size_t)n_entries, dec);
     e = hipMemcpy(d_dec, dec.data(), dec.size() * 4, hipMemcpyHostToDevice);
   }
   rule::Cfg cfg{n, d_g, d_g + n, 24};
@@ -245,9 +252,15 @@ extern "C" lbddc_status lbddc_implicit_tensors(lbddc_ctx* x, int32_t family, int
     const int nb = std::min(batch, count - b0);
     e = hipMemcpyAsync(d_mu, mu + (size_t)b0 * 4, (size_t)nb * 4 * 8, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) break;
+    if (ent_mode && entries_per_rule) {
+      decode(entries + (size_t)b0 * n_entries, (size_t)nb * n_entries, dec);
+      e = hipMemcpy(d_dec, dec.data(), dec.size() * 4, hipMemcpyHostToDevice);
+      if (e != hipSuccess) break;
+    }
     if (ent_mode)
       hipLaunchKernelGGL(k_rule_entries, dim3((nb + 63) / 64), dim3(64), 0, c->stream, d_mu, (int)family, nb, cfg, p, q,
-                         sa.nodes, sa.qnodes, d_dec, (int)n_entries, d_out, d_err);
+                         sa.nodes, sa.qnodes, d_dec, (int)n_entries, entries_per_rule ? 8 * (int)n_entries : 0, d_out,
+                         d_err);
     else
       hipLaunchKernelGGL(k_rules, dim3((nb + 63) / 64), dim3(64), 0, c->stream, d_mu, (int)family, nb, cfg, d_px, d_py,
                          d_pw, cap, d_np, d_err);

@@ -109,7 +109,7 @@ def library():
         "lbddc_assemble_fp32_noalloc": (C.c_int, [P, P]),
         "lbddc_coarse_solve": (C.c_int, [P, dp, dp]),
         "lbddc_implicit_tensors": (C.c_int, [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32,
-                                             C.POINTER(C.c_int64), dp]),
+                                             C.POINTER(C.c_int64), C.c_int32, dp]),
         "lbddc_implicit_rule_host": (C.c_int, [C.c_int32, dp, C.c_int32, C.c_int32, dp, dp, dp,
                                                C.POINTER(C.c_int32)]),
     }
@@ -244,18 +244,23 @@ class Solver:
 
     def implicit_tensors(self, family, p, q, mu, entries=None):
         """Offline snapshots of a Table 1 family on the GPU: I(mu) for every row
-        of mu [count, 4], whole ([count, n_i]) or at `entries` ([count, ne])."""
+        of mu [count, 4], whole ([count, n_i]) or at `entries` ([count, ne]):
+        one list [ne] for all rows, or one per row [count, ne]."""
         mu = _f64(np.atleast_2d(mu))
         count = mu.shape[0]
         n_i = (p + 1) ** 4 * 4 * (q + 1) ** 2
+        per_rule = 0
         if entries is None:
             out = np.zeros((count, n_i))
             ne, ep = 0, None
         else:
             ent = np.ascontiguousarray(entries, dtype=np.int64)
-            out = np.zeros((count, len(ent)))
-            ne, ep = len(ent), ent.ctypes.data_as(C.POINTER(C.c_int64))
-        self._check(self.lib.lbddc_implicit_tensors(self.ctx, family, p, q, count, _dptr(mu), ne, ep, _dptr(out)))
+            per_rule = int(ent.ndim == 2)
+            ne = ent.shape[-1]
+            out = np.zeros((count, ne))
+            ep = ent.ctypes.data_as(C.POINTER(C.c_int64))
+        self._check(self.lib.lbddc_implicit_tensors(self.ctx, family, p, q, count, _dptr(mu), ne, ep, per_rule,
+                                                    _dptr(out)))
         return out
 
     def export(self, which, first, count):

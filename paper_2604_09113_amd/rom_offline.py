@@ -196,46 +196,55 @@ def train_implicit(solver, family, p, q, lo, hi, n_k, n_s, n_r, r, lhs_u, lhs_pe
     snapshots and fitting values integrated on the GPU (solver: an
     lbddc.Solver).  lhs_u [n_k^4, n_s, 4] offsets and lhs_perm [n_k^4, 4, n_s]
     stratum orders of the Latin-hypercube sampling; `only` restricts training
-    to the listed clusters (the others keep zero arrays).  Returns the arrays
-    of lbddc_load_rom with dim = 4."""
+    to the listed clusters (the others keep zero arrays).  The snapshots of
+    four clusters go to the GPU together, and the fitting nodes of all
+    clusters in one call (each with its cluster's magic points).  Returns the
+    arrays of lbddc_load_rom with dim = 4."""
     ncl = n_k ** 4
     w = (hi - lo) / n_k
     g = gll_nodes01(r)
-    bases, coefs, ranks = [], [], []
-    for k in range(ncl):
+    todo = [k for k in range(ncl) if only is None or k in only]
+    boxes = {}
+    for k in todo:
         c = [(k // n_k ** i) % n_k for i in range(4)]
-        box = [(lo + ci * w, lo + (ci + 1) * w) for ci in c]
-        if only is not None and k not in only:
-            bases.append(None)
-            coefs.append(None)
-            ranks.append(0)
-            continue
-        X = np.stack([_lhs(box[i][0], box[i][1], lhs_u[k][:, i], lhs_perm[k][i]) for i in range(4)], axis=1)
-        snaps = solver.implicit_tensors(family, p, q, X).T
-        U, s, _ = np.linalg.svd(snaps, full_matrices=False)
-        big = np.argmax(np.abs(U), axis=0)
-        U = U * np.sign(U[big, np.arange(U.shape[1])])
-        rank = min(n_r, int(np.sum(s / s[0] > rank_tol)))
-        Ur = U[:, :rank]
-        mp = _deim(Ur)
-        # fitting grid: first threshold fastest
-        f = [box[i][0] + (box[i][1] - box[i][0]) * g for i in range(4)]
-        grid = np.array([[f[0][a], f[1][b], f[2][cc], f[3][d]]
-                         for d in range(r + 1) for cc in range(r + 1) for b in range(r + 1) for a in range(r + 1)])
-        vals = solver.implicit_tensors(family, p, q, grid, entries=mp)
-        coef = np.linalg.solve(Ur[mp], vals.T).T
-        bases.append(Ur)
-        coefs.append(coef)
-        ranks.append(rank)
-        if log:
-            log(f"family {family} cluster {k}: rank {rank}, sigma ratio {s[rank - 1] / s[0]:.1e}")
-    nr = max(ranks)
+        boxes[k] = [(lo + ci * w, lo + (ci + 1) * w) for ci in c]
+    bases, ranks, mps = {}, {}, {}
+    for c0 in range(0, len(todo), 4):
+        group = todo[c0:c0 + 4]
+        X = np.concatenate([np.stack([_lhs(boxes[k][i][0], boxes[k][i][1], lhs_u[k][:, i], lhs_perm[k][i])
+                                      for i in range(4)], axis=1) for k in group])
+        snaps_all = solver.implicit_tensors(family, p, q, X)
+        for j, k in enumerate(group):
+            snaps = snaps_all[j * n_s:(j + 1) * n_s].T
+            U, s, _ = np.linalg.svd(snaps, full_matrices=False)
+            big = np.argmax(np.abs(U), axis=0)
+            U = U * np.sign(U[big, np.arange(U.shape[1])])
+            rank = min(n_r, int(np.sum(s / s[0] > rank_tol)))
+            bases[k] = U[:, :rank]
+            ranks[k] = rank
+            mps[k] = _deim(bases[k])
+            if log:
+                log(f"family {family} cluster {k}: rank {rank}, sigma ratio {s[rank - 1] / s[0]:.1e}")
+        del snaps_all
+    # fitting grids (first threshold fastest) and magic points of every cluster, one GPU call
+    nr = max(ranks.values()) if ranks else 1
+    nn = (r + 1) ** 4
+    grids, ents = [], []
+    for k in todo:
+        f = [boxes[k][i][0] + (boxes[k][i][1] - boxes[k][i][0]) * g for i in range(4)]
+        grids.append(np.array([[f[0][a], f[1][b], f[2][cc], f[3][d]]
+                               for d in range(r + 1) for cc in range(r + 1) for b in range(r + 1) for a in range(r + 1)]))
+        e = np.zeros(nr, dtype=np.int64)
+        e[:ranks[k]] = mps[k]
+        ents.append(np.repeat(e[None, :], nn, axis=0))
+    vals = solver.implicit_tensors(family, p, q, np.concatenate(grids), entries=np.concatenate(ents))
     n_i = (p + 1) ** 4 * 4 * (q + 1) ** 2
     U = np.zeros((ncl, n_i, nr))
-    C = np.zeros((ncl, (r + 1) ** 4, nr))
-    for k in range(ncl):
-        if bases[k] is not None:
-            U[k, :, :ranks[k]] = bases[k]
-            C[k, :, :ranks[k]] = coefs[k]
+    C = np.zeros((ncl, nn, nr))
+    for j, k in enumerate(todo):
+        rk = ranks[k]
+        v = vals[j * nn:(j + 1) * nn, :rk]
+        U[k, :, :rk] = bases[k]
+        C[k, :, :rk] = np.linalg.solve(bases[k][mps[k]], v.T).T
     return dict(family=family, p=p, q=q, n_k=n_k, n_r=nr, r=r, lo=lo, hi=hi, U=U, coeff=C,
                 I_pi=_Integrator(p, q).untrimmed(), dim=4)
