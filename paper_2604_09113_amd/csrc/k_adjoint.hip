@@ -149,20 +149,21 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
     Gw[(col * ns + s) * 4 + grp] += gm;
   };
   if constexpr (LEAN) {
-    double aA[KC], aB[KC], a2[RB][4];
+    double aA[KC], aB[KC], a2A[RB][4], a2B[RB][4];
     load_a(wave, 0, aA);
+    load_h(wave, 0, a2A);
     load_a(wave, 1, aB);
-    load_h(wave, 0, a2);
+    load_h(wave, 1, a2B);
     for (int pt = wave; pt < NPT; pt += 4) {
       pair_load(pt);
       pair_products(uu);
       for (int s = 0; s < ns; s += 2) {  // ns = 4 (q + 1)^2 is even
-        step(s, aA, a2);
+        step(s, aA, a2A);
         load_a(pt, s + 2, aA);
-        load_h(pt, s + 1, a2);
-        step(s + 1, aB, a2);
+        load_h(pt, s + 2, a2A);
+        step(s + 1, aB, a2B);
         load_a(pt, s + 3, aB);
-        load_h(pt, s + 2, a2);
+        load_h(pt, s + 3, a2B);
       }
     }
   } else {
