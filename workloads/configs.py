@@ -81,6 +81,16 @@ CONFIGS = {
             t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=2e-3, moments=True,
             rtol=1e-8, nrhs=1, load="unit", mu_mode="graded", mu_noise=0.05,
             rom={2: dict(lo=0.1, hi=0.9, n_k=2, n_s=100, n_r=40, r=6, dim=4)}),
+    # the paper's benchmark geometry (Sec. 5.2): a quarter annulus r in
+    # [0.6, 1] of 184 x 92 = 16,928 cells (twice as many along xi~_1), Schwarz
+    # Diamond cells with mu = 0.9 - 0.8 xi~_1 at the vertices, E = 5, nu = 0.25,
+    # xi~_1 = 0 clamped and a traction of 0.1 pointing down (-y) on xi~_1 = 1;
+    # the map of every cell is an order-3 Bezier patch whose control points lie
+    # on the (mirrored) annulus at the uniform grid of the auxiliary coordinates
+    7: dict(nx=184, ny=92, p=8, q=2, m=3, jitter=0.0, warp=0.0, topo="schwarz_d", map="annulus",
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=2e-3, moments=True, E=5.0, nu=0.25,
+            rtol=1e-8, nrhs=1, load="down", load_value=0.1, mu_mode="graded", mu_noise=0.0,
+            rom={2: dict(lo=0.1, hi=0.9, n_k=2, n_s=100, n_r=40, r=6, dim=4)}),
 }
 
 
@@ -108,6 +118,15 @@ def make_problem(config=1, seed=None, **overrides):
     rng = np.random.default_rng(seed)
     nx, ny, m = cfg["nx"], cfg["ny"], cfg["m"]
     net = _uniform_net(nx, ny, m)
+    if cfg.get("map") == "annulus":
+        # the quarter annulus r = 0.6 + 0.4 u, angle pi/2 s at the net's uniform
+        # auxiliary coordinates s = jx / (m nx), u = jy / (m ny), mirrored in x
+        # (x = -r sin(pi/2 s), y = -r cos(pi/2 s)): the paper's orientation has
+        # det J < 0, and the library takes positively oriented maps
+        s_ = net[:, :, 0] / nx
+        u_ = net[:, :, 1] / ny
+        rad = 0.6 + 0.4 * u_
+        net = np.stack([-rad * np.sin(0.5 * np.pi * s_), -rad * np.cos(0.5 * np.pi * s_)], axis=2)
     interior = np.zeros(net.shape[:2], dtype=bool)
     interior[1:-1, 1:-1] = True
     jit = rng.normal(0.0, 1.0, size=net.shape)
@@ -154,7 +173,10 @@ def make_problem(config=1, seed=None, **overrides):
     clamped = tuple(cfg.get("clamped", ("left",)))
     loaded = cfg.get("loaded", "right")
     n_side = ny if loaded in ("left", "right") else nx
-    if cfg["load"] == "unit":
+    if cfg["load"] == "down":
+        traction = np.zeros((nrhs, n_side, 2))
+        traction[:, :, 1] = -cfg.get("load_value", 1.0)
+    elif cfg["load"] == "unit":
         # unit traction along the outward normal of the loaded side
         traction = np.zeros((nrhs, n_side, 2))
         normal = {"left": (-1.0, 0.0), "right": (1.0, 0.0), "bottom": (0.0, -1.0), "top": (0.0, 1.0)}[loaded]
@@ -165,7 +187,8 @@ def make_problem(config=1, seed=None, **overrides):
     rom = {f: cfg["rom"][f] for f in cfg["rom"] if f in present or len(present) == 0}
     return dict(config=config, seed=seed, nx=nx, ny=ny, p=cfg["p"], q=cfg["q"],
                 m=m, ctrl=np.ascontiguousarray(net), family=family,
-                t=np.ascontiguousarray(t, dtype=np.float64), mu=np.ascontiguousarray(mu), E=1.0, nu=0.3,
+                t=np.ascontiguousarray(t, dtype=np.float64), mu=np.ascontiguousarray(mu),
+                E=cfg.get("E", 1.0), nu=cfg.get("nu", 0.3),
                 rho=cfg["rho"], moments=cfg["moments"], rtol=cfg["rtol"],
                 traction=np.ascontiguousarray(traction), clamped=clamped, loaded=loaded, rom=rom)
 
