@@ -47,24 +47,51 @@ def edge_map(X, e, xi):
     return B.T @ P, dB.T @ P
 
 
-def edge_constraint_rows(X, p, e, moments):
+def edge_material_intervals(dom, e):
+    """The material part {phi < 0} of edge e of a trimmed cell (Sec. 2.1.2),
+    as intervals of the edge parameter in [0, 1]: breaks at the roots of phi
+    along the edge, kept where phi at the interval midpoint is negative."""
+    from .implicit import _face_roots
+    k, face = (0, 0.0 if e == "left" else 1.0) if e in ("left", "right") else \
+        (1, 0.0 if e == "bottom" else 1.0)
+    br = sorted([0.0, 1.0] + _face_roots(dom, k, face, 0.0, 1.0))
+    out = []
+    for a, b in zip(br[:-1], br[1:]):
+        if b <= a:
+            continue
+        s = np.array([0.5 * (a + b)])
+        f = dom.f(np.array([face]), s) if k == 0 else dom.f(s, np.array([face]))
+        if f[0] < 0.0:
+            out.append((a, b))
+    return out
+
+
+def edge_constraint_rows(X, p, e, moments, dom=None):
     """Coarse-dof rows of edge e over its p+1 nodes x 2 components:
     averages  int_e u_c ds   and moment  int_e f . u ds  with
     f = (x2 - xbar2, xbar1 - x1), xbar = image of the edge midpoint
     (Sec. 3.3.1).  Arc length of the physical edge, Gauss-Legendre with
-    2p+2 points.  Returns [nce, p+1, 2]."""
-    xi, w = gauss_legendre(2 * p + 2)
-    x, dx = edge_map(X, e, xi)
-    ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
-    b = lagrange(gll_nodes(p), xi)          # [p+1, nq]
+    2p+2 points.  For a trimmed cell (dom, a TrimmedCell) the domain of the
+    edge is its material part, each of its intervals with its own 2p+2
+    points.  Returns [nce, p+1, 2]."""
+    if dom is None:
+        pieces = [(0.0, 1.0)]
+    else:
+        pieces = edge_material_intervals(dom, e)
+    xg, wg = gauss_legendre(2 * p + 2)
     xbar, _ = edge_map(X, e, np.array([0.5]))
     xbar = xbar[0]
     rows = np.zeros((3 if moments else 2, p + 1, 2))
-    rows[0, :, 0] = b @ (w * ds)
-    rows[1, :, 1] = b @ (w * ds)
-    if moments:
-        rows[2, :, 0] = b @ (w * ds * (x[:, 1] - xbar[1]))
-        rows[2, :, 1] = b @ (w * ds * (xbar[0] - x[:, 0]))
+    for a, b in pieces:
+        xi, w = a + (b - a) * xg, (b - a) * wg
+        x, dx = edge_map(X, e, xi)
+        ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
+        bl = lagrange(gll_nodes(p), xi)          # [p+1, nq]
+        rows[0, :, 0] += bl @ (w * ds)
+        rows[1, :, 1] += bl @ (w * ds)
+        if moments:
+            rows[2, :, 0] += bl @ (w * ds * (x[:, 1] - xbar[1]))
+            rows[2, :, 1] += bl @ (w * ds * (xbar[0] - x[:, 0]))
     return rows
 
 
@@ -173,8 +200,13 @@ class Problem:
         for k, (a, b) in enumerate(corners):
             for comp in range(2):
                 Cfull[2 * k + comp, slot_of_nat[d.natural(a, b, comp)]] = 1.0
+        fam = int(self.prob["family"][c])
+        dom = None
+        if param_dim(fam) == 4:
+            from .implicit import TrimmedCell
+            dom = TrimmedCell(fam, self.cell_param(c))
         for ei, e in enumerate(EDGES):
-            rows = edge_constraint_rows(cell.X, p, e, self.moments)
+            rows = edge_constraint_rows(cell.X, p, e, self.moments, dom)
             for n, (a, b) in enumerate(edge_nodes_local(p, e)):
                 for comp in range(2):
                     Cfull[8 + nce * ei:8 + nce * (ei + 1), slot_of_nat[d.natural(a, b, comp)]] = rows[:, n, comp]

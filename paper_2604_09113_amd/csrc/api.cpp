@@ -87,6 +87,7 @@ static lbddc_status check_flags(Ctx* c, const char* phase) {
   else if (f & 8) what = "non-positive pivot in K_II (local Schur complement)";
   else if (f & 16) what = "non-positive pivot in the constrained local factorization";
   else if (f & 32) what = "non-positive pivot in the coarse factorization";
+  else if (f & 128) what = "root search along a trimmed cell edge ran out of room";
   snprintf(buf, sizeof buf, "%s: %s (flags 0x%x)", phase, what, f);
   c->err = buf;
   int zero[8] = {0};

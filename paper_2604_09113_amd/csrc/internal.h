@@ -53,6 +53,8 @@ struct Tables {
   int off_edge_b;      // [p+1][nq] GLL Lagrange values
   int off_edge_B;      // [m+1][nq] Bernstein values
   int off_edge_dB;     // [m+1][nq] Bernstein derivatives
+  int off_edge_x;      // [nq] the edge rule's Gauss nodes on [0, 1]
+  int off_edge_nodes;  // [p+1] GLL nodes
   int off_mid_B;       // [m+1] Bernstein values at 1/2
   // loads: Gauss p+2m+2 points
   int nq_load;

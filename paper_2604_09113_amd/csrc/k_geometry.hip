@@ -18,6 +18,7 @@
 //  (Sec. 3.3.1) by Gauss quadrature along the physical edge.
 // k_loads: consistent load of the right-edge traction (Sec. 2.2.1).
 #include "internal.h"
+#include "implicit_rule.h"
 
 namespace lbddc {
 
@@ -274,6 +275,8 @@ struct ConsArgs {
   const double* ctrl; const double* tab; Tables T;
   int ncell, nx, netx, m, p, nce;
   double* cons;  // [ncell][4][nce][p+1][2]
+  const int* family; const double* mu; const int* fam_slot; int dim[4];
+  int* flags;
 };
 
 __device__ inline void edge_points(const double* ctrl, int netx, int m, int ix, int iy, int e, double P[5][2]) {
@@ -289,7 +292,22 @@ __device__ inline void edge_points(const double* ctrl, int netx, int m, int ix, 
   }
 }
 
-// one thread per (cell, edge, edge node): the rows of one node of one edge
+// Root sink of the constraint rows: the face-root search of the implicit rule
+// emits no points.
+struct NoPoints {
+  int err;
+  __device__ void emit(double, double, double) {}
+};
+
+// one thread per (cell, edge, edge node): the rows of one node of one edge.
+// The edge integrals run over the whole physical edge for the one-parameter
+// families, and over the material part of the edge (phi_0 < mu) for the
+// level sets of Table 1: on a lattice that meets the trimmed compatibility of
+// Sec. 2.1.3 both cells sharing an edge see the same material part, so the
+// averages and moments stay one functional of the shared edge values.  Its
+// ends are the roots of phi along the edge (the implicit rule's
+// interval-checked search); every material interval gets the 2p+2 point
+// Gauss rule.
 __global__ void k_constraints(ConsArgs g) {
   const int p = g.p, id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= g.ncell * 4 * (p + 1)) return;
@@ -299,24 +317,89 @@ __global__ void k_constraints(ConsArgs g) {
   edge_points(g.ctrl, g.netx, m, ix, iy, e, P);
   const int nq = g.T.nq_edge;
   const double* w = g.tab + g.T.off_edge_w;
-  const double* bl = g.tab + g.T.off_edge_b;
-  const double* B = g.tab + g.T.off_edge_B;
-  const double* dB = g.tab + g.T.off_edge_dB;
   const double* Bm = g.tab + g.T.off_mid_B;
   double xb0 = 0, xb1 = 0;
   for (int k = 0; k <= m; ++k) { xb0 += Bm[k] * P[k][0]; xb1 += Bm[k] * P[k][1]; }
   double* out = g.cons + ((size_t)cell * 4 + e) * g.nce * (p + 1) * 2;
   double avg = 0, m0 = 0, m1 = 0;
-  for (int qd = 0; qd < nq; ++qd) {
-    double x0 = 0, x1 = 0, d0 = 0, d1 = 0;
-    for (int k = 0; k <= m; ++k) {
-      x0 += B[k * nq + qd] * P[k][0]; x1 += B[k * nq + qd] * P[k][1];
-      d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1];
+  const int fam = g.family[cell];
+  const int slot = (fam >= 0 && fam < 64) ? g.fam_slot[fam] : -1;
+  if (slot >= 0 && g.dim[slot] == 4) {
+    rule::Cell c;
+    c.fam = fam;
+    for (int k = 0; k < 4; ++k) c.mu[k] = g.mu[(size_t)cell * 4 + k];
+    // the edge as a face of the unit cell: xi_k = face, running coordinate in [0, 1]
+    const int k = e < 2 ? 0 : 1;
+    const double face = (e == 1 || e == 3) ? 1.0 : 0.0;
+    double br[16];
+    int nb = 0;
+    br[nb++] = 0.0;
+    br[nb++] = 1.0;
+    NoPoints sink{0};
+    rule::face_roots(c, k, face, 0.0, 1.0, br, nb, 16, sink);
+    for (int i = 1; i < nb; ++i) {
+      const double v = br[i];
+      int j = i - 1;
+      while (j >= 0 && br[j] > v) {
+        br[j + 1] = br[j];
+        --j;
+      }
+      br[j + 1] = v;
     }
-    double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
-    avg += ws;
-    m0 += ws * (x1 - xb1);
-    m1 += ws * (xb0 - x0);
+    if (sink.err) atomicOr(g.flags, 1 << 7);
+    const double* xq = g.tab + g.T.off_edge_x;
+    const double* nodes = g.tab + g.T.off_edge_nodes;
+    for (int iv = 0; iv + 1 < nb; ++iv) {
+      const double a = br[iv], b = br[iv + 1];
+      if (!(b > a)) continue;
+      const double mid = 0.5 * (a + b);
+      if (!(rule::phi(c, k == 0 ? face : mid, k == 0 ? mid : face) < 0.0)) continue;  // void interval
+      for (int qd = 0; qd < nq; ++qd) {
+        const double xi = a + (b - a) * xq[qd];
+        double bn = 1.0;
+        for (int l = 0; l <= p; ++l)
+          if (l != n) bn *= (xi - nodes[l]) / (nodes[n] - nodes[l]);
+        // the edge curve and its tangent: Bernstein of degree m at xi
+        double x0 = 0, x1 = 0, d0 = 0, d1 = 0, binom = 1.0;
+        for (int kk = 0; kk <= m; ++kk) {
+          if (kk > 0) binom = binom * (m - kk + 1) / kk;
+          double pw = binom, dl = 0.0, dr = 0.0;
+          for (int j = 0; j < kk; ++j) pw *= xi;
+          for (int j = 0; j < m - kk; ++j) pw *= 1.0 - xi;
+          if (kk > 0) {
+            dl = kk * binom;
+            for (int j = 0; j < kk - 1; ++j) dl *= xi;
+            for (int j = 0; j < m - kk; ++j) dl *= 1.0 - xi;
+          }
+          if (kk < m) {
+            dr = (m - kk) * binom;
+            for (int j = 0; j < kk; ++j) dr *= xi;
+            for (int j = 0; j < m - kk - 1; ++j) dr *= 1.0 - xi;
+          }
+          x0 += pw * P[kk][0]; x1 += pw * P[kk][1];
+          d0 += (dl - dr) * P[kk][0]; d1 += (dl - dr) * P[kk][1];
+        }
+        const double ws = (b - a) * w[qd] * sqrt(d0 * d0 + d1 * d1) * bn;
+        avg += ws;
+        m0 += ws * (x1 - xb1);
+        m1 += ws * (xb0 - x0);
+      }
+    }
+  } else {
+    const double* bl = g.tab + g.T.off_edge_b;
+    const double* B = g.tab + g.T.off_edge_B;
+    const double* dB = g.tab + g.T.off_edge_dB;
+    for (int qd = 0; qd < nq; ++qd) {
+      double x0 = 0, x1 = 0, d0 = 0, d1 = 0;
+      for (int kk = 0; kk <= m; ++kk) {
+        x0 += B[kk * nq + qd] * P[kk][0]; x1 += B[kk * nq + qd] * P[kk][1];
+        d0 += dB[kk * nq + qd] * P[kk][0]; d1 += dB[kk * nq + qd] * P[kk][1];
+      }
+      double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
+      avg += ws;
+      m0 += ws * (x1 - xb1);
+      m1 += ws * (xb0 - x0);
+    }
   }
   out[(0 * (p + 1) + n) * 2 + 0] = avg;
   out[(0 * (p + 1) + n) * 2 + 1] = 0.0;
@@ -412,6 +495,8 @@ hipError_t launch_geometry(Ctx* c) {
 
 hipError_t launch_constraints_loads(Ctx* c) {
   ConsArgs a = {c->d_ctrl, c->d_tab, c->tab, c->ncell, c->nx, c->netx, c->m, c->p, c->nce, c->d_cons};
+  a.family = c->d_family; a.mu = c->d_mu; a.fam_slot = c->d_flags + 8; a.flags = c->d_flags;
+  for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) a.dim[s] = c->roms[c->fam_ids[s]].dim;
   const int nth = c->ncell * 4 * (c->p + 1);
   hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, c->stream, a);
   LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs,

@@ -459,6 +459,10 @@ void build_tables(Ctx* c, std::vector<double>& tab) {
     for (double x : gx) tab.push_back(bernstein_derivative(m, a, x));
   T.off_mid_B = mark();
   for (int a = 0; a <= m; ++a) tab.push_back(bernstein_value(m, a, 0.5));
+  T.off_edge_x = mark();
+  for (double x : gx) tab.push_back(x);
+  T.off_edge_nodes = mark();
+  for (double x : gp) tab.push_back(x);
   // load rule: p+2m+2 Gauss points
   gauss_rule(p + 2 * m + 2, gx, gw);
   T.nq_load = (int)gx.size();
