@@ -341,6 +341,7 @@ static lbddc_status build_problem(Ctx* c, const lbddc_problem_desc* d, const std
             dalloc_t(c, &c->d_ucell, (size_t)c->nrhs * ncell * c->ndof) &&
             dalloc_t(c, &c->d_H, (size_t)ncell * 4 * c->KC) && dalloc_t(c, &c->d_G, (size_t)ncell * c->ns * 4) &&
             dalloc_t(c, &c->d_gcell, (size_t)ncell * (c->m + 1) * (c->m + 1) * 2) &&
+            dalloc_t(c, &c->d_edge_br, (size_t)ncell * 4 * kEdgeBreaks) && dalloc_t(c, &c->d_edge_nm, (size_t)ncell * 8) &&
             dalloc_t(c, &c->d_gt, (size_t)c->nrhs * ncell) && dalloc_t(c, &c->d_gmu, (size_t)c->nrhs * ncell * 4) &&
             dalloc_t(c, &c->d_gX, (size_t)c->nrhs * netx * nety * 2) && dalloc_t(c, &c->d_J, c->nrhs) &&
             dalloc_t(c, &c->d_adj_tiles, (size_t)4 * (ncell / 16 + 64)) && dalloc(c, &c->d_adj_ptrs, 64 * 8);

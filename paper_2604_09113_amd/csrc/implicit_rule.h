@@ -241,45 +241,76 @@ RULE_HD double bracket_root(const Cell& c, int mode, int k, double fix, double a
   return x;
 }
 
-// roots in [a, b] of phi on the face xi_k = face (appended to br[nb..])
+// roots in [a, b] of phi on the face xi_k = face (appended to br[nb..]).
+// Depth-first over the bisection tree of [a, b], left half first, without a
+// stack: the node at depth d and index i is reached by halving from [a, b]
+// along the bits of i, and after a resolved node the walk climbs while it is
+// a right half and then steps to the right sibling.  A sign-change bracket
+// takes its slot in br when found; its Newton solve is deferred and the
+// pending ones run together (up to kPend at a time), so that the lanes of a
+// wave, each on its own face, run their solves side by side rather than one
+// walk step after another.
 template <class Sink>
 RULE_HD void face_roots(const Cell& c, int k, double face, double a, double b, double* br, int& nb, int brcap, Sink& o) {
-  double st[2 * 50][2];
-  int sd[2 * 50];
-  int top = 0;
-  st[0][0] = a;
-  st[0][1] = b;
-  sd[0] = 0;
-  top = 1;
-  while (top > 0) {
-    --top;
-    const double u0 = st[top][0], u1 = st[top][1];
-    const int d = sd[top];
+  constexpr int kMaxDepth = 48;
+  constexpr int kPend = 8;
+  double pa[kPend], pb[kPend];
+  int pslot[kPend];
+  unsigned pneg = 0;
+  int np = 0;
+  auto flush = [&]() {
+    for (int j = 0; j < np; ++j) br[pslot[j]] = bracket_root(c, 1, k, face, pa[j], pb[j], (pneg >> j) & 1, o);
+    np = 0;
+    pneg = 0;
+  };
+  long long i = 0;
+  int d = 0;
+  for (;;) {
+    double u0 = a, u1 = b;
+    for (int l = d - 1; l >= 0; --l) {
+      const double m = 0.5 * (u0 + u1);
+      if ((i >> l) & 1) u0 = m;
+      else u1 = m;
+    }
+    bool split = false;
     Iv B, Gx, Gy;
     if (k == 1) bounds(c, u0, u1, face, face, B, Gx, Gy);
     else bounds(c, face, face, u0, u1, B, Gx, Gy);
-    if (no_zero(B)) continue;
-    if (fmax(fabs(B.lo), fabs(B.hi)) < 1e-11) continue;  // phi vanishes on this part of the face
-    const Iv G = (k == 1) ? Gx : Gy;
-    double f0, f1, d0;
-    on_face(c, k, face, u0, f0, d0);
-    on_face(c, k, face, u1, f1, d0);
-    if (no_zero(G)) {
+    if (no_zero(B)) {
+    } else if (fmax(fabs(B.lo), fabs(B.hi)) < 1e-11) {
+      // phi vanishes on this part of the face
+    } else if (no_zero(k == 1 ? Gx : Gy)) {
+      double f0, f1, d0;
+      on_face(c, k, face, u0, f0, d0);
+      on_face(c, k, face, u1, f1, d0);
       if ((f0 < 0.0) != (f1 < 0.0)) {
-        if (nb >= brcap) { o.err = 3; return; }
-        br[nb++] = bracket_root(c, 1, k, face, u0, u1, f0 < 0.0, o);
+        if (nb >= brcap) { flush(); o.err = 3; return; }
+        if (np == kPend) flush();
+        pa[np] = u0;
+        pb[np] = u1;
+        if (f0 < 0.0) pneg |= 1u << np;
+        pslot[np++] = nb++;
       }
-      continue;
-    }
-    if (d >= 48) {
-      if (nb >= brcap) { o.err = 3; return; }
+    } else if (d >= kMaxDepth) {
+      if (nb >= brcap) { flush(); o.err = 3; return; }
       br[nb++] = 0.5 * (u0 + u1);
+    } else {
+      split = true;
+    }
+    if (split) {
+      ++d;
+      i <<= 1;
       continue;
     }
-    if (top + 2 > 2 * 50) { o.err = 3; return; }
-    const double m = 0.5 * (u0 + u1);
-    st[top][0] = m; st[top][1] = u1; sd[top] = d + 1; ++top;
-    st[top][0] = u0; st[top][1] = m; sd[top] = d + 1; ++top;
+    while (d > 0 && (i & 1)) {
+      i >>= 1;
+      --d;
+    }
+    if (d == 0) {
+      flush();
+      return;
+    }
+    ++i;
   }
 }
 

@@ -19,6 +19,7 @@ constexpr int kMaxKC = 11;  // reduced basis + stabilisation column padded to 4*
 constexpr int kMaxDevices = 64;
 // load cases solved together by the block PCG (more are taken in blocks)
 constexpr int kBlockRhs = 8;
+constexpr int kEdgeBreaks = 16;  // breaks of one cell edge's material part (ends and roots)
 
 // Doubles per cell of the interior elimination multipliers W of the local
 // Schur complement: interior and skeleton dofs each padded to 16-row tiles
@@ -55,6 +56,7 @@ struct Tables {
   int off_edge_dB;     // [m+1][nq] Bernstein derivatives
   int off_edge_x;      // [nq] the edge rule's Gauss nodes on [0, 1]
   int off_edge_nodes;  // [p+1] GLL nodes
+  int off_edge_bw;     // [p+1] barycentric weights 1 / prod_{l != a} (x_a - x_l) of the GLL nodes
   int off_mid_B;       // [m+1] Bernstein values at 1/2
   // loads: Gauss p+2m+2 points
   int nq_load;
@@ -380,6 +382,8 @@ struct Ctx {
   double* d_H = nullptr;       // [ncell][4*KC]
   double* d_G = nullptr;       // [ncell][ns][4]
   double* d_gcell = nullptr;   // [ncell][(m+1)^2][2]
+  double* d_edge_br = nullptr; // [ncell * 4][16] sorted breaks of each edge's material part (Table 1 cells)
+  int* d_edge_nm = nullptr;    // [ncell * 4][2] break count and material-interval mask (-1: whole edge)
   double* d_gt = nullptr;      // [nrhs][ncell]
   double* d_gmu = nullptr;     // [nrhs][ncell][4]
   double* d_gX = nullptr;      // [nrhs][nety*netx*2]

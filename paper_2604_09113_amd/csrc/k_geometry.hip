@@ -277,6 +277,7 @@ struct ConsArgs {
   double* cons;  // [ncell][4][nce][p+1][2]
   const int* family; const double* mu; const int* fam_slot; int dim[4];
   int* flags;
+  double* edge_br; int* edge_nm;  // the material part of each edge
 };
 
 __device__ inline void edge_points(const double* ctrl, int netx, int m, int ix, int iy, int e, double P[5][2]) {
@@ -299,31 +300,18 @@ struct NoPoints {
   __device__ void emit(double, double, double) {}
 };
 
-// one thread per (cell, edge, edge node): the rows of one node of one edge.
-// The edge integrals run over the whole physical edge for the one-parameter
-// families, and over the material part of the edge (phi_0 < mu) for the
-// level sets of Table 1: on a lattice that meets the trimmed compatibility of
-// Sec. 2.1.3 both cells sharing an edge see the same material part, so the
-// averages and moments stay one functional of the shared edge values.  Its
-// ends are the roots of phi along the edge (the implicit rule's
-// interval-checked search); every material interval gets the 2p+2 point
-// Gauss rule.
-__global__ void k_constraints(ConsArgs g) {
-  const int p = g.p, id = blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= g.ncell * 4 * (p + 1)) return;
-  const int n = id % (p + 1), ce = id / (p + 1), cell = ce >> 2, e = ce & 3;
-  const int ix = cell % g.nx, iy = cell / g.nx, m = g.m;
-  double P[5][2];
-  edge_points(g.ctrl, g.netx, m, ix, iy, e, P);
-  const int nq = g.T.nq_edge;
-  const double* w = g.tab + g.T.off_edge_w;
-  const double* Bm = g.tab + g.T.off_mid_B;
-  double xb0 = 0, xb1 = 0;
-  for (int k = 0; k <= m; ++k) { xb0 += Bm[k] * P[k][0]; xb1 += Bm[k] * P[k][1]; }
-  double* out = g.cons + ((size_t)cell * 4 + e) * g.nce * (p + 1) * 2;
-  double avg = 0, m0 = 0, m1 = 0;
+// The material part of each cell edge of a Table 1 level set: the sorted
+// breaks (the ends and the roots of phi along the edge, found by the implicit
+// rule's interval-checked search) and the mask of the intervals between them
+// where phi < 0.  One lane per (cell, edge); edges of the one-parameter
+// families get the mask -1 (the whole edge).
+__global__ __launch_bounds__(64) void k_edge_roots(ConsArgs g) {
+  const int ce = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ce >= g.ncell * 4) return;
+  const int cell = ce >> 2, e = ce & 3;
   const int fam = g.family[cell];
   const int slot = (fam >= 0 && fam < 64) ? g.fam_slot[fam] : -1;
+  int nb = 0, mat = -1;
   if (slot >= 0 && g.dim[slot] == 4) {
     rule::Cell c;
     c.fam = fam;
@@ -331,12 +319,12 @@ __global__ void k_constraints(ConsArgs g) {
     // the edge as a face of the unit cell: xi_k = face, running coordinate in [0, 1]
     const int k = e < 2 ? 0 : 1;
     const double face = (e == 1 || e == 3) ? 1.0 : 0.0;
-    double br[16];
-    int nb = 0;
+    double br[kEdgeBreaks];
     br[nb++] = 0.0;
     br[nb++] = 1.0;
     NoPoints sink{0};
-    rule::face_roots(c, k, face, 0.0, 1.0, br, nb, 16, sink);
+    rule::face_roots(c, k, face, 0.0, 1.0, br, nb, kEdgeBreaks, sink);
+    if (sink.err) atomicOr(g.flags, 1 << 7);
     for (int i = 1; i < nb; ++i) {
       const double v = br[i];
       int j = i - 1;
@@ -346,37 +334,63 @@ __global__ void k_constraints(ConsArgs g) {
       }
       br[j + 1] = v;
     }
-    if (sink.err) atomicOr(g.flags, 1 << 7);
+    mat = 0;
+    for (int i = 0; i + 1 < nb; ++i) {
+      const double mid = 0.5 * (br[i] + br[i + 1]);
+      if (br[i + 1] > br[i] && rule::phi(c, k == 0 ? face : mid, k == 0 ? mid : face) < 0.0) mat |= 1 << i;
+    }
+    for (int i = 0; i < nb; ++i) g.edge_br[(size_t)ce * kEdgeBreaks + i] = br[i];
+  }
+  g.edge_nm[2 * ce] = nb;
+  g.edge_nm[2 * ce + 1] = mat;
+}
+
+// The coarse rows of one node of one cell edge, one thread per (cell, edge,
+// edge node).  The edge integrals run over the whole physical edge for the
+// one-parameter families, and over the material part of the edge (phi_0 < mu)
+// for the level sets of Table 1: on a lattice that meets the trimmed
+// compatibility of Sec. 2.1.3 both cells sharing an edge see the same
+// material part, so the averages and moments stay one functional of the
+// shared edge values.  Every material interval gets the 2p+2 point Gauss rule.
+__global__ __launch_bounds__(256) void k_constraints(ConsArgs g) {
+  const int p = g.p, m = g.m, nq = g.T.nq_edge;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.ncell * 4 * (p + 1)) return;
+  const int n = id % (p + 1), ce = id / (p + 1), cell = ce >> 2, e = ce & 3;
+  const int ix = cell % g.nx, iy = cell / g.nx;
+  double P[5][2];
+  edge_points(g.ctrl, g.netx, m, ix, iy, e, P);
+  const double* w = g.tab + g.T.off_edge_w;
+  const double* Bm = g.tab + g.T.off_mid_B;
+  double xb0 = 0, xb1 = 0;
+  for (int k = 0; k <= m; ++k) { xb0 += Bm[k] * P[k][0]; xb1 += Bm[k] * P[k][1]; }
+  double avg = 0, m0 = 0, m1 = 0;
+  const int nb = g.edge_nm[2 * ce], mat = g.edge_nm[2 * ce + 1];
+  if (mat >= 0) {
     const double* xq = g.tab + g.T.off_edge_x;
     const double* nodes = g.tab + g.T.off_edge_nodes;
+    const double bw = g.tab[g.T.off_edge_bw + n];
+    const double* br = g.edge_br + (size_t)ce * kEdgeBreaks;
     for (int iv = 0; iv + 1 < nb; ++iv) {
+      if (!((mat >> iv) & 1)) continue;  // void interval
       const double a = br[iv], b = br[iv + 1];
-      if (!(b > a)) continue;
-      const double mid = 0.5 * (a + b);
-      if (!(rule::phi(c, k == 0 ? face : mid, k == 0 ? mid : face) < 0.0)) continue;  // void interval
       for (int qd = 0; qd < nq; ++qd) {
         const double xi = a + (b - a) * xq[qd];
-        double bn = 1.0;
+        // GLL Lagrange polynomial of node n in barycentric form
+        double bn = bw;
         for (int l = 0; l <= p; ++l)
-          if (l != n) bn *= (xi - nodes[l]) / (nodes[n] - nodes[l]);
-        // the edge curve and its tangent: Bernstein of degree m at xi
+          if (l != n) bn *= xi - nodes[l];
+        // the edge curve and its tangent: Bernstein polynomials of degree m at xi
+        double pw[5], pw1[5];  // xi^j and (1 - xi)^j
+        pw[0] = pw1[0] = 1.0;
+        for (int j = 1; j <= m; ++j) { pw[j] = pw[j - 1] * xi; pw1[j] = pw1[j - 1] * (1.0 - xi); }
         double x0 = 0, x1 = 0, d0 = 0, d1 = 0, binom = 1.0;
         for (int kk = 0; kk <= m; ++kk) {
           if (kk > 0) binom = binom * (m - kk + 1) / kk;
-          double pw = binom, dl = 0.0, dr = 0.0;
-          for (int j = 0; j < kk; ++j) pw *= xi;
-          for (int j = 0; j < m - kk; ++j) pw *= 1.0 - xi;
-          if (kk > 0) {
-            dl = kk * binom;
-            for (int j = 0; j < kk - 1; ++j) dl *= xi;
-            for (int j = 0; j < m - kk; ++j) dl *= 1.0 - xi;
-          }
-          if (kk < m) {
-            dr = (m - kk) * binom;
-            for (int j = 0; j < kk; ++j) dr *= xi;
-            for (int j = 0; j < m - kk - 1; ++j) dr *= 1.0 - xi;
-          }
-          x0 += pw * P[kk][0]; x1 += pw * P[kk][1];
+          const double bv = binom * pw[kk] * pw1[m - kk];
+          const double dl = kk > 0 ? kk * binom * pw[kk - 1] * pw1[m - kk] : 0.0;
+          const double dr = kk < m ? (m - kk) * binom * pw[kk] * pw1[m - kk - 1] : 0.0;
+          x0 += bv * P[kk][0]; x1 += bv * P[kk][1];
           d0 += (dl - dr) * P[kk][0]; d1 += (dl - dr) * P[kk][1];
         }
         const double ws = (b - a) * w[qd] * sqrt(d0 * d0 + d1 * d1) * bn;
@@ -395,12 +409,13 @@ __global__ void k_constraints(ConsArgs g) {
         x0 += B[kk * nq + qd] * P[kk][0]; x1 += B[kk * nq + qd] * P[kk][1];
         d0 += dB[kk * nq + qd] * P[kk][0]; d1 += dB[kk * nq + qd] * P[kk][1];
       }
-      double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
+      const double ws = w[qd] * sqrt(d0 * d0 + d1 * d1) * bl[n * nq + qd];
       avg += ws;
       m0 += ws * (x1 - xb1);
       m1 += ws * (xb0 - x0);
     }
   }
+  double* out = g.cons + (size_t)ce * g.nce * (p + 1) * 2;
   out[(0 * (p + 1) + n) * 2 + 0] = avg;
   out[(0 * (p + 1) + n) * 2 + 1] = 0.0;
   out[(1 * (p + 1) + n) * 2 + 0] = 0.0;
@@ -496,8 +511,10 @@ hipError_t launch_geometry(Ctx* c) {
 hipError_t launch_constraints_loads(Ctx* c) {
   ConsArgs a = {c->d_ctrl, c->d_tab, c->tab, c->ncell, c->nx, c->netx, c->m, c->p, c->nce, c->d_cons};
   a.family = c->d_family; a.mu = c->d_mu; a.fam_slot = c->d_flags + 8; a.flags = c->d_flags;
+  a.edge_br = c->d_edge_br; a.edge_nm = c->d_edge_nm;
   for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) a.dim[s] = c->roms[c->fam_ids[s]].dim;
-  const int nth = c->ncell * 4 * (c->p + 1);
+  const int nedge = c->ncell * 4, nth = nedge * (c->p + 1);
+  hipLaunchKernelGGL(k_edge_roots, dim3((nedge + 63) / 64), dim3(64), 0, c->stream, a);
   hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, c->stream, a);
   LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs,
                 c->load_edge, c->n_side, c->d_load};

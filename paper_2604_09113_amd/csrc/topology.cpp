@@ -463,6 +463,13 @@ void build_tables(Ctx* c, std::vector<double>& tab) {
   for (double x : gx) tab.push_back(x);
   T.off_edge_nodes = mark();
   for (double x : gp) tab.push_back(x);
+  T.off_edge_bw = mark();
+  for (int a = 0; a <= p; ++a) {
+    double d = 1.0;
+    for (int l = 0; l <= p; ++l)
+      if (l != a) d *= gp[a] - gp[l];
+    tab.push_back(1.0 / d);
+  }
   // load rule: p+2m+2 Gauss points
   gauss_rule(p + 2 * m + 2, gx, gw);
   T.nq_load = (int)gx.size();
