@@ -290,6 +290,12 @@ lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
  *   RC     [nC] the global coarse dof of each coarse slot (-1: inactive); the
  *          coarse dofs are numbered in the elimination order of the coarse
  *          factorization (RU and RC are integers stored as doubles)
+ *   CONS   [4][nce][p+1][2] the edge constraint rows (Sec. 3.3.1) of the edges
+ *          [left, right, bottom, top]: for each edge node (in increasing running
+ *          coordinate, corners included) and component, its weight in the edge's
+ *          average x, average y and (nce = 3) moment; over the material part of
+ *          the edge for Table 1 level sets, over the whole edge otherwise
+ *          (available after assemble)
  * Skeleton slots (nU = 8p): nodes [BL, BR, TL, TR, left edge, right edge, bottom
  * edge, top edge] (edge nodes in increasing running coordinate, excluding
  * corners), slot = 2*node + component.  Coarse slots (nC = 20 with moments, 16
@@ -299,7 +305,8 @@ lbddc_status lbddc_query(const lbddc_ctx* ctx, int32_t what, int64_t* value);
  * their D, PSI, SC and FINE entries are zero. */
 enum {
   LBDDC_X_K = 0, LBDDC_X_THETA = 1, LBDDC_X_ITIL = 2, LBDDC_X_S = 3, LBDDC_X_D = 4,
-  LBDDC_X_PSI = 5, LBDDC_X_SC = 6, LBDDC_X_LOAD = 7, LBDDC_X_FINE = 8, LBDDC_X_RU = 9, LBDDC_X_RC = 10
+  LBDDC_X_PSI = 5, LBDDC_X_SC = 6, LBDDC_X_LOAD = 7, LBDDC_X_FINE = 8, LBDDC_X_RU = 9, LBDDC_X_RC = 10,
+  LBDDC_X_CONS = 11
 };
 lbddc_status lbddc_export_cells(lbddc_ctx* ctx, int32_t which, int32_t first, int32_t count, double* out);
 

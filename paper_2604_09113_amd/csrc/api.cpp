@@ -750,7 +750,7 @@ lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int3
   Ctx* c = &x->c;
   if (!c->have_problem) return fail(c, LBDDC_E_STATE, "export: no problem");
   if (!out || first < 0 || count < 0 || first + count > c->ncell) return fail(c, LBDDC_E_ARG, "export: bad range");
-  const bool need_asm = which == LBDDC_X_K || which == LBDDC_X_LOAD;
+  const bool need_asm = which == LBDDC_X_K || which == LBDDC_X_LOAD || which == LBDDC_X_CONS;
   const bool need_setup = which == LBDDC_X_S || which == LBDDC_X_D || which == LBDDC_X_PSI || which == LBDDC_X_SC || which == LBDDC_X_FINE;
   if (need_asm && !c->assembled && !(which == LBDDC_X_K && c->k32_valid)) return fail(c, LBDDC_E_STATE, "export: assemble first");
   if (need_setup && !c->setup_done) return fail(c, LBDDC_E_STATE, "export: setup first");
@@ -866,6 +866,11 @@ lbddc_status lbddc_export_cells(lbddc_ctx* x, int32_t which, int32_t first, int3
             o[(size_t)(8 + j) * nU + 8 + i] = v;
           }
       }
+      break;
+    }
+    case LBDDC_X_CONS: {
+      auto h = fetch(c->d_cons, (size_t)4 * c->nce * (c->p + 1) * 2, 8);
+      memcpy(out, h.data(), h.size());
       break;
     }
     case LBDDC_X_RU:

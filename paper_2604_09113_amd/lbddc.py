@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "OK", -1: "E_ARG", -2: "E_NOMEM", -3: "E_HIP", -4: "E_STATE",
                 -6: "E_PARAM_RANGE", -7: "E_ROM", -8: "E_NOT_CONVERGED", -9: "E_BREAKDOWN", -10: "E_NUMERIC",
                 -11: "E_UNSUPPORTED"}
 FP64, MIXED, FP32_CONTRACTION = 0, 1, 2
-X_K, X_THETA, X_ITIL, X_S, X_D, X_PSI, X_SC, X_LOAD, X_FINE, X_RU, X_RC = range(11)
+X_K, X_THETA, X_ITIL, X_S, X_D, X_PSI, X_SC, X_LOAD, X_FINE, X_RU, X_RC, X_CONS = range(12)
 Q_NCELL, Q_NDOF_FREE, Q_N_SKELETON, Q_N_INTERIOR, Q_N_COARSE, Q_N_I_ROM, Q_NU_CELL, Q_NC_CELL, Q_NRHS, \
     Q_NR_MAX, Q_DEVICE_BYTES, Q_COARSE_SOLVE_BYTES, Q_COARSE_LEVELS, Q_COARSE_FWD_BYTES, \
     Q_COARSE_SWEEP_LAUNCHES, Q_NPAIR = range(16)
@@ -268,7 +268,7 @@ class Solver:
         nB, nU, nC, nL = (p + 1) ** 2, 8 * p, self.query(Q_NC_CELL), (q + 1) ** 2
         per = {X_K: (2 * nB, 2 * nB), X_THETA: (2, 2, 2, 2, nL), X_ITIL: (self.query(Q_NR_MAX),),
                X_S: (nU, nU), X_D: (nU,), X_PSI: (nU, nC), X_SC: (nC, nC), X_LOAD: (self.nrhs, nU),
-               X_FINE: (nU, nU), X_RU: (nU,), X_RC: (nC,)}[which]
+               X_FINE: (nU, nU), X_RU: (nU,), X_RC: (nC,), X_CONS: (4, (nC - 8) // 4, p + 1, 2)}[which]
         out = np.zeros((count,) + per)
         self._check(self.lib.lbddc_export_cells(self.ctx, which, first, count, _dptr(out)))
         return out

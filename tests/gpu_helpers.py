@@ -161,3 +161,17 @@ def coarse_solve_errors(s, A, nz=3, seed=5):
         worst = max(worst, np.abs(r).max() / (anorm * np.abs(g).max() + np.abs(z).max()))
         out.append((z, g))
     return worst, out
+
+
+def oracle_rows(prob, c, p):
+    """The oracle's edge rows of cell c, [4 edges][nce][p+1][2]."""
+    from oracle.bddc import edge_constraint_rows
+    from oracle.dofs import EDGES
+    from oracle.geometry import cell_control_points
+    from oracle.implicit import TrimmedCell
+    from oracle.trimmed import param_dim
+    iy, ix = divmod(int(c), prob["nx"])
+    X = cell_control_points(prob["ctrl"], prob["m"], ix, iy)
+    fam = int(prob["family"][c])
+    dom = TrimmedCell(fam, prob["mu"][c]) if param_dim(fam) == 4 else None
+    return np.stack([edge_constraint_rows(X, p, e, prob["moments"], dom) for e in EDGES])

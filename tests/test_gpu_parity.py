@@ -98,6 +98,19 @@ def test_fp32_contraction_parity(case):
     s.close()
 
 
+def test_constraint_rows(case):
+    """Edge rows over the whole physical edge (one-parameter families) of
+    every cell against the oracle's (1e-12 of the largest entry)."""
+    from gpu_helpers import oracle_rows
+    from paper_2604_09113_amd import lbddc
+    name, prob, roms, P, s, _ = case
+    n = P.dofs.ncell
+    rows = s.export(lbddc.X_CONS, 0, n)
+    worst = max(np.abs(rows[c] - oracle_rows(prob, c, prob["p"])).max() / np.abs(rows[c]).max() for c in range(n))
+    print(f"[{name}] edge rows: {worst:.2e}")
+    assert worst <= 1e-12
+
+
 def test_schur_weights_coarse_parity(case):
     from gpu_helpers import rel, oracle_fine_operator
     name, prob, roms, P, s, _ = case

@@ -80,6 +80,25 @@ def test_itil_and_stiffness(case):
     assert e_it <= 1e-13 and e_K <= 1e-10
 
 
+def test_constraint_rows(case):
+    """The exported edge rows of every cell against the oracle's, entry by
+    entry (1e-12 of the largest row entry)."""
+    from gpu_helpers import make_solver, oracle_rows
+    from paper_2604_09113_amd import lbddc
+    name, prob, roms, P, _ = case
+    s = make_solver(prob, roms)
+    s.assemble()
+    nc = prob["nx"] * prob["ny"]
+    rows = s.export(lbddc.X_CONS, 0, nc)
+    s.close()
+    worst = 0.0
+    for c in range(nc):
+        ref = oracle_rows(prob, c, prob["p"])
+        worst = max(worst, np.abs(rows[c] - ref).max() / np.abs(ref).max())
+    print(f"[tpms {name}] edge rows on the material part: {worst:.2e}")
+    assert worst <= 1e-12
+
+
 def test_trimmed_coarse_space(case):
     from gpu_helpers import make_solver, rel
     from paper_2604_09113_amd import lbddc

@@ -8,7 +8,10 @@ clusters x 7^4 fitting nodes, n_r = 40) trained on the GPU:
     evaluation of the same ROM (1e-13) and K_i against the oracle's ROM
     stiffness (1e-10);
   - the FP64 solve to rtol 1e-10 has a true residual below 1e-9, and the
-    mixed solve at rtol 1e-10 lands within 1e-8 of it.
+    mixed solve at rtol 1e-10 lands within 1e-8 of it;
+
+and the paper's own benchmark lattice (the quarter annulus of 184 x 92
+cells): sampled edge rows against the oracle and the FP64 solve.
 """
 import numpy as np
 import pytest
@@ -77,3 +80,36 @@ def test_schwarz_d_128_p8():
     print(f"[tpms128] FP64 {inf[0]['iters']} its, true residual {inf[0]['true_rel_res']:.1e}; mixed {infm[0]['iters']} "
           f"its, |u_mixed - u_fp64| / |u| = {e:.1e}")
     assert inf[0]["true_rel_res"] <= 1e-9 and e <= 1e-8
+
+
+def test_paper_annulus_184x92_p8():
+    """The paper's benchmark geometry at its largest size (184 x 92 cells on
+    the quarter annulus, p = 8, order-3 maps): the edge rows on the material
+    part of sampled cells against the oracle's (1e-12), and the FP64 solve to
+    rtol 1e-8 with a true residual below 1e-8.  The iteration count is
+    printed and held to at most 20 (17 when measured; the paper reports 17
+    for this lattice, and the whole-edge rows took 46)."""
+    from gpu_helpers import oracle_rows, set_problem
+    from paper_2604_09113_amd import lbddc, rom_offline
+    prob = make_problem(7)
+    sc = prob["rom"][2]
+    s = lbddc.Solver(0)
+    print("\n[annulus] training the ROM on the GPU", flush=True)
+    u, perm = rom_lhs_draws(2, sc["n_k"], sc["n_s"], 4)
+    rom = rom_offline.train_implicit(s, 2, 8, 2, sc["lo"], sc["hi"], sc["n_k"], sc["n_s"], sc["n_r"], sc["r"], u, perm)
+    s.load_rom(**rom)
+    set_problem(s, prob)
+    s.assemble(lbddc.FP64)
+    nc = prob["nx"] * prob["ny"]
+    worst = 0.0
+    for c in np.linspace(0, nc - 1, 24).astype(int):
+        rows = s.export(lbddc.X_CONS, int(c), 1)[0]
+        ref = oracle_rows(prob, c, prob["p"])
+        worst = max(worst, np.abs(rows - ref).max() / np.abs(ref).max())
+    print(f"[annulus] sampled edge rows: {worst:.2e}", flush=True)
+    assert worst <= 1e-12
+    s.setup(lbddc.FP64)
+    inf = s.solve(rtol=1e-8, max_iter=500)
+    s.close()
+    print(f"[annulus] FP64: {inf[0]['iters']} iterations, true residual {inf[0]['true_rel_res']:.1e}")
+    assert inf[0]["true_rel_res"] <= 1e-8 and inf[0]["iters"] <= 20
