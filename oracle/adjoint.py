@@ -19,7 +19,7 @@ from .basis import bernstein, bernstein_deriv, gauss_legendre, gll_nodes, lagran
 from .geometry import map_eval
 from .rom import reduced_coordinates_dt
 from .assembly import rom_Ieff, contract
-from .bddc import edge_map
+from .bddc import edge_material_intervals, edge_map
 from .dofs import edge_nodes_local
 
 
@@ -97,23 +97,48 @@ def compliance_gradient(P, unodes, thresholds=False):
             if c in P.load_pos:
                 e = P.loaded
                 trac = prob["traction"][r, P.load_pos[c]]
-                xi, w = gauss_legendre(p + 2 * m + 2)
-                _, dx = edge_map(X, e, xi)
-                ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
-                bn = lagrange(gll_nodes(p), xi)               # [p+1, nq]
-                dB = bernstein_deriv(m, xi)                   # [m+1, nq]
+                dom = P.cell_domain(c)
+                pieces = [(0.0, 1.0)] if dom is None else edge_material_intervals(dom, e)
                 ue = np.array([[u[d.natural(a, b, comp)] for comp in range(2)]
                                for (a, b) in edge_nodes_local(p, e)])
-                # 2 u . df/dX for the control points (beta along the edge) of edge e
                 ut = ue @ trac                                # [p+1]
-                for beta in range(m + 1):
-                    ja, jb = {"left": (0, beta), "right": (m, beta), "bottom": (beta, 0), "top": (beta, m)}[e]
-                    for dd in range(2):
-                        dds = dx[:, dd] / ds * dB[beta]
-                        gX[r, m * iy + jb, m * ix + ja, dd] += 2.0 * ut @ (bn @ (w * dds))
+                xg, wg = gauss_legendre(p + 2 * m + 2)
+                for a0, b0 in pieces:
+                    xi, w = a0 + (b0 - a0) * xg, (b0 - a0) * wg
+                    _, dx = edge_map(X, e, xi)
+                    ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
+                    bn = lagrange(gll_nodes(p), xi)           # [p+1, nq]
+                    dB = bernstein_deriv(m, xi)               # [m+1, nq]
+                    # 2 u . df/dX for the control points (beta along the edge) of edge e
+                    for beta in range(m + 1):
+                        ja, jb = {"left": (0, beta), "right": (m, beta), "bottom": (beta, 0), "top": (beta, m)}[e]
+                        for dd in range(2):
+                            dds = dx[:, dd] / ds * dB[beta]
+                            gX[r, m * iy + jb, m * ix + ja, dd] += 2.0 * ut @ (bn @ (w * dds))
+                    # 2 u . df/dmu: the ends of the material part move with the
+                    # thresholds (Leibniz rule), s* with phi(s*) = 0 moving by
+                    # l_k(s*) / (d phi / d s)(s*) per unit of mu_k
+                    if dom is not None:
+                        for s_end, sign in ((b0, 1.0), (a0, -1.0)):
+                            if s_end <= 0.0 or s_end >= 1.0:
+                                continue
+                            gmu[r, c, :] += sign * 2.0 * _load_end_rate(dom, e, X, p, ut, s_end)
     if thresholds:
         return J, gX, gt, gmu
     return J, gX, gt
+
+
+def _load_end_rate(dom, e, X, p, ut, s):
+    """(sum_n ut_n b_n(s)) |x'(s)| ds/dmu_k at a root s of phi on edge e: the
+    rate at which the traction's virtual work on the material part grows as
+    the end s moves, per unit of each corner threshold."""
+    x0, y0 = {"left": (0.0, s), "right": (1.0, s), "bottom": (s, 0.0), "top": (s, 1.0)}[e]
+    gx, gy = dom.grad(np.array([x0]), np.array([y0]))
+    dphi_ds = (gy if e in ("left", "right") else gx)[0]
+    ell = np.array([(1 - x0) * (1 - y0), x0 * (1 - y0), (1 - x0) * y0, x0 * y0])
+    _, dx = edge_map(X, e, np.array([s]))
+    g = (ut @ lagrange(gll_nodes(p), np.array([s]))[:, 0]) * np.hypot(dx[0, 0], dx[0, 1])
+    return g * ell / dphi_ds
 
 
 def compliance_direct(prob, roms):

@@ -95,18 +95,24 @@ def edge_constraint_rows(X, p, e, moments, dom=None):
     return rows
 
 
-def traction_load(X, p, trac, e="right"):
+def traction_load(X, p, trac, e="right", dom=None):
     """Consistent load of a constant traction on edge e of the cell:
-    f[node, comp] = int_0^1 b_node(xi) t_comp |dx/dxi| dxi along the edge,
+    f[node, comp] = int b_node(xi) t_comp |dx/dxi| dxi along the edge,
     nodes in increasing running coordinate, p+2m+2 Gauss points (Sec. 2.2.1,
     external virtual work on the Neumann part of the boundary; traction times
-    the curve Jacobian)."""
+    the curve Jacobian).  The traction acts on the boundary of the material:
+    for a trimmed cell (dom, a TrimmedCell) on the material part of the edge
+    only, each of its intervals with its own rule; otherwise on the whole
+    edge."""
     m = X.shape[0] - 1
-    xi, w = gauss_legendre(p + 2 * m + 2)
-    _, dx = edge_map(X, e, xi)
-    ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
-    b = lagrange(gll_nodes(p), xi)
-    f = b @ (w * ds)
+    pieces = [(0.0, 1.0)] if dom is None else edge_material_intervals(dom, e)
+    xg, wg = gauss_legendre(p + 2 * m + 2)
+    f = np.zeros(p + 1)
+    for a, b in pieces:
+        xi, w = a + (b - a) * xg, (b - a) * wg
+        _, dx = edge_map(X, e, xi)
+        ds = np.sqrt(dx[:, 0] ** 2 + dx[:, 1] ** 2)
+        f += lagrange(gll_nodes(p), xi) @ (w * ds)
     return np.outer(f, trac)  # [p+1, 2]
 
 
@@ -156,6 +162,16 @@ class Problem:
             return np.asarray(self.prob["mu"][c], dtype=np.float64)
         return float(self.prob["t"][c])
 
+    def cell_domain(self, c):
+        """The trimmed cell {phi_0 < mu} of a Table 1 level set (its edges'
+        material parts carry the edge constraints and the traction), or None
+        for the one-parameter families (whole edges)."""
+        fam = int(self.prob["family"][c])
+        if param_dim(fam) == 4:
+            from .implicit import TrimmedCell
+            return TrimmedCell(fam, self.cell_param(c))
+        return None
+
     def cell_K(self, c):
         X = self.control_points(c)
         fam, t = int(self.prob["family"][c]), self.cell_param(c)
@@ -186,7 +202,7 @@ class Problem:
         if c in self.load_pos:
             k = self.load_pos[c]
             for r in range(self.nrhs):
-                fe = traction_load(cell.X, p, self.prob["traction"][r, k], self.loaded)
+                fe = traction_load(cell.X, p, self.prob["traction"][r, k], self.loaded, self.cell_domain(c))
                 for n, (a, b) in enumerate(edge_nodes_local(p, self.loaded)):
                     for comp in range(2):
                         f[d.natural(a, b, comp), r] += fe[n, comp]
@@ -200,11 +216,7 @@ class Problem:
         for k, (a, b) in enumerate(corners):
             for comp in range(2):
                 Cfull[2 * k + comp, slot_of_nat[d.natural(a, b, comp)]] = 1.0
-        fam = int(self.prob["family"][c])
-        dom = None
-        if param_dim(fam) == 4:
-            from .implicit import TrimmedCell
-            dom = TrimmedCell(fam, self.cell_param(c))
+        dom = self.cell_domain(c)
         for ei, e in enumerate(EDGES):
             rows = edge_constraint_rows(cell.X, p, e, self.moments, dom)
             for n, (a, b) in enumerate(edge_nodes_local(p, e)):

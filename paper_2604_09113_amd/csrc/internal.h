@@ -61,6 +61,7 @@ struct Tables {
   // loads: Gauss p+2m+2 points
   int nq_load;
   int off_load_w, off_load_b, off_load_dB;
+  int off_load_x;      // [nq_load] the load rule's Gauss nodes on [0, 1]
   // MDEIM: GLL points of degree r for each family slot (max 4 families)
   int off_rnodes[4];
   // adjoint chain rule: Bernstein gradients at interpolation points (= geo_dN)
@@ -70,6 +71,25 @@ struct Tables {
 // cluster index and local coordinates of a cell's thresholds (the clamped
 // per-coordinate interval, as in k_geometry; a value outside the box has
 // already raised the range flag there)
+// GLL Lagrange polynomial n (of p + 1 tabulated nodes, barycentric weights bw)
+// at s.
+__device__ inline double gll_lagrange(const double* nodes, const double* bw, int p, int n, double s) {
+  double v = bw[n];
+  for (int l = 0; l <= p; ++l)
+    if (l != n) v *= s - nodes[l];
+  return v;
+}
+
+// Derivatives at s of the m + 1 Bernstein polynomials of degree m (m <= 4):
+// dB[k] = m (B_{k-1,m-1}(s) - B_{k,m-1}(s)), the degree m - 1 values by the
+// triangular recurrence (no divisions).
+__device__ inline void bernstein_deriv_at(int m, double s, double dB[5]) {
+  double b[5] = {1.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = 1; j < m; ++j)
+    for (int k = j; k >= 0; --k) b[k] = (1.0 - s) * b[k] + (k > 0 ? s * b[k - 1] : 0.0);
+  for (int k = 0; k <= m; ++k) dB[k] = m * ((k > 0 ? b[k - 1] : 0.0) - (k < m ? b[k] : 0.0));
+}
+
 __device__ inline int mdeim4_cluster(const double* mu, double lo, double hi, int nk, double tau[4], double hstep[4]) {
   const double w = (hi - lo) / nk;
   int k = 0;

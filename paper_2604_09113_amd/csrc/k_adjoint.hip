@@ -16,6 +16,7 @@
 // pulled-back tensor Chat(J) and the Bernstein map.  The traction load depends
 // on the loaded edge's control points through the curve Jacobian.
 #include "internal.h"
+#include "implicit_rule.h"
 
 namespace lbddc {
 
@@ -219,6 +220,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const double* const* __restrict
 
 struct ChainArgs {
   const double* ctrl; const int* family; const double* t; const double* tab; const int* fam_slot;
+  const double* thr;  // [ncell][4] corner thresholds (Table 1 cells)
   const double* coeff[4];
   double lo[4], hi[4];
   int n_k[4], n_r[4], r[4], dim[4];
@@ -229,6 +231,8 @@ struct ChainArgs {
   const double* H; const double* G; const double* ucell; const double* trac;
   double* gcell;  // [ncell][(m+1)^2][2] per-cell dJ/dX (already with the minus sign and load term)
   double* gt;     // [ncell] dJ/dt
+  const double* edge_br; const int* edge_nm;  // the material part of each edge (k_edge_roots)
+  double* gmu;    // [ncell][4] dJ/dmu (k_load_mu adds the moving ends of the loaded edge)
 };
 
 // one thread per cell, templated on the map order so that the control points
@@ -376,23 +380,60 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
                                  : (nn == p ? ((e == 0) ? 2 : (e == 2) ? 1 : 3) : 4 + e * (p - 1) + (nn - 1));
       ut[n] = u[g.nI + 2 * node] * t0 + u[g.nI + 2 * node + 1] * t1;
     }
-    for (int qd = 0; qd < nq; ++qd) {
-      double d0 = 0, d1 = 0;
+    const int ce = cell * 4 + e, mat = g.edge_nm[2 * ce + 1];
+    if (mat >= 0) {
+      // a Table 1 cell: the load acts on the material part of the edge, whose
+      // ends (parametric) do not move with the control points
+      const double* xq = g.tab + g.T.off_load_x;
+      const double* nodes = g.tab + g.T.off_edge_nodes;
+      const double* bw = g.tab + g.T.off_edge_bw;
+      const double* br = g.edge_br + (size_t)ce * kEdgeBreaks;
+      const int nb = g.edge_nm[2 * ce];
+      for (int iv = 0; iv + 1 < nb; ++iv) {
+        if (!((mat >> iv) & 1)) continue;
+        const double a = br[iv], b = br[iv + 1];
+        for (int qd = 0; qd < nq; ++qd) {
+          const double s = a + (b - a) * xq[qd];
+          double dBs[5];
+          bernstein_deriv_at(M, s, dBs);
+          double d0 = 0, d1 = 0;
 #pragma unroll
-      for (int k = 0; k <= M; ++k) {
-        d0 += dB[k * nq + qd] * Pe[k][0];
-        d1 += dB[k * nq + qd] * Pe[k][1];
+          for (int k = 0; k <= M; ++k) {
+            d0 += dBs[k] * Pe[k][0];
+            d1 += dBs[k] * Pe[k][1];
+          }
+          const double ds = sqrt(d0 * d0 + d1 * d1);
+          double ub = 0.0;
+#pragma unroll
+          for (int n = 0; n < 17; ++n)
+            if (n <= p) ub += ut[n] * gll_lagrange(nodes, bw, p, n, s);
+          const double f = 2.0 * (b - a) * w[qd] * ub / ds;
+#pragma unroll
+          for (int k = 0; k <= M; ++k) {
+            gE[k][0] += f * d0 * dBs[k];
+            gE[k][1] += f * d1 * dBs[k];
+          }
+        }
       }
-      const double ds = sqrt(d0 * d0 + d1 * d1);
-      double ub = 0.0;
+    } else {
+      for (int qd = 0; qd < nq; ++qd) {
+        double d0 = 0, d1 = 0;
 #pragma unroll
-      for (int n = 0; n < 17; ++n)
-        if (n <= p) ub += ut[n] * bl[n * nq + qd];
-      const double f = 2.0 * w[qd] * ub / ds;
+        for (int k = 0; k <= M; ++k) {
+          d0 += dB[k * nq + qd] * Pe[k][0];
+          d1 += dB[k * nq + qd] * Pe[k][1];
+        }
+        const double ds = sqrt(d0 * d0 + d1 * d1);
+        double ub = 0.0;
 #pragma unroll
-      for (int k = 0; k <= M; ++k) {
-        gE[k][0] += f * d0 * dB[k * nq + qd];
-        gE[k][1] += f * d1 * dB[k * nq + qd];
+        for (int n = 0; n < 17; ++n)
+          if (n <= p) ub += ut[n] * bl[n * nq + qd];
+        const double f = 2.0 * w[qd] * ub / ds;
+#pragma unroll
+        for (int k = 0; k <= M; ++k) {
+          gE[k][0] += f * d0 * dB[k * nq + qd];
+          gE[k][1] += f * d1 * dB[k * nq + qd];
+        }
       }
     }
 #pragma unroll
@@ -408,6 +449,69 @@ __global__ __launch_bounds__(64) void k_chain(ChainArgs g) {
   double* out = g.gcell + (size_t)cell * NP1 * 2;
 #pragma unroll
   for (int a = 0; a < NP1; ++a) { out[2 * a] = gX[a][0]; out[2 * a + 1] = gX[a][1]; }
+}
+
+// The traction on a Table 1 cell acts on the material part of the loaded
+// edge, whose ends s* (roots of phi along the edge) move with the corner
+// thresholds: phi = phi_0 - sum_k l_k mu_k gives ds*/dmu_k = l_k(s*) /
+// (d phi / d s)(s*).  By the Leibniz rule the end adds
+//   2 u . df/dmu_k = +-2 (sum_n (u_n . t) b_n(s*)) |x'(s*)| ds*/dmu_k
+// (+ at the upper end of a material interval, - at the lower), added to
+// dJ/dmu after k_chain_mu4.  One thread per cell.
+__global__ __launch_bounds__(64) void k_load_mu(ChainArgs g) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const int ix = cell % g.nx, iy = cell / g.nx, e = g.edge, m = g.m, p = g.p;
+  const bool on_side = (e == 0 && ix == 0) || (e == 1 && ix == g.nx - 1) || (e == 2 && iy == 0) ||
+                       (e == 3 && iy == g.ny - 1);
+  if (!on_side) return;
+  const int ce = cell * 4 + e, mat = g.edge_nm[2 * ce + 1];
+  if (mat < 0) return;
+  const int k_side = e < 2 ? iy : ix;
+  const double t0 = g.trac[k_side * 2], t1 = g.trac[k_side * 2 + 1];
+  const double* u = g.ucell + (size_t)cell * g.ndof;
+  double P[5][2];
+  for (int k = 0; k <= m; ++k) {
+    const int a = e == 0 ? 0 : e == 1 ? m : k, b = e < 2 ? k : (e == 2 ? 0 : m);
+    const double* Q = g.ctrl + ((size_t)(m * iy + b) * g.netx + m * ix + a) * 2;
+    P[k][0] = Q[0];
+    P[k][1] = Q[1];
+  }
+  rule::Cell c;
+  c.fam = g.family[cell];
+  for (int k = 0; k < 4; ++k) c.mu[k] = g.thr[(size_t)cell * 4 + k];
+  const double* nodes = g.tab + g.T.off_edge_nodes;
+  const double* bw = g.tab + g.T.off_edge_bw;
+  const double* br = g.edge_br + (size_t)ce * kEdgeBreaks;
+  const int nb = g.edge_nm[2 * ce];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int iv = 0; iv + 1 < nb; ++iv) {
+    if (!((mat >> iv) & 1)) continue;
+    for (int side = 0; side < 2; ++side) {
+      const double s = br[iv + side];
+      if (s <= 0.0 || s >= 1.0) continue;  // a corner of the cell: fixed
+      const double x0 = e == 0 ? 0.0 : e == 1 ? 1.0 : s, y0 = e < 2 ? s : (e == 2 ? 0.0 : 1.0);
+      double f, gx, gy;
+      rule::phi_grad(c, x0, y0, f, gx, gy);
+      const double dphi = e < 2 ? gy : gx;
+      double dBs[5];
+      bernstein_deriv_at(m, s, dBs);
+      double d0 = 0, d1 = 0;
+      for (int k = 0; k <= m; ++k) { d0 += dBs[k] * P[k][0]; d1 += dBs[k] * P[k][1]; }
+      double ub = 0.0;
+      for (int n = 0; n <= p; ++n) {
+        const int node = (n == 0) ? ((e == 1) ? 1 : (e == 3) ? 2 : 0)
+                                  : (n == p ? ((e == 0) ? 2 : (e == 2) ? 1 : 3) : 4 + e * (p - 1) + (n - 1));
+        ub += (u[g.nI + 2 * node] * t0 + u[g.nI + 2 * node + 1] * t1) * gll_lagrange(nodes, bw, p, n, s);
+      }
+      const double v = (side ? 2.0 : -2.0) * ub * sqrt(d0 * d0 + d1 * d1) / dphi;
+      acc[0] += v * (1.0 - x0) * (1.0 - y0);
+      acc[1] += v * x0 * (1.0 - y0);
+      acc[2] += v * (1.0 - x0) * y0;
+      acc[3] += v * x0 * y0;
+    }
+  }
+  for (int k = 0; k < 4; ++k) g.gmu[(size_t)cell * 4 + k] += acc[k];
 }
 
 // dJ/dmu_i = -(1 - rho) sum_nodes d/dmu_i [l_1 l_2 l_3 l_4](node) h(node),
@@ -646,6 +750,8 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
   a.trac = c->d_trac + (size_t)rhs * c->n_side * 2;
   a.edge = c->load_edge;
   a.gcell = c->d_gcell; a.gt = c->d_gt + (size_t)rhs * c->ncell;
+  a.thr = c->d_mu; a.edge_br = c->d_edge_br; a.edge_nm = c->d_edge_nm;
+  a.gmu = c->d_gmu + (size_t)rhs * c->ncell * 4;
   switch (c->m) {
 #define CHN(mm) case mm: hipLaunchKernelGGL(k_chain<mm>, dim3((c->ncell + 63) / 64), dim3(64), 0, c->stream, a); break;
     CHN(1) CHN(2) CHN(3) CHN(4)
@@ -665,6 +771,7 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
       hipLaunchKernelGGL(k_chain_mu4, dim3(c->tile_fam_n[sl], 2), dim3(256), 0, c->stream, b, c->d_sorted,
                          reinterpret_cast<const int4*>(c->d_tiles) + c->tile_fam_first[sl]);
     }
+    hipLaunchKernelGGL(k_load_mu, dim3((c->ncell + 63) / 64), dim3(64), 0, c->stream, a);
   }
   const int nnet = c->netx * c->nety;
   hipLaunchKernelGGL(k_net_gather, dim3((nnet + 255) / 256), dim3(256), 0, c->stream, c->d_gcell, c->d_net_ptr,

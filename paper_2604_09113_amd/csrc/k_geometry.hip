@@ -16,7 +16,8 @@
 //    tensor-product interpolant.
 // k_constraints: edge-average and edge-moment rows of the coarse dofs
 //  (Sec. 3.3.1) by Gauss quadrature along the physical edge.
-// k_loads: consistent load of the right-edge traction (Sec. 2.2.1).
+// k_loads: consistent load of the traction on the loaded side (Sec. 2.2.1),
+//  on the material part of the edge for Table 1 cells.
 #include "internal.h"
 #include "implicit_rule.h"
 
@@ -433,6 +434,7 @@ struct LoadArgs {
   int ncell, nx, ny, netx, m, p, nU, nrhs;
   int edge, n_side;  // loaded side as a cell edge (0 left, 1 right, 2 bottom, 3 top)
   double* load;  // [nrhs][ncell][nU]
+  const double* edge_br; const int* edge_nm;  // the material part of each edge (k_edge_roots)
 };
 
 // Skeleton node slot of node n (0..p, increasing running coordinate) of edge e:
@@ -470,10 +472,32 @@ __global__ __launch_bounds__(64) void k_loads(LoadArgs g) {
   const double* dB = g.tab + g.T.off_load_dB;
   const double tc = g.trac[((size_t)rhs * g.n_side + k_side) * 2 + comp];
   double f = 0;
-  for (int qd = 0; qd < nq; ++qd) {
-    double d0 = 0, d1 = 0;
-    for (int k = 0; k <= g.m; ++k) { d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1]; }
-    f += w[qd] * bl[n * nq + qd] * sqrt(d0 * d0 + d1 * d1);
+  const int ce = cell * 4 + e, mat = g.edge_nm[2 * ce + 1];
+  if (mat >= 0) {
+    // a Table 1 cell: the traction acts on the material part of the edge
+    const double* xq = g.tab + g.T.off_load_x;
+    const double* nodes = g.tab + g.T.off_edge_nodes;
+    const double* bw = g.tab + g.T.off_edge_bw;
+    const double* br = g.edge_br + (size_t)ce * kEdgeBreaks;
+    const int nb = g.edge_nm[2 * ce];
+    for (int iv = 0; iv + 1 < nb; ++iv) {
+      if (!((mat >> iv) & 1)) continue;
+      const double a = br[iv], b = br[iv + 1];
+      for (int qd = 0; qd < nq; ++qd) {
+        const double s = a + (b - a) * xq[qd];
+        double dBs[5];
+        bernstein_deriv_at(g.m, s, dBs);
+        double d0 = 0, d1 = 0;
+        for (int k = 0; k <= g.m; ++k) { d0 += dBs[k] * P[k][0]; d1 += dBs[k] * P[k][1]; }
+        f += (b - a) * w[qd] * gll_lagrange(nodes, bw, p, n, s) * sqrt(d0 * d0 + d1 * d1);
+      }
+    }
+  } else {
+    for (int qd = 0; qd < nq; ++qd) {
+      double d0 = 0, d1 = 0;
+      for (int k = 0; k <= g.m; ++k) { d0 += dB[k * nq + qd] * P[k][0]; d1 += dB[k * nq + qd] * P[k][1]; }
+      f += w[qd] * bl[n * nq + qd] * sqrt(d0 * d0 + d1 * d1);
+    }
   }
   out[l] = f * tc;
 }
@@ -518,6 +542,7 @@ hipError_t launch_constraints_loads(Ctx* c) {
   hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, c->stream, a);
   LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs,
                 c->load_edge, c->n_side, c->d_load};
+  l.edge_br = c->d_edge_br; l.edge_nm = c->d_edge_nm;
   if (c->nU > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_loads, dim3(c->ncell, c->nrhs), dim3(64), 0, c->stream, l);
   return hipGetLastError();

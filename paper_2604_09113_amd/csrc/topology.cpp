@@ -481,6 +481,8 @@ void build_tables(Ctx* c, std::vector<double>& tab) {
   T.off_load_dB = mark();
   for (int a = 0; a <= m; ++a)
     for (double x : gx) tab.push_back(bernstein_derivative(m, a, x));
+  T.off_load_x = mark();
+  for (double x : gx) tab.push_back(x);
   // GLL points of the MDEIM interpolation degree of each family slot
   for (int s = 0; s < 4; ++s) T.off_rnodes[s] = -1;
   for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) {

@@ -182,3 +182,52 @@ def test_trimmed_edge_rows_shared_by_neighbours():
         ra = edge_constraint_rows(A, 4, "top", True, TrimmedCell(fam, muA))
         rc = edge_constraint_rows(C, 4, "bottom", True, TrimmedCell(fam, muC))
         np.testing.assert_allclose(ra, rc, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.4, -0.7])
+def test_trimmed_traction_closed_form(mu):
+    """The traction on the material part of the loaded edge: Schwarz
+    Primitive at a constant threshold on [0, L]^2, right edge, material part
+    (a, 1 - a) with a = arccos(mu) / (2 pi): the nodal loads sum to
+    L (1 - 2a) t and their first moment is L ((1 - a)^2 - a^2) / 2 t; with
+    phi_0 < mu everywhere they equal the whole-edge loads."""
+    from oracle.basis import gll_nodes
+    from oracle.bddc import traction_load
+    from oracle.implicit import TrimmedCell
+    p, L, t = 6, 1.7, np.array([0.3, -1.1])
+    a = np.arccos(mu) / (2 * np.pi)
+    f = traction_load(_square(L), p, t, "right", TrimmedCell(3, (mu,) * 4))
+    s = gll_nodes(p)
+    np.testing.assert_allclose(f.sum(axis=0), L * (1 - 2 * a) * t, rtol=1e-13)
+    np.testing.assert_allclose(s @ f, L * ((1 - a) ** 2 - a ** 2) / 2 * t, rtol=1e-13)
+    rng = np.random.default_rng(4)
+    X = _square(1.2) + 0.05 * rng.normal(size=(3, 3, 2))
+    np.testing.assert_allclose(traction_load(X, p, t, "right", TrimmedCell(2, (1.1, 1.3, 1.2, 1.05))),
+                               traction_load(X, p, t, "right"), rtol=0, atol=1e-14)
+
+
+def test_moving_end_term_of_the_load():
+    """dJ/dmu of a lattice whose loaded edges are partly void against central
+    differences along thresholds of the loaded cells only; without the
+    Leibniz term of the moving ends the adjoint misses by far more than the
+    tolerance."""
+    import oracle.adjoint as A
+    prob = small_tpms()
+    roms = oracle_roms(prob)
+    P = Problem(prob, roms)
+    u = P.direct_solve()
+    _, _, _, gmu = A.compliance_gradient(P, u, thresholds=True)
+    loaded = np.array(sorted(P.load_pos))
+    dmu = np.zeros_like(prob["mu"])
+    dmu[loaded] = np.random.default_rng(8).normal(size=(len(loaded), 4))
+    dmu /= np.linalg.norm(dmu)
+    fd = A.fd_directional(prob, roms, np.zeros_like(prob["ctrl"]), np.zeros_like(prob["t"]), h=1e-6, dmu=dmu)[0]
+    ad = (gmu[0] * dmu).sum()
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+    orig = A._load_end_rate
+    try:
+        A._load_end_rate = lambda *a: np.zeros(4)
+        _, _, _, g0 = A.compliance_gradient(P, u, thresholds=True)
+    finally:
+        A._load_end_rate = orig
+    assert abs(fd - (g0[0] * dmu).sum()) > 1e-3 * abs(ad)
