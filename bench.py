@@ -91,19 +91,20 @@ def kernel_bytes(prob, roms, nC):
     return out
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, record="lattice128_p8_hbm_traffic.md", workload=None):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
-    counter records (profiles/lattice128_p8_hbm_traffic.md), or None when there is
-    no record for it or its source file has changed since the counters were taken."""
+    counter records (profiles/<record>; for `workload` only, when the record
+    names one), or None when there is no record for it or its source file has
+    changed since the counters were taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "lattice128_p8_hbm_traffic.md")
+    path = os.path.join(root, "profiles", record)
     try:
         for line in open(path):
             if not line.startswith("traffic-record:"):
                 continue
             rec = json.loads(line.split(":", 1)[1])
-            if rec["kernel"] != kernel:
+            if rec["kernel"] != kernel or rec.get("workload", workload) != workload:
                 continue
             src = open(os.path.join(root, rec["source"]), "rb").read()
             if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
@@ -500,7 +501,8 @@ def bench_tpms(args, prob, solver):
                 note="2 x 2 npair 36 (n_r + 1 + 4) FP64 flops per cell (the assembly contraction's count, "
                      "transposed product included) over the event-timed adjoint kernel")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    # counter-measured bytes per launch (profiles/annulus184x92_p8_adjoint_traffic.md), for that workload only
+    roof["traffic"] = measured_traffic(roof["kernel"], "annulus184x92_p8_adjoint_traffic.md", prob["config"])
     out = {
         "metric": METRIC, "value": ncell / (mixed["ms_per_step"] * 1e-3), "unit": "cells/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms_per_step"], "higher_is_better": True,
