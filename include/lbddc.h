@@ -43,7 +43,12 @@
  * (homogeneous Dirichlet on both components, strongly, on the whole side) and
  * one loaded side that carries a traction, constant on each cell edge of that
  * side (per unit physical length); the other sides are traction free.  The
- * benchmark lattices clamp the left side (x = 0) and load the right side.
+ * traction acts on the boundary of the material (Sec. 4.1): on a cell of a
+ * four-parameter family only on the material part {phi_0 < mu} of its loaded
+ * edge, whose ends then also enter dJ/dmu; on the other families on the whole
+ * edge.  The edge averages and moments of the coarse space (Sec. 3.3.1) take
+ * the same domain of each edge.  The benchmark lattices clamp the left side
+ * (x = 0) and load the right side.
  *
  * Level sets: each cell belongs to a level-set family.  A family has either one
  * parameter per cell, t (a thickness), or four: the corner values mu_1..mu_4
