@@ -119,8 +119,12 @@ def compliance_gradient(P, unodes, thresholds=False):
                     # thresholds (Leibniz rule), s* with phi(s*) = 0 moving by
                     # l_k(s*) / (d phi / d s)(s*) per unit of mu_k
                     if dom is not None:
+                        # a break shared by two material intervals is the upper
+                        # end of one and the lower end of the other: the two
+                        # terms cancel, and are skipped
+                        shared = {a for a, _ in pieces} & {b for _, b in pieces}
                         for s_end, sign in ((b0, 1.0), (a0, -1.0)):
-                            if s_end <= 0.0 or s_end >= 1.0:
+                            if s_end <= 0.0 or s_end >= 1.0 or s_end in shared:
                                 continue
                             gmu[r, c, :] += sign * 2.0 * _load_end_rate(dom, e, X, p, ut, s_end)
     if thresholds:

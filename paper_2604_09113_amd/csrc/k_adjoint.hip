@@ -490,6 +490,10 @@ __global__ __launch_bounds__(64) void k_load_mu(ChainArgs g) {
     for (int side = 0; side < 2; ++side) {
       const double s = br[iv + side];
       if (s <= 0.0 || s >= 1.0) continue;  // a corner of the cell: fixed
+      // a break between two material intervals is the upper end of one and
+      // the lower end of the other: the two terms cancel, and are skipped
+      const int other = side ? iv + 1 : iv - 1;
+      if (other >= 0 && ((mat >> other) & 1)) continue;
       const double x0 = e == 0 ? 0.0 : e == 1 ? 1.0 : s, y0 = e < 2 ? s : (e == 2 ? 0.0 : 1.0);
       double f, gx, gy;
       rule::phi_grad(c, x0, y0, f, gx, gy);
