@@ -133,3 +133,27 @@ def test_cell_control_points_by_hand():
         assert tuple(X[1, 1]) == (2 * ix + 1.0, 100 + 2 * iy + 1.0)
         F, _ = g.map_eval(X, np.array([1.0, 0.5]), np.array([0.0, 0.5]))
         np.testing.assert_allclose(F, [[2 * ix + 2, 100 + 2 * iy], [2 * ix + 1, 101 + 2 * iy]], atol=1e-13)
+
+
+def test_cell_control_points_on_the_annulus():
+    """cell_control_points against the closed form of the benchmark's quarter
+    annulus (no jitter): the map of cell (ix, iy) takes its parametric corners
+    to the annulus points at s = ix/nx or (ix+1)/nx and u = iy/ny or
+    (iy+1)/ny, x = -r sin(pi s / 2), y = -r cos(pi s / 2), r = 0.6 + 0.4 u.
+    A lattice of 5 x 3 cells (nx != ny), so a transposed (ix, iy) or a
+    swapped corner fails."""
+    from workloads import make_problem
+    prob = make_problem(7, nx=5, ny=3, p=4)
+    nx, ny, m = prob["nx"], prob["ny"], prob["m"]
+
+    def annulus(s, u):
+        r = 0.6 + 0.4 * u
+        return np.array([-r * np.sin(0.5 * np.pi * s), -r * np.cos(0.5 * np.pi * s)])
+
+    for iy in range(ny):
+        for ix in range(nx):
+            X = g.cell_control_points(prob["ctrl"], m, ix, iy)
+            for a in (0, 1):
+                for b in (0, 1):
+                    F, _ = g.map_eval(X, np.array([float(a)]), np.array([float(b)]))
+                    np.testing.assert_allclose(F[0], annulus((ix + a) / nx, (iy + b) / ny), rtol=0, atol=1e-14)
