@@ -210,9 +210,13 @@ lbddc_status lbddc_set_geometry_device(lbddc_ctx* ctx, const double* d_ctrl, con
 lbddc_status lbddc_assemble_fp32_noalloc(lbddc_ctx* ctx, float* d_K);
 
 /* Per-cell geometry coefficients, MDEIM evaluation and the batched contraction
- * K_i = sum_q theta_q Khat_q (Alg. 4, 5), plus the cell loads.  `prec`:
- * LBDDC_FP64 and LBDDC_MIXED both contract in FP64 (the operator); see
- * LBDDC_FP32_CONTRACTION for the FP32 variant. */
+ * K_i = sum_q theta_q Khat_q (Alg. 4, 5), plus the cell loads and the edge
+ * constraint rows (Sec. 3.3.1; on the material part of the edges of
+ * four-parameter cells, whose ends come from an interval-checked root search
+ * along each edge).  `prec`: LBDDC_FP64 and LBDDC_MIXED both contract in FP64
+ * (the operator); see LBDDC_FP32_CONTRACTION for the FP32 variant.
+ * LBDDC_E_NUMERIC if an edge's material part needs more than 16 breaks (ends
+ * and roots) or its root search does not converge. */
 lbddc_status lbddc_assemble(lbddc_ctx* ctx, lbddc_precision prec);
 
 /* Local Schur complements, weights, constrained local factorizations, coarse
