@@ -515,7 +515,7 @@ def bench_tpms(args, prob, solver):
                                 f"{prob['m']} jittered maps, bilinear corner thresholds (d = 4) graded 0.9 -> 0.1 "
                                 f"across x") + f", ROM of {scfg['n_k'] ** 4} clusters x {nn} fitting nodes trained "
                                                f"on the GPU",
-                   "cells": ncell, "p": prob["p"], "n_r": rom["n_r"]},
+                   "cells": ncell, "p": prob["p"], "n_r": rom["n_r"], "n_s": scfg["n_s"], "rho": prob["rho"]},
         "roofline": roof,
         "assembly_fp64_mfma_frac": assembly_flops(prob, roms) / (mixed["phases_ms"]["assembly_kernel"] * 1e-3) / 1e12
         / PEAK["fp64_TFs"],

@@ -74,9 +74,10 @@ CONFIGS = {
     # threshold (d = 4), graded across the lattice like the paper's benchmark
     # (mu = 0.9 - 0.8 x / L at the vertices) plus U[-0.05, 0.05], clipped to
     # the box [0.1, 0.9]; 2 clusters per threshold (16), r = 6 (7^4 nodes).
-    # rho = 2e-3: with 100 snapshots per cluster and n_r = 40 the surrogate's
-    # error (up to ~4e-4 of |I|) outweighs rho = 5e-4 and leaves the coarse
-    # matrix indefinite
+    # rho = 2e-3: with n_r = 40 the surrogate's error (up to ~4e-4 of |I| with
+    # 100 snapshots per cluster) outweighs rho = 5e-4 on these jittered cells
+    # with noisy thresholds and leaves the coarse matrix or the interface
+    # operator indefinite (also with 200 snapshots)
     6: dict(nx=128, ny=128, p=8, q=2, m=2, jitter=0.03, warp=0.0, topo="schwarz_d",
             t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=2e-3, moments=True,
             rtol=1e-8, nrhs=1, load="unit", mu_mode="graded", mu_noise=0.05,
@@ -86,11 +87,13 @@ CONFIGS = {
     # Diamond cells with mu = 0.9 - 0.8 xi~_1 at the vertices, E = 5, nu = 0.25,
     # xi~_1 = 0 clamped and a traction of 0.1 pointing down (-y) on xi~_1 = 1;
     # the map of every cell is an order-3 Bezier patch whose control points lie
-    # on the (mirrored) annulus at the uniform grid of the auxiliary coordinates
+    # on the (mirrored) annulus at the uniform grid of the auxiliary coordinates;
+    # the paper's rho = 5e-4, which 200 Latin-hypercube snapshots per cluster
+    # keep positive definite (100 do not)
     7: dict(nx=184, ny=92, p=8, q=2, m=3, jitter=0.0, warp=0.0, topo="schwarz_d", map="annulus",
-            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=2e-3, moments=True, E=5.0, nu=0.25,
+            t_mode="uniform", t_lo=0.1, t_hi=0.3, rho=5e-4, moments=True, E=5.0, nu=0.25,
             rtol=1e-8, nrhs=1, load="down", load_value=0.1, mu_mode="graded", mu_noise=0.0,
-            rom={2: dict(lo=0.1, hi=0.9, n_k=2, n_s=100, n_r=40, r=6, dim=4)}),
+            rom={2: dict(lo=0.1, hi=0.9, n_k=2, n_s=200, n_r=40, r=6, dim=4)}),
 }
 
 
