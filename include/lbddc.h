@@ -86,8 +86,9 @@ typedef enum {
 
 typedef enum {
   LBDDC_FP64 = 0,   /* every step in FP64 */
-  LBDDC_MIXED = 1,  /* FP64 operator, recurrence and coarse solve; the constrained local
-                       factorizations and the preconditioner data and solves in FP32 */
+  LBDDC_MIXED = 1,  /* FP64 operator, recurrence and coarse solve; the preconditioner's
+                       data (fine operator, coarse basis) formed in FP64, stored and
+                       applied in FP32 */
   /* lbddc_assemble only: the theta x Khat contraction (Sec. 4.1, Alg. 4 with
    * the MDEIM reconstruction of Alg. 5) in FP32 on MFMA with FP32
    * accumulation, from FP32 copies of the geometry coefficients, the MDEIM

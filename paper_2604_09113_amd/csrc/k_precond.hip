@@ -23,7 +23,11 @@
 // Partition-of-unity weights (Sec. 3.3.3): D_jj = K_jj / sum over the cells
 // sharing the dof of their K_jj.
 //
-// T = double (plain path) or float (mixed path: Shat, That, P, Psi in FP32).
+// T is the arithmetic, TO the stored precision of P and Psi: double/double on
+// the plain path; double/float on the mixed path, whose solve streams P and
+// Psi in FP32.  Forming the inverses in FP64 keeps the stored operator within
+// FP32 rounding of the FP64 one even when rho makes Shat ill conditioned (an
+// FP32 Gauss-Jordan loses about cond(Shat) times FP32 epsilon).
 #include "internal.h"
 #include "wave_gj.h"
 
@@ -82,11 +86,11 @@ __device__ __forceinline__ void mfma_mm(FA a, FB b, FO out) {
   }
 }
 
-template <typename T, int P, int NCE>
+template <typename T, typename TO, int P, int NCE>
 __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, const double* __restrict__ cons,
                                                  const double* __restrict__ diagK, const double* __restrict__ Ktot,
-                                                 const int* __restrict__ RU, T* __restrict__ Pout,
-                                                 T* __restrict__ Psiout, double* __restrict__ Dout,
+                                                 const int* __restrict__ RU, TO* __restrict__ Pout,
+                                                 TO* __restrict__ Psiout, double* __restrict__ Dout,
                                                  double* __restrict__ ScOut, int* __restrict__ flags) {
   constexpr int NU = 8 * P, NE = NU - 8, NCC = 4 * NCE, NC = 8 + NCC;
   constexpr int NSP = NU * (NU + 1) / 2;
@@ -201,10 +205,10 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
                           [&](int i, int j, T v) { A[i][j] -= v; });
   __syncthreads();
   // store D_E P D_E packed lower
-  T* Pc = Pout + (size_t)cell * (NE * (NE + 1) / 2);
+  TO* Pc = Pout + (size_t)cell * (NE * (NE + 1) / 2);
   for (int i = tid >> 6; i < NE; i += 4)
     for (int j = tid & 63; j <= i; j += 64)
-      Pc[i * (i + 1) / 2 + j] = (T)(Dv[8 + i] * (double)A[i][j] * Dv[8 + j]);
+      Pc[i * (i + 1) / 2 + j] = (TO)(Dv[8 + i] * (double)A[i][j] * Dv[8 + j]);
   // coarse basis Psi [NU][NC]: corner rows are the identity (masked for
   // clamped corners); edge rows: edge constraint columns W2, corner columns
   // -P S[E, c] - W2 C[:, c] (one product of depth NE + NCC)
@@ -227,10 +231,10 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   __syncthreads();
   // stored column by column, [NC][NU]: the PCG kernels read entry i of every
   // column in lane i
-  T* Pso = Psiout + (size_t)cell * NU * NC;
+  TO* Pso = Psiout + (size_t)cell * NU * NC;
   for (int idx = tid; idx < NU * NC; idx += 256) {
     const int j = idx / NU, i = idx % NU;
-    Pso[idx] = (T)(Dv[i] * Ps[i][j]);
+    Pso[idx] = (TO)(Dv[i] * Ps[i][j]);
   }
   for (int j = tid; j < NU; j += 256) Dout[(size_t)cell * NU + j] = Dv[j];
   // S Psi in FP64 (S packed lower, read through the cache), then Psi^T S Psi;
@@ -267,14 +271,14 @@ hipError_t launch_weights(Ctx* c) {
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename TO>
 static hipError_t precond_T(Ctx* c) {
   dim3 grid(c->ncell), block(256);
-  T* Pout = (T*)c->d_P;
-  T* Psi = (T*)c->d_Psi;
+  TO* Pout = (TO*)c->d_P;
+  TO* Psi = (TO*)c->d_Psi;
 #define PC_CASE(pp, ncv)                                                                                          \
   if (c->p == pp && c->nce == ncv) {                                                                             \
-    hipLaunchKernelGGL((k_precond<T, pp, ncv>), grid, block, 0, c->stream, c->d_S, c->d_cons, c->d_diagK,         \
+    hipLaunchKernelGGL((k_precond<T, TO, pp, ncv>), grid, block, 0, c->stream, c->d_S, c->d_cons, c->d_diagK,     \
                        c->d_Ktot, c->d_RU, Pout, Psi, c->d_D, c->d_ScLoc, c->d_flags);                    \
     return hipGetLastError();                                                                                    \
   }
@@ -284,6 +288,8 @@ static hipError_t precond_T(Ctx* c) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_precond(Ctx* c, bool fp32) { return fp32 ? precond_T<float>(c) : precond_T<double>(c); }
+hipError_t launch_precond(Ctx* c, bool fp32) {
+  return fp32 ? precond_T<double, float>(c) : precond_T<double, double>(c);
+}
 
 }  // namespace lbddc
