@@ -96,33 +96,45 @@ __global__ __launch_bounds__(256) void k_precond(const double* __restrict__ Sg, 
   constexpr int NSP = NU * (NU + 1) / 2;
   static_assert(NU <= 64, "one row per lane");
   const int cell = blockIdx.x, tid = threadIdx.x;
-  // the first-stage arrays are dead once Psi is formed; S Psi takes their space
+  // The first-stage arrays are dead once Psi is formed; S Psi takes the space
+  // of A.  X, That and Chat are dead once P is formed, before Psi is written,
+  // so the coarse basis takes theirs (the LDS of a workgroup then allows three
+  // per CU in FP64 instead of two).
+  struct Early {
+    T X[NE][NCC + 1];    // Shat^-1 Chat^T
+    T Tm[NCC][NCC + 1];  // That, then That^-1
+    T Ch[NCC][NE];
+  };
   struct Stage1 {
     T A[NE][NE + 1];     // Shat, then Shat^-1, then P
-    T X[NE][NCC + 1];    // Shat^-1 Chat^T
     T W2[NE][NCC + 1];   // X That^-1
-    T Ch[NCC][NE];
     T Cc[NCC][8];
-    T Tm[NCC][NCC + 1];  // That, then That^-1
     T Scol[NE][8];
+    union {
+      Early e;
+      double Ps[NU][NC + 1];  // coarse basis (unscaled)
+    } tail;
   };
   union Work {
     Stage1 s;
     double SPs[NU][NC + 1];  // S Psi
   };
+  static_assert(sizeof(double[NU][NC + 1]) <= sizeof(T[NE][NE + 1]) + sizeof(T[NE][NCC + 1]) +
+                    sizeof(T[NCC][8]) + sizeof(T[NE][8]),
+                "S Psi stays clear of the coarse basis it is formed from");
   __shared__ Work wk;
   __shared__ double Dv[NU];
-  __shared__ double Ps[NU][NC + 1];  // coarse basis (unscaled)
+  auto& Ps = wk.s.tail.Ps;
   __shared__ int bad;
   // clamped corners [0, 4) and clamped edges [4, 8) of the cell: their slots
   // have no global skeleton dof (Dirichlet), so they carry no constraint
   __shared__ int clamp[8];
   auto& A = wk.s.A;
-  auto& X = wk.s.X;
+  auto& X = wk.s.tail.e.X;
   auto& W2 = wk.s.W2;
-  auto& Ch = wk.s.Ch;
+  auto& Ch = wk.s.tail.e.Ch;
   auto& Cc = wk.s.Cc;
-  auto& Tm = wk.s.Tm;
+  auto& Tm = wk.s.tail.e.Tm;
   auto& Scol = wk.s.Scol;
   const double* S = Sg + (size_t)cell * NSP;
   if (tid == 0) bad = 0;
