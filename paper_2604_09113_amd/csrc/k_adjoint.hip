@@ -540,6 +540,9 @@ struct ChainMu4Args {
   double* gmu;  // [ncell][4]
 };
 
+// R1 = r + 1 nodes per threshold, a compile-time constant (the node decode
+// becomes multiplications).
+template <int R1>
 __global__ __launch_bounds__(256) void k_chain_mu4(ChainMu4Args g, const int* __restrict__ sorted,
                                                    const int4* __restrict__ tiles) {
   const int4 td = tiles[blockIdx.x];
@@ -547,7 +550,8 @@ __global__ __launch_bounds__(256) void k_chain_mu4(ChainMu4Args g, const int* __
   const int ncells = td.z - c0;
   if (ncells <= 0) return;  // uniform over the workgroup
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int R = g.r, R1 = R + 1, nr = g.n_r, nn = R1 * R1 * R1 * R1;
+  constexpr int R = R1 - 1, nn = R1 * R1 * R1 * R1;
+  const int nr = g.n_r;
   __shared__ double ell[64][4][9], dell[64][4][9];
   __shared__ double cf[64][49];
   {
@@ -772,8 +776,14 @@ hipError_t launch_gradient(Ctx* c, int rhs) {
       b.n_k = R.n_k; b.n_r = R.n_r; b.r = R.r; b.off_rnodes = c->tab.off_rnodes[sl];
       b.itil_stride = 4 * c->KC; b.rho = c->rho; b.H = c->d_H;
       b.gmu = c->d_gmu + (size_t)rhs * c->ncell * 4;
-      hipLaunchKernelGGL(k_chain_mu4, dim3(c->tile_fam_n[sl], 2), dim3(256), 0, c->stream, b, c->d_sorted,
-                         reinterpret_cast<const int4*>(c->d_tiles) + c->tile_fam_first[sl]);
+      const int4* tl = reinterpret_cast<const int4*>(c->d_tiles) + c->tile_fam_first[sl];
+      const dim3 grid(c->tile_fam_n[sl], 2);
+      switch (R.r) {
+#define CM4(rr) case rr: hipLaunchKernelGGL(k_chain_mu4<rr + 1>, grid, dim3(256), 0, c->stream, b, c->d_sorted, tl); break;
+        CM4(1) CM4(2) CM4(3) CM4(4) CM4(5) CM4(6) CM4(7) CM4(8)
+#undef CM4
+        default: return hipErrorInvalidValue;
+      }
     }
     hipLaunchKernelGGL(k_load_mu, dim3((c->ncell + 63) / 64), dim3(64), 0, c->stream, a);
   }

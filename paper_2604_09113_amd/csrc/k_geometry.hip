@@ -189,6 +189,9 @@ struct Mdeim4Args {
   double* itil; float* itil32;
 };
 
+// R1 = r + 1 nodes per threshold, a compile-time constant so that the node
+// decode n -> (a1, a2, a3, a4) is multiplications, not integer divisions.
+template <int R1>
 __global__ __launch_bounds__(256) void k_mdeim4(Mdeim4Args g, const int* __restrict__ sorted,
                                                 const int4* __restrict__ tiles) {
   const int4 td = tiles[blockIdx.x];
@@ -196,7 +199,8 @@ __global__ __launch_bounds__(256) void k_mdeim4(Mdeim4Args g, const int* __restr
   const int ncells = td.z - c0;
   if (ncells <= 0) return;  // uniform over the workgroup
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int R = g.r, R1 = R + 1, nr = g.n_r, nn = R1 * R1 * R1 * R1;
+  constexpr int R = R1 - 1, nn = R1 * R1 * R1 * R1;
+  const int nr = g.n_r;
   __shared__ double ell[64][4][9];
   __shared__ double cf[64][49];
   {
@@ -264,8 +268,13 @@ hipError_t launch_mdeim4(Ctx* c, int slot, const int* d_tiles, int first, int n)
   a.mu = c->d_mu; a.tab = c->d_tab; a.coeff = R.coeff; a.lo = R.lo; a.hi = R.hi;
   a.n_k = R.n_k; a.n_r = R.n_r; a.r = R.r; a.off_rnodes = c->tab.off_rnodes[slot];
   a.itil_stride = 4 * c->KC; a.rho = c->rho; a.itil = c->d_itil; a.itil32 = c->d_itil32;
-  hipLaunchKernelGGL(k_mdeim4, dim3(n, 2), dim3(256), 0, c->stream, a, c->d_sorted,
-                     reinterpret_cast<const int4*>(d_tiles) + first);
+  const int4* tl = reinterpret_cast<const int4*>(d_tiles) + first;
+  switch (R.r) {
+#define MD4(rr) case rr: hipLaunchKernelGGL(k_mdeim4<rr + 1>, dim3(n, 2), dim3(256), 0, c->stream, a, c->d_sorted, tl); break;
+    MD4(1) MD4(2) MD4(3) MD4(4) MD4(5) MD4(6) MD4(7) MD4(8)
+#undef MD4
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
