@@ -39,7 +39,7 @@ static void release_problem(Ctx* c) {
   c->dev_bytes = 0;
 }
 
-// A context holding only what outlives a problem: device, stream, ROMs,
+// A context holding only what outlives a problem: device, streams, ROMs,
 // events, timing mask and the context-wide pinned buffers.  The ROM table is
 // shared (shallow copy): only one of the two contexts ever frees it.
 static void copy_persistent(const Ctx* c, Ctx* n) {
@@ -48,6 +48,9 @@ static void copy_persistent(const Ctx* c, Ctx* n) {
   n->own_stream = c->own_stream;
   n->roms = c->roms;
   for (int i = 0; i < Ctx::kNumEv; ++i) n->ev[i] = c->ev[i];
+  n->side = c->side;
+  n->side_fork = c->side_fork;
+  n->side_join = c->side_join;
   for (int i = 0; i < Ctx::kRing; ++i)
     for (int k = 0; k < Ctx::kRingEv; ++k) n->pev[i][k] = c->pev[i][k];
   n->timing = c->timing;
@@ -120,6 +123,12 @@ lbddc_status lbddc_create(int device, void* stream, lbddc_ctx** out) {
   }
   for (int i = 0; i < Ctx::kNumEv; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete x; return LBDDC_E_HIP; }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->side_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->side_join, hipEventDisableTiming) != hipSuccess) {
+    delete x;
+    return LBDDC_E_HIP;
+  }
   for (int i = 0; i < Ctx::kRing; ++i)
     for (int k = 0; k < Ctx::kRingEv; ++k)
       if (hipEventCreate(&c->pev[i][k]) != hipSuccess) { delete x; return LBDDC_E_HIP; }
@@ -152,6 +161,9 @@ void lbddc_destroy(lbddc_ctx* x) {
   if (c->h_flags) hipHostFree(c->h_flags);
   if (c->h_scal) hipHostFree(c->h_scal);
   if (c->h_red) hipHostFree(c->h_red);
+  if (c->side_fork) hipEventDestroy(c->side_fork);
+  if (c->side_join) hipEventDestroy(c->side_join);
+  if (c->side) hipStreamDestroy(c->side);
   if (c->own_stream) hipStreamDestroy(c->stream);
   delete x;
 }
@@ -512,10 +524,22 @@ lbddc_status lbddc_assemble(lbddc_ctx* x, lbddc_precision prec) {
   c->assembled = c->setup_done = c->solved = false;
   c->k32_valid = false;
   HIPCHK(hipEventRecord(c->ev[6], c->stream), "assemble");
+  // The edge rows and loads depend on the control net and the thresholds
+  // only.  On four-parameter lattices their root searches take about half a
+  // millisecond, so they run on the second stream beside the geometry pass and
+  // the contraction, joined before the end of the call.
+  const bool side = c->any_dim4;
+  if (side) {
+    HIPCHK(hipEventRecord(c->side_fork, c->stream), "assemble");
+    HIPCHK(hipStreamWaitEvent(c->side, c->side_fork, 0), "assemble");
+    HIPCHK(launch_constraints_loads(c, c->side), "assemble constraints");
+    HIPCHK(hipEventRecord(c->side_join, c->side), "assemble");
+  }
   HIPCHK(launch_geometry(c), "assemble geometry");
   HIPCHK(hipEventRecord(c->ev[2], c->stream), "assemble");
-  HIPCHK(launch_constraints_loads(c), "assemble constraints");
+  if (!side) HIPCHK(launch_constraints_loads(c, c->stream), "assemble constraints");
   HIPCHK(launch_assembly(c, fp32, c->ev[0], c->ev[1]), "assemble contraction");
+  if (side) HIPCHK(hipStreamWaitEvent(c->stream, c->side_join, 0), "assemble");
   HIPCHK(hipEventRecord(c->ev[7], c->stream), "assemble");
   lbddc_status s = check_flags(c, "assemble");
   if (s != LBDDC_OK) return s;

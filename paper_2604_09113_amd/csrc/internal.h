@@ -428,6 +428,11 @@ struct Ctx {
   double phase_ms[15] = {0};
   static constexpr int kNumEv = 9;
   hipEvent_t ev[kNumEv] = {};
+  // a second stream (default priority) for the edge rows and loads of
+  // four-parameter lattices, which run beside the geometry pass and the
+  // contraction; fork and join events without timing
+  hipStream_t side = nullptr;
+  hipEvent_t side_fork = nullptr, side_join = nullptr;
   // events of the timed PCG phases, a ring of kRing iterations read back at the
   // end of the solve (no host wait inside the loop): per slot [0, 1] operator,
   // [2, 3] preconditioner local kernel, [4, 5, 6] coarse solve start, between
@@ -455,7 +460,7 @@ hipError_t launch_geometry(Ctx* c);          // theta, det check, MDEIM eval (A1
 // MDEIM evaluation of a four-parameter family over its tiles [first, first + n)
 // of the cluster-sorted cell order (after the group sort of the contraction)
 hipError_t launch_mdeim4(Ctx* c, int slot, const int* d_tiles, int first, int n);
-hipError_t launch_constraints_loads(Ctx* c); // edge constraint rows and loads
+hipError_t launch_constraints_loads(Ctx* c, hipStream_t st); // edge constraint rows and loads
 hipError_t launch_assembly(Ctx* c, bool fp32, hipEvent_t e0, hipEvent_t e1);  // A3
 hipError_t noalloc_scratch_init(int device);                          // address of the static scratch (device current)
 lbddc_status assemble_fp32_noalloc(Ctx* c, float* d_K);               // A3, FP32, caller's output, static scratch

@@ -541,19 +541,19 @@ hipError_t launch_geometry(Ctx* c) {
   return hipGetLastError();
 }
 
-hipError_t launch_constraints_loads(Ctx* c) {
+hipError_t launch_constraints_loads(Ctx* c, hipStream_t st) {
   ConsArgs a = {c->d_ctrl, c->d_tab, c->tab, c->ncell, c->nx, c->netx, c->m, c->p, c->nce, c->d_cons};
   a.family = c->d_family; a.mu = c->d_mu; a.fam_slot = c->d_flags + 8; a.flags = c->d_flags;
   a.edge_br = c->d_edge_br; a.edge_nm = c->d_edge_nm;
   for (size_t s = 0; s < c->fam_ids.size() && s < 4; ++s) a.dim[s] = c->roms[c->fam_ids[s]].dim;
   const int nedge = c->ncell * 4, nth = nedge * (c->p + 1);
-  hipLaunchKernelGGL(k_edge_roots, dim3((nedge + 63) / 64), dim3(64), 0, c->stream, a);
-  hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, c->stream, a);
+  hipLaunchKernelGGL(k_edge_roots, dim3((nedge + 63) / 64), dim3(64), 0, st, a);
+  hipLaunchKernelGGL(k_constraints, dim3((nth + 255) / 256), dim3(256), 0, st, a);
   LoadArgs l = {c->d_ctrl, c->d_tab, c->d_trac, c->tab, c->ncell, c->nx, c->ny, c->netx, c->m, c->p, c->nU, c->nrhs,
                 c->load_edge, c->n_side, c->d_load};
   l.edge_br = c->d_edge_br; l.edge_nm = c->d_edge_nm;
   if (c->nU > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_loads, dim3(c->ncell, c->nrhs), dim3(64), 0, c->stream, l);
+  hipLaunchKernelGGL(k_loads, dim3(c->ncell, c->nrhs), dim3(64), 0, st, l);
   return hipGetLastError();
 }
 
